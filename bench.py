@@ -1,0 +1,162 @@
+"""Throughput of the noisy-trajectory ensemble on one MI355X.
+
+Workload (default): QAOA MaxCut p=4 on a seeded random 3-regular graph with
+n=26 qubits, depolarizing noise after every gate (1q 1e-3, 2q 1e-2), K=4096
+trajectories per job, complex64 contraction with FP64 reductions.  One step is
+one whole job: Philox sampling + Pauli frame, contraction of every
+trajectory, FP64 reduction and the read of <C> +- SE.  The plan (host
+lowering) is built once outside the timed region and reported separately.
+
+Prints one JSON line (value = trajectories/s over the timed steps) with the
+dominant kernel's roofline (algorithmic bytes per launch / HIP-event launch
+time, against 8 TB/s HBM) and the CPU FP64 oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "noisy trajectories/s at n=26 QAOA p=4 (⟨C⟩ err vs FP64); p50/p99 job latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def cpu_baseline(problem, sample_gates):
+    """The oracle's per-trajectory statevector (literal Kraus insertion,
+    complex128) on its first `sample_gates` gates of trajectory 0, scaled to
+    whole trajectories per second; one BLAS thread."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import simulate as sim
+    idx = sim.kraus_indices(problem, problem.seed, 0, 1)[0]
+    tabs = sim.site_tables(problem)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        sim.trajectory(problem, idx, tabs, max_gates=sample_gates)
+        dt = time.perf_counter() - t0
+    G = len(problem.gates)
+    per_traj = dt * G / sample_gates
+    return {"value": 1.0 / per_traj, "unit": "trajectories/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {sample_gates} of {G} gates (+ their noise sites) of trajectory 0 at "
+                      f"n={problem.n_qubits}, complex128, {dt:.1f} s, scaled by {G}/{sample_gates}"}
+
+
+def fp64_check(energies_by_k, problem):
+    """Largest |<C>_k - <C>_k(oracle, FP64)| / m over the stored oracle samples."""
+    path = os.path.join(ROOT, "tests", "golden", "config2_sampled.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        g = json.load(f)
+    m = len(problem.edges)
+    errs = [abs(energies_by_k[r["k"]] - r["energy"]) / m for r in g["trajectories"] if r["k"] in energies_by_k]
+    return {"max_abs_err_per_edge": max(errs) if errs else None, "trajectories": len(errs),
+            "reference": "oracle complex128, same draws (tests/golden/config2_sampled.json)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--K", type=int, default=None, help="trajectories per job (default: the workload's 4096)")
+    ap.add_argument("--batch", type=int, default=0, help="trajectories per launch (0: from the HBM budget)")
+    ap.add_argument("--hbm-budget-gib", type=float, default=160.0)
+    ap.add_argument("--cpu-sample-gates", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the trajectory ensemble shards by trajectory range across GPUs "
+              "with one FP64 all-reduce of the partial sums (not built in this repository); run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    from workloads import config_problem
+    problem = config_problem(2, K=args.K)
+    K = problem.K
+
+    cpu = None if args.no_cpu else cpu_baseline(problem, args.cpu_sample_gates)
+
+    import torch
+
+    import paper_2210_15874_amd as stn
+    torch.cuda.set_device(0)
+    stn.load()
+    t0 = time.perf_counter()
+    plan = stn.Plan(problem, outputs=stn.OUT_ENERGY, precision=64, max_batch=args.batch,
+                    hbm_budget=int(args.hbm_budget_gib * (1 << 30)))
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    info = plan.info()
+    B = info["max_batch"]
+
+    def job():
+        acc = plan.accum()
+        for k0 in range(0, K, B):
+            b = plan.sample(problem.seed, k0, min(B, K - k0))
+            plan.contract(b)
+            plan.reduce(b, acc)
+            b.close()
+        r = acc.read()
+        acc.close()
+        return r
+
+    for _ in range(args.warmup):
+        job()
+    torch.cuda.synchronize()
+    plan.profile(True)
+    times = []
+    t_all = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        res = job()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_all
+    prof = plan.profile_read()
+    plan.profile(False)
+
+    value = K * args.steps / wall
+    kern = prof["sv_pass"] if prof["sv_pass"]["launches"] else prof["sv_lds"]
+    kname = "sv_pass" if prof["sv_pass"]["launches"] else "sv_lds"
+    achieved = kern["bytes"] / (kern["ms"] * 1e-3) / 1e9 if kern["ms"] else None
+    energies = {k: float(e) for k, e in enumerate(res["energies"])}
+    times.sort()
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "trajectories/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": problem.name, "n_qubits": problem.n_qubits, "p": problem.p,
+                   "graph": "random 3-regular (seed 1002)", "K": K, "lambda1": 1e-3, "lambda2": 1e-2,
+                   "contraction": "complex64 (FP32), FP64 reductions", "plan": info["plan_name"],
+                   "trajectories_per_launch": B, "passes_per_trajectory": info["n_passes"],
+                   "plan_ms": plan_ms},
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                     "launches": kern["launches"], "avg_launch_ms": kern["ms"] / max(1, kern["launches"]),
+                     "bytes_per_launch": kern["bytes"] / max(1, kern["launches"])},
+        "kernels": {k: {"launches": v["launches"], "ms": v["ms"]} for k, v in prof.items() if v["launches"]},
+        "result": {"energy_mean": res["energy_mean"], "energy_se": res["energy_se"],
+                   "fp64_check": fp64_check(energies, problem)},
+        "job_latency_ms": {"p50": times[len(times) // 2] * 1e3, "max": times[-1] * 1e3},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

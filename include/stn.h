@@ -1,0 +1,275 @@
+/*
+ * stn.h - C ABI of the stochastic-noise trajectory-ensemble library (gfx950).
+ *
+ * Method (arXiv 2210.15874, Sec. III-G "Stochastic Noise Implementation"):
+ * a noisy circuit is simulated as an ensemble of K noiseless-structure
+ * circuits; after every gate that carries noise channels, one uniform draw
+ * per channel picks a Kraus operator of the channel (Eq.(1), Sec. III-F) and
+ * the operator it names is inserted.  Each member (trajectory) is contracted
+ * to a statevector psi_k and the ensemble is reduced to
+ *     rho_hat = (1/K) sum_k |psi_k><psi_k|,   sigma_approx = diag(rho_hat),
+ * or to the QAOA MaxCut energy <C> = (1/K) sum_k <psi_k|C|psi_k>.
+ *
+ * The call sequence is plan -> sample -> contract -> reduce -> read:
+ *   stn_plan_create   host: validates the circuit and noise model, builds the
+ *                     noise-site table and the lowering (see stn_plan_kind),
+ *                     uploads gate tables.  Once per job.
+ *   stn_sample        device: Kraus index of every (trajectory, site) from
+ *                     Philox4x32-10, plus the per-trajectory gate signs and
+ *                     final Pauli frame.
+ *   stn_contract      device: contracts every trajectory of a batch; the
+ *                     trajectory index is the batch dimension of every kernel.
+ *   stn_reduce        device: FP64 ensemble reduction into an accumulator.
+ *   stn_accum_read    device -> host: K, rho_hat / sigma / <C> +- SE.
+ *
+ * Conventions
+ *   - Qubit q is bit q of a basis index (little-endian).  A k-qubit matrix
+ *     acting on (q0, q1) has local index bit(q0) + 2*bit(q1).
+ *   - Complex matrices are row-major, interleaved (re, im) doubles.
+ *   - rx/ry/rz(theta) = exp(-i theta P/2); zz(theta) = diag(1, e^{-i theta},
+ *     e^{-i theta}, 1); cx has control q0, target q1.
+ *   - Draw of site s in trajectory k: Philox4x32-10 with key (seed low, seed
+ *     high) and counter (k low, k high, s, 0); word 0 is r.  With the
+ *     selection probabilities q_j of the channel and binary64 prefix sums
+ *     c_j, thresholds T_j = min(2^32, floor(c_j * 2^32)), T_{J-1} = 2^32, and
+ *     the picked index is j = min{ j : r < T_j }.  The inserted operator is
+ *     K_j / sqrt(q_j) with q_j = Tr(K_j^dagger K_j)/d.
+ *
+ * Ownership: every input is copied by the call that receives it; handles are
+ * owned by the library until the matching *_destroy.  Device memory is taken
+ * from opts->dev_alloc / dev_free when given, else from hipMalloc / hipFree.
+ *
+ * Streams: calls taking `stream` (a hipStream_t, NULL = legacy default stream)
+ * only enqueue work; stn_accum_read and stn_batch_* readers synchronise it.
+ *
+ * Errors: every call returns a stn_status; no exception or abort crosses the
+ * ABI.  A failing call leaves its output handles NULL and the accumulator
+ * unchanged.  stn_last_error() returns a message for the last failure on the
+ * calling thread.
+ */
+#ifndef STN_H
+#define STN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    STN_OK = 0,
+    STN_E_INVALID = 1,      /* malformed input (qubit out of range, non-CPTP channel, ...) */
+    STN_E_UNSUPPORTED = 2,  /* valid input outside what the chosen lowering handles */
+    STN_E_OOM = 3,          /* device allocation failed or budget exceeded */
+    STN_E_DEVICE = 4,       /* HIP runtime error */
+    STN_E_STATE = 5         /* call out of order (e.g. reduce before contract) */
+} stn_status;
+
+typedef enum {
+    STN_G_H = 0, STN_G_X = 1, STN_G_Y = 2, STN_G_Z = 3,
+    STN_G_RX = 4, STN_G_RY = 5, STN_G_RZ = 6, STN_G_ZZ = 7, STN_G_CX = 8,
+    STN_G_U1 = 9,   /* explicit 2x2: mat = 8 doubles */
+    STN_G_U2 = 10   /* explicit 4x4: mat = 32 doubles */
+} stn_gate_kind;
+
+typedef struct {
+    uint32_t kind;          /* stn_gate_kind */
+    uint32_t q0, q1;        /* q1 ignored for one-qubit gates */
+    double theta;           /* rotation angle (rx, ry, rz, zz) */
+    const double* mat;      /* U1 / U2 only, else NULL */
+} stn_gate;
+
+typedef struct {
+    uint32_t n_qubits;
+    uint32_t n_gates;
+    const stn_gate* gates;
+} stn_circuit;
+
+typedef enum {
+    STN_CH_BITFLIP = 0,     /* [sqrt(p) X, sqrt(1-p) I]                      (Sec. III-F) */
+    STN_CH_DEPOL1 = 1,      /* [sqrt(1-3l/4) I, sqrt(l/4) X, Y, Z]           (Sec. III-F) */
+    STN_CH_DEPOL2 = 2,      /* 16 Pauli products P_a(x)P_b, index 4a+b, P_a on q0,
+                               weights 1-15l/16 (I(x)I) and l/16                        */
+    STN_CH_AMPDAMP = 3,     /* [[1,0],[0,sqrt(1-g)]], [[0,sqrt(g)],[0,0]]                */
+    STN_CH_KRAUS = 4        /* explicit: n_kraus matrices of 2x2 or 4x4 (by qubit count) */
+} stn_channel_kind;
+
+typedef struct {
+    uint32_t after_gate;    /* index of the gate it follows; non-decreasing along the list */
+    uint32_t kind;          /* stn_channel_kind */
+    uint32_t n_qubits;      /* 1 or 2 */
+    uint32_t q0, q1;
+    double param;           /* p, lambda or gamma */
+    uint32_t n_kraus;       /* STN_CH_KRAUS only */
+    const double* kraus;    /* STN_CH_KRAUS only: n_kraus row-major interleaved matrices */
+} stn_channel;
+
+typedef struct {
+    uint32_t n_channels;
+    const stn_channel* channels;   /* site s = position in this array */
+} stn_noise_model;
+
+/* MaxCut-type observable C = sum_t w_t (1 - Z_{u_t} Z_{v_t}) / 2. */
+typedef struct {
+    uint32_t n_terms;
+    const uint32_t* uv;     /* 2 * n_terms qubit indices */
+    const double* w;        /* n_terms weights */
+} stn_observable;
+
+enum {
+    STN_OUT_RHO = 1,        /* rho_hat (n <= 13) */
+    STN_OUT_DIAG = 2,       /* sigma_approx = diag(rho_hat) (n <= 13) */
+    STN_OUT_ENERGY = 4,     /* <C> and its standard error (needs an observable) */
+    STN_OUT_STATES = 8      /* keep per-trajectory statevectors in the batch (n <= 13) */
+};
+
+typedef enum {
+    STN_PLAN_AUTO = 0,
+    STN_PLAN_SV_LDS = 1,    /* whole trajectory state in LDS, any circuit, n <= 13 (c64) / 12 (c128) */
+    STN_PLAN_SV_TILED = 2,  /* HBM statevector, LDS/register-tiled passes, QAOA-structured
+                               circuits with Pauli noise, energy only */
+    STN_PLAN_LIGHTCONE = 3  /* per-term lightcone tensor networks, energy only */
+} stn_plan_kind;
+
+typedef void* (*stn_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*stn_free_fn)(void* ptr, void* ctx);
+
+typedef struct {
+    uint32_t precision;     /* 64: complex64 contraction (FP32 arithmetic); 128: complex128 */
+    uint32_t outputs;       /* STN_OUT_* bits */
+    uint32_t plan_kind;     /* stn_plan_kind */
+    uint32_t max_batch;     /* trajectories contracted per launch; 0 = derive from hbm_budget */
+    uint64_t hbm_budget;    /* bytes of device working memory allowed; 0 = 64 GiB */
+    uint32_t order_restarts;/* lightcone plans: randomized min-fill restarts (0 = 1 pass) */
+    uint64_t order_seed;
+    stn_alloc_fn dev_alloc; /* optional device allocator (e.g. a caching allocator) */
+    stn_free_fn dev_free;
+    void* alloc_ctx;
+} stn_plan_opts;
+
+typedef struct {
+    uint32_t plan_kind;     /* the lowering chosen */
+    uint32_t n_qubits, n_gates, n_sites;
+    uint32_t max_batch;
+    uint32_t width;         /* contraction width: n for statevector plans, max rank for lightcone */
+    uint32_t n_passes;      /* statevector HBM passes per trajectory (tiled plan) */
+    uint32_t n_steps;       /* contraction steps (lightcone plan) */
+    double bytes_per_traj;  /* algorithmic HBM bytes per trajectory (cost model) */
+    double flops_per_traj;  /* algorithmic flops per trajectory (cost model) */
+    double peak_bytes;      /* device working memory at max_batch */
+} stn_plan_stats;
+
+typedef struct {
+    uint64_t k_done;        /* trajectories reduced so far */
+    double energy_mean;     /* <C>_hat (ENERGY) */
+    double energy_se;       /* std(<C>_k, ddof=1)/sqrt(K) */
+    double trace_mean;      /* Tr rho_hat (RHO / DIAG); 1 up to rounding for Pauli noise */
+    const double* rho;      /* 2^n x 2^n interleaved complex128, row-major, /K applied (RHO) */
+    const double* diag;     /* 2^n doubles, /K applied (DIAG) */
+    const double* energies; /* k_done per-trajectory <C>_k in trajectory order (ENERGY) */
+} stn_result;
+
+typedef struct stn_plan stn_plan;
+typedef struct stn_batch stn_batch;
+typedef struct stn_accum stn_accum;
+
+/* Version string of the library. */
+const char* stn_version(void);
+
+/* Message for the last non-OK status returned on this thread. */
+const char* stn_last_error(void);
+
+/* Fills *opts with defaults: precision 64, outputs ENERGY, plan AUTO. */
+void stn_plan_opts_default(stn_plan_opts* opts);
+
+/* Plan one job (Sec. III-G: the ideal circuit, the noise model; III-A:
+ * bucket elimination order for lightcone plans).  observable may be NULL when
+ * ENERGY is not requested.  On success *out owns copies of all inputs and the
+ * device tables; STN_E_INVALID / STN_E_UNSUPPORTED describe the offending
+ * gate / channel in stn_last_error(). */
+stn_status stn_plan_create(const stn_circuit* circuit, const stn_noise_model* noise,
+                           const stn_observable* observable, const stn_plan_opts* opts,
+                           stn_plan** out);
+stn_status stn_plan_info(const stn_plan* plan, stn_plan_stats* out);
+void stn_plan_destroy(stn_plan* plan);
+
+/* Noise-site table of a plan (Sec. III-G selection rule): *n_ops receives
+ * the site's operator count J and thresholds[0 .. min(J, cap)) its integer
+ * thresholds T_j (T_{J-1} = 2^32).  Host-only; needs no device.  Planning
+ * itself touches no device either: device tables are uploaded by the first
+ * stn_sample / stn_batch_from_indices / stn_contract on the plan. */
+stn_status stn_plan_site(const stn_plan* plan, uint32_t site, uint32_t* n_ops, uint64_t* thresholds,
+                         uint32_t cap);
+
+/* Draw trajectories k0 .. k0+K-1 of job `seed` (Sec. III-G: one uniform
+ * number per channel picks its Kraus operator).  The draws depend only on
+ * (seed, k, site).  K may exceed max_batch: contract splits it. */
+stn_status stn_sample(stn_plan* plan, uint64_t seed, uint64_t k0, uint32_t K,
+                      stn_batch** out, void* stream);
+
+/* Batch from caller-chosen Kraus indices: idx is a host array [K x n_sites]
+ * of uint8 (index j of each site's operator, < the channel's operator count).
+ * Used to enumerate outcomes exactly. k0 only labels the trajectories. */
+stn_status stn_batch_from_indices(stn_plan* plan, const uint8_t* idx, uint64_t k0, uint32_t K,
+                                  stn_batch** out, void* stream);
+
+/* Copies the batch's Kraus index table [K x n_sites] to host memory. Syncs. */
+stn_status stn_batch_indices(const stn_batch* batch, uint8_t* host_out);
+
+/* Contract every trajectory of the batch (Sec. III-G: simulate each noisy
+ * circuit to its statevector).  Produces per-trajectory energies and, for
+ * RHO / DIAG / STATES outputs, the statevectors. */
+stn_status stn_contract(stn_plan* plan, stn_batch* batch, void* stream);
+
+/* Copies per-trajectory results to host memory (syncs): energies[K] (FP64)
+ * and, when the batch keeps states, states[K x 2^n] complex (interleaved
+ * doubles; complex64 batches are widened).  Either pointer may be NULL. */
+stn_status stn_batch_results(const stn_batch* batch, double* energies, double* states);
+uint32_t stn_batch_size(const stn_batch* batch);
+void stn_batch_destroy(stn_batch* batch);
+
+/* Per-kernel timing of a plan's launches, taken with HIP events recorded on
+ * the stream each kernel is launched on.  bytes / flops are the algorithmic
+ * HBM traffic and arithmetic of the launches (the cost model's counts, not
+ * hardware counters). */
+enum {
+    STN_K_SAMPLE = 0,       /* Philox selection of every (trajectory, site) */
+    STN_K_FRAME = 1,        /* Pauli-frame scan */
+    STN_K_SV_LDS = 2,       /* whole-state-in-LDS contraction */
+    STN_K_SV_PASS = 3,      /* tiled statevector pass */
+    STN_K_TILE_SUM = 4,     /* per-trajectory energy from tile partials */
+    STN_K_HERK = 5,         /* FP64 rho_hat accumulation */
+    STN_K_DIAG = 6,         /* FP64 sigma accumulation */
+    STN_K_TN_STEP = 7,      /* lightcone tensor-network step */
+    STN_K_COUNT = 8
+};
+typedef struct {
+    uint64_t launches;
+    double ms;              /* summed event time */
+    double bytes;           /* summed algorithmic bytes */
+    double flops;           /* summed algorithmic flops */
+} stn_kernel_stats;
+
+/* Enables (1) or disables (0) per-kernel timing on the plan and clears it. */
+stn_status stn_profile(stn_plan* plan, int enable);
+/* Fills out[0 .. STN_K_COUNT) with the timings since enabling. Syncs. */
+stn_status stn_profile_read(stn_plan* plan, stn_kernel_stats* out);
+
+/* Accumulator of one job's ensemble sums (FP64, device-resident). */
+stn_status stn_accum_create(stn_plan* plan, stn_accum** out);
+
+/* FP64 reduction of a contracted batch (Sec. III-G: sigma_approx = sum phi_k/K,
+ * generalised to rho_hat and <C>). */
+stn_status stn_reduce(stn_plan* plan, stn_batch* batch, stn_accum* acc, void* stream);
+
+/* Finishes the fixed-order reductions and copies the result to host memory
+ * owned by the accumulator (valid until the next read or destroy). Syncs. */
+stn_status stn_accum_read(stn_accum* acc, stn_result* out, void* stream);
+void stn_accum_destroy(stn_accum* acc);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STN_H */

@@ -84,17 +84,26 @@ def kraus_indices(problem, seed, k0, K):
     return idx
 
 
-def trajectory(problem, idx_row, tabs=None):
-    """Statevector of one trajectory given its Kraus indices (one per site)."""
+def trajectory(problem, idx_row, tabs=None, max_gates=None):
+    """Statevector of one trajectory given its Kraus indices (one per site).
+
+    An inserted operator that is exactly the identity matrix (the no-error
+    outcome of a Pauli channel: sqrt(q)/sqrt(q) = 1 exactly) is skipped, which
+    changes no bit of the result.  max_gates truncates the circuit (timing
+    samples only)."""
     if tabs is None:
         tabs = site_tables(problem)
     n = problem.n_qubits
     by = _channels_by_gate(problem)
     psi = zero_state(n)
     for i, g in enumerate(problem.gates):
+        if max_gates is not None and i >= max_gates:
+            break
         psi = apply_to_state(psi, gate_matrix(g), g.qubits)
         for s, ch in by.get(i, []):
             op = tabs[s][2][int(idx_row[s])]
+            if np.array_equal(op, np.eye(op.shape[0])):
+                continue
             psi = apply_to_state(psi, op, ch.qubits)
     return psi.reshape(-1).copy()
 

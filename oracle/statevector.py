@@ -6,32 +6,22 @@ axis n-1-q.  A density matrix rho[i, j] = <i|rho|j> is a tensor of shape
 (2,)*(2n): the first n axes carry the row (ket) bits, the last n the column
 (bra) bits.
 
-Every operator is applied as out_o = sum_i M[o, i] in_i over the 2^d slices of
-the tensor selected by the local index bits (zero matrix entries skipped).
+Every k-qubit operator is applied as a tensor contraction of its 2^k x 2^k
+matrix with the k tensor axes it acts on.
 """
 import numpy as np
 
 
-def _slice(ndim, axes, local):
-    idx = [slice(None)] * ndim
-    for t, ax in enumerate(axes):
-        idx[ax] = (local >> t) & 1
-    return tuple(idx)
-
-
 def apply_matrix(t, M, axes):
     """Apply the 2^d x 2^d matrix M (local index = sum_t bit_t << t) to the
-    tensor axes `axes` (axes[t] carries local bit t) of tensor t."""
-    M = np.asarray(M, dtype=np.complex128)
+    tensor axes `axes` (axes[t] carries local bit t) of tensor t:
+    out[..o..] = sum_i M[o, i] t[..i..], as one tensordot over the d axes."""
     d = len(axes)
-    out = np.zeros_like(t)
-    for o in range(1 << d):
-        so = _slice(t.ndim, axes, o)
-        for i in range(1 << d):
-            m = M[o, i]
-            if m != 0:
-                out[so] += m * t[_slice(t.ndim, axes, i)]
-    return out
+    Mt = np.asarray(M, dtype=np.complex128).reshape((2,) * (2 * d))
+    # Mt axes: output bits d-1..0, then input bits d-1..0 (C order of the local index)
+    in_axes = [axes[d - 1 - i] for i in range(d)]
+    r = np.tensordot(Mt, t, axes=(list(range(d, 2 * d)), in_axes))
+    return np.ascontiguousarray(np.moveaxis(r, list(range(d)), in_axes))
 
 
 def zero_state(n):

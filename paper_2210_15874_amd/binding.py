@@ -1,0 +1,370 @@
+"""ctypes binding of libstn.so (include/stn.h): argument marshalling only.
+
+Every step of the ensemble path (sampling, contraction, reduction) runs in the
+library's HIP kernels; this module converts a ``workloads.Problem`` into the
+C structures, passes PyTorch's caching allocator and current stream to the
+library, and copies results back.  There is no fallback: if the library is
+missing or the device is unavailable the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstn.so")
+
+GATE_KIND = {"h": 0, "x": 1, "y": 2, "z": 3, "rx": 4, "ry": 5, "rz": 6, "zz": 7, "cx": 8, "u1": 9, "u2": 10}
+CHANNEL_KIND = {"bitflip": 0, "depol1": 1, "depol2": 2, "ampdamp": 3, "kraus": 4}
+
+OUT_RHO, OUT_DIAG, OUT_ENERGY, OUT_STATES = 1, 2, 4, 8
+PLAN_AUTO, PLAN_SV_LDS, PLAN_SV_TILED, PLAN_LIGHTCONE = 0, 1, 2, 3
+PLAN_NAMES = {0: "auto", 1: "sv_lds", 2: "sv_tiled", 3: "lightcone"}
+STATUS = {0: "OK", 1: "INVALID", 2: "UNSUPPORTED", 3: "OOM", 4: "DEVICE", 5: "STATE"}
+
+
+class StnError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"stn {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Gate(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("q0", C.c_uint32), ("q1", C.c_uint32), ("theta", C.c_double),
+                ("mat", C.POINTER(C.c_double))]
+
+
+class Circuit(C.Structure):
+    _fields_ = [("n_qubits", C.c_uint32), ("n_gates", C.c_uint32), ("gates", C.POINTER(Gate))]
+
+
+class Channel(C.Structure):
+    _fields_ = [("after_gate", C.c_uint32), ("kind", C.c_uint32), ("n_qubits", C.c_uint32), ("q0", C.c_uint32),
+                ("q1", C.c_uint32), ("param", C.c_double), ("n_kraus", C.c_uint32),
+                ("kraus", C.POINTER(C.c_double))]
+
+
+class NoiseModel(C.Structure):
+    _fields_ = [("n_channels", C.c_uint32), ("channels", C.POINTER(Channel))]
+
+
+class Observable(C.Structure):
+    _fields_ = [("n_terms", C.c_uint32), ("uv", C.POINTER(C.c_uint32)), ("w", C.POINTER(C.c_double))]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class PlanOpts(C.Structure):
+    _fields_ = [("precision", C.c_uint32), ("outputs", C.c_uint32), ("plan_kind", C.c_uint32),
+                ("max_batch", C.c_uint32), ("hbm_budget", C.c_uint64), ("order_restarts", C.c_uint32),
+                ("order_seed", C.c_uint64), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
+                ("alloc_ctx", C.c_void_p)]
+
+
+class PlanStats(C.Structure):
+    _fields_ = [("plan_kind", C.c_uint32), ("n_qubits", C.c_uint32), ("n_gates", C.c_uint32),
+                ("n_sites", C.c_uint32), ("max_batch", C.c_uint32), ("width", C.c_uint32),
+                ("n_passes", C.c_uint32), ("n_steps", C.c_uint32), ("bytes_per_traj", C.c_double),
+                ("flops_per_traj", C.c_double), ("peak_bytes", C.c_double)]
+
+
+class KernelStats(C.Structure):
+    _fields_ = [("launches", C.c_uint64), ("ms", C.c_double), ("bytes", C.c_double), ("flops", C.c_double)]
+
+
+KERNEL_NAMES = ["sample", "frame", "sv_lds", "sv_pass", "tile_sum", "herk", "diag", "tn_step"]
+
+
+class Result(C.Structure):
+    _fields_ = [("k_done", C.c_uint64), ("energy_mean", C.c_double), ("energy_se", C.c_double),
+                ("trace_mean", C.c_double), ("rho", C.POINTER(C.c_double)), ("diag", C.POINTER(C.c_double)),
+                ("energies", C.POINTER(C.c_double))]
+
+
+EXPORTS = {
+    "stn_version": (C.c_char_p, []),
+    "stn_last_error": (C.c_char_p, []),
+    "stn_plan_opts_default": (None, [C.POINTER(PlanOpts)]),
+    "stn_plan_create": (C.c_int, [C.POINTER(Circuit), C.POINTER(NoiseModel), C.POINTER(Observable),
+                                  C.POINTER(PlanOpts), C.POINTER(C.c_void_p)]),
+    "stn_plan_info": (C.c_int, [C.c_void_p, C.POINTER(PlanStats)]),
+    "stn_plan_destroy": (None, [C.c_void_p]),
+    "stn_plan_site": (C.c_int, [C.c_void_p, C.c_uint32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint64), C.c_uint32]),
+    "stn_sample": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint32, C.POINTER(C.c_void_p), C.c_void_p]),
+    "stn_batch_from_indices": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint8), C.c_uint64, C.c_uint32,
+                                         C.POINTER(C.c_void_p), C.c_void_p]),
+    "stn_batch_indices": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint8)]),
+    "stn_contract": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "stn_batch_results": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "stn_batch_size": (C.c_uint32, [C.c_void_p]),
+    "stn_batch_destroy": (None, [C.c_void_p]),
+    "stn_profile": (C.c_int, [C.c_void_p, C.c_int]),
+    "stn_profile_read": (C.c_int, [C.c_void_p, C.POINTER(KernelStats)]),
+    "stn_accum_create": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
+    "stn_reduce": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "stn_accum_read": (C.c_int, [C.c_void_p, C.POINTER(Result), C.c_void_p]),
+    "stn_accum_destroy": (None, [C.c_void_p]),
+}
+
+_lib = None
+
+
+def load(path: Optional[str] = None):
+    """Loads libstn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError(f"{p} not built: run python -m paper_2210_15874_amd.build")
+    lib = C.CDLL(p)
+    for name, (res, args) in EXPORTS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(st):
+    if st != 0:
+        raise StnError(st, _lib.stn_last_error().decode())
+
+
+def current_stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class _TorchAllocator:
+    """Device memory for the library from PyTorch's caching allocator."""
+
+    def __init__(self, device=0):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.alloc = ALLOC_FN(self._alloc)
+        self.free = FREE_FN(self._free)
+
+    def _alloc(self, nbytes, ctx):
+        try:
+            return self.torch.cuda.caching_allocator_alloc(int(nbytes), self.device)
+        except Exception:  # out of memory: the library reports STN_E_OOM
+            return None
+
+    def _free(self, ptr, ctx):
+        self.torch.cuda.caching_allocator_delete(ptr)
+
+
+def _problem_structs(problem, with_observable):
+    gates = (Gate * max(1, len(problem.gates)))()
+    keep = []
+    for i, g in enumerate(problem.gates):
+        gates[i].kind = GATE_KIND[g.kind]
+        gates[i].q0 = g.qubits[0]
+        gates[i].q1 = g.qubits[1] if len(g.qubits) > 1 else 0
+        gates[i].theta = float(g.theta)
+        if g.matrix is not None:
+            m = np.ascontiguousarray(np.array(g.matrix, dtype=np.complex128).view(np.float64))
+            keep.append(m)
+            gates[i].mat = m.ctypes.data_as(C.POINTER(C.c_double))
+    circ = Circuit(problem.n_qubits, len(problem.gates), gates)
+    chans = (Channel * max(1, len(problem.channels)))()
+    for i, ch in enumerate(problem.channels):
+        chans[i].after_gate = ch.after_gate
+        chans[i].kind = CHANNEL_KIND[ch.kind]
+        chans[i].n_qubits = len(ch.qubits)
+        chans[i].q0 = ch.qubits[0]
+        chans[i].q1 = ch.qubits[1] if len(ch.qubits) > 1 else 0
+        chans[i].param = float(ch.param)
+        if ch.kraus is not None:
+            m = np.ascontiguousarray(np.array(ch.kraus, dtype=np.complex128).reshape(-1).view(np.float64))
+            keep.append(m)
+            chans[i].n_kraus = len(ch.kraus)
+            chans[i].kraus = m.ctypes.data_as(C.POINTER(C.c_double))
+    noise = NoiseModel(len(problem.channels), chans)
+    obs = None
+    if with_observable:
+        uv = np.ascontiguousarray(np.array(problem.edges, dtype=np.uint32).reshape(-1))
+        w = np.ascontiguousarray(np.array(problem.weights, dtype=np.float64))
+        keep += [uv, w]
+        obs = Observable(len(problem.edges), uv.ctypes.data_as(C.POINTER(C.c_uint32)),
+                         w.ctypes.data_as(C.POINTER(C.c_double)))
+    return circ, noise, obs, (gates, chans, keep)
+
+
+class Plan:
+    """stn_plan_create for a workloads.Problem."""
+
+    def __init__(self, problem, outputs=OUT_ENERGY, precision=64, plan_kind=PLAN_AUTO, max_batch=0,
+                 hbm_budget=0, torch_allocator=True, device=0):
+        self.lib = load()
+        self.problem = problem
+        self.n = problem.n_qubits
+        self.S = len(problem.channels)
+        self.outputs = outputs
+        self.precision = precision
+        opts = PlanOpts()
+        self.lib.stn_plan_opts_default(C.byref(opts))
+        opts.precision = precision
+        opts.outputs = outputs
+        opts.plan_kind = plan_kind
+        opts.max_batch = max_batch
+        opts.hbm_budget = hbm_budget
+        self._alloc = None
+        if torch_allocator:
+            self._alloc = _TorchAllocator(device)
+            opts.dev_alloc = self._alloc.alloc
+            opts.dev_free = self._alloc.free
+        circ, noise, obs, self._keep = _problem_structs(problem, bool(outputs & OUT_ENERGY))
+        h = C.c_void_p()
+        _check(self.lib.stn_plan_create(C.byref(circ), C.byref(noise), C.byref(obs) if obs else None,
+                                        C.byref(opts), C.byref(h)))
+        self.h = h
+
+    def info(self):
+        s = PlanStats()
+        _check(self.lib.stn_plan_info(self.h, C.byref(s)))
+        d = {f: getattr(s, f) for f, _ in PlanStats._fields_}
+        d["plan_name"] = PLAN_NAMES.get(d["plan_kind"], "?")
+        return d
+
+    def site_thresholds(self, s):
+        J = C.c_uint32()
+        T = (C.c_uint64 * 16)()
+        _check(self.lib.stn_plan_site(self.h, s, C.byref(J), T, 16))
+        return [int(T[j]) for j in range(J.value)]
+
+    def sample(self, seed, k0, K, stream=None):
+        h = C.c_void_p()
+        _check(self.lib.stn_sample(self.h, int(seed), int(k0), int(K), C.byref(h),
+                                   stream if stream is not None else current_stream()))
+        return Batch(self, h, K)
+
+    def batch_from_indices(self, idx, k0=0, stream=None):
+        idx = np.ascontiguousarray(idx, dtype=np.uint8)
+        K = idx.shape[0]
+        assert idx.shape == (K, self.S)
+        h = C.c_void_p()
+        _check(self.lib.stn_batch_from_indices(self.h, idx.ctypes.data_as(C.POINTER(C.c_uint8)), int(k0), K,
+                                               C.byref(h), stream if stream is not None else current_stream()))
+        return Batch(self, h, K)
+
+    def contract(self, batch, stream=None):
+        _check(self.lib.stn_contract(self.h, batch.h, stream if stream is not None else current_stream()))
+
+    def profile(self, enable=True):
+        _check(self.lib.stn_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        arr = (KernelStats * len(KERNEL_NAMES))()
+        _check(self.lib.stn_profile_read(self.h, arr))
+        return {name: {"launches": arr[i].launches, "ms": arr[i].ms, "bytes": arr[i].bytes,
+                       "flops": arr[i].flops} for i, name in enumerate(KERNEL_NAMES)}
+
+    def accum(self):
+        h = C.c_void_p()
+        _check(self.lib.stn_accum_create(self.h, C.byref(h)))
+        return Accum(self, h)
+
+    def reduce(self, batch, acc, stream=None):
+        _check(self.lib.stn_reduce(self.h, batch.h, acc.h, stream if stream is not None else current_stream()))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.stn_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    def __init__(self, plan, h, K):
+        self.plan, self.h, self.K = plan, h, K
+
+    def indices(self):
+        out = np.zeros((self.K, self.plan.S), dtype=np.uint8)
+        if self.plan.S:
+            _check(self.plan.lib.stn_batch_indices(self.h, out.ctypes.data_as(C.POINTER(C.c_uint8))))
+        return out
+
+    def energies(self):
+        e = np.zeros(self.K, dtype=np.float64)
+        _check(self.plan.lib.stn_batch_results(self.h, e.ctypes.data_as(C.POINTER(C.c_double)), None))
+        return e
+
+    def states(self):
+        st = np.zeros((self.K, 1 << self.plan.n), dtype=np.complex128)
+        _check(self.plan.lib.stn_batch_results(self.h, None,
+                                               st.view(np.float64).ctypes.data_as(C.POINTER(C.c_double))))
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.plan.lib.stn_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Accum:
+    def __init__(self, plan, h):
+        self.plan, self.h = plan, h
+
+    def read(self, stream=None):
+        r = Result()
+        _check(self.plan.lib.stn_accum_read(self.h, C.byref(r), stream if stream is not None else current_stream()))
+        N = 1 << self.plan.n
+        out = {"k_done": r.k_done, "energy_mean": r.energy_mean, "energy_se": r.energy_se,
+               "trace": r.trace_mean}
+        if r.energies:
+            out["energies"] = np.ctypeslib.as_array(r.energies, shape=(r.k_done,)).copy()
+        if r.diag:
+            out["diag"] = np.ctypeslib.as_array(r.diag, shape=(N,)).copy()
+        if r.rho:
+            out["rho"] = np.ctypeslib.as_array(r.rho, shape=(N * N * 2,)).copy().view(np.complex128).reshape(N, N)
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.plan.lib.stn_accum_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def simulate_batch_ensemble(problem, K=None, seed=None, outputs=OUT_ENERGY, precision=64, batch=None,
+                            plan_kind=PLAN_AUTO, plan=None):
+    """The ensemble of Sec. III-G for one job: plan, then sample / contract /
+    reduce in batches of `batch` trajectories, then read the FP64 result."""
+    K = K if K is not None else problem.K
+    seed = seed if seed is not None else problem.seed
+    pl = plan or Plan(problem, outputs=outputs, precision=precision, plan_kind=plan_kind)
+    acc = pl.accum()
+    step = batch or K
+    for k0 in range(0, K, step):
+        b = pl.sample(seed, k0, min(step, K - k0))
+        pl.contract(b)
+        pl.reduce(b, acc)
+        b.close()
+    res = acc.read()
+    acc.close()
+    return res

@@ -1,0 +1,454 @@
+// extern "C" entry points of include/stn.h: argument checks, handle
+// lifetimes, device memory, and dispatch to the kernel launchers.
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+#include "stn_internal.h"
+
+namespace stn {
+
+namespace {
+thread_local std::string g_last_error;
+
+stn_status set_error(stn_status s, const std::string& m) {
+    g_last_error = m;
+    return s;
+}
+}  // namespace
+
+void fail(stn_status s, const std::string& msg) { throw Error{s, msg}; }
+
+void hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) {
+        if (e == hipErrorOutOfMemory) fail(STN_E_OOM, std::string(what) + ": out of device memory");
+        fail(STN_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+void* Allocator::alloc(size_t bytes) const {
+    void* p = nullptr;
+    if (fn) {
+        p = fn(bytes, ctx);
+        if (!p) fail(STN_E_OOM, "device allocator returned NULL for " + std::to_string(bytes) + " bytes");
+        return p;
+    }
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(e == hipErrorOutOfMemory ? STN_E_OOM : STN_E_DEVICE,
+             "hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    }
+    return p;
+}
+
+void Allocator::release(void* p) const {
+    if (!p) return;
+    if (ffn) ffn(p, ctx);
+    else (void)hipFree(p);
+}
+
+void upload(DevBuf& d, const Allocator* a, const void* host, size_t bytes, hipStream_t s) {
+    d.ensure(a, bytes);
+    if (bytes) STN_HIP(hipMemcpyAsync(d.p, host, bytes, hipMemcpyHostToDevice, s));
+}
+
+template <class F>
+stn_status guarded(F&& f) {
+    try {
+        f();
+        return STN_OK;
+    } catch (const Error& e) {
+        return set_error(e.status, e.msg);
+    } catch (const std::bad_alloc&) {
+        return set_error(STN_E_OOM, "host allocation failed");
+    } catch (const std::exception& e) {
+        return set_error(STN_E_INVALID, e.what());
+    }
+}
+
+void upload_plan_tables(stn_plan* p, hipStream_t s);
+
+// Device tables are uploaded on the first call that needs the device, so a
+// plan can be built and inspected on a host without a GPU.
+void ensure_uploaded(stn_plan* p, hipStream_t s) {
+    if (p->uploaded) return;
+    upload_plan_tables(p, s);
+    STN_HIP(hipStreamSynchronize(s));
+    p->uploaded = true;
+}
+
+}  // namespace stn
+
+using namespace stn;
+
+namespace stn {
+
+static hipEvent_t take_event(stn_plan* p) {
+    if (!p->ev_pool.empty()) {
+        hipEvent_t e = p->ev_pool.back();
+        p->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    STN_HIP(hipEventCreate(&e));
+    return e;
+}
+
+void prof_begin(stn_plan* p, int cls, hipStream_t s) {
+    if (!p->prof) return;
+    hipEvent_t a = take_event(p), b = take_event(p);
+    STN_HIP(hipEventRecord(a, s));
+    p->prof_cls[cls].ev.push_back({a, b});
+}
+
+void prof_end(stn_plan* p, int cls, hipStream_t s, double bytes, double flops) {
+    if (!p->prof) return;
+    STN_HIP(hipEventRecord(p->prof_cls[cls].ev.back().second, s));
+    p->prof_cls[cls].bytes.push_back(bytes);
+    p->prof_cls[cls].flops.push_back(flops);
+}
+
+void prof_clear(stn_plan* p) {
+    for (auto& c : p->prof_cls) {
+        for (auto& e : c.ev) {
+            p->ev_pool.push_back(e.first);
+            p->ev_pool.push_back(e.second);
+        }
+        c.ev.clear();
+        c.bytes.clear();
+        c.flops.clear();
+    }
+}
+
+}  // namespace stn
+
+stn_plan::~stn_plan() {
+    if (lc && lc_free) lc_free(lc);
+    (void)hipDeviceSynchronize();
+    stn::prof_clear(this);
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
+}
+
+extern "C" {
+
+const char* stn_version(void) { return "stn 0.1 (gfx950)"; }
+
+const char* stn_last_error(void) { return g_last_error.c_str(); }
+
+void stn_plan_opts_default(stn_plan_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = 64;
+    o->outputs = STN_OUT_ENERGY;
+    o->plan_kind = STN_PLAN_AUTO;
+}
+
+stn_status stn_plan_create(const stn_circuit* circuit, const stn_noise_model* noise,
+                           const stn_observable* observable, const stn_plan_opts* opts, stn_plan** out) {
+    if (!out) return set_error(STN_E_INVALID, "out is NULL");
+    *out = nullptr;
+    stn_plan* p = nullptr;
+    stn_status st = guarded([&] {
+        p = new stn_plan();
+        if (opts) p->opts = *opts;
+        else stn_plan_opts_default(&p->opts);
+        if (p->opts.precision != 64 && p->opts.precision != 128) fail(STN_E_INVALID, "precision must be 64 or 128");
+        if ((p->opts.dev_alloc == nullptr) != (p->opts.dev_free == nullptr))
+            fail(STN_E_INVALID, "dev_alloc and dev_free must be given together");
+        p->alloc.fn = p->opts.dev_alloc;
+        p->alloc.ffn = p->opts.dev_free;
+        p->alloc.ctx = p->opts.alloc_ctx;
+        build_plan(p, circuit, noise, observable);
+    });
+    if (st != STN_OK) {
+        delete p;
+        return st;
+    }
+    *out = p;
+    return STN_OK;
+}
+
+stn_status stn_plan_info(const stn_plan* p, stn_plan_stats* o) {
+    if (!p || !o) return set_error(STN_E_INVALID, "NULL argument");
+    std::memset(o, 0, sizeof(*o));
+    o->plan_kind = p->kind;
+    o->n_qubits = p->n;
+    o->n_gates = (uint32_t)p->gates.size();
+    o->n_sites = (uint32_t)p->sites.size();
+    o->max_batch = p->max_batch;
+    o->width = p->width;
+    o->n_passes = p->n_passes;
+    o->n_steps = p->n_steps;
+    o->bytes_per_traj = p->bytes_per_traj;
+    o->flops_per_traj = p->flops_per_traj;
+    o->peak_bytes = p->peak_bytes;
+    return STN_OK;
+}
+
+void stn_plan_destroy(stn_plan* p) { delete p; }
+
+stn_status stn_profile(stn_plan* p, int enable) {
+    if (!p) return set_error(STN_E_INVALID, "NULL argument");
+    return guarded([&] {
+        STN_HIP(hipDeviceSynchronize());
+        prof_clear(p);
+        p->prof = enable != 0;
+    });
+}
+
+stn_status stn_profile_read(stn_plan* p, stn_kernel_stats* out) {
+    if (!p || !out) return set_error(STN_E_INVALID, "NULL argument");
+    return guarded([&] {
+        STN_HIP(hipDeviceSynchronize());
+        for (int c = 0; c < STN_K_COUNT; ++c) {
+            stn_kernel_stats& o = out[c];
+            o = stn_kernel_stats{};
+            const ProfClass& pc = p->prof_cls[c];
+            for (size_t i = 0; i < pc.ev.size(); ++i) {
+                float ms = 0;
+                STN_HIP(hipEventElapsedTime(&ms, pc.ev[i].first, pc.ev[i].second));
+                o.ms += ms;
+                o.bytes += pc.bytes[i];
+                o.flops += pc.flops[i];
+                ++o.launches;
+            }
+        }
+    });
+}
+
+stn_status stn_plan_site(const stn_plan* p, uint32_t site, uint32_t* n_ops, uint64_t* thresholds, uint32_t cap) {
+    if (!p || !n_ops) return set_error(STN_E_INVALID, "NULL argument");
+    if (site >= p->sites.size()) return set_error(STN_E_INVALID, "site out of range");
+    const SiteRec& r = p->sites[site];
+    *n_ops = r.J;
+    if (thresholds)
+        for (uint32_t j = 0; j < r.J && j < cap; ++j) thresholds[j] = r.T[j];
+    return STN_OK;
+}
+
+static void batch_alloc(stn_plan* p, stn_batch* b, uint32_t K) {
+    const size_t S = p->sites.size();
+    b->plan = p;
+    b->K = K;
+    b->words = (uint32_t)((p->gates.size() + 31) / 32);
+    b->d_idx.ensure(&p->alloc, (size_t)K * S);
+    if (p->kind != STN_PLAN_SV_LDS) {
+        b->d_signs.ensure(&p->alloc, (size_t)K * std::max<uint32_t>(b->words, 1) * 4);
+        b->d_frame.ensure(&p->alloc, (size_t)K * 16);
+    }
+    b->d_energy.ensure(&p->alloc, (size_t)K * 8);
+}
+
+stn_status stn_sample(stn_plan* p, uint64_t seed, uint64_t k0, uint32_t K, stn_batch** out, void* stream) {
+    if (!p || !out) return set_error(STN_E_INVALID, "NULL argument");
+    *out = nullptr;
+    if (K == 0) return set_error(STN_E_INVALID, "K must be positive");
+    stn_batch* b = nullptr;
+    stn_status st = guarded([&] {
+        b = new stn_batch();
+        b->k0 = k0;
+        batch_alloc(p, b, K);
+        hipStream_t s = (hipStream_t)stream;
+        ensure_uploaded(p, s);
+        launch_sample(p, b, seed, s);
+        if (p->kind != STN_PLAN_SV_LDS) launch_frame(p, b, s);
+    });
+    if (st != STN_OK) {
+        delete b;
+        return st;
+    }
+    *out = b;
+    return STN_OK;
+}
+
+stn_status stn_batch_from_indices(stn_plan* p, const uint8_t* idx, uint64_t k0, uint32_t K, stn_batch** out,
+                                  void* stream) {
+    if (!p || !out || (!idx && K && !p->sites.empty())) return set_error(STN_E_INVALID, "NULL argument");
+    *out = nullptr;
+    if (K == 0) return set_error(STN_E_INVALID, "K must be positive");
+    stn_batch* b = nullptr;
+    stn_status st = guarded([&] {
+        const size_t S = p->sites.size();
+        for (size_t k = 0; k < K; ++k)
+            for (size_t s = 0; s < S; ++s)
+                if (idx[k * S + s] >= p->sites[s].J)
+                    fail(STN_E_INVALID, "index out of range at trajectory " + std::to_string(k) + ", site " +
+                                            std::to_string(s));
+        hipStream_t s = (hipStream_t)stream;
+        ensure_uploaded(p, s);
+        b = new stn_batch();
+        b->k0 = k0;
+        batch_alloc(p, b, K);
+        if (S) STN_HIP(hipMemcpyAsync(b->d_idx.p, idx, (size_t)K * S, hipMemcpyHostToDevice, s));
+        if (p->kind != STN_PLAN_SV_LDS) launch_frame(p, b, s);
+        STN_HIP(hipStreamSynchronize(s));
+    });
+    if (st != STN_OK) {
+        delete b;
+        return st;
+    }
+    *out = b;
+    return STN_OK;
+}
+
+stn_status stn_batch_indices(const stn_batch* b, uint8_t* host_out) {
+    if (!b || !host_out) return set_error(STN_E_INVALID, "NULL argument");
+    return guarded([&] {
+        const size_t bytes = (size_t)b->K * b->plan->sites.size();
+        STN_HIP(hipDeviceSynchronize());
+        if (bytes) STN_HIP(hipMemcpy(host_out, b->d_idx.p, bytes, hipMemcpyDeviceToHost));
+    });
+}
+
+stn_status stn_contract(stn_plan* p, stn_batch* b, void* stream) {
+    if (!p || !b) return set_error(STN_E_INVALID, "NULL argument");
+    if (b->plan != p) return set_error(STN_E_INVALID, "batch belongs to another plan");
+    return guarded([&] {
+        hipStream_t s = (hipStream_t)stream;
+        ensure_uploaded(p, s);
+        switch (p->kind) {
+            case STN_PLAN_SV_LDS: launch_sv_lds(p, b, s); break;
+            case STN_PLAN_SV_TILED: launch_sv_tiled(p, b, s); break;
+            case STN_PLAN_LIGHTCONE: launch_lightcone(p, b, s); break;
+            default: fail(STN_E_STATE, "plan has no lowering");
+        }
+        b->contracted = true;
+    });
+}
+
+stn_status stn_batch_results(const stn_batch* b, double* energies, double* states) {
+    if (!b) return set_error(STN_E_INVALID, "NULL argument");
+    if (!b->contracted) return set_error(STN_E_STATE, "batch not contracted");
+    if (states && !b->has_states) return set_error(STN_E_STATE, "batch keeps no states (request STN_OUT_STATES)");
+    return guarded([&] {
+        STN_HIP(hipDeviceSynchronize());
+        if (energies) STN_HIP(hipMemcpy(energies, b->d_energy.p, (size_t)b->K * 8, hipMemcpyDeviceToHost));
+        if (states) {
+            const size_t N = (size_t)1 << b->plan->n;
+            const size_t cnt = N * b->K;
+            if (b->plan->opts.precision == 128) {
+                STN_HIP(hipMemcpy(states, b->d_states.p, cnt * 16, hipMemcpyDeviceToHost));
+            } else {
+                std::vector<float> tmp(cnt * 2);
+                STN_HIP(hipMemcpy(tmp.data(), b->d_states.p, cnt * 8, hipMemcpyDeviceToHost));
+                for (size_t i = 0; i < cnt * 2; ++i) states[i] = tmp[i];
+            }
+        }
+    });
+}
+
+uint32_t stn_batch_size(const stn_batch* b) { return b ? b->K : 0; }
+
+void stn_batch_destroy(stn_batch* b) {
+    if (b) (void)hipDeviceSynchronize();
+    delete b;
+}
+
+stn_status stn_accum_create(stn_plan* p, stn_accum** out) {
+    if (!p || !out) return set_error(STN_E_INVALID, "NULL argument");
+    *out = nullptr;
+    stn_accum* a = nullptr;
+    stn_status st = guarded([&] {
+        a = new stn_accum();
+        a->plan = p;
+        const size_t N = (size_t)1 << p->n;
+        if (p->opts.outputs & STN_OUT_RHO) {
+            a->d_rho.ensure(&p->alloc, N * N * 16);
+            STN_HIP(hipMemset(a->d_rho.p, 0, N * N * 16));
+        }
+        if (p->opts.outputs & (STN_OUT_DIAG | STN_OUT_RHO)) {
+            a->d_diag.ensure(&p->alloc, N * 8);
+            STN_HIP(hipMemset(a->d_diag.p, 0, N * 8));
+        }
+    });
+    if (st != STN_OK) {
+        delete a;
+        return st;
+    }
+    *out = a;
+    return STN_OK;
+}
+
+stn_status stn_reduce(stn_plan* p, stn_batch* b, stn_accum* a, void* stream) {
+    if (!p || !b || !a) return set_error(STN_E_INVALID, "NULL argument");
+    if (b->plan != p || a->plan != p) return set_error(STN_E_INVALID, "batch / accumulator belong to another plan");
+    if (!b->contracted) return set_error(STN_E_STATE, "batch not contracted");
+    const uint64_t lo = b->k0, hi = b->k0 + b->K;
+    for (auto& r : a->ranges)
+        if (lo < r.second && r.first < hi) return set_error(STN_E_INVALID, "trajectory range already reduced");
+    stn_status st = guarded([&] {
+        // make sure the energy chunks covering [lo, hi) exist
+        if (p->opts.outputs & STN_OUT_ENERGY) {
+            const uint64_t last = (hi - 1) / kEnergyChunk;
+            if (last > (1ull << 24)) fail(STN_E_INVALID, "trajectory index too large");
+            if (a->e_chunks.size() <= last) a->e_chunks.resize(last + 1);
+            for (uint64_t c = lo / kEnergyChunk; c <= last; ++c) a->e_chunks[c].ensure(&p->alloc, kEnergyChunk * 8);
+        }
+        launch_reduce(p, b, a, (hipStream_t)stream);
+    });
+    if (st == STN_OK) {
+        a->ranges.push_back({lo, hi});
+        a->k_done += b->K;
+    }
+    return st;
+}
+
+stn_status stn_accum_read(stn_accum* a, stn_result* out, void* stream) {
+    if (!a || !out) return set_error(STN_E_INVALID, "NULL argument");
+    std::memset(out, 0, sizeof(*out));
+    return guarded([&] {
+        stn_plan* p = a->plan;
+        hipStream_t s = (hipStream_t)stream;
+        const size_t N = (size_t)1 << p->n;
+        out->k_done = a->k_done;
+        double st[4] = {0, 0, 0, 0};
+        a->d_stats.ensure(&p->alloc, 4 * 8);
+        STN_HIP(hipMemsetAsync(a->d_stats.p, 0, 4 * 8, s));
+        if ((p->opts.outputs & STN_OUT_ENERGY) && a->k_done) {
+            // gather the energies in trajectory order, then fixed-order statistics
+            a->d_egather.ensure(&p->alloc, a->k_done * 8);
+            std::sort(a->ranges.begin(), a->ranges.end());
+            uint64_t pos = 0;
+            for (auto& r : a->ranges) {
+                uint64_t k = r.first;
+                while (k < r.second) {
+                    const uint64_t c = k / kEnergyChunk, stop = std::min<uint64_t>(r.second, (c + 1) * kEnergyChunk);
+                    STN_HIP(hipMemcpyAsync(a->d_egather.as<double>() + pos, a->e_chunks[c].as<double>() + (k % kEnergyChunk),
+                                           (stop - k) * 8, hipMemcpyDeviceToDevice, s));
+                    pos += stop - k;
+                    k = stop;
+                }
+            }
+            launch_energy_stats(a, a->k_done, s);
+            a->h_energies.resize(a->k_done);
+            STN_HIP(hipMemcpyAsync(a->h_energies.data(), a->d_egather.p, a->k_done * 8, hipMemcpyDeviceToHost, s));
+            out->energies = a->h_energies.data();
+        }
+        if (p->opts.outputs & (STN_OUT_DIAG | STN_OUT_RHO)) {
+            if (p->opts.outputs & STN_OUT_RHO) a->d_rho_out.ensure(&p->alloc, N * N * 16);
+            a->d_diag_out.ensure(&p->alloc, N * 8);
+            launch_finish_dense(a, s);
+            a->h_diag.resize(N);
+            STN_HIP(hipMemcpyAsync(a->h_diag.data(), a->d_diag_out.p, N * 8, hipMemcpyDeviceToHost, s));
+            out->diag = a->h_diag.data();
+            if (p->opts.outputs & STN_OUT_RHO) {
+                a->h_rho.resize(N * N * 2);
+                STN_HIP(hipMemcpyAsync(a->h_rho.data(), a->d_rho_out.p, N * N * 16, hipMemcpyDeviceToHost, s));
+                out->rho = a->h_rho.data();
+            }
+        }
+        STN_HIP(hipMemcpyAsync(st, a->d_stats.p, 4 * 8, hipMemcpyDeviceToHost, s));
+        STN_HIP(hipStreamSynchronize(s));
+        out->energy_mean = st[0];
+        out->energy_se = st[1];
+        out->trace_mean = st[2];
+    });
+}
+
+void stn_accum_destroy(stn_accum* a) {
+    if (a) (void)hipDeviceSynchronize();
+    delete a;
+}
+
+}  // extern "C"

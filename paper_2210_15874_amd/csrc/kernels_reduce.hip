@@ -1,0 +1,223 @@
+// Ensemble reductions in binary64 (Sec. III-G: the probability vectors phi_k
+// are averaged to sigma_approx; here generalised to the full rho_hat and the
+// energy <C>).
+//
+// k_herk:     rho += Psi^T conj(Psi) over a batch of B statevectors, only the
+//             tiles on or above the diagonal (I <= J); products of complex64
+//             amplitudes are formed in binary64.  Every element has a single
+//             writer per launch and the batch is summed in trajectory order.
+// k_diag:     diag += sum_b |psi_b|^2 in trajectory order.
+// k_stats:    mean and standard error of the per-trajectory energies, summed
+//             in a fixed order (strided per thread, then a fixed tree), two
+//             passes (mean, then squared deviations).
+// k_finish_*: mirror the upper triangle (rho_ji = conj(rho_ij), real
+//             diagonal) and scale by 1/K into output buffers.
+#include "stn_internal.h"
+
+namespace stn {
+
+namespace {
+
+template <class V> __device__ __forceinline__ double2 widen(V v) { return make_double2((double)v.x, (double)v.y); }
+
+constexpr int kTile = 64;   // output tile edge
+constexpr int kChunk = 16;  // trajectories per LDS stage
+
+template <class V>
+__global__ __launch_bounds__(256) void k_herk(const V* __restrict__ Psi, uint32_t B, uint32_t N, uint32_t tiles,
+                                              double2* __restrict__ rho) {
+    // upper-triangle tile pair from the linear block index
+    uint32_t t = blockIdx.x, I = 0;
+    while (t >= tiles - I) {
+        t -= tiles - I;
+        ++I;
+    }
+    const uint32_t J = I + t;
+    __shared__ double2 A[kChunk][kTile];
+    __shared__ double2 C[kChunk][kTile];
+    const uint32_t tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    double2 acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = make_double2(0.0, 0.0);
+    const uint32_t i0 = I * kTile, j0 = J * kTile;
+    for (uint32_t b0 = 0; b0 < B; b0 += kChunk) {
+        for (uint32_t e = threadIdx.x; e < kChunk * kTile; e += 256) {
+            const uint32_t bb = e / kTile, x = e % kTile;
+            const bool ok = b0 + bb < B;
+            A[bb][x] = (ok && i0 + x < N) ? widen(Psi[(size_t)(b0 + bb) * N + i0 + x]) : make_double2(0.0, 0.0);
+            C[bb][x] = (ok && j0 + x < N) ? widen(Psi[(size_t)(b0 + bb) * N + j0 + x]) : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int bb = 0; bb < kChunk; ++bb) {
+            double2 a[4], c[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[r] = A[bb][ty + 16 * r];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) c[q] = C[bb][tx + 16 * q];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    // a * conj(c)
+                    acc[r][q].x = fma(a[r].x, c[q].x, fma(a[r].y, c[q].y, acc[r][q].x));
+                    acc[r][q].y = fma(a[r].y, c[q].x, fma(-a[r].x, c[q].y, acc[r][q].y));
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t i = i0 + ty + 16 * r, j = j0 + tx + 16 * q;
+            if (i < N && j < N && i <= j) {
+                double2* d = rho + (size_t)i * N + j;
+                double2 v = *d;
+                v.x += acc[r][q].x;
+                v.y += acc[r][q].y;
+                *d = v;
+            }
+        }
+}
+
+template <class V>
+__global__ __launch_bounds__(256) void k_diag(const V* __restrict__ Psi, uint32_t B, uint32_t N,
+                                              double* __restrict__ diag) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    double s = 0.0;
+    for (uint32_t b = 0; b < B; ++b) {
+        const double2 v = widen(Psi[(size_t)b * N + i]);
+        s += v.x * v.x + v.y * v.y;
+    }
+    diag[i] += s;
+}
+
+__device__ double block_sum(double v, double* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (uint32_t w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_stats(const double* __restrict__ e, uint64_t K, double* __restrict__ out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (uint64_t k = threadIdx.x; k < K; k += 256) s += e[k];
+    const double mean = block_sum(s, red) / (double)K;
+    double v = 0.0;
+    for (uint64_t k = threadIdx.x; k < K; k += 256) {
+        const double d = e[k] - mean;
+        v += d * d;
+    }
+    const double ss = block_sum(v, red);
+    if (threadIdx.x == 0) {
+        out[0] = mean;
+        out[1] = K > 1 ? sqrt(ss / (double)(K - 1) / (double)K) : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_finish_rho(const double2* __restrict__ rho, uint32_t N, double inv,
+                                                    double2* __restrict__ out) {
+    const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (size_t)N * N) return;
+    const uint32_t i = (uint32_t)(t / N), j = (uint32_t)(t % N);
+    double2 v;
+    if (i < j) {
+        v = rho[t];
+    } else if (i > j) {
+        v = rho[(size_t)j * N + i];
+        v.y = -v.y;
+    } else {
+        v = make_double2(rho[t].x, 0.0);
+    }
+    out[t] = make_double2(v.x * inv, v.y * inv);
+}
+
+__global__ __launch_bounds__(256) void k_finish_diag(const double* __restrict__ diag, uint32_t N, double inv,
+                                                     double* __restrict__ out, double* __restrict__ trace) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (uint32_t i = threadIdx.x; i < N; i += 256) {
+        const double v = diag[i] * inv;
+        out[i] = v;
+        s += v;
+    }
+    const double tr = block_sum(s, red);
+    if (threadIdx.x == 0) *trace = tr;
+}
+
+}  // namespace
+
+void launch_reduce(stn_plan* p, stn_batch* b, stn_accum* a, hipStream_t s) {
+    const uint32_t N = 1u << p->n;
+    const bool dbl = p->opts.precision == 128;
+    const uint32_t outs = p->opts.outputs;
+    if (outs & STN_OUT_RHO) {
+        const uint32_t tiles = (N + kTile - 1) / kTile;
+        const uint32_t blocks = tiles * (tiles + 1) / 2;
+        const double upper = (double)N * (N + 1) / 2;
+        prof_begin(p, STN_K_HERK, s);
+        if (dbl)
+            hipLaunchKernelGGL(k_herk<double2>, dim3(blocks), dim3(256), 0, s, b->d_states.as<double2>(), b->K, N,
+                               tiles, a->d_rho.as<double2>());
+        else
+            hipLaunchKernelGGL(k_herk<float2>, dim3(blocks), dim3(256), 0, s, b->d_states.as<float2>(), b->K, N,
+                               tiles, a->d_rho.as<double2>());
+        STN_HIP(hipGetLastError());
+        prof_end(p, STN_K_HERK, s, (double)b->K * N * (dbl ? 16 : 8) + upper * 32.0, upper * b->K * 8.0);
+    }
+    if (outs & (STN_OUT_RHO | STN_OUT_DIAG)) {
+        prof_begin(p, STN_K_DIAG, s);
+        if (dbl)
+            hipLaunchKernelGGL(k_diag<double2>, dim3((N + 255) / 256), dim3(256), 0, s, b->d_states.as<double2>(),
+                               b->K, N, a->d_diag.as<double>());
+        else
+            hipLaunchKernelGGL(k_diag<float2>, dim3((N + 255) / 256), dim3(256), 0, s, b->d_states.as<float2>(),
+                               b->K, N, a->d_diag.as<double>());
+        STN_HIP(hipGetLastError());
+        prof_end(p, STN_K_DIAG, s, (double)b->K * N * (dbl ? 16 : 8) + N * 16.0, (double)b->K * N * 4.0);
+    }
+    if (outs & STN_OUT_ENERGY) {
+        // per-trajectory energies into the chunk that holds trajectory k
+        uint64_t k = b->k0;
+        const uint64_t end = b->k0 + b->K;
+        while (k < end) {
+            const uint64_t c = k / kEnergyChunk, stop = std::min<uint64_t>(end, (c + 1) * kEnergyChunk);
+            STN_HIP(hipMemcpyAsync(a->e_chunks[c].as<double>() + (k % kEnergyChunk),
+                                   b->d_energy.as<double>() + (k - b->k0), (stop - k) * 8,
+                                   hipMemcpyDeviceToDevice, s));
+            k = stop;
+        }
+    }
+}
+
+void launch_energy_stats(stn_accum* a, uint64_t K, hipStream_t s) {
+    hipLaunchKernelGGL(k_stats, dim3(1), dim3(256), 0, s, a->d_egather.as<double>(), K, a->d_stats.as<double>());
+    STN_HIP(hipGetLastError());
+}
+
+void launch_finish_dense(stn_accum* a, hipStream_t s) {
+    stn_plan* p = a->plan;
+    const uint32_t N = 1u << p->n;
+    const double inv = a->k_done ? 1.0 / (double)a->k_done : 0.0;
+    if (p->opts.outputs & STN_OUT_RHO) {
+        const size_t tot = (size_t)N * N;
+        hipLaunchKernelGGL(k_finish_rho, dim3((uint32_t)((tot + 255) / 256)), dim3(256), 0, s,
+                           a->d_rho.as<double2>(), N, inv, a->d_rho_out.as<double2>());
+        STN_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_finish_diag, dim3(1), dim3(256), 0, s, a->d_diag.as<double>(), N, inv,
+                       a->d_diag_out.as<double>(), a->d_stats.as<double>() + 2);
+    STN_HIP(hipGetLastError());
+}
+
+}  // namespace stn

@@ -1,0 +1,235 @@
+// Internal declarations shared by the host planner, the ABI layer and the
+// kernel launchers of the trajectory-ensemble library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/stn.h"
+
+namespace stn {
+
+using cd = std::complex<double>;
+
+// ---------------------------------------------------------------- errors
+struct Error {
+    stn_status status;
+    std::string msg;
+};
+[[noreturn]] void fail(stn_status s, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+#define STN_HIP(x) ::stn::hip_check((x), #x)
+
+// ---------------------------------------------------------------- device memory
+struct Allocator {
+    stn_alloc_fn fn = nullptr;
+    stn_free_fn ffn = nullptr;
+    void* ctx = nullptr;
+    void* alloc(size_t bytes) const;
+    void release(void* p) const;
+};
+
+// Owning device buffer; memory comes from the plan's allocator.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    const Allocator* a = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept { *this = std::move(o); }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        if (this != &o) { reset(); p = o.p; bytes = o.bytes; a = o.a; o.p = nullptr; o.bytes = 0; }
+        return *this;
+    }
+    ~DevBuf() { reset(); }
+    void reset() { if (p && a) a->release(p); p = nullptr; bytes = 0; }
+    void ensure(const Allocator* al, size_t nbytes) {
+        if (p && bytes >= nbytes) return;
+        reset();
+        a = al;
+        bytes = nbytes ? nbytes : 1;
+        p = al->alloc(bytes);
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+void upload(DevBuf& d, const Allocator* a, const void* host, size_t bytes, hipStream_t s);
+
+// ---------------------------------------------------------------- plan data
+enum OpKind : uint32_t {
+    OP_DENSE1 = 0,   // 2x2 dense on q0
+    OP_DENSE2 = 1,   // 4x4 dense on (q0, q1)
+    OP_DIAG1 = 2,    // diag(d0, d1) on q0
+    OP_DIAG2 = 3,    // diag(d0..d3) on (q0, q1)
+    OP_PAULI = 4,    // Pauli string: x mask / z mask (global phase dropped)
+    OP_SITE = 5,     // noise site: operator picked by the trajectory's index
+    OP_IDENT = 6
+};
+
+// One instruction of the whole-state-in-LDS interpreter.  mat indexes the
+// complex value table (2, 4 or 16 entries).
+struct LdsOp {
+    uint32_t kind;
+    uint32_t q0, q1;
+    uint32_t mat;       // offset into value table (dense / diag)
+    uint64_t xmask, zmask;
+    uint32_t site;      // OP_SITE: site index; operator table at site_op[site_op_off[site] + j]
+    uint32_t pad;
+};
+
+struct SiteRec {
+    uint32_t gate = 0, nq = 1, q0 = 0, q1 = 0, J = 0;
+    std::vector<double> q;           // selection probabilities
+    std::vector<uint64_t> T;         // thresholds, T[J-1] = 2^32
+    std::vector<cd> ops;             // J * d*d inserted operators K_j/sqrt(q_j)
+    bool pauli = false;              // every inserted operator is a Pauli string (up to phase)
+    std::vector<uint64_t> px, pz;    // per operator: global x / z masks when pauli
+};
+
+struct GateRec {
+    uint32_t kind = 0, nq = 1, q0 = 0, q1 = 0;
+    double theta = 0;
+    std::vector<cd> m;               // 2x2 or 4x4 matrix
+    bool rotation = false;           // exp(-i theta/2 * P) with P a Pauli string
+    uint64_t gx = 0, gz = 0;         // generator P's x / z masks (rotations)
+};
+
+// Tiled statevector lowering (QAOA structure: H prefix, then layers of
+// diagonal zz blocks and rx mixer blocks, Pauli noise).
+struct TiledLayer {
+    std::vector<uint32_t> zz_gates;  // gate indices of the diagonal block
+    std::vector<int32_t> zz_mult;    // angle = mult * base_angle
+    double base_angle = 0;
+    int32_t mult_sum = 0;            // sum |mult|: phase index range [-mult_sum, mult_sum]
+    std::vector<int32_t> rx_gate;    // per qubit: rx gate index in the mixer block, -1 = none
+};
+
+struct TiledPass {
+    uint32_t tile_mask = 0;          // storage bits inside the tile (= qubits, identity layout)
+    int32_t layer = -1;              // layer whose diagonal is applied at load (-1 none)
+    int32_t mix_layer = -1;          // layer whose rx gates on tile qubits are applied
+    uint32_t mix_mask = 0;           // qubits mixed in this pass
+    bool init = false;               // generate |+>^n instead of loading
+    bool last = false;               // accumulate the energy instead of storing
+};
+
+// Event-timed launches of one kernel class (profiling on).
+struct ProfClass {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<double> bytes, flops;
+};
+
+}  // namespace stn
+
+struct stn_plan {
+    stn::Allocator alloc;
+    stn_plan_opts opts{};
+    uint32_t n = 0;
+    uint32_t kind = STN_PLAN_SV_LDS;
+    uint32_t max_batch = 0;
+    std::vector<stn::GateRec> gates;
+    std::vector<stn::SiteRec> sites;
+    std::vector<uint32_t> obs_u, obs_v;
+    std::vector<double> obs_w;
+    bool frame_ok = false;           // Pauli-frame rewrite valid for this circuit
+    bool uploaded = false;           // device tables present (uploaded on first device use)
+    // cost model
+    double bytes_per_traj = 0, flops_per_traj = 0, peak_bytes = 0;
+    uint32_t width = 0, n_passes = 0, n_steps = 0;
+
+    // device tables shared by every lowering
+    stn::DevBuf d_site_T;            // uint64 thresholds, flattened
+    stn::DevBuf d_site_off;          // uint32 offset of each site's thresholds, S+1 entries
+    stn::DevBuf d_site_gate;         // uint32 gate index of each site
+    stn::DevBuf d_site_px, d_site_pz;// uint64 Pauli masks per (site, op), flattened like T
+    stn::DevBuf d_gate_gx, d_gate_gz;// uint64 generator masks per gate (0,0 = not a rotation)
+    stn::DevBuf d_obs;               // observable: u, v (uint32 pairs)
+    stn::DevBuf d_obs_w;             // weights (double)
+
+    // SV_LDS lowering
+    std::vector<stn::LdsOp> lds_ops;
+    std::vector<stn::cd> lds_vals;          // dense / diag values of gates
+    std::vector<uint32_t> site_op_off;      // per site: first entry in site_ops
+    std::vector<stn::LdsOp> site_ops;       // per (site, j) operator descriptors
+    stn::DevBuf d_lds_ops, d_lds_vals32, d_lds_vals64, d_site_ops, d_site_op_off;
+
+    // SV_TILED lowering
+    std::vector<stn::TiledLayer> layers;
+    std::vector<stn::TiledPass> passes;
+    stn::DevBuf d_phase32, d_phase64;       // per layer: phase table e^{-i base m}, m in [-M, M]
+    std::vector<uint32_t> phase_off;
+    stn::DevBuf d_rx32, d_rx64;             // per gate (rx): (cos(theta/2), sin(theta/2))
+    stn::DevBuf d_layer_edges;              // per layer: (u, v, mult, gate) int32 quads
+    std::vector<uint32_t> layer_edge_off;
+    stn::DevBuf d_work;                     // psi workspace [max_batch x 2^n]
+    stn::DevBuf d_partials;                 // per (trajectory, tile) energy partials
+
+    // per-kernel timing (stn_profile)
+    bool prof = false;
+    stn::ProfClass prof_cls[STN_K_COUNT];
+    std::vector<hipEvent_t> ev_pool;
+
+    // lightcone lowering (see lightcone.cpp)
+    void* lc = nullptr;
+    void (*lc_free)(void*) = nullptr;
+
+    ~stn_plan();
+};
+
+struct stn_batch {
+    stn_plan* plan = nullptr;
+    uint64_t k0 = 0;
+    uint32_t K = 0;
+    uint32_t words = 0;              // sign words per trajectory
+    stn::DevBuf d_idx;               // uint8 [K x S]
+    stn::DevBuf d_signs;             // uint32 [K x words]: bit g = rotation gate g flipped
+    stn::DevBuf d_frame;             // uint64 [K x 2]: final frame x mask, z mask
+    stn::DevBuf d_energy;            // double [K]
+    stn::DevBuf d_states;            // complex [K x 2^n] (float2 or double2)
+    bool contracted = false;
+    bool has_states = false;
+};
+
+struct stn_accum {
+    stn_plan* plan = nullptr;
+    uint64_t k_done = 0;
+    std::vector<std::pair<uint64_t, uint64_t>> ranges;  // reduced k ranges [a, b)
+    std::vector<stn::DevBuf> e_chunks;                  // per-k energies, 65536 per chunk
+    stn::DevBuf d_rho;               // double2 [2^n x 2^n] (upper triangle accumulated)
+    stn::DevBuf d_diag;              // double [2^n]
+    stn::DevBuf d_rho_out;           // double2 [2^n x 2^n]: mirrored, scaled by 1/K
+    stn::DevBuf d_diag_out;          // double [2^n]: scaled by 1/K
+    stn::DevBuf d_stats;             // double [4]: energy mean, SE, trace
+    stn::DevBuf d_egather;           // double [k_done]: energies in trajectory order
+    std::vector<double> h_rho, h_diag, h_energies;
+};
+
+namespace stn {
+constexpr uint32_t kEnergyChunk = 65536;
+
+// profiling hooks around a kernel launch on stream s (no-ops when off)
+void prof_begin(stn_plan* p, int cls, hipStream_t s);
+void prof_end(stn_plan* p, int cls, hipStream_t s, double bytes, double flops);
+void prof_clear(stn_plan* p);
+
+// planner (plan.cpp)
+void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, const stn_observable* ob);
+
+// launchers (kernels_*.hip)
+void launch_sample(stn_plan* p, stn_batch* b, uint64_t seed, hipStream_t s);
+void launch_frame(stn_plan* p, stn_batch* b, hipStream_t s);
+void launch_sv_lds(stn_plan* p, stn_batch* b, hipStream_t s);
+void launch_sv_tiled(stn_plan* p, stn_batch* b, hipStream_t s);
+void launch_reduce(stn_plan* p, stn_batch* b, stn_accum* a, hipStream_t s);
+// fixed-order energy statistics over the gathered per-trajectory energies
+void launch_energy_stats(stn_accum* a, uint64_t K, hipStream_t s);
+// rho_out = mirror(rho)/K, diag_out = diag/K, stats[2] = trace
+void launch_finish_dense(stn_accum* a, hipStream_t s);
+void launch_lightcone(stn_plan* p, stn_batch* b, hipStream_t s);
+}  // namespace stn

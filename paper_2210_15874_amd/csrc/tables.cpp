@@ -1,0 +1,112 @@
+// Device copies of the plan tables (noise sites, gate generators, observable,
+// and the lowering-specific programs).  Complex values are computed on the
+// host in binary64 and rounded once to the contraction precision.
+#include <cmath>
+
+#include "stn_internal.h"
+
+namespace stn {
+
+namespace {
+template <class T>
+void up(DevBuf& d, const Allocator* a, const std::vector<T>& v, hipStream_t s) {
+    upload(d, a, v.data(), v.size() * sizeof(T), s);
+}
+
+void up_complex(DevBuf& d32, DevBuf& d64, const Allocator* a, const std::vector<cd>& v, hipStream_t s) {
+    std::vector<float> f(2 * v.size() + 2);
+    std::vector<double> g(2 * v.size() + 2);
+    for (size_t i = 0; i < v.size(); ++i) {
+        f[2 * i] = (float)v[i].real();
+        f[2 * i + 1] = (float)v[i].imag();
+        g[2 * i] = v[i].real();
+        g[2 * i + 1] = v[i].imag();
+    }
+    up(d32, a, f, s);
+    up(d64, a, g, s);
+}
+}  // namespace
+
+void upload_plan_tables(stn_plan* p, hipStream_t s) {
+    const Allocator* a = &p->alloc;
+    std::vector<uint64_t> T, px, pz;
+    std::vector<uint32_t> off, sg;
+    for (auto& st : p->sites) {
+        off.push_back((uint32_t)T.size());
+        T.insert(T.end(), st.T.begin(), st.T.end());
+        px.insert(px.end(), st.px.begin(), st.px.end());
+        pz.insert(pz.end(), st.pz.begin(), st.pz.end());
+        sg.push_back(st.gate);
+    }
+    off.push_back((uint32_t)T.size());
+    T.push_back(0);
+    px.push_back(0);
+    pz.push_back(0);
+    sg.push_back(0);
+    up(p->d_site_T, a, T, s);
+    up(p->d_site_off, a, off, s);
+    up(p->d_site_gate, a, sg, s);
+    up(p->d_site_px, a, px, s);
+    up(p->d_site_pz, a, pz, s);
+    std::vector<uint64_t> gx, gz;
+    for (auto& g : p->gates) {
+        gx.push_back(g.rotation ? g.gx : 0);
+        gz.push_back(g.rotation ? g.gz : 0);
+    }
+    gx.push_back(0);
+    gz.push_back(0);
+    up(p->d_gate_gx, a, gx, s);
+    up(p->d_gate_gz, a, gz, s);
+    std::vector<uint32_t> uv;
+    for (size_t t = 0; t < p->obs_u.size(); ++t) {
+        uv.push_back(p->obs_u[t]);
+        uv.push_back(p->obs_v[t]);
+    }
+    uv.push_back(0);
+    uv.push_back(0);
+    std::vector<double> w = p->obs_w;
+    w.push_back(0);
+    up(p->d_obs, a, uv, s);
+    up(p->d_obs_w, a, w, s);
+
+    if (p->kind == STN_PLAN_SV_LDS) {
+        std::vector<LdsOp> ops = p->lds_ops, sops = p->site_ops;
+        ops.push_back(LdsOp{});
+        sops.push_back(LdsOp{});
+        up(p->d_lds_ops, a, ops, s);
+        up(p->d_site_ops, a, sops, s);
+        up(p->d_site_op_off, a, p->site_op_off, s);
+        up_complex(p->d_lds_vals32, p->d_lds_vals64, a, p->lds_vals, s);
+    } else if (p->kind == STN_PLAN_SV_TILED) {
+        // phase tables e^{-i base m}, m = -M..M, and per-layer edge lists
+        std::vector<cd> ph;
+        std::vector<int32_t> edges;
+        p->phase_off.clear();
+        p->layer_edge_off.clear();
+        for (auto& L : p->layers) {
+            p->phase_off.push_back((uint32_t)ph.size());
+            for (int m = -L.mult_sum; m <= L.mult_sum; ++m) ph.push_back(std::exp(cd(0, -L.base_angle * m)));
+            p->layer_edge_off.push_back((uint32_t)edges.size() / 4);
+            for (size_t e = 0; e < L.zz_gates.size(); ++e) {
+                const GateRec& g = p->gates[L.zz_gates[e]];
+                edges.push_back((int32_t)g.q0);
+                edges.push_back((int32_t)g.q1);
+                edges.push_back(L.zz_mult[e]);
+                edges.push_back((int32_t)L.zz_gates[e]);
+            }
+        }
+        p->phase_off.push_back((uint32_t)ph.size());
+        p->layer_edge_off.push_back((uint32_t)edges.size() / 4);
+        edges.insert(edges.end(), {0, 0, 0, 0});
+        up_complex(p->d_phase32, p->d_phase64, a, ph, s);
+        up(p->d_layer_edges, a, edges, s);
+        // rx gates: (cos(theta/2), sin(theta/2))
+        std::vector<cd> cs(p->gates.size() + 1);
+        for (size_t g = 0; g < p->gates.size(); ++g)
+            if (p->gates[g].kind == STN_G_RX)
+                cs[g] = cd(std::cos(p->gates[g].theta / 2), std::sin(p->gates[g].theta / 2));
+        up_complex(p->d_rx32, p->d_rx64, a, cs, s);
+    }
+}
+
+}  // namespace stn

@@ -1,0 +1,97 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every function include/stn.h declares, plans the workloads, and its integer
+selection thresholds are bit-identical to the oracle's (the sampler's
+bit-exactness rests on them)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2210_15874_amd", "libstn.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libstn.so not built")
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "stn.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(stn_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    lib = C.CDLL(LIB)
+    names = declared_functions()
+    assert len(names) >= 18
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_header():
+    from paper_2210_15874_amd.binding import EXPORTS
+    assert set(declared_functions()) == set(EXPORTS)
+
+
+def plan(problem, **kw):
+    from paper_2210_15874_amd import Plan
+    return Plan(problem, torch_allocator=False, **kw)
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2])
+def test_thresholds_bit_identical_to_oracle(cfg):
+    from oracle import channels as chn
+    from workloads import config_problem
+    pr = config_problem(cfg)
+    pl = plan(pr)
+    for s, ch in enumerate(pr.channels):
+        assert pl.site_thresholds(s) == chn.thresholds(chn.selection_probs(ch)), s
+
+
+def test_thresholds_random_rates():
+    from oracle import channels as chn
+    from workloads import Channel, Gate, Problem
+    rng = np.random.default_rng(3)
+    lams = list(rng.random(40)) + [0.0, 1.0, 1e-4, 0.5, 1 / 3]
+    gates = [Gate("h", (0,)), Gate("zz", (0, 1), 0.3)]
+    chans = []
+    for lam in lams:
+        chans += [Channel(1, "depol1", (0,), float(lam)), Channel(1, "depol2", (0, 1), float(lam)),
+                  Channel(1, "bitflip", (1,), float(lam)), Channel(1, "ampdamp", (0,), float(lam))]
+    pr = Problem(2, gates, chans, [(0, 1)], [1.0])
+    pl = plan(pr)
+    for s, ch in enumerate(chans):
+        assert pl.site_thresholds(s) == chn.thresholds(chn.selection_probs(ch)), (s, ch)
+
+
+def test_plan_kinds_and_cost_model():
+    from workloads import config_problem
+    from paper_2210_15874_amd import OUT_ENERGY, OUT_RHO
+    i0 = plan(config_problem(0), outputs=OUT_RHO | OUT_ENERGY).info()
+    assert i0["plan_name"] == "sv_lds" and i0["n_sites"] == 21
+    i2 = plan(config_problem(2)).info()
+    assert i2["plan_name"] == "sv_tiled" and i2["n_gates"] == 286 and i2["n_sites"] == 286
+    # every pass reads and writes the 2^26 complex64 state, except the first
+    # (generated) and last (reduced to the energy)
+    N = 2 ** 26 * 8
+    assert i2["bytes_per_traj"] == (2 * i2["n_passes"] - 2) * N
+
+
+def test_validation_errors():
+    from paper_2210_15874_amd import OUT_RHO, StnError
+    from workloads import Channel, Gate, Problem, config_problem
+    bad_q = Problem(2, [Gate("h", (2,))], [])
+    with pytest.raises(StnError, match="INVALID"):
+        plan(bad_q, outputs=OUT_RHO)
+    non_cptp = Problem(1, [Gate("h", (0,))], [Channel(0, "kraus", (0,), 0.0, ((1, 0, 0, 1), (1, 0, 0, 0)))])
+    with pytest.raises(StnError, match="trace preserving"):
+        plan(non_cptp, outputs=OUT_RHO)
+    order = Problem(2, [Gate("h", (0,)), Gate("h", (1,))],
+                    [Channel(1, "depol1", (1,), 0.1), Channel(0, "depol1", (0,), 0.1)])
+    with pytest.raises(StnError, match="ordered"):
+        plan(order, outputs=OUT_RHO)
+    with pytest.raises(StnError, match="UNSUPPORTED"):
+        plan(config_problem(2), outputs=OUT_RHO)
+    with pytest.raises(StnError, match="INVALID"):
+        plan(bad_q)  # ENERGY without edges is fine, bad qubit is not
