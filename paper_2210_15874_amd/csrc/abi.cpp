@@ -125,6 +125,7 @@ void prof_clear(stn_plan* p) {
 
 stn_plan::~stn_plan() {
     if (lc && lc_free) lc_free(lc);
+    if (tiled && tiled_free) tiled_free(tiled);
     (void)hipDeviceSynchronize();
     stn::prof_clear(this);
     for (auto e : ev_pool) (void)hipEventDestroy(e);

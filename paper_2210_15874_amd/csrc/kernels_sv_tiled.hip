@@ -1,18 +1,35 @@
 // Tiled HBM statevector contraction for QAOA-structured circuits under Pauli
-// noise (Sec. III-G, with the trajectory index as batch dimension).
+// noise (Sec. III-G: every noisy circuit of the ensemble is simulated to its
+// statevector; the trajectory index is the batch dimension of every launch).
 //
 // Every trajectory is the noiseless circuit with some rotation angles negated
 // (Pauli-frame rewrite, see kernels_sample.hip) followed by a final Pauli
 // frame F.  The circuit is H on every qubit, then layers of a diagonal block
 // (zz gates, angle = mult * base) and a mixer block (rx per qubit).  The state
-// psi[b][z] (complex64, z = basis index) is updated in place by passes; a
-// pass loads a tile of 2^13 amplitudes (13 storage bits, the rest fixed) into
-// LDS, applies the layer's diagonal phase exp(-i base m(z)) with the integer
-// m(z) = sum_e mult_e sigma_e [z_u != z_v] looked up in a table computed in
-// binary64 on the host, rotates the tile's qubits with rx(sigma theta), and
-// writes the tile back.  The first pass generates |+>^n instead of loading;
-// the last pass accumulates the energy sum_z |psi_z|^2 C(z xor F_x) (the frame
-// flips measured bits) in binary64 instead of storing.
+// psi[b][z] (complex64) is updated in place by passes over tiles of 2^14
+// amplitudes: 14 storage bits vary inside a tile, the others are fixed.  The
+// first pass of a layer holds storage bits 0..13; the next holds bits 0, 1
+// and the next 12 high qubits, so a layer of n = 26 qubits costs two passes.
+//
+// Inside a workgroup (512 threads) the tile lives in registers, 32 amplitudes
+// per thread, in three layouts L0 -> L1 -> L2 exchanged through LDS; in each
+// layout the thread's 5 register bits are the qubits it rotates.  The diagonal
+// phase exp(-i base m(z)) with integer m(z) = sum_e mult_e sigma_e [z_u != z_v]
+// is looked up in a per-layer table (binary64 on the host, rounded once);
+// m(z) is split into a per-thread part and the contributions of the 5
+// register bits, so each amplitude costs a few integer adds.  An rx(theta)
+// with c = cos(theta/2), s = sin(theta/2) is applied as c [[1, -i t], [-i t, 1]]
+// (t = s/c) or s [[k, -i], [-i, k]] (k = c/s), two FMAs per amplitude; the
+// dropped factor |c| or |s| is restored in the next pass's phase table or in
+// the energy.  The first pass generates |+>^n; the last pass accumulates
+// sum_z |psi_z|^2 C(z xor F_x) in binary64 (F flips measured bits) instead of
+// storing.
+//
+// Passes whose tile holds only two low storage bits read 32-byte runs; the
+// four workgroups that share each 128-byte line are given block indices
+// x, x+8, x+16, x+24, which the dispatcher places on the same XCD at the same
+// time, so each line is fetched from HBM once and served to the other three
+// from that XCD's L2.
 #include <cmath>
 
 #include "stn_internal.h"
@@ -21,122 +38,275 @@ namespace stn {
 
 namespace {
 
-constexpr int kTileBits = 13;
-constexpr int kTileN = 1 << kTileBits;
-constexpr int kThreads = 256;
+constexpr int kQ = 14;          // tile bits
+constexpr int kThreads = 512;   // 9 thread bits
+constexpr int kRegs = 32;       // 5 register bits
+constexpr int kMaxPhase = 511;  // phase table entries (2M+1)
 
-struct PassArgs {
-    uint32_t n;
-    uint32_t tile_bit[kTileBits];  // storage bit of tile index bit t (ascending)
-    uint32_t fixed_mask;           // storage bits outside the tile
-    int32_t layer;                 // diagonal layer applied at load, -1 = none
-    uint32_t edge_off, n_edges, phase_off, mult_sum;
-    uint32_t n_mix;
-    uint32_t mix_pos[kTileBits];   // tile index bit of each rotated qubit
-    int32_t mix_gate[kTileBits];   // its rx gate index
-    uint32_t init, last;
-    float amp0;                    // 2^{-n/2}
+// layouts: tile-index bit of each register bit / thread bit
+__device__ constexpr int L0R[5] = {0, 10, 11, 12, 13};
+__device__ constexpr int L0T[9] = {1, 2, 3, 4, 5, 6, 7, 8, 9};
+__device__ constexpr int L1R[5] = {1, 2, 3, 4, 5};
+__device__ constexpr int L1T[9] = {0, 6, 7, 8, 9, 10, 11, 12, 13};
+__device__ constexpr int L2R[5] = {0, 6, 7, 8, 9};
+__device__ constexpr int L2T[9] = {1, 2, 3, 4, 5, 10, 11, 12, 13};
+constexpr int hL0R[5] = {0, 10, 11, 12, 13};
+constexpr int hL1R[5] = {1, 2, 3, 4, 5};
+constexpr int hL2R[5] = {0, 6, 7, 8, 9};
+
+struct Pass2 {
+    uint32_t tb[kQ];            // storage bit of tile-index bit i
+    uint64_t fixed_mask;        // storage bits outside the tile
+    uint32_t share;             // fixed storage bits below the 128-byte line (0..2)
+    uint32_t init, last, diag;
+    float amp0;
+    int32_t mix_gate[3][5];     // per layout and register bit: rx gate, -1 = not rotated here
+    float mix_coef[3][5];       // t = s/c (form 0) or k = c/s (form 1), before the sign
+    uint32_t mix_form[3][5];
+    uint32_t d_off[7], d_n[7];  // diagonal edges: [0] both endpoints fixed, [1..5] one in register r-1, [6] both in registers
+    uint32_t ph_off, ph_mid;    // phase table entries [ph_off, ph_off + 2*ph_mid]
+    uint32_t e_off[7], e_n[7];  // observable terms in the same categories w.r.t. L2
+    double e_scale;             // squared product of the rotation factors since the last diagonal
 };
 
-__device__ __forceinline__ uint32_t ins0(uint32_t p, uint32_t q) {
-    const uint32_t lo = p & ((1u << q) - 1u);
-    return ((p ^ lo) << 1) | lo;
+__device__ __forceinline__ uint32_t swz(uint32_t t) { return t ^ (((t >> 6) & 7u) << 1); }
+
+template <const int* T>
+__device__ __forceinline__ uint32_t thread_part(uint32_t tid) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int b = 0; b < 9; ++b) t |= ((tid >> b) & 1u) << T[b];
+    return t;
+}
+
+template <const int* R>
+__device__ __forceinline__ uint32_t reg_part(int j) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int r = 0; r < 5; ++r) t |= (uint32_t)((j >> r) & 1) << R[r];
+    return t;
+}
+
+template <const int* T>
+__device__ __forceinline__ uint64_t storage_thread(const Pass2& P, uint32_t tid) {
+    uint64_t z = 0;
+#pragma unroll
+    for (int b = 0; b < 9; ++b) z |= (uint64_t)((tid >> b) & 1u) << P.tb[T[b]];
+    return z;
 }
 
 __device__ __forceinline__ uint64_t pdep64(uint64_t v, uint64_t mask) {
     uint64_t r = 0;
     for (uint64_t m = mask; m; m &= m - 1) {
-        const uint64_t bit = m & (~m + 1);
-        if (v & 1) r |= bit;
+        if (v & 1) r |= m & (~m + 1);
         v >>= 1;
     }
     return r;
 }
 
-__global__ __launch_bounds__(kThreads) void k_sv_pass(float2* __restrict__ psi, PassArgs a,
-                                                      const uint32_t* __restrict__ signs, uint32_t words,
-                                                      const uint64_t* __restrict__ frame,
-                                                      const int4* __restrict__ edges,
-                                                      const float2* __restrict__ phase,
-                                                      const float2* __restrict__ rxcs,
-                                                      const uint32_t* __restrict__ obs_uv,
-                                                      const double* __restrict__ obs_w, uint32_t n_terms,
-                                                      double* __restrict__ partials) {
-    __shared__ float2 tile[kTileN];
-    __shared__ uint32_t sg[64];
-    __shared__ double red[kThreads];
-    const uint32_t tid = threadIdx.x;
-    const uint32_t b = blockIdx.y;
-    const uint64_t N = 1ull << a.n;
-    const uint64_t base = pdep64(blockIdx.x, a.fixed_mask);
-    float2* st = psi + (size_t)b * N;
-    for (uint32_t w = tid; w < words && w < 64; w += kThreads) sg[w] = signs[(size_t)b * words + w];
-    __syncthreads();
-    for (uint32_t i = tid; i < kTileN; i += kThreads) {
-        uint64_t z = base;
+__device__ __forceinline__ bool sign_bit(const uint32_t* sg, int g) { return (sg[g >> 5] >> (g & 31)) & 1u; }
+
+// rotate register bit r of layout L: pairs (j, j | 1<<r)
+template <int L>
+__device__ __forceinline__ void mix(float2 (&v)[kRegs], const Pass2& P, const uint32_t* sg) {
 #pragma unroll
-        for (int t = 0; t < kTileBits; ++t) z |= (uint64_t)((i >> t) & 1) << a.tile_bit[t];
-        float2 v = a.init ? make_float2(a.amp0, 0.f) : st[z];
-        if (a.layer >= 0) {
-            int m = 0;
-            for (uint32_t e = 0; e < a.n_edges; ++e) {
-                const int4 E = edges[a.edge_off + e];
-                const int neg = (sg[E.w >> 5] >> (E.w & 31)) & 1;
-                const int cut = (int)(((z >> E.x) ^ (z >> E.y)) & 1);
-                m += cut * (neg ? -E.z : E.z);
+    for (int r = 0; r < 5; ++r) {
+        const int g = P.mix_gate[L][r];
+        if (g < 0) continue;
+        const float c0 = P.mix_coef[L][r];
+        const float t = sign_bit(sg, g) ? -c0 : c0;
+        if (P.mix_form[L][r] == 0) {
+            // x0' = x0 - i t x1, x1' = x1 - i t x0
+#pragma unroll
+            for (int j = 0; j < kRegs; ++j) {
+                if (j & (1 << r)) continue;
+                const float2 a = v[j], b = v[j | (1 << r)];
+                v[j] = make_float2(fmaf(t, b.y, a.x), fmaf(-t, b.x, a.y));
+                v[j | (1 << r)] = make_float2(fmaf(t, a.y, b.x), fmaf(-t, a.x, b.y));
             }
-            const float2 ph = phase[a.phase_off + a.mult_sum + m];
-            v = make_float2(ph.x * v.x - ph.y * v.y, ph.x * v.y + ph.y * v.x);
-        }
-        tile[i] = v;
-    }
-    __syncthreads();
-    for (uint32_t q = 0; q < a.n_mix; ++q) {
-        const uint32_t pos = a.mix_pos[q];
-        const int32_t g = a.mix_gate[q];
-        const float2 cs = rxcs[g];
-        const float c = cs.x, s = ((sg[g >> 5] >> (g & 31)) & 1) ? -cs.y : cs.y;
-        for (uint32_t p = tid; p < kTileN / 2; p += kThreads) {
-            const uint32_t i0 = ins0(p, pos), i1 = i0 | (1u << pos);
-            const float2 x0 = tile[i0], x1 = tile[i1];
-            // rx: [[c, -i s], [-i s, c]]
-            tile[i0] = make_float2(c * x0.x + s * x1.y, c * x0.y - s * x1.x);
-            tile[i1] = make_float2(c * x1.x + s * x0.y, c * x1.y - s * x0.x);
-        }
-        __syncthreads();
-    }
-    if (a.last) {
-        const uint64_t fx = frame[2 * (size_t)b];
-        double acc = 0.0;
-        for (uint32_t i = tid; i < kTileN; i += kThreads) {
-            uint64_t z = base;
+        } else {
+            // x0' = t x0 - i x1, x1' = t x1 - i x0
 #pragma unroll
-            for (int t = 0; t < kTileBits; ++t) z |= (uint64_t)((i >> t) & 1) << a.tile_bit[t];
-            z ^= fx;
-            double c = 0.0;
-            for (uint32_t t = 0; t < n_terms; ++t)
-                c += ((z >> obs_uv[2 * t]) ^ (z >> obs_uv[2 * t + 1])) & 1 ? obs_w[t] : 0.0;
-            const float2 v = tile[i];
-            acc += ((double)v.x * v.x + (double)v.y * v.y) * c;
-        }
-        red[tid] = acc;
-        __syncthreads();
-        for (uint32_t w = kThreads / 2; w > 0; w >>= 1) {
-            if (tid < w) red[tid] += red[tid + w];
-            __syncthreads();
-        }
-        if (tid == 0) partials[(size_t)b * gridDim.x + blockIdx.x] = red[0];
-    } else {
-        for (uint32_t i = tid; i < kTileN; i += kThreads) {
-            uint64_t z = base;
-#pragma unroll
-            for (int t = 0; t < kTileBits; ++t) z |= (uint64_t)((i >> t) & 1) << a.tile_bit[t];
-            st[z] = tile[i];
+            for (int j = 0; j < kRegs; ++j) {
+                if (j & (1 << r)) continue;
+                const float2 a = v[j], b = v[j | (1 << r)];
+                v[j] = make_float2(fmaf(t, a.x, b.y), fmaf(t, a.y, -b.x));
+                v[j | (1 << r)] = make_float2(fmaf(t, b.x, a.y), fmaf(t, b.y, -a.x));
+            }
         }
     }
 }
 
-// energy[b] = sum over tiles of partials[b][t], in tile order
+// write registers in layout A, read them back in layout B
+template <const int* AR, const int* AT, const int* BR, const int* BT>
+__device__ __forceinline__ void exchange(float2 (&v)[kRegs], float2* lds, uint32_t tid) {
+    const uint32_t ta = swz(thread_part<AT>(tid));
+#pragma unroll
+    for (int j = 0; j < kRegs; ++j) lds[ta ^ swz(reg_part<AR>(j))] = v[j];
+    __syncthreads();
+    const uint32_t tbp = swz(thread_part<BT>(tid));
+#pragma unroll
+    for (int j = 0; j < kRegs; ++j) v[j] = lds[tbp ^ swz(reg_part<BR>(j))];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kThreads) void k_sv_pass2(float2* __restrict__ psi, const Pass2 P, uint32_t n,
+                                                       uint32_t tiles_log2, const uint32_t* __restrict__ signs,
+                                                       uint32_t words, const uint64_t* __restrict__ frame,
+                                                       const int4* __restrict__ dedges,
+                                                       const float2* __restrict__ phase,
+                                                       const int2* __restrict__ eedges,
+                                                       const double* __restrict__ ew,
+                                                       double* __restrict__ partials) {
+    __shared__ float2 lds[1 << kQ];
+    __shared__ uint32_t sg[64];
+    __shared__ float2 ph[kMaxPhase];
+    __shared__ double red[kThreads / 64];
+    const uint32_t tid = threadIdx.x;
+
+    // block -> (trajectory, tile); line-sharing tiles go to one XCD together
+    const uint32_t x = blockIdx.x;
+    uint32_t f = x;
+    if (P.share) {
+        const uint32_t xcd = x & 7u, r = x >> 3;
+        const uint32_t j = r & ((1u << P.share) - 1u), g = ((r >> P.share) << 3) | xcd;
+        f = (g << P.share) | j;
+    }
+    const uint32_t b = f >> tiles_log2;
+    const uint64_t base = pdep64(f & ((1u << tiles_log2) - 1u), P.fixed_mask);
+    float2* st = psi + ((size_t)b << n);
+
+    for (uint32_t w = tid; w < words; w += kThreads) sg[w] = signs[(size_t)b * words + w];
+    if (P.diag)
+        for (uint32_t i = tid; i <= 2 * P.ph_mid; i += kThreads) ph[i] = phase[P.ph_off + i];
+
+    float2 v[kRegs];
+    const uint64_t z0 = base | storage_thread<L0T>(P, tid);
+    if (P.init) {
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) v[j] = make_float2(P.amp0, 0.f);
+    } else {
+#pragma unroll
+        for (int jp = 0; jp < kRegs / 2; ++jp) {
+            uint64_t z = z0;
+#pragma unroll
+            for (int r = 1; r < 5; ++r) z |= (uint64_t)((jp >> (r - 1)) & 1) << P.tb[L0R[r]];
+            const float4 w = *reinterpret_cast<const float4*>(st + z);
+            v[2 * jp] = make_float2(w.x, w.y);
+            v[2 * jp + 1] = make_float2(w.z, w.w);
+        }
+    }
+    __syncthreads();  // sg, ph
+
+    if (P.diag) {
+        int C = 0, h[5] = {0, 0, 0, 0, 0};
+        for (uint32_t e = 0; e < P.d_n[0]; ++e) {
+            const int4 E = dedges[P.d_off[0] + e];
+            const int w = sign_bit(sg, E.w) ? -E.z : E.z;
+            C += (int)(((z0 >> E.x) ^ (z0 >> E.y)) & 1u) * w;
+        }
+#pragma unroll
+        for (int r = 0; r < 5; ++r)
+            for (uint32_t e = 0; e < P.d_n[1 + r]; ++e) {
+                const int4 E = dedges[P.d_off[1 + r] + e];
+                const int w = sign_bit(sg, E.w) ? -E.z : E.z;
+                const int bv = (int)((z0 >> E.x) & 1u);
+                C += w * bv;
+                h[r] += w * (1 - 2 * bv);
+            }
+        int m[kRegs];
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) {
+            int a = C;
+#pragma unroll
+            for (int r = 0; r < 5; ++r)
+                if (j & (1 << r)) a += h[r];
+            m[j] = a;
+        }
+        for (uint32_t e = 0; e < P.d_n[6]; ++e) {
+            const int4 E = dedges[P.d_off[6] + e];
+            const int w = sign_bit(sg, E.w) ? -E.z : E.z;
+#pragma unroll
+            for (int j = 0; j < kRegs; ++j) m[j] += (((j >> E.x) ^ (j >> E.y)) & 1) ? w : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) {
+            const float2 p = ph[P.ph_mid + m[j]];
+            const float2 a = v[j];
+            v[j] = make_float2(p.x * a.x - p.y * a.y, fmaf(p.x, a.y, p.y * a.x));
+        }
+    }
+
+    mix<0>(v, P, sg);
+    exchange<L0R, L0T, L1R, L1T>(v, lds, tid);
+    mix<1>(v, P, sg);
+    exchange<L1R, L1T, L2R, L2T>(v, lds, tid);
+    mix<2>(v, P, sg);
+
+    const uint64_t z2 = base | storage_thread<L2T>(P, tid);
+    if (!P.last) {
+#pragma unroll
+        for (int jp = 0; jp < kRegs / 2; ++jp) {
+            uint64_t z = z2;
+#pragma unroll
+            for (int r = 1; r < 5; ++r) z |= (uint64_t)((jp >> (r - 1)) & 1) << P.tb[L2R[r]];
+            *reinterpret_cast<float4*>(st + z) =
+                make_float4(v[2 * jp].x, v[2 * jp].y, v[2 * jp + 1].x, v[2 * jp + 1].y);
+        }
+        return;
+    }
+
+    // energy: sum_j |v_j|^2 C(z_j xor F_x), C(z) = sum_t w_t [z_u != z_v]
+    const uint64_t fx = frame[2 * (size_t)b];
+    const uint64_t zf = z2 ^ fx;
+    uint32_t fr = 0;  // frame bits on the register positions
+#pragma unroll
+    for (int r = 0; r < 5; ++r) fr |= (uint32_t)((fx >> P.tb[L2R[r]]) & 1u) << r;
+    double C = 0.0, h[5] = {0, 0, 0, 0, 0};
+    for (uint32_t e = 0; e < P.e_n[0]; ++e) {
+        const int2 E = eedges[P.e_off[0] + e];
+        if (((zf >> E.x) ^ (zf >> E.y)) & 1u) C += ew[P.e_off[0] + e];
+    }
+#pragma unroll
+    for (int r = 0; r < 5; ++r)
+        for (uint32_t e = 0; e < P.e_n[1 + r]; ++e) {
+            const int2 E = eedges[P.e_off[1 + r] + e];
+            const double w = ew[P.e_off[1 + r] + e];
+            const int c = (int)(((zf >> E.x) & 1u) ^ ((fr >> r) & 1u));
+            C += c ? w : 0.0;
+            h[r] += c ? -w : w;
+        }
+    double cz[kRegs];
+#pragma unroll
+    for (int j = 0; j < kRegs; ++j) {
+        double a = C;
+#pragma unroll
+        for (int r = 0; r < 5; ++r)
+            if (j & (1 << r)) a += h[r];
+        cz[j] = a;
+    }
+    for (uint32_t e = 0; e < P.e_n[6]; ++e) {
+        const int2 E = eedges[P.e_off[6] + e];
+        const double w = ew[P.e_off[6] + e];
+        const bool flip = ((fr >> E.x) ^ (fr >> E.y)) & 1u;
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) cz[j] += ((((j >> E.x) ^ (j >> E.y)) & 1) != (int)flip) ? w : 0.0;
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < kRegs; ++j) acc += (double)fmaf(v[j].x, v[j].x, v[j].y * v[j].y) * cz[j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        double s = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+        partials[f] = s * P.e_scale;
+    }
+}
+
+// energy[b] = sum over the trajectory's tiles of partials, in tile order
 __global__ __launch_bounds__(256) void k_tile_sum(const double* __restrict__ partials, uint32_t tiles,
                                                   double* __restrict__ energy) {
     __shared__ double red[256];
@@ -152,60 +322,176 @@ __global__ __launch_bounds__(256) void k_tile_sum(const double* __restrict__ par
     if (threadIdx.x == 0) energy[b] = red[0];
 }
 
+struct TiledTables {
+    std::vector<Pass2> passes;
+    std::vector<int4> dedges;
+    std::vector<cd> phase;
+    std::vector<int2> eedges;
+    std::vector<double> ew;
+};
+
+int reg_index(const int* R, const uint32_t* tb, uint32_t q) {
+    for (int r = 0; r < 5; ++r)
+        if (tb[R[r]] == q) return r;
+    return -1;
+}
+
+TiledTables build_tables(stn_plan* p) {
+    TiledTables T;
+    const uint32_t n = p->n;
+    const uint64_t N = 1ull << n;
+    double acc_scale = 1.0;
+    for (auto& ps : p->passes) {
+        Pass2 P{};
+        int t = 0;
+        for (uint32_t q = 0; q < n; ++q)
+            if ((ps.tile_mask >> q) & 1) P.tb[t++] = q;
+        if (t != kQ || P.tb[0] != 0) fail(STN_E_INVALID, "tile must hold 14 storage bits including bit 0");
+        P.fixed_mask = (N - 1) & ~(uint64_t)ps.tile_mask;
+        P.share = (uint32_t)__builtin_popcountll(P.fixed_mask & 0xFull);
+        P.init = ps.init;
+        P.last = ps.last;
+        P.diag = ps.layer >= 0;
+        P.amp0 = (float)std::pow(2.0, -0.5 * n);
+        // diagonal (layout L0 registers)
+        if (P.diag) {
+            const TiledLayer& L = p->layers[ps.layer];
+            std::vector<int4> cat[7];
+            for (size_t e = 0; e < L.zz_gates.size(); ++e) {
+                const GateRec& g = p->gates[L.zz_gates[e]];
+                const int ru = reg_index(hL0R, P.tb, g.q0), rv = reg_index(hL0R, P.tb, g.q1);
+                const int mult = L.zz_mult[e], gi = (int)L.zz_gates[e];
+                if (ru < 0 && rv < 0) cat[0].push_back({(int)g.q0, (int)g.q1, mult, gi});
+                else if (ru >= 0 && rv < 0) cat[1 + ru].push_back({(int)g.q1, 0, mult, gi});
+                else if (ru < 0 && rv >= 0) cat[1 + rv].push_back({(int)g.q0, 0, mult, gi});
+                else cat[6].push_back({ru, rv, mult, gi});
+            }
+            for (int c = 0; c < 7; ++c) {
+                P.d_off[c] = (uint32_t)T.dedges.size();
+                P.d_n[c] = (uint32_t)cat[c].size();
+                T.dedges.insert(T.dedges.end(), cat[c].begin(), cat[c].end());
+            }
+            if (2 * L.mult_sum + 1 > kMaxPhase) fail(STN_E_UNSUPPORTED, "diagonal block too large for the phase table");
+            P.ph_off = (uint32_t)T.phase.size();
+            P.ph_mid = (uint32_t)L.mult_sum;
+            for (int m = -L.mult_sum; m <= L.mult_sum; ++m)
+                T.phase.push_back(acc_scale * std::exp(cd(0, -L.base_angle * m)));
+            acc_scale = 1.0;
+        }
+        // rotations: each mixed qubit once, in the first layout holding it in a register
+        const int* LR[3] = {hL0R, hL1R, hL2R};
+        uint32_t done = 0;
+        for (int l = 0; l < 3; ++l)
+            for (int r = 0; r < 5; ++r) {
+                P.mix_gate[l][r] = -1;
+                const uint32_t q = P.tb[LR[l][r]];
+                if (!((ps.mix_mask >> q) & 1) || ((done >> q) & 1)) continue;
+                done |= 1u << q;
+                const int g = p->layers[ps.mix_layer].rx_gate[q];
+                const double c = std::cos(p->gates[g].theta / 2), s = std::sin(p->gates[g].theta / 2);
+                P.mix_gate[l][r] = g;
+                if (std::abs(c) >= std::abs(s)) {
+                    P.mix_form[l][r] = 0;
+                    P.mix_coef[l][r] = (float)(s / c);
+                    acc_scale *= std::abs(c);
+                } else {
+                    P.mix_form[l][r] = 1;
+                    P.mix_coef[l][r] = (float)(c / s);
+                    acc_scale *= std::abs(s);
+                }
+            }
+        if (done != ps.mix_mask) fail(STN_E_INVALID, "pass mixes a qubit outside its tile");
+        // observable (layout L2 registers)
+        if (P.last) {
+            std::vector<int2> cat[7];
+            std::vector<double> cw[7];
+            for (size_t t2 = 0; t2 < p->obs_u.size(); ++t2) {
+                const uint32_t u = p->obs_u[t2], v = p->obs_v[t2];
+                const int ru = reg_index(hL2R, P.tb, u), rv = reg_index(hL2R, P.tb, v);
+                int c = 0;
+                int2 e{(int)u, (int)v};
+                if (ru < 0 && rv < 0) {
+                    c = 0;
+                } else if (ru >= 0 && rv < 0) {
+                    c = 1 + ru;
+                    e = {(int)v, 0};
+                } else if (ru < 0 && rv >= 0) {
+                    c = 1 + rv;
+                    e = {(int)u, 0};
+                } else {
+                    c = 6;
+                    e = {ru, rv};
+                }
+                cat[c].push_back(e);
+                cw[c].push_back(p->obs_w[t2]);
+            }
+            for (int c = 0; c < 7; ++c) {
+                P.e_off[c] = (uint32_t)T.eedges.size();
+                P.e_n[c] = (uint32_t)cat[c].size();
+                T.eedges.insert(T.eedges.end(), cat[c].begin(), cat[c].end());
+                T.ew.insert(T.ew.end(), cw[c].begin(), cw[c].end());
+            }
+            P.e_scale = acc_scale * acc_scale;
+        }
+        T.passes.push_back(P);
+    }
+    return T;
+}
+
+struct TiledDevice {
+    TiledTables t;
+    DevBuf dedges, phase, eedges, ew;
+};
+
 }  // namespace
 
 void launch_sv_tiled(stn_plan* p, stn_batch* b, hipStream_t s) {
     const uint32_t n = p->n;
     const uint64_t N = 1ull << n;
-    const uint32_t tiles = 1u << (n - kTileBits);
+    const uint32_t tiles_log2 = n - kQ;
+    const uint32_t tiles = 1u << tiles_log2;
     const uint32_t B = std::min(p->max_batch, b->K);
     if (b->words > 64) fail(STN_E_UNSUPPORTED, "tiled lowering supports at most 2048 gates");
-    if (B > 65535) fail(STN_E_UNSUPPORTED, "batch slice too large");
+    if ((uint64_t)B * tiles > 0x7fffffffull) fail(STN_E_UNSUPPORTED, "batch slice too large");
+    if (!p->tiled) {
+        auto* d = new TiledDevice();
+        p->tiled = d;
+        p->tiled_free = [](void* v) { delete static_cast<TiledDevice*>(v); };
+        d->t = build_tables(p);
+        std::vector<float2> ph32;
+        for (auto& c : d->t.phase) ph32.push_back(make_float2((float)c.real(), (float)c.imag()));
+        if (d->t.dedges.empty()) d->t.dedges.push_back(int4{0, 0, 0, 0});
+        if (ph32.empty()) ph32.push_back(make_float2(0.f, 0.f));
+        if (d->t.eedges.empty()) d->t.eedges.push_back(int2{0, 0});
+        if (d->t.ew.empty()) d->t.ew.push_back(0.0);
+        upload(d->dedges, &p->alloc, d->t.dedges.data(), d->t.dedges.size() * sizeof(int4), s);
+        upload(d->phase, &p->alloc, ph32.data(), ph32.size() * sizeof(float2), s);
+        upload(d->eedges, &p->alloc, d->t.eedges.data(), d->t.eedges.size() * sizeof(int2), s);
+        upload(d->ew, &p->alloc, d->t.ew.data(), d->t.ew.size() * sizeof(double), s);
+        STN_HIP(hipStreamSynchronize(s));
+    }
+    auto* d = static_cast<TiledDevice*>(p->tiled);
     p->d_work.ensure(&p->alloc, (size_t)B * N * 8);
     p->d_partials.ensure(&p->alloc, (size_t)B * tiles * 8);
-    std::vector<PassArgs> args;
-    for (auto& ps : p->passes) {
-        PassArgs a{};
-        a.n = n;
-        int t = 0;
-        for (uint32_t q = 0; q < n; ++q)
-            if ((ps.tile_mask >> q) & 1) a.tile_bit[t++] = q;
-        if (t != kTileBits) fail(STN_E_INVALID, "tile does not have 13 bits");
-        a.fixed_mask = (uint32_t)((N - 1) & ~(uint64_t)ps.tile_mask);
-        a.layer = ps.layer;
-        if (ps.layer >= 0) {
-            a.edge_off = p->layer_edge_off[ps.layer];
-            a.n_edges = p->layer_edge_off[ps.layer + 1] - a.edge_off;
-            a.phase_off = p->phase_off[ps.layer];
-            a.mult_sum = (uint32_t)p->layers[ps.layer].mult_sum;
-        }
-        a.n_mix = 0;
-        for (int tt = 0; tt < kTileBits; ++tt) {
-            const uint32_t q = a.tile_bit[tt];
-            if ((ps.mix_mask >> q) & 1) {
-                a.mix_pos[a.n_mix] = (uint32_t)tt;
-                a.mix_gate[a.n_mix] = p->layers[ps.mix_layer].rx_gate[q];
-                ++a.n_mix;
-            }
-        }
-        a.init = ps.init;
-        a.last = ps.last;
-        a.amp0 = (float)std::pow(2.0, -0.5 * n);
-        args.push_back(a);
-    }
     for (uint32_t c0 = 0; c0 < b->K; c0 += B) {
         const uint32_t nb = std::min(B, b->K - c0);
-        for (auto& a : args) {
+        const uint32_t blocks = nb * tiles;
+        for (const Pass2& P0 : d->t.passes) {
+            Pass2 P = P0;
+            if (blocks % (8u << P.share)) P.share = 0;  // grouping needs whole XCD rounds
+            int nmix = 0;
+            for (int l = 0; l < 3; ++l)
+                for (int r = 0; r < 5; ++r) nmix += P.mix_gate[l][r] >= 0;
             const double elems = (double)nb * (double)N;
             prof_begin(p, STN_K_SV_PASS, s);
-            hipLaunchKernelGGL(k_sv_pass, dim3(tiles, nb), dim3(kThreads), 0, s, p->d_work.as<float2>(), a,
-                               b->d_signs.as<uint32_t>() + (size_t)c0 * b->words, b->words,
-                               b->d_frame.as<uint64_t>() + 2 * (size_t)c0, p->d_layer_edges.as<int4>(),
-                               p->d_phase32.as<float2>(), p->d_rx32.as<float2>(), p->d_obs.as<uint32_t>(),
-                               p->d_obs_w.as<double>(), (uint32_t)p->obs_u.size(), p->d_partials.as<double>());
+            hipLaunchKernelGGL(k_sv_pass2, dim3(blocks), dim3(kThreads), 0, s, p->d_work.as<float2>(), P, n,
+                               tiles_log2, b->d_signs.as<uint32_t>() + (size_t)c0 * b->words, b->words,
+                               b->d_frame.as<uint64_t>() + 2 * (size_t)c0, d->dedges.as<int4>(),
+                               d->phase.as<float2>(), d->eedges.as<int2>(), d->ew.as<double>(),
+                               p->d_partials.as<double>());
             STN_HIP(hipGetLastError());
-            prof_end(p, STN_K_SV_PASS, s, elems * 8.0 * ((a.init ? 0 : 1) + (a.last ? 0 : 1)),
-                     elems * (6.0 * a.n_mix + (a.layer >= 0 ? 6.0 : 0.0) + (a.last ? 4.0 : 0.0)));
+            prof_end(p, STN_K_SV_PASS, s, elems * 8.0 * ((P.init ? 0 : 1) + (P.last ? 0 : 1)),
+                     elems * (6.0 * nmix + (P.diag ? 6.0 : 0.0) + (P.last ? 4.0 : 0.0)));
         }
         prof_begin(p, STN_K_TILE_SUM, s);
         hipLaunchKernelGGL(k_tile_sum, dim3(nb), dim3(256), 0, s, p->d_partials.as<double>(), tiles,

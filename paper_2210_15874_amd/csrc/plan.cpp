@@ -495,7 +495,7 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
         if (n < 14) fail(STN_E_UNSUPPORTED, "the tiled lowering needs n >= 14");
         if (p->layers.empty() && !build_tiled(p, why)) fail(STN_E_UNSUPPORTED, "tiled lowering: " + why);
         if (p->opts.precision == 128) fail(STN_E_UNSUPPORTED, "the tiled lowering is complex64 only");
-        schedule_tiled(p, 13, 3);
+        schedule_tiled(p, 14, 2);
     } else if (kind == STN_PLAN_LIGHTCONE) {
         fail(STN_E_UNSUPPORTED, "lightcone lowering not available");
     } else {

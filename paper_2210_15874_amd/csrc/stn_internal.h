@@ -167,6 +167,8 @@ struct stn_plan {
     stn::DevBuf d_rx32, d_rx64;             // per gate (rx): (cos(theta/2), sin(theta/2))
     stn::DevBuf d_layer_edges;              // per layer: (u, v, mult, gate) int32 quads
     std::vector<uint32_t> layer_edge_off;
+    void* tiled = nullptr;                  // pass tables of the tiled kernels (kernels_sv_tiled.hip)
+    void (*tiled_free)(void*) = nullptr;
     stn::DevBuf d_work;                     // psi workspace [max_batch x 2^n]
     stn::DevBuf d_partials;                 // per (trajectory, tile) energy partials
 

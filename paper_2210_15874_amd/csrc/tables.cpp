@@ -77,35 +77,6 @@ void upload_plan_tables(stn_plan* p, hipStream_t s) {
         up(p->d_site_ops, a, sops, s);
         up(p->d_site_op_off, a, p->site_op_off, s);
         up_complex(p->d_lds_vals32, p->d_lds_vals64, a, p->lds_vals, s);
-    } else if (p->kind == STN_PLAN_SV_TILED) {
-        // phase tables e^{-i base m}, m = -M..M, and per-layer edge lists
-        std::vector<cd> ph;
-        std::vector<int32_t> edges;
-        p->phase_off.clear();
-        p->layer_edge_off.clear();
-        for (auto& L : p->layers) {
-            p->phase_off.push_back((uint32_t)ph.size());
-            for (int m = -L.mult_sum; m <= L.mult_sum; ++m) ph.push_back(std::exp(cd(0, -L.base_angle * m)));
-            p->layer_edge_off.push_back((uint32_t)edges.size() / 4);
-            for (size_t e = 0; e < L.zz_gates.size(); ++e) {
-                const GateRec& g = p->gates[L.zz_gates[e]];
-                edges.push_back((int32_t)g.q0);
-                edges.push_back((int32_t)g.q1);
-                edges.push_back(L.zz_mult[e]);
-                edges.push_back((int32_t)L.zz_gates[e]);
-            }
-        }
-        p->phase_off.push_back((uint32_t)ph.size());
-        p->layer_edge_off.push_back((uint32_t)edges.size() / 4);
-        edges.insert(edges.end(), {0, 0, 0, 0});
-        up_complex(p->d_phase32, p->d_phase64, a, ph, s);
-        up(p->d_layer_edges, a, edges, s);
-        // rx gates: (cos(theta/2), sin(theta/2))
-        std::vector<cd> cs(p->gates.size() + 1);
-        for (size_t g = 0; g < p->gates.size(); ++g)
-            if (p->gates[g].kind == STN_G_RX)
-                cs[g] = cd(std::cos(p->gates[g].theta / 2), std::sin(p->gates[g].theta / 2));
-        up_complex(p->d_rx32, p->d_rx64, a, cs, s);
     }
 }
 
