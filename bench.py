@@ -68,6 +68,9 @@ def main():
     ap.add_argument("--hbm-budget-gib", type=float, default=160.0)
     ap.add_argument("--cpu-sample-gates", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="copy a buffer of this size once before the timed region (a known-size reference "
+                         "for hardware byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -105,6 +108,13 @@ def main():
         acc.close()
         return r
 
+    if args.copy_probe_gib > 0:
+        nbytes = int(args.copy_probe_gib * (1 << 30))
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         job()
     torch.cuda.synchronize()

@@ -10,7 +10,8 @@
 //   dropped).  A Pauli rotation exp(-i theta P/2) that F anticommutes with is
 //   equal, after moving F past it, to the rotation by -theta (up to a global
 //   phase), so its sign bit is set; F itself moves unchanged to the end of the
-//   circuit (the final frame).
+//   circuit (the final frame).  A gate the planner rewrote as a rotation
+//   followed by a fixed X (see GateRec::det_x) adds that X to F after the gate.
 #include "stn_internal.h"
 
 namespace stn {
@@ -52,7 +53,8 @@ __global__ __launch_bounds__(64) void k_frame(const uint8_t* __restrict__ idx, u
                                               const uint32_t* __restrict__ site_gate,
                                               const uint32_t* __restrict__ off, const uint64_t* __restrict__ px,
                                               const uint64_t* __restrict__ pz, const uint64_t* __restrict__ gx,
-                                              const uint64_t* __restrict__ gz, uint32_t G, uint32_t words,
+                                              const uint64_t* __restrict__ gz,
+                                              const uint64_t* __restrict__ dx, uint32_t G, uint32_t words,
                                               uint32_t* __restrict__ signs, uint64_t* __restrict__ frame) {
     const uint32_t k = blockIdx.x * 64 + threadIdx.x;
     if (k >= K) return;
@@ -67,6 +69,7 @@ __global__ __launch_bounds__(64) void k_frame(const uint8_t* __restrict__ idx, u
             signs[(size_t)k * words + (g >> 5)] = w;
             w = 0;
         }
+        x ^= dx[g];  // deterministic X of a rewritten gate, before the gate's noise
         for (; s < S && site_gate[s] == g; ++s) {
             const uint32_t o = off[s] + row[s];
             x ^= px[o];
@@ -99,7 +102,8 @@ void launch_frame(stn_plan* p, stn_batch* b, hipStream_t s) {
     prof_begin(p, STN_K_FRAME, s);
     hipLaunchKernelGGL(k_frame, dim3((b->K + 63) / 64), dim3(64), 0, s, b->d_idx.as<uint8_t>(), S, b->K,
                        p->d_site_gate.as<uint32_t>(), p->d_site_off.as<uint32_t>(), p->d_site_px.as<uint64_t>(),
-                       p->d_site_pz.as<uint64_t>(), p->d_gate_gx.as<uint64_t>(), p->d_gate_gz.as<uint64_t>(), G,
+                       p->d_site_pz.as<uint64_t>(), p->d_gate_gx.as<uint64_t>(), p->d_gate_gz.as<uint64_t>(),
+                       p->d_gate_dx.as<uint64_t>(), G,
                        b->words, b->d_signs.as<uint32_t>(), b->d_frame.as<uint64_t>());
     STN_HIP(hipGetLastError());
     prof_end(p, STN_K_FRAME, s, (double)b->K * (S + 4.0 * b->words + 16.0), 0.0);

@@ -18,12 +18,14 @@
 // is looked up in a per-layer table (binary64 on the host, rounded once);
 // m(z) is split into a per-thread part and the contributions of the 5
 // register bits, so each amplitude costs a few integer adds.  An rx(theta)
-// with c = cos(theta/2), s = sin(theta/2) is applied as c [[1, -i t], [-i t, 1]]
-// (t = s/c) or s [[k, -i], [-i, k]] (k = c/s), two FMAs per amplitude; the
-// dropped factor |c| or |s| is restored in the next pass's phase table or in
-// the energy.  The first pass generates |+>^n; the last pass accumulates
-// sum_z |psi_z|^2 C(z xor F_x) in binary64 (F flips measured bits) instead of
-// storing.
+// is applied as cos(theta/2) [[1, -i t], [-i t, 1]] with t = tan(theta/2),
+// two FMAs per amplitude; the planner keeps |t| <= 1 by writing
+// rx(theta) = -i X rx(theta - pi) and moving the X into the Pauli frame, and
+// the dropped factor |cos(theta/2)| is restored in the next pass's phase
+// table or in the energy.  The first pass generates |+>^n; the last pass
+// accumulates sum_z |psi_z|^2 C(z xor F_x) (F flips measured bits) instead of
+// storing: FP32 within a thread, binary64 across threads, tiles and
+// trajectories.
 //
 // Passes whose tile holds only two low storage bits read 32-byte runs; the
 // four workgroups that share each 128-byte line are given block indices
@@ -42,6 +44,7 @@ constexpr int kQ = 14;          // tile bits
 constexpr int kThreads = 512;   // 9 thread bits
 constexpr int kRegs = 32;       // 5 register bits
 constexpr int kMaxPhase = 511;  // phase table entries (2M+1)
+constexpr int kMaxEdges = 512;  // zz gates of one diagonal block
 
 // layouts: tile-index bit of each register bit / thread bit
 __device__ constexpr int L0R[5] = {0, 10, 11, 12, 13};
@@ -61,8 +64,7 @@ struct Pass2 {
     uint32_t init, last, diag;
     float amp0;
     int32_t mix_gate[3][5];     // per layout and register bit: rx gate, -1 = not rotated here
-    float mix_coef[3][5];       // t = s/c (form 0) or k = c/s (form 1), before the sign
-    uint32_t mix_form[3][5];
+    float mix_coef[3][5];       // t = tan(theta_eff/2), |t| <= 1, before the trajectory's sign
     uint32_t d_off[7], d_n[7];  // diagonal edges: [0] both endpoints fixed, [1..5] one in register r-1, [6] both in registers
     uint32_t ph_off, ph_mid;    // phase table entries [ph_off, ph_off + 2*ph_mid]
     uint32_t e_off[7], e_n[7];  // observable terms in the same categories w.r.t. L2
@@ -106,7 +108,8 @@ __device__ __forceinline__ uint64_t pdep64(uint64_t v, uint64_t mask) {
 
 __device__ __forceinline__ bool sign_bit(const uint32_t* sg, int g) { return (sg[g >> 5] >> (g & 31)) & 1u; }
 
-// rotate register bit r of layout L: pairs (j, j | 1<<r)
+// rotate register bit r of layout L: pairs (j, j | 1<<r) get
+// x0' = x0 - i t x1, x1' = x1 - i t x0 (rx(theta) / cos(theta/2), t = +-tan(theta/2))
 template <int L>
 __device__ __forceinline__ void mix(float2 (&v)[kRegs], const Pass2& P, const uint32_t* sg) {
 #pragma unroll
@@ -115,24 +118,12 @@ __device__ __forceinline__ void mix(float2 (&v)[kRegs], const Pass2& P, const ui
         if (g < 0) continue;
         const float c0 = P.mix_coef[L][r];
         const float t = sign_bit(sg, g) ? -c0 : c0;
-        if (P.mix_form[L][r] == 0) {
-            // x0' = x0 - i t x1, x1' = x1 - i t x0
 #pragma unroll
-            for (int j = 0; j < kRegs; ++j) {
-                if (j & (1 << r)) continue;
-                const float2 a = v[j], b = v[j | (1 << r)];
-                v[j] = make_float2(fmaf(t, b.y, a.x), fmaf(-t, b.x, a.y));
-                v[j | (1 << r)] = make_float2(fmaf(t, a.y, b.x), fmaf(-t, a.x, b.y));
-            }
-        } else {
-            // x0' = t x0 - i x1, x1' = t x1 - i x0
-#pragma unroll
-            for (int j = 0; j < kRegs; ++j) {
-                if (j & (1 << r)) continue;
-                const float2 a = v[j], b = v[j | (1 << r)];
-                v[j] = make_float2(fmaf(t, a.x, b.y), fmaf(t, a.y, -b.x));
-                v[j | (1 << r)] = make_float2(fmaf(t, b.x, a.y), fmaf(t, b.y, -a.x));
-            }
+        for (int j = 0; j < kRegs; ++j) {
+            if (j & (1 << r)) continue;
+            const float2 a = v[j], b = v[j | (1 << r)];
+            v[j] = make_float2(fmaf(t, b.y, a.x), fmaf(-t, b.x, a.y));
+            v[j | (1 << r)] = make_float2(fmaf(t, a.y, b.x), fmaf(-t, a.x, b.y));
         }
     }
 }
@@ -150,9 +141,38 @@ __device__ __forceinline__ void exchange(float2 (&v)[kRegs], float2* lds, uint32
     __syncthreads();
 }
 
+__device__ __forceinline__ uint32_t tile_of(uint32_t x, uint32_t share) {
+    // line-sharing tiles (differing only in the fixed storage bits below the
+    // 128-byte line) get indices x, x+8, x+16, x+24: the same XCD, same time
+    if (!share) return x;
+    const uint32_t xcd = x & 7u, r = x >> 3;
+    const uint32_t j = r & ((1u << share) - 1u), g = ((r >> share) << 3) | xcd;
+    return (g << share) | j;
+}
+
+__device__ __forceinline__ void load_tile(float2 (&v)[kRegs], const float2* st, uint64_t z0, const Pass2& P) {
+#pragma unroll
+    for (int jp = 0; jp < kRegs / 2; ++jp) {
+        uint64_t z = z0;
+#pragma unroll
+        for (int r = 1; r < 5; ++r) z |= (uint64_t)((jp >> (r - 1)) & 1) << P.tb[L0R[r]];
+        const float4 w = *reinterpret_cast<const float4*>(st + z);
+        v[2 * jp] = make_float2(w.x, w.y);
+        v[2 * jp + 1] = make_float2(w.z, w.w);
+    }
+}
+
+// Persistent pass kernel: workgroup w processes tiles w, w + G, w + 2G, ...
+// (G = grid size, a multiple of 32, so a workgroup stays on its XCD's share of
+// line-sharing tiles) and prefetches the next tile's amplitudes into
+// registers before working on the current one.
+// FL: bit 0 = first pass (generate |+>^n), bit 1 = diagonal at load,
+// bit 2 = last pass (energy instead of store)
+template <int FL>
 __global__ __launch_bounds__(kThreads) void k_sv_pass2(float2* __restrict__ psi, const Pass2 P, uint32_t n,
-                                                       uint32_t tiles_log2, const uint32_t* __restrict__ signs,
-                                                       uint32_t words, const uint64_t* __restrict__ frame,
+                                                       uint32_t tiles_log2, uint32_t total,
+                                                       const uint32_t* __restrict__ signs, uint32_t words,
+                                                       const uint64_t* __restrict__ frame,
                                                        const int4* __restrict__ dedges,
                                                        const float2* __restrict__ phase,
                                                        const int2* __restrict__ eedges,
@@ -162,147 +182,179 @@ __global__ __launch_bounds__(kThreads) void k_sv_pass2(float2* __restrict__ psi,
     __shared__ uint32_t sg[64];
     __shared__ float2 ph[kMaxPhase];
     __shared__ double red[kThreads / 64];
+    __shared__ int wt[kMaxEdges];  // this trajectory's signed multiplicities of the pass's zz gates
+    constexpr bool kInit = FL & 1, kDiag = FL & 2, kLast = FL & 4;
     const uint32_t tid = threadIdx.x;
+    const uint32_t e0 = P.d_off[0], ne = P.d_off[6] + P.d_n[6] - P.d_off[0];
+    const uint64_t zt0 = storage_thread<L0T>(P, tid), zt2 = storage_thread<L2T>(P, tid);
+    const uint32_t tmask = (1u << tiles_log2) - 1u;
 
-    // block -> (trajectory, tile); line-sharing tiles go to one XCD together
-    const uint32_t x = blockIdx.x;
-    uint32_t f = x;
-    if (P.share) {
-        const uint32_t xcd = x & 7u, r = x >> 3;
-        const uint32_t j = r & ((1u << P.share) - 1u), g = ((r >> P.share) << 3) | xcd;
-        f = (g << P.share) | j;
-    }
-    const uint32_t b = f >> tiles_log2;
-    const uint64_t base = pdep64(f & ((1u << tiles_log2) - 1u), P.fixed_mask);
-    float2* st = psi + ((size_t)b << n);
-
-    for (uint32_t w = tid; w < words; w += kThreads) sg[w] = signs[(size_t)b * words + w];
-    if (P.diag)
+    if (kDiag)
         for (uint32_t i = tid; i <= 2 * P.ph_mid; i += kThreads) ph[i] = phase[P.ph_off + i];
 
+    uint32_t x = blockIdx.x;
+    if (x >= total) return;
+    uint32_t f = tile_of(x, P.share);
+    uint32_t b = f >> tiles_log2;
+    uint64_t base = pdep64(f & tmask, P.fixed_mask);
     float2 v[kRegs];
-    const uint64_t z0 = base | storage_thread<L0T>(P, tid);
-    if (P.init) {
+    if (kInit) {
 #pragma unroll
         for (int j = 0; j < kRegs; ++j) v[j] = make_float2(P.amp0, 0.f);
     } else {
-#pragma unroll
-        for (int jp = 0; jp < kRegs / 2; ++jp) {
-            uint64_t z = z0;
-#pragma unroll
-            for (int r = 1; r < 5; ++r) z |= (uint64_t)((jp >> (r - 1)) & 1) << P.tb[L0R[r]];
-            const float4 w = *reinterpret_cast<const float4*>(st + z);
-            v[2 * jp] = make_float2(w.x, w.y);
-            v[2 * jp + 1] = make_float2(w.z, w.w);
-        }
+        load_tile(v, psi + ((size_t)b << n), base | zt0, P);
     }
-    __syncthreads();  // sg, ph
-
-    if (P.diag) {
-        int C = 0, h[5] = {0, 0, 0, 0, 0};
-        for (uint32_t e = 0; e < P.d_n[0]; ++e) {
-            const int4 E = dedges[P.d_off[0] + e];
-            const int w = sign_bit(sg, E.w) ? -E.z : E.z;
-            C += (int)(((z0 >> E.x) ^ (z0 >> E.y)) & 1u) * w;
+    uint32_t sb = 0xffffffffu;  // trajectory whose signs are in LDS
+    while (true) {
+        // prefetch the next tile
+        const uint32_t xn = x + gridDim.x;
+        const bool more = xn < total;
+        uint32_t fn = 0, bn = 0;
+        uint64_t basen = 0;
+        float2 nx[kRegs];
+        if (more) {
+            fn = tile_of(xn, P.share);
+            bn = fn >> tiles_log2;
+            basen = pdep64(fn & tmask, P.fixed_mask);
+            if (!kInit) load_tile(nx, psi + ((size_t)bn << n), basen | zt0, P);
         }
-#pragma unroll
-        for (int r = 0; r < 5; ++r)
-            for (uint32_t e = 0; e < P.d_n[1 + r]; ++e) {
-                const int4 E = dedges[P.d_off[1 + r] + e];
-                const int w = sign_bit(sg, E.w) ? -E.z : E.z;
-                const int bv = (int)((z0 >> E.x) & 1u);
-                C += w * bv;
-                h[r] += w * (1 - 2 * bv);
+        if (b != sb) {  // uniform: a new trajectory's signs and zz weights
+            __syncthreads();
+            for (uint32_t w = tid; w < words; w += kThreads) sg[w] = signs[(size_t)b * words + w];
+            __syncthreads();
+            if (kDiag)
+                for (uint32_t e = tid; e < ne; e += kThreads) {
+                    const int4 E = dedges[e0 + e];
+                    wt[e] = sign_bit(sg, E.w) ? -E.z : E.z;
+                }
+            __syncthreads();
+            sb = b;
+        }
+        float2* st = psi + ((size_t)b << n);
+
+        if (kDiag) {
+            const uint64_t z0 = base | zt0;
+            int C = 0, h[5] = {0, 0, 0, 0, 0};
+            const uint32_t zl = (uint32_t)z0, zh = (uint32_t)(z0 >> 32);
+            for (uint32_t e = 0; e < P.d_n[0]; ++e) {
+                const int4 E = dedges[P.d_off[0] + e];
+                const uint32_t bu = E.x < 32 ? zl >> E.x : zh >> (E.x - 32);
+                const uint32_t bv = E.y < 32 ? zl >> E.y : zh >> (E.y - 32);
+                C += ((bu ^ bv) & 1u) ? wt[P.d_off[0] + e - e0] : 0;
             }
-        int m[kRegs];
-#pragma unroll
-        for (int j = 0; j < kRegs; ++j) {
-            int a = C;
 #pragma unroll
             for (int r = 0; r < 5; ++r)
-                if (j & (1 << r)) a += h[r];
-            m[j] = a;
-        }
-        for (uint32_t e = 0; e < P.d_n[6]; ++e) {
-            const int4 E = dedges[P.d_off[6] + e];
-            const int w = sign_bit(sg, E.w) ? -E.z : E.z;
+                for (uint32_t e = 0; e < P.d_n[1 + r]; ++e) {
+                    const int4 E = dedges[P.d_off[1 + r] + e];
+                    const int w = wt[P.d_off[1 + r] + e - e0];
+                    const uint32_t bv = (E.x < 32 ? zl >> E.x : zh >> (E.x - 32)) & 1u;
+                    C += bv ? w : 0;
+                    h[r] += bv ? -w : w;
+                }
+            int m[kRegs];
 #pragma unroll
-            for (int j = 0; j < kRegs; ++j) m[j] += (((j >> E.x) ^ (j >> E.y)) & 1) ? w : 0;
-        }
+            for (int j = 0; j < kRegs; ++j) {
+                int a = C;
 #pragma unroll
-        for (int j = 0; j < kRegs; ++j) {
-            const float2 p = ph[P.ph_mid + m[j]];
-            const float2 a = v[j];
-            v[j] = make_float2(p.x * a.x - p.y * a.y, fmaf(p.x, a.y, p.y * a.x));
+                for (int r = 0; r < 5; ++r)
+                    if (j & (1 << r)) a += h[r];
+                m[j] = a;
+            }
+            for (uint32_t e = 0; e < P.d_n[6]; ++e) {
+                const int4 E = dedges[P.d_off[6] + e];
+                const int w = wt[P.d_off[6] + e - e0];
+#pragma unroll
+                for (int j = 0; j < kRegs; ++j) m[j] += (((j >> E.x) ^ (j >> E.y)) & 1) ? w : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < kRegs; ++j) {
+                const float2 p = ph[P.ph_mid + m[j]];
+                const float2 a = v[j];
+                v[j] = make_float2(p.x * a.x - p.y * a.y, fmaf(p.x, a.y, p.y * a.x));
+            }
         }
-    }
 
-    mix<0>(v, P, sg);
-    exchange<L0R, L0T, L1R, L1T>(v, lds, tid);
-    mix<1>(v, P, sg);
-    exchange<L1R, L1T, L2R, L2T>(v, lds, tid);
-    mix<2>(v, P, sg);
+        mix<0>(v, P, sg);
+        exchange<L0R, L0T, L1R, L1T>(v, lds, tid);
+        mix<1>(v, P, sg);
+        exchange<L1R, L1T, L2R, L2T>(v, lds, tid);
+        mix<2>(v, P, sg);
 
-    const uint64_t z2 = base | storage_thread<L2T>(P, tid);
-    if (!P.last) {
+        const uint64_t z2 = base | zt2;
+        if (!kLast) {
 #pragma unroll
-        for (int jp = 0; jp < kRegs / 2; ++jp) {
-            uint64_t z = z2;
+            for (int jp = 0; jp < kRegs / 2; ++jp) {
+                uint64_t z = z2;
 #pragma unroll
-            for (int r = 1; r < 5; ++r) z |= (uint64_t)((jp >> (r - 1)) & 1) << P.tb[L2R[r]];
-            *reinterpret_cast<float4*>(st + z) =
-                make_float4(v[2 * jp].x, v[2 * jp].y, v[2 * jp + 1].x, v[2 * jp + 1].y);
+                for (int r = 1; r < 5; ++r) z |= (uint64_t)((jp >> (r - 1)) & 1) << P.tb[L2R[r]];
+                *reinterpret_cast<float4*>(st + z) =
+                    make_float4(v[2 * jp].x, v[2 * jp].y, v[2 * jp + 1].x, v[2 * jp + 1].y);
+            }
+        } else {
+            // energy: sum_j |v_j|^2 C(z_j xor F_x), C(z) = sum_t w_t [z_u != z_v];
+            // per amplitude in FP32 (cut values are small sums of weights), summed
+            // over the thread's 32 amplitudes in FP32, then in binary64
+            const uint64_t fx = frame[2 * (size_t)b];
+            const uint64_t zf = z2 ^ fx;
+            uint32_t fr = 0;  // frame bits on the register positions
+#pragma unroll
+            for (int r = 0; r < 5; ++r) fr |= (uint32_t)((fx >> P.tb[L2R[r]]) & 1u) << r;
+            float C = 0.f, h[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+            for (uint32_t e = 0; e < P.e_n[0]; ++e) {
+                const int2 E = eedges[P.e_off[0] + e];
+                if (((zf >> E.x) ^ (zf >> E.y)) & 1u) C += (float)ew[P.e_off[0] + e];
+            }
+#pragma unroll
+            for (int r = 0; r < 5; ++r)
+                for (uint32_t e = 0; e < P.e_n[1 + r]; ++e) {
+                    const int2 E = eedges[P.e_off[1 + r] + e];
+                    const float w = (float)ew[P.e_off[1 + r] + e];
+                    const int c = (int)(((zf >> E.x) & 1u) ^ ((fr >> r) & 1u));
+                    C += c ? w : 0.f;
+                    h[r] += c ? -w : w;
+                }
+            float cz[kRegs];
+#pragma unroll
+            for (int j = 0; j < kRegs; ++j) {
+                float a = C;
+#pragma unroll
+                for (int r = 0; r < 5; ++r)
+                    if (j & (1 << r)) a += h[r];
+                cz[j] = a;
+            }
+            for (uint32_t e = 0; e < P.e_n[6]; ++e) {
+                const int2 E = eedges[P.e_off[6] + e];
+                const float w = (float)ew[P.e_off[6] + e];
+                const bool flip = ((fr >> E.x) ^ (fr >> E.y)) & 1u;
+#pragma unroll
+                for (int j = 0; j < kRegs; ++j) cz[j] += ((((j >> E.x) ^ (j >> E.y)) & 1) != (int)flip) ? w : 0.f;
+            }
+            float accf = 0.f;
+#pragma unroll
+            for (int j = 0; j < kRegs; ++j) accf = fmaf(fmaf(v[j].x, v[j].x, v[j].y * v[j].y), cz[j], accf);
+            double acc = (double)accf;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+            if ((tid & 63) == 0) red[tid >> 6] = acc;
+            __syncthreads();
+            if (tid == 0) {
+                double s = 0.0;
+                for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+                partials[f] = s * P.e_scale;
+            }
         }
-        return;
-    }
-
-    // energy: sum_j |v_j|^2 C(z_j xor F_x), C(z) = sum_t w_t [z_u != z_v]
-    const uint64_t fx = frame[2 * (size_t)b];
-    const uint64_t zf = z2 ^ fx;
-    uint32_t fr = 0;  // frame bits on the register positions
+        if (!more) break;
+        x = xn;
+        f = fn;
+        b = bn;
+        base = basen;
+        if (kInit) {
 #pragma unroll
-    for (int r = 0; r < 5; ++r) fr |= (uint32_t)((fx >> P.tb[L2R[r]]) & 1u) << r;
-    double C = 0.0, h[5] = {0, 0, 0, 0, 0};
-    for (uint32_t e = 0; e < P.e_n[0]; ++e) {
-        const int2 E = eedges[P.e_off[0] + e];
-        if (((zf >> E.x) ^ (zf >> E.y)) & 1u) C += ew[P.e_off[0] + e];
-    }
+            for (int j = 0; j < kRegs; ++j) v[j] = make_float2(P.amp0, 0.f);
+        } else {
 #pragma unroll
-    for (int r = 0; r < 5; ++r)
-        for (uint32_t e = 0; e < P.e_n[1 + r]; ++e) {
-            const int2 E = eedges[P.e_off[1 + r] + e];
-            const double w = ew[P.e_off[1 + r] + e];
-            const int c = (int)(((zf >> E.x) & 1u) ^ ((fr >> r) & 1u));
-            C += c ? w : 0.0;
-            h[r] += c ? -w : w;
+            for (int j = 0; j < kRegs; ++j) v[j] = nx[j];
         }
-    double cz[kRegs];
-#pragma unroll
-    for (int j = 0; j < kRegs; ++j) {
-        double a = C;
-#pragma unroll
-        for (int r = 0; r < 5; ++r)
-            if (j & (1 << r)) a += h[r];
-        cz[j] = a;
-    }
-    for (uint32_t e = 0; e < P.e_n[6]; ++e) {
-        const int2 E = eedges[P.e_off[6] + e];
-        const double w = ew[P.e_off[6] + e];
-        const bool flip = ((fr >> E.x) ^ (fr >> E.y)) & 1u;
-#pragma unroll
-        for (int j = 0; j < kRegs; ++j) cz[j] += ((((j >> E.x) ^ (j >> E.y)) & 1) != (int)flip) ? w : 0.0;
-    }
-    double acc = 0.0;
-#pragma unroll
-    for (int j = 0; j < kRegs; ++j) acc += (double)fmaf(v[j].x, v[j].x, v[j].y * v[j].y) * cz[j];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    if ((tid & 63) == 0) red[tid >> 6] = acc;
-    __syncthreads();
-    if (tid == 0) {
-        double s = 0.0;
-        for (int w = 0; w < kThreads / 64; ++w) s += red[w];
-        partials[f] = s * P.e_scale;
     }
 }
 
@@ -371,7 +423,8 @@ TiledTables build_tables(stn_plan* p) {
                 P.d_n[c] = (uint32_t)cat[c].size();
                 T.dedges.insert(T.dedges.end(), cat[c].begin(), cat[c].end());
             }
-            if (2 * L.mult_sum + 1 > kMaxPhase) fail(STN_E_UNSUPPORTED, "diagonal block too large for the phase table");
+            if (2 * L.mult_sum + 1 > kMaxPhase || L.zz_gates.size() > (size_t)kMaxEdges)
+                fail(STN_E_UNSUPPORTED, "diagonal block too large for the phase table");
             P.ph_off = (uint32_t)T.phase.size();
             P.ph_mid = (uint32_t)L.mult_sum;
             for (int m = -L.mult_sum; m <= L.mult_sum; ++m)
@@ -388,17 +441,12 @@ TiledTables build_tables(stn_plan* p) {
                 if (!((ps.mix_mask >> q) & 1) || ((done >> q) & 1)) continue;
                 done |= 1u << q;
                 const int g = p->layers[ps.mix_layer].rx_gate[q];
-                const double c = std::cos(p->gates[g].theta / 2), s = std::sin(p->gates[g].theta / 2);
+                const double th = p->gates[g].theta_eff;
+                const double c = std::cos(th / 2), s = std::sin(th / 2);
+                if (std::abs(s) > std::abs(c) * (1 + 1e-12)) fail(STN_E_INVALID, "rx gate not in reduced form");
                 P.mix_gate[l][r] = g;
-                if (std::abs(c) >= std::abs(s)) {
-                    P.mix_form[l][r] = 0;
-                    P.mix_coef[l][r] = (float)(s / c);
-                    acc_scale *= std::abs(c);
-                } else {
-                    P.mix_form[l][r] = 1;
-                    P.mix_coef[l][r] = (float)(c / s);
-                    acc_scale *= std::abs(s);
-                }
+                P.mix_coef[l][r] = (float)(s / c);
+                acc_scale *= std::abs(c);
             }
         if (done != ps.mix_mask) fail(STN_E_INVALID, "pass mixes a qubit outside its tile");
         // observable (layout L2 registers)
@@ -473,6 +521,11 @@ void launch_sv_tiled(stn_plan* p, stn_batch* b, hipStream_t s) {
     auto* d = static_cast<TiledDevice*>(p->tiled);
     p->d_work.ensure(&p->alloc, (size_t)B * N * 8);
     p->d_partials.ensure(&p->alloc, (size_t)B * tiles * 8);
+    int dev = 0, cus = 0;
+    STN_HIP(hipGetDevice(&dev));
+    STN_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    // one resident workgroup per CU, a multiple of 32 (XCD rounds of line groups)
+    const uint32_t grid_max = std::max(32u, (uint32_t)cus / 32u * 32u);
     for (uint32_t c0 = 0; c0 < b->K; c0 += B) {
         const uint32_t nb = std::min(B, b->K - c0);
         const uint32_t blocks = nb * tiles;
@@ -484,8 +537,14 @@ void launch_sv_tiled(stn_plan* p, stn_batch* b, hipStream_t s) {
                 for (int r = 0; r < 5; ++r) nmix += P.mix_gate[l][r] >= 0;
             const double elems = (double)nb * (double)N;
             prof_begin(p, STN_K_SV_PASS, s);
-            hipLaunchKernelGGL(k_sv_pass2, dim3(blocks), dim3(kThreads), 0, s, p->d_work.as<float2>(), P, n,
-                               tiles_log2, b->d_signs.as<uint32_t>() + (size_t)c0 * b->words, b->words,
+            const int fl = (P.init ? 1 : 0) | (P.diag ? 2 : 0) | (P.last ? 4 : 0);
+            auto kern = fl == 0 ? k_sv_pass2<0> : fl == 1 ? k_sv_pass2<1> : fl == 2 ? k_sv_pass2<2>
+                      : fl == 3 ? k_sv_pass2<3> : fl == 4 ? k_sv_pass2<4> : fl == 5 ? k_sv_pass2<5>
+                      : fl == 6 ? k_sv_pass2<6> : k_sv_pass2<7>;
+            const uint32_t grid = std::min(grid_max, blocks);
+            if (P.share && grid % 32) P.share = 0;
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, s, p->d_work.as<float2>(), P, n,
+                               tiles_log2, blocks, b->d_signs.as<uint32_t>() + (size_t)c0 * b->words, b->words,
                                b->d_frame.as<uint64_t>() + 2 * (size_t)c0, d->dedges.as<int4>(),
                                d->phase.as<float2>(), d->eedges.as<int2>(), d->ew.as<double>(),
                                p->d_partials.as<double>());

@@ -360,6 +360,19 @@ bool build_tiled(stn_plan* p, std::string& why) {
             if (L.rx_gate[p->gates[g].q0] >= 0) break;
             L.rx_gate[p->gates[g].q0] = (int32_t)g;
         }
+        // every rotation in the form c [[1, -i t], [-i t, 1]] with |t| <= 1:
+        // rx(theta) = -i X rx(theta - pi) when |sin(theta/2)| > |cos(theta/2)|
+        for (int32_t gi : L.rx_gate) {
+            if (gi < 0) continue;
+            GateRec& r = p->gates[gi];
+            const double c = std::cos(r.theta / 2), s = std::sin(r.theta / 2);
+            r.theta_eff = r.theta;
+            r.det_x = 0;
+            if (std::abs(s) > std::abs(c)) {
+                r.theta_eff = r.theta - M_PI;
+                r.det_x = 1ull << r.q0;
+            }
+        }
         if (L.zz_gates.empty() && std::all_of(L.rx_gate.begin(), L.rx_gate.end(), [](int32_t v) { return v < 0; })) {
             why = "gate " + std::to_string(g) + " is neither zz nor rx";
             return false;

@@ -98,6 +98,11 @@ struct GateRec {
     std::vector<cd> m;               // 2x2 or 4x4 matrix
     bool rotation = false;           // exp(-i theta/2 * P) with P a Pauli string
     uint64_t gx = 0, gz = 0;         // generator P's x / z masks (rotations)
+    // Tiled lowering: rx(theta) = -i X rx(theta - pi); when |sin(theta/2)| >
+    // |cos(theta/2)| the gate is applied as rx(theta_eff = theta - pi) and the
+    // X (det_x mask) joins the trajectory's Pauli frame right after the gate.
+    double theta_eff = 0;
+    uint64_t det_x = 0;
 };
 
 // Tiled statevector lowering (QAOA structure: H prefix, then layers of
@@ -149,6 +154,7 @@ struct stn_plan {
     stn::DevBuf d_site_gate;         // uint32 gate index of each site
     stn::DevBuf d_site_px, d_site_pz;// uint64 Pauli masks per (site, op), flattened like T
     stn::DevBuf d_gate_gx, d_gate_gz;// uint64 generator masks per gate (0,0 = not a rotation)
+    stn::DevBuf d_gate_dx;           // uint64 deterministic X mask applied after each gate (tiled lowering)
     stn::DevBuf d_obs;               // observable: u, v (uint32 pairs)
     stn::DevBuf d_obs_w;             // weights (double)
 

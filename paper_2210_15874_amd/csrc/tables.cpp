@@ -48,15 +48,18 @@ void upload_plan_tables(stn_plan* p, hipStream_t s) {
     up(p->d_site_gate, a, sg, s);
     up(p->d_site_px, a, px, s);
     up(p->d_site_pz, a, pz, s);
-    std::vector<uint64_t> gx, gz;
+    std::vector<uint64_t> gx, gz, dx;
     for (auto& g : p->gates) {
         gx.push_back(g.rotation ? g.gx : 0);
         gz.push_back(g.rotation ? g.gz : 0);
+        dx.push_back(g.det_x);
     }
     gx.push_back(0);
     gz.push_back(0);
+    dx.push_back(0);
     up(p->d_gate_gx, a, gx, s);
     up(p->d_gate_gz, a, gz, s);
+    up(p->d_gate_dx, a, dx, s);
     std::vector<uint32_t> uv;
     for (size_t t = 0; t < p->obs_u.size(); ++t) {
         uv.push_back(p->obs_u[t]);
