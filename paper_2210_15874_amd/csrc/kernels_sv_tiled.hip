@@ -8,30 +8,33 @@
 // (zz gates, angle = mult * base) and a mixer block (rx per qubit).  The state
 // psi[b][z] (complex64) is updated in place by passes over tiles of 2^14
 // amplitudes: 14 storage bits vary inside a tile, the others are fixed.  The
-// first pass of a layer holds storage bits 0..13; the next holds bits 0, 1
-// and the next 12 high qubits, so a layer of n = 26 qubits costs two passes.
+// planner's schedule (plan.cpp, schedule_tiled) alternates the order of a
+// layer's tiles so that one pass can rotate the last tile of layer l, apply
+// the diagonal of layer l+1 and rotate the same tile for layer l+1: n = 26,
+// p = 4 costs 5 passes per trajectory.
 //
 // Inside a workgroup (512 threads) the tile lives in registers, 32 amplitudes
-// per thread, in three layouts L0 -> L1 -> L2 exchanged through LDS; in each
-// layout the thread's 5 register bits are the qubits it rotates.  The diagonal
-// phase exp(-i base m(z)) with integer m(z) = sum_e mult_e sigma_e [z_u != z_v]
-// is looked up in a per-layer table (binary64 on the host, rounded once);
-// m(z) is split into a per-thread part and the contributions of the 5
-// register bits, so each amplitude costs a few integer adds.  An rx(theta)
-// is applied as cos(theta/2) [[1, -i t], [-i t, 1]] with t = tan(theta/2),
-// two FMAs per amplitude; the planner keeps |t| <= 1 by writing
-// rx(theta) = -i X rx(theta - pi) and moving the X into the Pauli frame, and
-// the dropped factor |cos(theta/2)| is restored in the next pass's phase
+// per thread, in three layouts exchanged through LDS; in each layout the
+// thread's 5 register bits are the qubits it rotates.  A pass runs the
+// layouts L0 -> L1 -> L2 for its first segment and L2 -> L1 -> L0 for its
+// second.  The diagonal phase exp(-i base m(z)) with integer
+// m(z) = sum_e mult_e sigma_e [z_u != z_v] is looked up in a per-layer table
+// (binary64 on the host, rounded once); m(z) is split into a per-thread part
+// and the contributions of the 5 register bits, so each amplitude costs a few
+// integer adds.  An rx(theta) is applied as cos(theta/2) [[1, -i t], [-i t, 1]]
+// with t = tan(theta/2), two FMAs per amplitude; the planner keeps |t| <= 1 by
+// writing rx(theta) = -i X rx(theta - pi) and moving the X into the Pauli
+// frame, and the dropped factor |cos(theta/2)| is restored in the next phase
 // table or in the energy.  The first pass generates |+>^n; the last pass
 // accumulates sum_z |psi_z|^2 C(z xor F_x) (F flips measured bits) instead of
 // storing: FP32 within a thread, binary64 across threads, tiles and
 // trajectories.
 //
-// Passes whose tile holds only two low storage bits read 32-byte runs; the
-// four workgroups that share each 128-byte line are given block indices
-// x, x+8, x+16, x+24, which the dispatcher places on the same XCD at the same
-// time, so each line is fetched from HBM once and served to the other three
-// from that XCD's L2.
+// Tiles that hold only two low storage bits read 32-byte runs; the four
+// workgroups that share each 128-byte line get tile indices x, x+8, x+16,
+// x+24, which the dispatcher places on the same XCD at the same time, so each
+// line comes from HBM once.  Workgroups are persistent (one per CU) and
+// prefetch the next tile into registers while working on the current one.
 #include <cmath>
 
 #include "stn_internal.h"
@@ -43,8 +46,8 @@ namespace {
 constexpr int kQ = 14;          // tile bits
 constexpr int kThreads = 512;   // 9 thread bits
 constexpr int kRegs = 32;       // 5 register bits
-constexpr int kMaxPhase = 511;  // phase table entries (2M+1)
-constexpr int kMaxEdges = 512;  // zz gates of one diagonal block
+constexpr int kMaxPhase = 511;  // phase table entries (2M+1) per diagonal
+constexpr int kMaxEdges = 512;  // zz gates of the pass's diagonals
 
 // layouts: tile-index bit of each register bit / thread bit
 __device__ constexpr int L0R[5] = {0, 10, 11, 12, 13};
@@ -53,25 +56,35 @@ __device__ constexpr int L1R[5] = {1, 2, 3, 4, 5};
 __device__ constexpr int L1T[9] = {0, 6, 7, 8, 9, 10, 11, 12, 13};
 __device__ constexpr int L2R[5] = {0, 6, 7, 8, 9};
 __device__ constexpr int L2T[9] = {1, 2, 3, 4, 5, 10, 11, 12, 13};
-constexpr int hL0R[5] = {0, 10, 11, 12, 13};
-constexpr int hL1R[5] = {1, 2, 3, 4, 5};
-constexpr int hL2R[5] = {0, 6, 7, 8, 9};
+constexpr int hLR[3][5] = {{0, 10, 11, 12, 13}, {1, 2, 3, 4, 5}, {0, 6, 7, 8, 9}};
+
+// zz gates of one diagonal, split by where their qubits sit in a layout:
+// [0] both outside the registers, [1 + r] one in register bit r, [6] both in
+// registers (stored as register-bit indices)
+struct DiagTab {
+    uint32_t off[7], n[7];
+    uint32_t ph_off, ph_mid;    // phase table entries [ph_off, ph_off + 2 ph_mid]
+};
 
 struct Pass2 {
     uint32_t tb[kQ];            // storage bit of tile-index bit i
     uint64_t fixed_mask;        // storage bits outside the tile
     uint32_t share;             // fixed storage bits below the 128-byte line (0..2)
-    uint32_t init, last, diag;
     float amp0;
-    int32_t mix_gate[3][5];     // per layout and register bit: rx gate, -1 = not rotated here
-    float mix_coef[3][5];       // t = tan(theta_eff/2), |t| <= 1, before the trajectory's sign
-    uint32_t d_off[7], d_n[7];  // diagonal edges: [0] both endpoints fixed, [1..5] one in register r-1, [6] both in registers
-    uint32_t ph_off, ph_mid;    // phase table entries [ph_off, ph_off + 2*ph_mid]
-    uint32_t e_off[7], e_n[7];  // observable terms in the same categories w.r.t. L2
+    int32_t mix_gate[2][3][5];  // [segment][layout][register bit]: rx gate, -1 = none (t = 0)
+    float mix_coef[2][3][5];    // tan(theta_eff / 2) before the trajectory's sign
+    DiagTab da, db;             // diagonal after the load (layout L0) / between the segments (L2)
+    uint32_t w_off, w_n;        // zz weights of da then db: dedges[w_off .. w_off + w_n)
+    uint32_t e_off[7], e_n[7];  // observable terms by category w.r.t. the final layout
     double e_scale;             // squared product of the rotation factors since the last diagonal
 };
 
-__device__ __forceinline__ uint32_t swz(uint32_t t) { return t ^ (((t >> 6) & 7u) << 1); }
+// LDS slot of tile index t: rows of 64 amplitudes shifted by 2 per row within
+// a group of 8 rows, groups of 512 padded by 16.  Every layout's accesses
+// then hit distinct banks, and the map is additive over disjoint bit sets,
+// so a thread's 32 slots are one base address plus immediate offsets.
+constexpr int kLdsSlots = 16894;  // pad(2^14 - 1) + 1
+__host__ __device__ constexpr uint32_t pad(uint32_t t) { return t + 2u * ((t >> 6) & 7u) + 16u * (t >> 9); }
 
 template <const int* T>
 __device__ __forceinline__ uint32_t thread_part(uint32_t tid) {
@@ -108,16 +121,22 @@ __device__ __forceinline__ uint64_t pdep64(uint64_t v, uint64_t mask) {
 
 __device__ __forceinline__ bool sign_bit(const uint32_t* sg, int g) { return (sg[g >> 5] >> (g & 31)) & 1u; }
 
-// rotate register bit r of layout L: pairs (j, j | 1<<r) get
-// x0' = x0 - i t x1, x1' = x1 - i t x0 (rx(theta) / cos(theta/2), t = +-tan(theta/2))
-template <int L>
-__device__ __forceinline__ void mix(float2 (&v)[kRegs], const Pass2& P, const uint32_t* sg) {
+__device__ __forceinline__ uint32_t bit_of(uint64_t z, int q) {
+    return (uint32_t)(q < 32 ? ((uint32_t)z >> q) : ((uint32_t)(z >> 32) >> (q - 32))) & 1u;
+}
+
+// Rotate the register bits of layout L in segment S: pairs (j, j | 1<<r) get
+// x0' = x0 - i t x1, x1' = x1 - i t x0.  A slot the pass does not rotate runs
+// with t = 0 (amplitudes unchanged), so there are no data-dependent branches;
+// tile bit 0 sits in two layouts and only its first slot in the segment's
+// layout order is compiled (the other is SKIP).
+// tt holds this trajectory's signed coefficients of the pass, [S][L][r].
+template <int S, int L, int SKIP_R>
+__device__ __forceinline__ void mix(float2 (&v)[kRegs], const float* tt) {
 #pragma unroll
     for (int r = 0; r < 5; ++r) {
-        const int g = P.mix_gate[L][r];
-        if (g < 0) continue;
-        const float c0 = P.mix_coef[L][r];
-        const float t = sign_bit(sg, g) ? -c0 : c0;
+        if (r == SKIP_R) continue;
+        const float t = tt[15 * S + 5 * L + r];
 #pragma unroll
         for (int j = 0; j < kRegs; ++j) {
             if (j & (1 << r)) continue;
@@ -131,66 +150,181 @@ __device__ __forceinline__ void mix(float2 (&v)[kRegs], const Pass2& P, const ui
 // write registers in layout A, read them back in layout B
 template <const int* AR, const int* AT, const int* BR, const int* BT>
 __device__ __forceinline__ void exchange(float2 (&v)[kRegs], float2* lds, uint32_t tid) {
-    const uint32_t ta = swz(thread_part<AT>(tid));
+    float2* wa = lds + pad(thread_part<AT>(tid));
 #pragma unroll
-    for (int j = 0; j < kRegs; ++j) lds[ta ^ swz(reg_part<AR>(j))] = v[j];
+    for (int j = 0; j < kRegs; ++j) wa[pad(reg_part<AR>(j))] = v[j];
     __syncthreads();
-    const uint32_t tbp = swz(thread_part<BT>(tid));
+    const float2* rb = lds + pad(thread_part<BT>(tid));
 #pragma unroll
-    for (int j = 0; j < kRegs; ++j) v[j] = lds[tbp ^ swz(reg_part<BR>(j))];
+    for (int j = 0; j < kRegs; ++j) v[j] = rb[pad(reg_part<BR>(j))];
     __syncthreads();
 }
 
+// Diagonal exp(-i base m(z)) on the registers of the layout whose register
+// bits sit at storage bits rs[] and whose other bits form z0.
+__device__ __forceinline__ void diag(float2 (&v)[kRegs], const DiagTab& D, uint64_t z0, const int4* dedges,
+                                     const int* wt, uint32_t w_base, const float2* ph) {
+    int C = 0, h[5] = {0, 0, 0, 0, 0};
+    for (uint32_t e = 0; e < D.n[0]; ++e) {
+        const int4 E = dedges[D.off[0] + e];
+        C += (bit_of(z0, E.x) ^ bit_of(z0, E.y)) ? wt[D.off[0] + e - w_base] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < 5; ++r)
+        for (uint32_t e = 0; e < D.n[1 + r]; ++e) {
+            const int4 E = dedges[D.off[1 + r] + e];
+            const int w = wt[D.off[1 + r] + e - w_base];
+            const uint32_t bv = bit_of(z0, E.x);
+            C += bv ? w : 0;
+            h[r] += bv ? -w : w;
+        }
+    // in chunks of 8 amplitudes, so that only 8 phases are live at a time
+#pragma unroll
+    for (int j0 = 0; j0 < kRegs; j0 += 8) {
+        int m[8];
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) {
+            const int j = j0 + jj;
+            int a = C;
+#pragma unroll
+            for (int r = 0; r < 5; ++r)
+                if (j & (1 << r)) a += h[r];
+            m[jj] = a;
+        }
+        for (uint32_t e = 0; e < D.n[6]; ++e) {
+            const int4 E = dedges[D.off[6] + e];
+            const int w = wt[D.off[6] + e - w_base];
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) m[jj] += ((((j0 + jj) >> E.x) ^ ((j0 + jj) >> E.y)) & 1) ? w : 0;
+        }
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) {
+            const float2 p = ph[D.ph_mid + m[jj]];
+            const float2 a = v[j0 + jj];
+            v[j0 + jj] = make_float2(p.x * a.x - p.y * a.y, fmaf(p.x, a.y, p.y * a.x));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 __device__ __forceinline__ uint32_t tile_of(uint32_t x, uint32_t share) {
-    // line-sharing tiles (differing only in the fixed storage bits below the
-    // 128-byte line) get indices x, x+8, x+16, x+24: the same XCD, same time
     if (!share) return x;
     const uint32_t xcd = x & 7u, r = x >> 3;
     const uint32_t j = r & ((1u << share) - 1u), g = ((r >> share) << 3) | xcd;
     return (g << share) | j;
 }
 
+// float4 = the amplitude pair of tile bit 0 (storage bit 0)
+template <const int* R>
 __device__ __forceinline__ void load_tile(float2 (&v)[kRegs], const float2* st, uint64_t z0, const Pass2& P) {
 #pragma unroll
     for (int jp = 0; jp < kRegs / 2; ++jp) {
         uint64_t z = z0;
 #pragma unroll
-        for (int r = 1; r < 5; ++r) z |= (uint64_t)((jp >> (r - 1)) & 1) << P.tb[L0R[r]];
+        for (int r = 1; r < 5; ++r) z |= (uint64_t)((jp >> (r - 1)) & 1) << P.tb[R[r]];
         const float4 w = *reinterpret_cast<const float4*>(st + z);
         v[2 * jp] = make_float2(w.x, w.y);
         v[2 * jp + 1] = make_float2(w.z, w.w);
     }
 }
 
-// Persistent pass kernel: workgroup w processes tiles w, w + G, w + 2G, ...
-// (G = grid size, a multiple of 32, so a workgroup stays on its XCD's share of
-// line-sharing tiles) and prefetches the next tile's amplitudes into
-// registers before working on the current one.
-// FL: bit 0 = first pass (generate |+>^n), bit 1 = diagonal at load,
-// bit 2 = last pass (energy instead of store)
+template <const int* R>
+__device__ __forceinline__ void store_tile(const float2 (&v)[kRegs], float2* st, uint64_t z0, const Pass2& P) {
+#pragma unroll
+    for (int jp = 0; jp < kRegs / 2; ++jp) {
+        uint64_t z = z0;
+#pragma unroll
+        for (int r = 1; r < 5; ++r) z |= (uint64_t)((jp >> (r - 1)) & 1) << P.tb[R[r]];
+        *reinterpret_cast<float4*>(st + z) = make_float4(v[2 * jp].x, v[2 * jp].y, v[2 * jp + 1].x, v[2 * jp + 1].y);
+    }
+}
+
+// sum_j |v_j|^2 C(z_j xor F_x) for the layout with register storage bits of R
+template <const int* R>
+__device__ __forceinline__ float energy_part(const float2 (&v)[kRegs], const Pass2& P, uint64_t z0, uint64_t fx,
+                                             const int2* eedges, const double* ew) {
+    const uint64_t zf = z0 ^ fx;
+    uint32_t fr = 0;  // frame bits on the register positions
+#pragma unroll
+    for (int r = 0; r < 5; ++r) fr |= bit_of(fx, P.tb[R[r]]) << r;
+    float C = 0.f, h[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    for (uint32_t e = 0; e < P.e_n[0]; ++e) {
+        const int2 E = eedges[P.e_off[0] + e];
+        if (bit_of(zf, E.x) ^ bit_of(zf, E.y)) C += (float)ew[P.e_off[0] + e];
+    }
+#pragma unroll
+    for (int r = 0; r < 5; ++r)
+        for (uint32_t e = 0; e < P.e_n[1 + r]; ++e) {
+            const int2 E = eedges[P.e_off[1 + r] + e];
+            const float w = (float)ew[P.e_off[1 + r] + e];
+            const uint32_t c = bit_of(zf, E.x) ^ ((fr >> r) & 1u);
+            C += c ? w : 0.f;
+            h[r] += c ? -w : w;
+        }
+    float acc = 0.f;
+#pragma unroll
+    for (int j0 = 0; j0 < kRegs; j0 += 8) {
+        float cz[8];
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) {
+            const int j = j0 + jj;
+            float a = C;
+#pragma unroll
+            for (int r = 0; r < 5; ++r)
+                if (j & (1 << r)) a += h[r];
+            cz[jj] = a;
+        }
+        for (uint32_t e = 0; e < P.e_n[6]; ++e) {
+            const int2 E = eedges[P.e_off[6] + e];
+            const float w = (float)ew[P.e_off[6] + e];
+            const int flip = (int)(((fr >> E.x) ^ (fr >> E.y)) & 1u);
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj)
+                cz[jj] += (((((j0 + jj) >> E.x) ^ ((j0 + jj) >> E.y)) & 1) != flip) ? w : 0.f;
+        }
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) {
+            const float2 a = v[j0 + jj];
+            acc = fmaf(fmaf(a.x, a.x, a.y * a.y), cz[jj], acc);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    return acc;
+}
+
+// FL bits: 1 = first pass (generate |+>^n), 2 = diagonal after the load,
+// 4 = second segment (diagonal + rotations back through L1 to L0),
+// 8 = last pass (energy instead of store).
+// Workgroup w processes tiles w, w + G, ... (G = grid, a multiple of 32 so
+// every workgroup keeps its XCD's share of line-sharing tiles).
 template <int FL>
-__global__ __launch_bounds__(kThreads) void k_sv_pass2(float2* __restrict__ psi, const Pass2 P, uint32_t n,
-                                                       uint32_t tiles_log2, uint32_t total,
-                                                       const uint32_t* __restrict__ signs, uint32_t words,
-                                                       const uint64_t* __restrict__ frame,
-                                                       const int4* __restrict__ dedges,
-                                                       const float2* __restrict__ phase,
-                                                       const int2* __restrict__ eedges,
-                                                       const double* __restrict__ ew,
-                                                       double* __restrict__ partials) {
-    __shared__ float2 lds[1 << kQ];
+__global__ __launch_bounds__(kThreads) void k_sv_pass(float2* __restrict__ psi, const Pass2 P, uint32_t n,
+                                                      uint32_t tiles_log2, uint32_t total,
+                                                      const uint32_t* __restrict__ signs, uint32_t words,
+                                                      const uint64_t* __restrict__ frame,
+                                                      const int4* __restrict__ dedges,
+                                                      const float2* __restrict__ phase,
+                                                      const int2* __restrict__ eedges,
+                                                      const double* __restrict__ ew,
+                                                      double* __restrict__ partials) {
+    __shared__ float2 lds[kLdsSlots];
     __shared__ uint32_t sg[64];
-    __shared__ float2 ph[kMaxPhase];
+    __shared__ float2 pha[kMaxPhase], phb[kMaxPhase];
     __shared__ double red[kThreads / 64];
     __shared__ int wt[kMaxEdges];  // this trajectory's signed multiplicities of the pass's zz gates
-    constexpr bool kInit = FL & 1, kDiag = FL & 2, kLast = FL & 4;
+    __shared__ float tt[32];       // this trajectory's signed rotation coefficients [segment][layout][r]
+    constexpr bool kInit = FL & 1, kDiagA = FL & 2, kSeg2 = FL & 4, kLast = FL & 8;
+    // the next tile is prefetched into registers when they allow it (one
+    // segment); two-segment passes load it after finishing the current one
+    constexpr bool kPrefetch = !kSeg2;
     const uint32_t tid = threadIdx.x;
-    const uint32_t e0 = P.d_off[0], ne = P.d_off[6] + P.d_n[6] - P.d_off[0];
     const uint64_t zt0 = storage_thread<L0T>(P, tid), zt2 = storage_thread<L2T>(P, tid);
     const uint32_t tmask = (1u << tiles_log2) - 1u;
 
-    if (kDiag)
-        for (uint32_t i = tid; i <= 2 * P.ph_mid; i += kThreads) ph[i] = phase[P.ph_off + i];
+    if (kDiagA)
+        for (uint32_t i = tid; i <= 2 * P.da.ph_mid; i += kThreads) pha[i] = phase[P.da.ph_off + i];
+    if (kSeg2)
+        for (uint32_t i = tid; i <= 2 * P.db.ph_mid; i += kThreads) phb[i] = phase[P.db.ph_off + i];
 
     uint32_t x = blockIdx.x;
     if (x >= total) return;
@@ -202,7 +336,7 @@ __global__ __launch_bounds__(kThreads) void k_sv_pass2(float2* __restrict__ psi,
 #pragma unroll
         for (int j = 0; j < kRegs; ++j) v[j] = make_float2(P.amp0, 0.f);
     } else {
-        load_tile(v, psi + ((size_t)b << n), base | zt0, P);
+        load_tile<L0R>(v, psi + ((size_t)b << n), base | zt0, P);
     }
     uint32_t sb = 0xffffffffu;  // trajectory whose signs are in LDS
     while (true) {
@@ -216,122 +350,48 @@ __global__ __launch_bounds__(kThreads) void k_sv_pass2(float2* __restrict__ psi,
             fn = tile_of(xn, P.share);
             bn = fn >> tiles_log2;
             basen = pdep64(fn & tmask, P.fixed_mask);
-            if (!kInit) load_tile(nx, psi + ((size_t)bn << n), basen | zt0, P);
+            if (!kInit && kPrefetch) load_tile<L0R>(nx, psi + ((size_t)bn << n), basen | zt0, P);
         }
         if (b != sb) {  // uniform: a new trajectory's signs and zz weights
             __syncthreads();
             for (uint32_t w = tid; w < words; w += kThreads) sg[w] = signs[(size_t)b * words + w];
             __syncthreads();
-            if (kDiag)
-                for (uint32_t e = tid; e < ne; e += kThreads) {
-                    const int4 E = dedges[e0 + e];
-                    wt[e] = sign_bit(sg, E.w) ? -E.z : E.z;
-                }
+            for (uint32_t e = tid; e < P.w_n; e += kThreads) {
+                const int4 E = dedges[P.w_off + e];
+                wt[e] = sign_bit(sg, E.w) ? -E.z : E.z;
+            }
+            if (tid < 30) {
+                const int g = (&P.mix_gate[0][0][0])[tid];
+                const float c0 = g < 0 ? 0.f : (&P.mix_coef[0][0][0])[tid];
+                tt[tid] = (g >= 0 && sign_bit(sg, g)) ? -c0 : c0;
+            }
             __syncthreads();
             sb = b;
         }
         float2* st = psi + ((size_t)b << n);
 
-        if (kDiag) {
-            const uint64_t z0 = base | zt0;
-            int C = 0, h[5] = {0, 0, 0, 0, 0};
-            const uint32_t zl = (uint32_t)z0, zh = (uint32_t)(z0 >> 32);
-            for (uint32_t e = 0; e < P.d_n[0]; ++e) {
-                const int4 E = dedges[P.d_off[0] + e];
-                const uint32_t bu = E.x < 32 ? zl >> E.x : zh >> (E.x - 32);
-                const uint32_t bv = E.y < 32 ? zl >> E.y : zh >> (E.y - 32);
-                C += ((bu ^ bv) & 1u) ? wt[P.d_off[0] + e - e0] : 0;
-            }
-#pragma unroll
-            for (int r = 0; r < 5; ++r)
-                for (uint32_t e = 0; e < P.d_n[1 + r]; ++e) {
-                    const int4 E = dedges[P.d_off[1 + r] + e];
-                    const int w = wt[P.d_off[1 + r] + e - e0];
-                    const uint32_t bv = (E.x < 32 ? zl >> E.x : zh >> (E.x - 32)) & 1u;
-                    C += bv ? w : 0;
-                    h[r] += bv ? -w : w;
-                }
-            int m[kRegs];
-#pragma unroll
-            for (int j = 0; j < kRegs; ++j) {
-                int a = C;
-#pragma unroll
-                for (int r = 0; r < 5; ++r)
-                    if (j & (1 << r)) a += h[r];
-                m[j] = a;
-            }
-            for (uint32_t e = 0; e < P.d_n[6]; ++e) {
-                const int4 E = dedges[P.d_off[6] + e];
-                const int w = wt[P.d_off[6] + e - e0];
-#pragma unroll
-                for (int j = 0; j < kRegs; ++j) m[j] += (((j >> E.x) ^ (j >> E.y)) & 1) ? w : 0;
-            }
-#pragma unroll
-            for (int j = 0; j < kRegs; ++j) {
-                const float2 p = ph[P.ph_mid + m[j]];
-                const float2 a = v[j];
-                v[j] = make_float2(p.x * a.x - p.y * a.y, fmaf(p.x, a.y, p.y * a.x));
-            }
+        if (kDiagA) diag(v, P.da, base | zt0, dedges, wt, P.w_off, pha);
+        mix<0, 0, 5>(v, tt);
+        exchange<L0R, L0T, L1R, L1T>(v, lds, tid);
+        mix<0, 1, 5>(v, tt);
+        exchange<L1R, L1T, L2R, L2T>(v, lds, tid);
+        mix<0, 2, 0>(v, tt);
+        if (kSeg2) {
+            diag(v, P.db, base | zt2, dedges, wt, P.w_off, phb);
+            mix<1, 2, 5>(v, tt);
+            exchange<L2R, L2T, L1R, L1T>(v, lds, tid);
+            mix<1, 1, 5>(v, tt);
+            exchange<L1R, L1T, L0R, L0T>(v, lds, tid);
+            mix<1, 0, 0>(v, tt);
         }
 
-        mix<0>(v, P, sg);
-        exchange<L0R, L0T, L1R, L1T>(v, lds, tid);
-        mix<1>(v, P, sg);
-        exchange<L1R, L1T, L2R, L2T>(v, lds, tid);
-        mix<2>(v, P, sg);
-
-        const uint64_t z2 = base | zt2;
         if (!kLast) {
-#pragma unroll
-            for (int jp = 0; jp < kRegs / 2; ++jp) {
-                uint64_t z = z2;
-#pragma unroll
-                for (int r = 1; r < 5; ++r) z |= (uint64_t)((jp >> (r - 1)) & 1) << P.tb[L2R[r]];
-                *reinterpret_cast<float4*>(st + z) =
-                    make_float4(v[2 * jp].x, v[2 * jp].y, v[2 * jp + 1].x, v[2 * jp + 1].y);
-            }
+            if (kSeg2) store_tile<L0R>(v, st, base | zt0, P);
+            else store_tile<L2R>(v, st, base | zt2, P);
         } else {
-            // energy: sum_j |v_j|^2 C(z_j xor F_x), C(z) = sum_t w_t [z_u != z_v];
-            // per amplitude in FP32 (cut values are small sums of weights), summed
-            // over the thread's 32 amplitudes in FP32, then in binary64
             const uint64_t fx = frame[2 * (size_t)b];
-            const uint64_t zf = z2 ^ fx;
-            uint32_t fr = 0;  // frame bits on the register positions
-#pragma unroll
-            for (int r = 0; r < 5; ++r) fr |= (uint32_t)((fx >> P.tb[L2R[r]]) & 1u) << r;
-            float C = 0.f, h[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-            for (uint32_t e = 0; e < P.e_n[0]; ++e) {
-                const int2 E = eedges[P.e_off[0] + e];
-                if (((zf >> E.x) ^ (zf >> E.y)) & 1u) C += (float)ew[P.e_off[0] + e];
-            }
-#pragma unroll
-            for (int r = 0; r < 5; ++r)
-                for (uint32_t e = 0; e < P.e_n[1 + r]; ++e) {
-                    const int2 E = eedges[P.e_off[1 + r] + e];
-                    const float w = (float)ew[P.e_off[1 + r] + e];
-                    const int c = (int)(((zf >> E.x) & 1u) ^ ((fr >> r) & 1u));
-                    C += c ? w : 0.f;
-                    h[r] += c ? -w : w;
-                }
-            float cz[kRegs];
-#pragma unroll
-            for (int j = 0; j < kRegs; ++j) {
-                float a = C;
-#pragma unroll
-                for (int r = 0; r < 5; ++r)
-                    if (j & (1 << r)) a += h[r];
-                cz[j] = a;
-            }
-            for (uint32_t e = 0; e < P.e_n[6]; ++e) {
-                const int2 E = eedges[P.e_off[6] + e];
-                const float w = (float)ew[P.e_off[6] + e];
-                const bool flip = ((fr >> E.x) ^ (fr >> E.y)) & 1u;
-#pragma unroll
-                for (int j = 0; j < kRegs; ++j) cz[j] += ((((j >> E.x) ^ (j >> E.y)) & 1) != (int)flip) ? w : 0.f;
-            }
-            float accf = 0.f;
-#pragma unroll
-            for (int j = 0; j < kRegs; ++j) accf = fmaf(fmaf(v[j].x, v[j].x, v[j].y * v[j].y), cz[j], accf);
+            const float accf = kSeg2 ? energy_part<L0R>(v, P, base | zt0, fx, eedges, ew)
+                                     : energy_part<L2R>(v, P, base | zt2, fx, eedges, ew);
             double acc = (double)accf;
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
@@ -351,9 +411,11 @@ __global__ __launch_bounds__(kThreads) void k_sv_pass2(float2* __restrict__ psi,
         if (kInit) {
 #pragma unroll
             for (int j = 0; j < kRegs; ++j) v[j] = make_float2(P.amp0, 0.f);
-        } else {
+        } else if (kPrefetch) {
 #pragma unroll
             for (int j = 0; j < kRegs; ++j) v[j] = nx[j];
+        } else {
+            load_tile<L0R>(v, psi + ((size_t)b << n), base | zt0, P);
         }
     }
 }
@@ -374,18 +436,57 @@ __global__ __launch_bounds__(256) void k_tile_sum(const double* __restrict__ par
     if (threadIdx.x == 0) energy[b] = red[0];
 }
 
+typedef void (*PassKernel)(float2*, const Pass2, uint32_t, uint32_t, uint32_t, const uint32_t*, uint32_t,
+                           const uint64_t*, const int4*, const float2*, const int2*, const double*, double*);
+
+PassKernel pass_kernel(int fl) {
+    static const PassKernel tab[16] = {
+        k_sv_pass<0>,  k_sv_pass<1>,  k_sv_pass<2>,  k_sv_pass<3>,  k_sv_pass<4>,  k_sv_pass<5>,
+        k_sv_pass<6>,  k_sv_pass<7>,  k_sv_pass<8>,  k_sv_pass<9>,  k_sv_pass<10>, k_sv_pass<11>,
+        k_sv_pass<12>, k_sv_pass<13>, k_sv_pass<14>, k_sv_pass<15>};
+    return tab[fl & 15];
+}
+
 struct TiledTables {
     std::vector<Pass2> passes;
+    std::vector<int> flags;
+    std::vector<double> flops;   // algorithmic flops per amplitude of each pass
     std::vector<int4> dedges;
     std::vector<cd> phase;
     std::vector<int2> eedges;
     std::vector<double> ew;
 };
 
-int reg_index(const int* R, const uint32_t* tb, uint32_t q) {
+int reg_index(int layout, const uint32_t* tb, uint32_t q) {
     for (int r = 0; r < 5; ++r)
-        if (tb[R[r]] == q) return r;
+        if (tb[hLR[layout][r]] == q) return r;
     return -1;
+}
+
+// zz gates of layer L by category w.r.t. the register bits of `layout`
+DiagTab diag_table(stn_plan* p, TiledTables& T, const Pass2& P, int layer, int layout, double scale) {
+    const TiledLayer& L = p->layers[layer];
+    if (2 * L.mult_sum + 1 > kMaxPhase) fail(STN_E_UNSUPPORTED, "diagonal block too large for the phase table");
+    DiagTab D{};
+    std::vector<int4> cat[7];
+    for (size_t e = 0; e < L.zz_gates.size(); ++e) {
+        const GateRec& g = p->gates[L.zz_gates[e]];
+        const int ru = reg_index(layout, P.tb, g.q0), rv = reg_index(layout, P.tb, g.q1);
+        const int mult = L.zz_mult[e], gi = (int)L.zz_gates[e];
+        if (ru < 0 && rv < 0) cat[0].push_back({(int)g.q0, (int)g.q1, mult, gi});
+        else if (ru >= 0 && rv < 0) cat[1 + ru].push_back({(int)g.q1, 0, mult, gi});
+        else if (ru < 0 && rv >= 0) cat[1 + rv].push_back({(int)g.q0, 0, mult, gi});
+        else cat[6].push_back({ru, rv, mult, gi});
+    }
+    for (int c = 0; c < 7; ++c) {
+        D.off[c] = (uint32_t)T.dedges.size();
+        D.n[c] = (uint32_t)cat[c].size();
+        T.dedges.insert(T.dedges.end(), cat[c].begin(), cat[c].end());
+    }
+    D.ph_off = (uint32_t)T.phase.size();
+    D.ph_mid = (uint32_t)L.mult_sum;
+    for (int m = -L.mult_sum; m <= L.mult_sum; ++m) T.phase.push_back(scale * std::exp(cd(0, -L.base_angle * m)));
+    return D;
 }
 
 TiledTables build_tables(stn_plan* p) {
@@ -393,6 +494,9 @@ TiledTables build_tables(stn_plan* p) {
     const uint32_t n = p->n;
     const uint64_t N = 1ull << n;
     double acc_scale = 1.0;
+    // segment s visits layouts in this order; tile bit 0 (L0 slot 0 and L2
+    // slot 0) is rotated at the first of them
+    const int order[2][3] = {{0, 1, 2}, {2, 1, 0}};
     for (auto& ps : p->passes) {
         Pass2 P{};
         int t = 0;
@@ -401,72 +505,65 @@ TiledTables build_tables(stn_plan* p) {
         if (t != kQ || P.tb[0] != 0) fail(STN_E_INVALID, "tile must hold 14 storage bits including bit 0");
         P.fixed_mask = (N - 1) & ~(uint64_t)ps.tile_mask;
         P.share = (uint32_t)__builtin_popcountll(P.fixed_mask & 0xFull);
-        P.init = ps.init;
-        P.last = ps.last;
-        P.diag = ps.layer >= 0;
         P.amp0 = (float)std::pow(2.0, -0.5 * n);
-        // diagonal (layout L0 registers)
-        if (P.diag) {
-            const TiledLayer& L = p->layers[ps.layer];
-            std::vector<int4> cat[7];
-            for (size_t e = 0; e < L.zz_gates.size(); ++e) {
-                const GateRec& g = p->gates[L.zz_gates[e]];
-                const int ru = reg_index(hL0R, P.tb, g.q0), rv = reg_index(hL0R, P.tb, g.q1);
-                const int mult = L.zz_mult[e], gi = (int)L.zz_gates[e];
-                if (ru < 0 && rv < 0) cat[0].push_back({(int)g.q0, (int)g.q1, mult, gi});
-                else if (ru >= 0 && rv < 0) cat[1 + ru].push_back({(int)g.q1, 0, mult, gi});
-                else if (ru < 0 && rv >= 0) cat[1 + rv].push_back({(int)g.q0, 0, mult, gi});
-                else cat[6].push_back({ru, rv, mult, gi});
+        int fl = (ps.init ? 1 : 0) | (ps.diag_a >= 0 ? 2 : 0) | (ps.mix2 >= 0 ? 4 : 0) | (ps.last ? 8 : 0);
+        if (ps.diag_b >= 0 && ps.mix2 < 0) fail(STN_E_INVALID, "diagonal between segments without a second segment");
+        const size_t w0 = T.dedges.size();
+        double nmix = 0;
+        auto rotations = [&](int seg, int layer, uint32_t mask) {
+            uint32_t done = 0;
+            for (int li = 0; li < 3; ++li) {
+                const int l = order[seg][li];
+                for (int r = 0; r < 5; ++r) {
+                    P.mix_gate[seg][l][r] = -1;
+                    P.mix_coef[seg][l][r] = 0.f;
+                    const uint32_t q = P.tb[hLR[l][r]];
+                    if (layer < 0 || !((mask >> q) & 1) || ((done >> q) & 1)) continue;
+                    done |= 1u << q;
+                    const int g = p->layers[layer].rx_gate[q];
+                    const double th = p->gates[g].theta_eff;
+                    const double c = std::cos(th / 2), s = std::sin(th / 2);
+                    if (std::abs(s) > std::abs(c) * (1 + 1e-12)) fail(STN_E_INVALID, "rx gate not in reduced form");
+                    P.mix_gate[seg][l][r] = g;
+                    P.mix_coef[seg][l][r] = (float)(s / c);
+                    acc_scale *= std::abs(c);
+                    nmix += 1;
+                }
             }
-            for (int c = 0; c < 7; ++c) {
-                P.d_off[c] = (uint32_t)T.dedges.size();
-                P.d_n[c] = (uint32_t)cat[c].size();
-                T.dedges.insert(T.dedges.end(), cat[c].begin(), cat[c].end());
-            }
-            if (2 * L.mult_sum + 1 > kMaxPhase || L.zz_gates.size() > (size_t)kMaxEdges)
-                fail(STN_E_UNSUPPORTED, "diagonal block too large for the phase table");
-            P.ph_off = (uint32_t)T.phase.size();
-            P.ph_mid = (uint32_t)L.mult_sum;
-            for (int m = -L.mult_sum; m <= L.mult_sum; ++m)
-                T.phase.push_back(acc_scale * std::exp(cd(0, -L.base_angle * m)));
+            if (layer >= 0 && done != mask) fail(STN_E_INVALID, "pass rotates a qubit outside its tile");
+        };
+        if (ps.diag_a >= 0) {
+            P.da = diag_table(p, T, P, ps.diag_a, 0, acc_scale);
             acc_scale = 1.0;
         }
-        // rotations: each mixed qubit once, in the first layout holding it in a register
-        const int* LR[3] = {hL0R, hL1R, hL2R};
-        uint32_t done = 0;
-        for (int l = 0; l < 3; ++l)
-            for (int r = 0; r < 5; ++r) {
-                P.mix_gate[l][r] = -1;
-                const uint32_t q = P.tb[LR[l][r]];
-                if (!((ps.mix_mask >> q) & 1) || ((done >> q) & 1)) continue;
-                done |= 1u << q;
-                const int g = p->layers[ps.mix_layer].rx_gate[q];
-                const double th = p->gates[g].theta_eff;
-                const double c = std::cos(th / 2), s = std::sin(th / 2);
-                if (std::abs(s) > std::abs(c) * (1 + 1e-12)) fail(STN_E_INVALID, "rx gate not in reduced form");
-                P.mix_gate[l][r] = g;
-                P.mix_coef[l][r] = (float)(s / c);
-                acc_scale *= std::abs(c);
-            }
-        if (done != ps.mix_mask) fail(STN_E_INVALID, "pass mixes a qubit outside its tile");
-        // observable (layout L2 registers)
-        if (P.last) {
+        rotations(0, ps.mix1, ps.mix1_mask);
+        if (ps.mix2 >= 0) {
+            P.db = diag_table(p, T, P, ps.diag_b, 2, acc_scale);
+            acc_scale = 1.0;
+            rotations(1, ps.mix2, ps.mix2_mask);
+        } else {
+            for (int l = 0; l < 3; ++l)
+                for (int r = 0; r < 5; ++r) P.mix_gate[1][l][r] = -1;
+        }
+        P.w_off = (uint32_t)w0;
+        P.w_n = (uint32_t)(T.dedges.size() - w0);
+        if (P.w_n > (uint32_t)kMaxEdges) fail(STN_E_UNSUPPORTED, "too many zz gates in one pass");
+        if (ps.last) {
+            const int layout = ps.mix2 >= 0 ? 0 : 2;
             std::vector<int2> cat[7];
             std::vector<double> cw[7];
             for (size_t t2 = 0; t2 < p->obs_u.size(); ++t2) {
                 const uint32_t u = p->obs_u[t2], v = p->obs_v[t2];
-                const int ru = reg_index(hL2R, P.tb, u), rv = reg_index(hL2R, P.tb, v);
+                const int ru = reg_index(layout, P.tb, u), rv = reg_index(layout, P.tb, v);
                 int c = 0;
                 int2 e{(int)u, (int)v};
-                if (ru < 0 && rv < 0) {
-                    c = 0;
-                } else if (ru >= 0 && rv < 0) {
+                if (ru >= 0 && rv < 0) {
                     c = 1 + ru;
                     e = {(int)v, 0};
                 } else if (ru < 0 && rv >= 0) {
                     c = 1 + rv;
                     e = {(int)u, 0};
-                } else {
+                } else if (ru >= 0 && rv >= 0) {
                     c = 6;
                     e = {ru, rv};
                 }
@@ -482,6 +579,8 @@ TiledTables build_tables(stn_plan* p) {
             P.e_scale = acc_scale * acc_scale;
         }
         T.passes.push_back(P);
+        T.flags.push_back(fl);
+        T.flops.push_back(6.0 * nmix + 6.0 * ((ps.diag_a >= 0) + (ps.mix2 >= 0)) + (ps.last ? 4.0 : 0.0));
     }
     return T;
 }
@@ -529,28 +628,21 @@ void launch_sv_tiled(stn_plan* p, stn_batch* b, hipStream_t s) {
     for (uint32_t c0 = 0; c0 < b->K; c0 += B) {
         const uint32_t nb = std::min(B, b->K - c0);
         const uint32_t blocks = nb * tiles;
-        for (const Pass2& P0 : d->t.passes) {
-            Pass2 P = P0;
-            if (blocks % (8u << P.share)) P.share = 0;  // grouping needs whole XCD rounds
-            int nmix = 0;
-            for (int l = 0; l < 3; ++l)
-                for (int r = 0; r < 5; ++r) nmix += P.mix_gate[l][r] >= 0;
+        for (size_t i = 0; i < d->t.passes.size(); ++i) {
+            Pass2 P = d->t.passes[i];
+            const int fl = d->t.flags[i];
+            const uint32_t grid = std::min(grid_max, blocks);
+            if (blocks % (8u << P.share) || grid % 32) P.share = 0;  // grouping needs whole XCD rounds
             const double elems = (double)nb * (double)N;
             prof_begin(p, STN_K_SV_PASS, s);
-            const int fl = (P.init ? 1 : 0) | (P.diag ? 2 : 0) | (P.last ? 4 : 0);
-            auto kern = fl == 0 ? k_sv_pass2<0> : fl == 1 ? k_sv_pass2<1> : fl == 2 ? k_sv_pass2<2>
-                      : fl == 3 ? k_sv_pass2<3> : fl == 4 ? k_sv_pass2<4> : fl == 5 ? k_sv_pass2<5>
-                      : fl == 6 ? k_sv_pass2<6> : k_sv_pass2<7>;
-            const uint32_t grid = std::min(grid_max, blocks);
-            if (P.share && grid % 32) P.share = 0;
-            hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, s, p->d_work.as<float2>(), P, n,
+            hipLaunchKernelGGL(pass_kernel(fl), dim3(grid), dim3(kThreads), 0, s, p->d_work.as<float2>(), P, n,
                                tiles_log2, blocks, b->d_signs.as<uint32_t>() + (size_t)c0 * b->words, b->words,
                                b->d_frame.as<uint64_t>() + 2 * (size_t)c0, d->dedges.as<int4>(),
                                d->phase.as<float2>(), d->eedges.as<int2>(), d->ew.as<double>(),
                                p->d_partials.as<double>());
             STN_HIP(hipGetLastError());
-            prof_end(p, STN_K_SV_PASS, s, elems * 8.0 * ((P.init ? 0 : 1) + (P.last ? 0 : 1)),
-                     elems * (6.0 * nmix + (P.diag ? 6.0 : 0.0) + (P.last ? 4.0 : 0.0)));
+            prof_end(p, STN_K_SV_PASS, s, elems * 8.0 * ((fl & 1 ? 0 : 1) + (fl & 8 ? 0 : 1)),
+                     elems * d->t.flops[i]);
         }
         prof_begin(p, STN_K_TILE_SUM, s);
         hipLaunchKernelGGL(k_tile_sum, dim3(nb), dim3(256), 0, s, p->d_partials.as<double>(), tiles,

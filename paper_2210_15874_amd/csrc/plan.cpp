@@ -400,9 +400,15 @@ bool build_tiled(stn_plan* p, std::string& why) {
 
 }  // namespace
 
-// Pass schedule of the tiled lowering: every layer mixes all qubits once; the
-// tile of the first pass of a layer is the low `tile_bits` storage bits, the
-// next passes take `coal` low bits (coalescing) plus the next high qubits.
+// Pass schedule of the tiled lowering.  A layer's rotations are split over
+// tiles: the first holds the low `tile_bits` storage bits, the next ones
+// `coal` low bits (coalescing) plus the next high qubits.  Rotations on
+// different qubits commute, so the tiles of a layer may be visited in any
+// order; visiting them in alternating order (forward for even layers,
+// backward for odd ones) makes the last tile of a layer and the first tile of
+// the next one the same, and those two become one pass: rotate (layer l),
+// diagonal (layer l+1), rotate (layer l+1).  p layers on k tiles cost
+// p (k - 1) + 1 passes instead of p k.
 void schedule_tiled(stn_plan* p, uint32_t tile_bits, uint32_t coal) {
     const uint32_t n = p->n;
     p->passes.clear();
@@ -418,21 +424,37 @@ void schedule_tiled(stn_plan* p, uint32_t tile_bits, uint32_t coal) {
         tiles.push_back(m);
         lo += take;
     }
+    struct Op { int32_t layer; uint32_t tile; uint32_t mask; bool first; };
+    std::vector<Op> ops;
+    const uint32_t k = (uint32_t)tiles.size();
     for (uint32_t l = 0; l < p->layers.size(); ++l) {
         uint32_t mixed = 0;
-        for (size_t t = 0; t < tiles.size(); ++t) {
-            TiledPass ps;
-            ps.tile_mask = tiles[t];
-            ps.layer = t == 0 ? (int32_t)l : -1;
-            ps.mix_layer = (int32_t)l;
+        for (uint32_t i = 0; i < k; ++i) {
+            const uint32_t t = (l % 2 == 0) ? i : k - 1 - i;
             uint32_t mm = 0;
             for (uint32_t qb = 0; qb < n; ++qb)
                 if (((tiles[t] >> qb) & 1) && !((mixed >> qb) & 1) && p->layers[l].rx_gate[qb] >= 0) mm |= 1u << qb;
             mixed |= tiles[t];
-            ps.mix_mask = mm;
-            if (t > 0 && mm == 0) continue;
-            p->passes.push_back(ps);
+            if (i > 0 && mm == 0) continue;
+            ops.push_back({(int32_t)l, t, mm, i == 0});
         }
+    }
+    for (const Op& o : ops) {
+        if (!p->passes.empty()) {
+            TiledPass& b = p->passes.back();
+            if (o.first && b.mix2 < 0 && b.mix1 == o.layer - 1 && b.tile_mask == tiles[o.tile]) {
+                b.diag_b = o.layer;
+                b.mix2 = o.layer;
+                b.mix2_mask = o.mask;
+                continue;
+            }
+        }
+        TiledPass ps;
+        ps.tile_mask = tiles[o.tile];
+        ps.diag_a = o.first ? o.layer : -1;
+        ps.mix1 = o.layer;
+        ps.mix1_mask = o.mask;
+        p->passes.push_back(ps);
     }
     if (p->passes.empty()) {
         TiledPass ps;
@@ -534,7 +556,8 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
         double bytes = 0, fl = 0;
         for (auto& ps : p->passes) {
             bytes += (ps.init ? 0 : N * elem) + (ps.last ? 0 : N * elem);
-            fl += N * 6.0 * __builtin_popcount(ps.mix_mask) + (ps.layer >= 0 ? N * 6.0 : 0) + (ps.last ? N * 4.0 : 0);
+            fl += N * 6.0 * (__builtin_popcount(ps.mix1_mask) + __builtin_popcount(ps.mix2_mask)) +
+                  N * 6.0 * ((ps.diag_a >= 0) + (ps.diag_b >= 0)) + (ps.last ? N * 4.0 : 0);
         }
         p->bytes_per_traj = bytes;
         p->flops_per_traj = fl;

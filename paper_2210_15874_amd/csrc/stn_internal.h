@@ -115,11 +115,18 @@ struct TiledLayer {
     std::vector<int32_t> rx_gate;    // per qubit: rx gate index in the mixer block, -1 = none
 };
 
+// One pass over the state: load a tile, [diagonal of layer diag_a], rotate the
+// tile's qubits of layer mix1, [diagonal of layer diag_b, rotate the tile's
+// qubits of layer mix2], store (or reduce to the energy).  The two segments
+// let the last tile of one layer and the first tile of the next share a pass.
 struct TiledPass {
     uint32_t tile_mask = 0;          // storage bits inside the tile (= qubits, identity layout)
-    int32_t layer = -1;              // layer whose diagonal is applied at load (-1 none)
-    int32_t mix_layer = -1;          // layer whose rx gates on tile qubits are applied
-    uint32_t mix_mask = 0;           // qubits mixed in this pass
+    int32_t diag_a = -1;             // layer whose diagonal is applied after the load (-1 none)
+    int32_t mix1 = -1;               // layer rotated in the first segment
+    uint32_t mix1_mask = 0;          // its qubits rotated here
+    int32_t diag_b = -1;             // layer whose diagonal is applied between the segments
+    int32_t mix2 = -1;               // layer rotated in the second segment (-1: no second segment)
+    uint32_t mix2_mask = 0;
     bool init = false;               // generate |+>^n instead of loading
     bool last = false;               // accumulate the energy instead of storing
 };
@@ -168,11 +175,6 @@ struct stn_plan {
     // SV_TILED lowering
     std::vector<stn::TiledLayer> layers;
     std::vector<stn::TiledPass> passes;
-    stn::DevBuf d_phase32, d_phase64;       // per layer: phase table e^{-i base m}, m in [-M, M]
-    std::vector<uint32_t> phase_off;
-    stn::DevBuf d_rx32, d_rx64;             // per gate (rx): (cos(theta/2), sin(theta/2))
-    stn::DevBuf d_layer_edges;              // per layer: (u, v, mult, gate) int32 quads
-    std::vector<uint32_t> layer_edge_off;
     void* tiled = nullptr;                  // pass tables of the tiled kernels (kernels_sv_tiled.hip)
     void (*tiled_free)(void*) = nullptr;
     stn::DevBuf d_work;                     // psi workspace [max_batch x 2^n]
