@@ -33,6 +33,8 @@ SOURCES = {
     "kernels_sv_lds.hip": "device",
     "kernels_sv_tiled.hip": "device",
     "kernels_reduce.hip": "device",
+    "kernels_tn.hip": "device",
+    "lightcone.cpp": "host",
 }
 
 

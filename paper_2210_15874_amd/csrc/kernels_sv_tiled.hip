@@ -652,6 +652,4 @@ void launch_sv_tiled(stn_plan* p, stn_batch* b, hipStream_t s) {
     }
 }
 
-void launch_lightcone(stn_plan*, stn_batch*, hipStream_t) { fail(STN_E_UNSUPPORTED, "lightcone lowering not built"); }
-
 }  // namespace stn

@@ -1,0 +1,276 @@
+// Lightcone tensor-network contraction (Sec. III-A bucket elimination,
+// batched over trajectories as Sec. III-G's ensemble).
+//
+// One workgroup contracts one (term, trajectory) network entirely in LDS:
+// the steps planned by lightcone.cpp run in order; a step computes, for every
+// index o of its output, sum_x prod_i T_i[index_i(o, x)] over the summed
+// variable x, where each input's index gathers its variables' bits from
+// (o, x).  Gate tensors are read from a host table holding both sign variants
+// of every gate (binary64, rounded once to the contraction precision) and
+// picked by the trajectory's sign bit; the bra side takes the conjugate.  The
+// result of a term is <Z_u Z_v> of the trajectory's noiseless-structure state;
+// k_tn_energy forms sum_t w_t (1 - f_t <Z_u Z_v>_t) / 2 in binary64 with the
+// final Pauli frame's sign f_t, in term order.
+#include <cmath>
+
+#include "lightcone.h"
+
+namespace stn {
+
+namespace {
+
+constexpr int kTnThreads = 256;
+constexpr int kMaxPos = 14;
+constexpr int kLdsBytes = 64 * 1024;
+
+struct TnIn {
+    int32_t kind, gate, conj, arena, npos;
+    int32_t pos[kMaxPos];
+};
+
+struct TnStep {
+    int32_t in_off, n_in, out_bits, sum, out_arena;
+};
+
+struct TnTerm {
+    int32_t step_off, n_steps, result;
+};
+
+template <class R> struct Cx;
+template <> struct Cx<float> { using T = float2; };
+template <> struct Cx<double> { using T = double2; };
+
+template <class V> __device__ __forceinline__ V cmul(V a, V b) {
+    V r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+
+template <class R>
+__global__ __launch_bounds__(kTnThreads) void k_tn(const TnTerm* __restrict__ terms, const TnStep* __restrict__ steps,
+                                                   const TnIn* __restrict__ ins,
+                                                   const typename Cx<R>::T* __restrict__ gtab,
+                                                   const uint32_t* __restrict__ signs, uint32_t words,
+                                                   double* __restrict__ zz, uint32_t T) {
+    using V = typename Cx<R>::T;
+    extern __shared__ char smem[];
+    V* arena = reinterpret_cast<V*>(smem);
+    const uint32_t t = blockIdx.x, b = blockIdx.y;
+    const TnTerm tm = terms[t];
+    const uint32_t* sg = signs + (size_t)b * words;
+    for (int s = 0; s < tm.n_steps; ++s) {
+        const TnStep st = steps[tm.step_off + s];
+        const uint32_t nout = 1u << st.out_bits;
+        for (uint32_t o = threadIdx.x; o < nout; o += kTnThreads) {
+            V acc;
+            acc.x = R(0);
+            acc.y = R(0);
+            for (int x = 0; x <= st.sum; ++x) {
+                const uint32_t full = o | ((uint32_t)x << st.out_bits);
+                V prod;
+                prod.x = R(1);
+                prod.y = R(0);
+                for (int i = 0; i < st.n_in; ++i) {
+                    const TnIn& in = ins[st.in_off + i];
+                    uint32_t loc = 0;
+                    for (int k = 0; k < in.npos; ++k) loc |= ((full >> in.pos[k]) & 1u) << k;
+                    V val;
+                    if (in.kind == TN_INTER) {
+                        val = arena[in.arena + loc];
+                    } else if (in.kind == TN_GATE) {
+                        const uint32_t neg = (sg[in.gate >> 5] >> (in.gate & 31)) & 1u;
+                        val = gtab[((size_t)in.gate * 2 + neg) * 16 + loc];
+                        if (in.conj) val.y = -val.y;
+                    } else if (in.kind == TN_OBS) {
+                        val.x = ((loc ^ (loc >> 1)) & 1u) ? R(-1) : R(1);
+                        val.y = R(0);
+                    } else {
+                        val.x = loc == 0 ? R(1) : R(0);
+                        val.y = R(0);
+                    }
+                    prod = cmul(prod, val);
+                }
+                acc.x += prod.x;
+                acc.y += prod.y;
+            }
+            arena[st.out_arena + o] = acc;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) zz[(size_t)b * T + t] = (double)arena[tm.result].x;
+}
+
+// energy[b] = sum_t w_t (1 - f_t zz[b][t]) / 2, f_t = (-1)^(F_x[u] xor F_x[v])
+__global__ __launch_bounds__(64) void k_tn_energy(const double* __restrict__ zz, uint32_t T,
+                                                  const uint32_t* __restrict__ uv, const double* __restrict__ w,
+                                                  const uint64_t* __restrict__ frame, uint32_t B,
+                                                  double* __restrict__ energy) {
+    const uint32_t b = blockIdx.x * 64 + threadIdx.x;
+    if (b >= B) return;
+    const uint64_t fx = frame[2 * (size_t)b];
+    double e = 0.0;
+    for (uint32_t t = 0; t < T; ++t) {
+        const double f = (((fx >> uv[2 * t]) ^ (fx >> uv[2 * t + 1])) & 1ull) ? -1.0 : 1.0;
+        e += w[t] * (1.0 - f * zz[(size_t)b * T + t]) * 0.5;
+    }
+    energy[b] = e;
+}
+
+struct TnDevice {
+    std::vector<TnNetwork> nets;
+    int arena = 0;
+    DevBuf terms, steps, ins, gtab32, gtab64, zz;
+};
+
+// tensor values of gate g over its local index, for sign s (0: theta, 1: -theta)
+void gate_tensor(const GateRec& g, int s, cd* out) {
+    for (int i = 0; i < 16; ++i) out[i] = 0;
+    const double th = s ? -g.theta : g.theta;
+    const cd I1(0, 1);
+    std::vector<cd> m;
+    const double c = std::cos(th / 2), sn = std::sin(th / 2);
+    switch (g.kind) {
+        case STN_G_RX: m = {c, -I1 * sn, -I1 * sn, c}; break;
+        case STN_G_RY: m = {c, -sn, sn, c}; break;
+        case STN_G_RZ: m = {std::exp(-I1 * (th / 2)), 0, 0, std::exp(I1 * (th / 2))}; break;
+        case STN_G_ZZ: {
+            const cd e = std::exp(-I1 * th);
+            m.assign(16, 0);
+            m[0] = 1; m[5] = e; m[10] = e; m[15] = 1;
+            break;
+        }
+        default: m = g.m; break;
+    }
+    const bool diag = g.kind == STN_G_RZ || g.kind == STN_G_Z || g.kind == STN_G_ZZ;
+    if (g.nq == 1) {
+        if (diag) {
+            out[0] = m[0];
+            out[1] = m[3];
+        } else {
+            // local index: bit 0 = input, bit 1 = output
+            for (int in = 0; in < 2; ++in)
+                for (int o = 0; o < 2; ++o) out[in | (o << 1)] = m[o * 2 + in];
+        }
+    } else {
+        if (diag) {
+            for (int l = 0; l < 4; ++l) out[l] = m[l * 4 + l];
+        } else {
+            // local index: in0, in1, out0, out1
+            for (int in = 0; in < 4; ++in)
+                for (int o = 0; o < 4; ++o) out[in | (o << 2)] = m[o * 4 + in];
+        }
+    }
+}
+
+}  // namespace
+
+// Builds the networks of every observable term; records width and cost.
+void build_lightcone(stn_plan* p) {
+    if (!p->frame_ok) fail(STN_E_UNSUPPORTED, "lightcone lowering needs Pauli noise and Pauli-rotation gates after the noise");
+    if (p->obs_u.empty()) fail(STN_E_UNSUPPORTED, "lightcone lowering needs an observable");
+    auto* d = new TnDevice();
+    p->lc = d;
+    p->lc_free = [](void* v) { delete static_cast<TnDevice*>(v); };
+    const size_t elem = p->opts.precision == 128 ? 16 : 8;
+    double cost = 0;
+    int width = 0;
+    for (size_t t = 0; t < p->obs_u.size(); ++t) {
+        d->nets.push_back(build_term(p, p->obs_u[t], p->obs_v[t], p->opts.order_restarts, p->opts.order_seed));
+        const TnNetwork& net = d->nets.back();
+        for (auto& st : net.steps)
+            for (auto& in : st.inputs)
+                if ((int)in.pos.size() > kMaxPos) fail(STN_E_UNSUPPORTED, "lightcone step rank above 14");
+        d->arena = std::max(d->arena, net.arena);
+        width = std::max(width, net.width);
+        cost += net.cost;
+    }
+    if ((size_t)d->arena * elem > (size_t)kLdsBytes)
+        fail(STN_E_UNSUPPORTED, "lightcone intermediates exceed the LDS arena (width " + std::to_string(width) + ")");
+    p->width = (uint32_t)width;
+    size_t steps = 0;
+    for (auto& net : d->nets) steps += net.steps.size();
+    p->n_steps = (uint32_t)steps;
+    p->flops_per_traj = 8.0 * cost;             // one complex multiply-add per input per index
+    p->bytes_per_traj = 8.0 * p->obs_u.size();  // per-term result; everything else stays in LDS
+}
+
+void upload_lightcone(stn_plan* p, hipStream_t s) {
+    auto* d = static_cast<TnDevice*>(p->lc);
+    std::vector<TnTerm> terms;
+    std::vector<TnStep> steps;
+    std::vector<TnIn> ins;
+    for (auto& net : d->nets) {
+        TnTerm tm{(int32_t)steps.size(), (int32_t)net.steps.size(), net.result};
+        for (auto& st : net.steps) {
+            TnStep ds{(int32_t)ins.size(), (int32_t)st.inputs.size(), (int32_t)st.out_vars.size(),
+                      st.elim >= 0 ? 1 : 0, st.out_arena};
+            for (auto& in : st.inputs) {
+                TnIn di{};
+                di.kind = in.kind;
+                di.gate = in.gate;
+                di.conj = in.conj;
+                di.arena = in.arena;
+                di.npos = (int32_t)in.pos.size();
+                for (size_t k = 0; k < in.pos.size(); ++k) di.pos[k] = in.pos[k];
+                ins.push_back(di);
+            }
+            steps.push_back(ds);
+        }
+        terms.push_back(tm);
+    }
+    if (ins.empty()) ins.push_back(TnIn{});
+    std::vector<float2> g32(p->gates.size() * 32 + 1);
+    std::vector<double2> g64(p->gates.size() * 32 + 1);
+    for (size_t g = 0; g < p->gates.size(); ++g)
+        for (int sgn = 0; sgn < 2; ++sgn) {
+            cd vals[16];
+            gate_tensor(p->gates[g], sgn, vals);
+            for (int l = 0; l < 16; ++l) {
+                g32[(g * 2 + sgn) * 16 + l] = make_float2((float)vals[l].real(), (float)vals[l].imag());
+                g64[(g * 2 + sgn) * 16 + l] = make_double2(vals[l].real(), vals[l].imag());
+            }
+        }
+    upload(d->terms, &p->alloc, terms.data(), terms.size() * sizeof(TnTerm), s);
+    upload(d->steps, &p->alloc, steps.data(), steps.size() * sizeof(TnStep), s);
+    upload(d->ins, &p->alloc, ins.data(), ins.size() * sizeof(TnIn), s);
+    upload(d->gtab32, &p->alloc, g32.data(), g32.size() * sizeof(float2), s);
+    upload(d->gtab64, &p->alloc, g64.data(), g64.size() * sizeof(double2), s);
+}
+
+void launch_lightcone(stn_plan* p, stn_batch* b, hipStream_t s) {
+    auto* d = static_cast<TnDevice*>(p->lc);
+    const uint32_t T = (uint32_t)d->nets.size();
+    const bool dbl = p->opts.precision == 128;
+    const size_t lds = (size_t)d->arena * (dbl ? 16 : 8);
+    const uint32_t B = std::min<uint32_t>(b->K, 65535);
+    d->zz.ensure(&p->alloc, (size_t)B * T * 8);
+    static bool attr[2] = {false, false};
+    if (!attr[dbl]) {
+        if (dbl) STN_HIP(hipFuncSetAttribute((const void*)k_tn<double>, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes));
+        else STN_HIP(hipFuncSetAttribute((const void*)k_tn<float>, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes));
+        attr[dbl] = true;
+    }
+    double cost = 0;
+    for (auto& net : d->nets) cost += net.cost;
+    for (uint32_t c0 = 0; c0 < b->K; c0 += B) {
+        const uint32_t nb = std::min(B, b->K - c0);
+        prof_begin(p, STN_K_TN_STEP, s);
+        if (dbl)
+            hipLaunchKernelGGL(k_tn<double>, dim3(T, nb), dim3(kTnThreads), lds, s, d->terms.as<TnTerm>(),
+                               d->steps.as<TnStep>(), d->ins.as<TnIn>(), d->gtab64.as<double2>(),
+                               b->d_signs.as<uint32_t>() + (size_t)c0 * b->words, b->words, d->zz.as<double>(), T);
+        else
+            hipLaunchKernelGGL(k_tn<float>, dim3(T, nb), dim3(kTnThreads), lds, s, d->terms.as<TnTerm>(),
+                               d->steps.as<TnStep>(), d->ins.as<TnIn>(), d->gtab32.as<float2>(),
+                               b->d_signs.as<uint32_t>() + (size_t)c0 * b->words, b->words, d->zz.as<double>(), T);
+        STN_HIP(hipGetLastError());
+        prof_end(p, STN_K_TN_STEP, s, (double)nb * T * 8.0, (double)nb * 8.0 * cost);
+        hipLaunchKernelGGL(k_tn_energy, dim3((nb + 63) / 64), dim3(64), 0, s, d->zz.as<double>(), T,
+                           p->d_obs.as<uint32_t>(), p->d_obs_w.as<double>(),
+                           b->d_frame.as<uint64_t>() + 2 * (size_t)c0, nb, b->d_energy.as<double>() + c0);
+        STN_HIP(hipGetLastError());
+    }
+}
+
+}  // namespace stn

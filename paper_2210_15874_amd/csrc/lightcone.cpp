@@ -1,0 +1,318 @@
+// Lightcone tensor-network lowering (host side).
+//
+// The energy of a trajectory is sum_t w_t (1 - f_t <Z_u Z_v>_t) / 2, where
+// <Z_u Z_v> is taken on the noiseless-structure state U(sigma)|0..0> of the
+// Pauli-frame rewrite and f_t = +-1 is the final frame's sign on the term.
+// For each term the planner keeps only the gates in the backward lightcone
+// of {u, v} (the others cancel against their conjugates), builds the doubled
+// network <0|U^dagger Z_u Z_v U|0> as tensors over binary variables (a
+// diagonal gate reuses its qubits' current variables; any other gate opens
+// new ones; the ket and bra chains of a qubit meet in one variable at the
+// observable), orders the variables by min-fill with seeded random tie
+// breaks, and lowers bucket elimination (Sec. III-A: contract the tensors
+// that share the next variable, sum it out, return the result to the pool)
+// into a list of steps.  Every trajectory shares the order and the steps;
+// only the gate values (signs) differ, so the trajectory index is the batch
+// dimension of the contraction kernel (kernels_tn.hip).
+//
+// Intermediates are placed in a per-workgroup arena by a first-fit
+// allocator; networks whose arena fits the LDS budget are contracted
+// entirely in LDS, one workgroup per (trajectory, term).
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <random>
+#include <set>
+
+#include "lightcone.h"
+
+namespace stn {
+
+namespace {
+
+struct Tensor {
+    int kind = TN_GATE;              // TnInputKind
+    int gate = -1;                   // gate index (TN_GATE)
+    int conj = 0;                    // bra side
+    std::vector<int> vars;           // variable ids; local index bit k = vars[k]
+    int arena = -1;                  // offset (TN_INTER)
+};
+
+bool diagonal_kind(uint32_t k) { return k == STN_G_RZ || k == STN_G_Z || k == STN_G_ZZ; }
+
+// min-fill order of the interaction graph; ties broken by degree, then randomly
+std::vector<int> minfill_order(int nv, const std::vector<std::vector<int>>& tensors, std::mt19937_64* rng) {
+    std::vector<std::set<int>> adj(nv);
+    for (auto& t : tensors)
+        for (int a : t)
+            for (int b : t)
+                if (a != b) adj[a].insert(b);
+    std::vector<char> done(nv, 0);
+    std::vector<int> order;
+    for (int it = 0; it < nv; ++it) {
+        long best_fill = -1;
+        int best_deg = 0;
+        std::vector<int> cands;
+        for (int v = 0; v < nv; ++v) {
+            if (done[v]) continue;
+            long fill = 0;
+            const std::vector<int> nb(adj[v].begin(), adj[v].end());
+            for (size_t i = 0; i < nb.size(); ++i)
+                for (size_t j = i + 1; j < nb.size(); ++j)
+                    if (!adj[nb[i]].count(nb[j])) ++fill;
+            const int deg = (int)nb.size();
+            if (best_fill < 0 || fill < best_fill || (fill == best_fill && deg < best_deg)) {
+                best_fill = fill;
+                best_deg = deg;
+                cands.assign(1, v);
+            } else if (fill == best_fill && deg == best_deg) {
+                cands.push_back(v);
+            }
+        }
+        int v = cands[0];
+        if (rng && cands.size() > 1) v = cands[(*rng)() % cands.size()];
+        done[v] = 1;
+        order.push_back(v);
+        const std::vector<int> nb(adj[v].begin(), adj[v].end());
+        for (int a : nb) {
+            adj[a].erase(v);
+            for (int b : nb)
+                if (a != b) adj[a].insert(b);
+        }
+        adj[v].clear();
+    }
+    return order;
+}
+
+// bucket elimination along `order`; fills steps, returns (width, cost)
+struct Lowered {
+    std::vector<TnStepRec> steps;
+    int width = 0;
+    double cost = 0;         // sum over steps of 2^(vars in the step) * inputs
+    int arena = 0;           // complex slots
+    int result = -1;         // final scalar tensor id
+};
+
+Lowered lower(const std::vector<Tensor>& base, int nv, const std::vector<int>& order) {
+    Lowered L;
+    std::vector<Tensor> pool = base;
+    std::vector<char> alive(pool.size(), 1);
+    // arena: first fit over [offset, size) free blocks
+    std::map<int, int> used;  // offset -> size
+    auto alloc = [&](int size) {
+        int off = 0;
+        for (auto& kv : used) {
+            if (kv.first - off >= size) break;
+            off = std::max(off, kv.first + kv.second);
+        }
+        used[off] = size;
+        L.arena = std::max(L.arena, off + size);
+        return off;
+    };
+    auto release = [&](int off) { used.erase(off); };
+    for (int v : order) {
+        std::vector<int> bucket;
+        for (size_t i = 0; i < pool.size(); ++i)
+            if (alive[i] && std::find(pool[i].vars.begin(), pool[i].vars.end(), v) != pool[i].vars.end())
+                bucket.push_back((int)i);
+        if (bucket.empty()) continue;
+        // output variables: union minus v, in first-seen order (largest input first)
+        std::sort(bucket.begin(), bucket.end(),
+                  [&](int a, int b) { return pool[a].vars.size() > pool[b].vars.size(); });
+        std::vector<int> out;
+        for (int i : bucket)
+            for (int x : pool[i].vars)
+                if (x != v && std::find(out.begin(), out.end(), x) == out.end()) out.push_back(x);
+        TnStepRec st;
+        st.elim = v;
+        st.out_vars = out;
+        const int full = (int)out.size() + 1;
+        L.width = std::max(L.width, full);
+        L.cost += std::ldexp(1.0, full) * bucket.size();
+        for (int i : bucket) {
+            TnInputRec in;
+            in.kind = pool[i].kind;
+            in.gate = pool[i].gate;
+            in.conj = pool[i].conj;
+            in.arena = pool[i].arena;
+            // position of each of the input's variables in the step's index space
+            // (output variables at bits 0..|out|-1, the summed variable at |out|)
+            for (int x : pool[i].vars) {
+                const auto it = std::find(out.begin(), out.end(), x);
+                in.pos.push_back(x == v ? (int)out.size() : (int)(it - out.begin()));
+            }
+            st.inputs.push_back(in);
+            alive[i] = 0;
+        }
+        // the output is written while the inputs are read: allocate it first
+        Tensor t;
+        t.kind = TN_INTER;
+        t.vars = out;
+        t.arena = alloc(1 << out.size());
+        for (int i : bucket)
+            if (pool[i].kind == TN_INTER) release(pool[i].arena);
+        st.out_arena = t.arena;
+        pool.push_back(t);
+        alive.push_back(1);
+        L.steps.push_back(st);
+    }
+    // remaining scalars (no variables) multiply into the result
+    TnStepRec fin;
+    fin.elim = -1;
+    for (size_t i = 0; i < pool.size(); ++i)
+        if (alive[i]) {
+            if (!pool[i].vars.empty()) fail(STN_E_INVALID, "tensor left with open indices");
+            TnInputRec in;
+            in.kind = pool[i].kind;
+            in.gate = pool[i].gate;
+            in.conj = pool[i].conj;
+            in.arena = pool[i].arena;
+            fin.inputs.push_back(in);
+        }
+    fin.out_arena = alloc(1);
+    for (auto& in : fin.inputs)
+        if (in.kind == TN_INTER) release(in.arena);
+    L.steps.push_back(fin);
+    L.result = fin.out_arena;
+    (void)nv;
+    return L;
+}
+
+}  // namespace
+
+// Network of one term: lightcone gates on the ket, the observable, the
+// conjugate gates on the bra, |0> at both ends of every chain.
+TnNetwork build_term(const stn_plan* p, uint32_t u, uint32_t v, uint32_t restarts, uint64_t seed) {
+    const uint32_t n = p->n;
+    // backward lightcone of {u, v}
+    std::vector<char> in_cone(p->gates.size(), 0);
+    uint64_t S = (1ull << u) | (1ull << v);
+    for (size_t gi = p->gates.size(); gi-- > 0;) {
+        const GateRec& g = p->gates[gi];
+        const uint64_t qm = (1ull << g.q0) | (g.nq == 2 ? (1ull << g.q1) : 0);
+        if (S & qm) {
+            in_cone[gi] = 1;
+            S |= qm;
+        }
+    }
+    // ket chain
+    int nv = 0;
+    std::vector<int> cur(n, -1), first(n, -1);
+    std::vector<Tensor> ts;
+    auto var_of = [&](uint32_t q) {
+        if (cur[q] < 0) {
+            cur[q] = first[q] = nv++;
+        }
+        return cur[q];
+    };
+    std::vector<int> cone_gates;
+    for (size_t gi = 0; gi < p->gates.size(); ++gi)
+        if (in_cone[gi]) cone_gates.push_back((int)gi);
+    auto add_gate = [&](int gi, int conj, std::vector<int>& curv, std::vector<int>& firstv) {
+        const GateRec& g = p->gates[gi];
+        auto v_of = [&](uint32_t q) {
+            if (curv[q] < 0) curv[q] = firstv[q] = nv++;
+            return curv[q];
+        };
+        Tensor t;
+        t.kind = TN_GATE;
+        t.gate = gi;
+        t.conj = conj;
+        if (diagonal_kind(g.kind)) {
+            t.vars.push_back(v_of(g.q0));
+            if (g.nq == 2) t.vars.push_back(v_of(g.q1));
+        } else if (g.nq == 1) {
+            // local index bit 0 = input variable, bit 1 = output variable
+            const int in = v_of(g.q0);
+            const int out = nv++;
+            curv[g.q0] = out;
+            t.vars = {in, out};
+        } else {
+            const int in0 = v_of(g.q0), in1 = v_of(g.q1);
+            const int o0 = nv++, o1 = nv++;
+            curv[g.q0] = o0;
+            curv[g.q1] = o1;
+            t.vars = {in0, in1, o0, o1};
+        }
+        ts.push_back(t);
+    };
+    (void)var_of;
+    for (int gi : cone_gates) add_gate(gi, 0, cur, first);
+    // observable on the final ket variables, shared with the bra
+    {
+        std::vector<int> dummy;
+        Tensor o;
+        o.kind = TN_OBS;
+        if (cur[u] < 0) cur[u] = first[u] = nv++;
+        if (cur[v] < 0) cur[v] = first[v] = nv++;
+        o.vars = {cur[u], cur[v]};
+        ts.push_back(o);
+    }
+    // bra chain, walked backward from the shared final variables
+    std::vector<int> bcur = cur, bfirst(n, -1);
+    for (size_t k = cone_gates.size(); k-- > 0;) {
+        const GateRec& g = p->gates[cone_gates[k]];
+        Tensor t;
+        t.kind = TN_GATE;
+        t.gate = cone_gates[k];
+        t.conj = 1;
+        if (diagonal_kind(g.kind)) {
+            t.vars.push_back(bcur[g.q0]);
+            if (g.nq == 2) t.vars.push_back(bcur[g.q1]);
+        } else if (g.nq == 1) {
+            const int out = bcur[g.q0];  // the gate's output side is later in time
+            const int in = nv++;
+            bcur[g.q0] = in;
+            t.vars = {in, out};
+        } else {
+            const int o0 = bcur[g.q0], o1 = bcur[g.q1];
+            const int i0 = nv++, i1 = nv++;
+            bcur[g.q0] = i0;
+            bcur[g.q1] = i1;
+            t.vars = {i0, i1, o0, o1};
+        }
+        ts.push_back(t);
+    }
+    // |0> at the start of both chains of every qubit that appears
+    for (uint32_t q = 0; q < n; ++q) {
+        if (first[q] >= 0) {
+            Tensor z;
+            z.kind = TN_ZERO;
+            z.vars = {first[q]};
+            ts.push_back(z);
+        }
+        if (cur[q] >= 0 && bcur[q] >= 0 && bcur[q] != first[q]) {
+            Tensor z;
+            z.kind = TN_ZERO;
+            z.vars = {bcur[q]};
+            ts.push_back(z);
+        } else if (cur[q] >= 0 && bcur[q] == first[q] && first[q] >= 0) {
+            // qubit with no non-diagonal gate: ket and bra start share one variable
+        }
+    }
+    std::vector<std::vector<int>> tv;
+    for (auto& t : ts) tv.push_back(t.vars);
+    TnNetwork net;
+    net.u = u;
+    net.v = v;
+    net.n_vars = nv;
+    Lowered best;
+    bool have = false;
+    std::mt19937_64 rng(seed ^ (0x9E3779B97F4A7C15ull * (u * 131 + v)));
+    for (uint32_t r = 0; r <= restarts; ++r) {
+        const std::vector<int> order = minfill_order(nv, tv, r == 0 ? nullptr : &rng);
+        Lowered L = lower(ts, nv, order);
+        if (!have || L.width < best.width || (L.width == best.width && L.cost < best.cost)) {
+            best = std::move(L);
+            have = true;
+        }
+    }
+    net.steps = std::move(best.steps);
+    net.width = best.width;
+    net.cost = best.cost;
+    net.arena = best.arena;
+    net.result = best.result;
+    return net;
+}
+
+}  // namespace stn

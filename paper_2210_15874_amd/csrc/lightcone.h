@@ -1,0 +1,43 @@
+// Lightcone tensor-network lowering: host records shared by the planner
+// (lightcone.cpp) and the contraction kernel (kernels_tn.hip).
+#pragma once
+
+#include "stn_internal.h"
+
+namespace stn {
+
+enum TnInputKind : int32_t {
+    TN_GATE = 0,     // a circuit gate's tensor (values from the gate and the trajectory's sign)
+    TN_OBS = 1,      // Z_u Z_v on the two shared final variables
+    TN_ZERO = 2,     // |0> at the start of a chain
+    TN_INTER = 3     // an intermediate result in the arena
+};
+
+struct TnInputRec {
+    int kind = TN_GATE;
+    int gate = -1;
+    int conj = 0;
+    int arena = -1;
+    std::vector<int> pos;   // local index bit k of the input = bit pos[k] of the step's index
+};
+
+struct TnStepRec {
+    int elim = -1;                 // summed variable (-1: the final product of scalars)
+    std::vector<int> out_vars;
+    std::vector<TnInputRec> inputs;
+    int out_arena = -1;
+};
+
+struct TnNetwork {
+    uint32_t u = 0, v = 0;
+    int n_vars = 0;
+    int width = 0;                 // largest step index space (output rank + 1)
+    double cost = 0;               // sum over steps of 2^width(step) * inputs
+    int arena = 0;                 // complex slots of intermediates
+    int result = -1;               // arena slot of the final scalar
+    std::vector<TnStepRec> steps;
+};
+
+TnNetwork build_term(const stn_plan* p, uint32_t u, uint32_t v, uint32_t restarts, uint64_t seed);
+
+}  // namespace stn

@@ -517,10 +517,44 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
     std::string why;
     uint32_t kind = p->opts.plan_kind;
     if (kind == STN_PLAN_AUTO) {
-        if (n <= lds_max) kind = STN_PLAN_SV_LDS;
-        else if (dense_out) fail(STN_E_UNSUPPORTED, "density-matrix / state outputs need n <= " + std::to_string(lds_max));
-        else if (build_tiled(p, why)) kind = STN_PLAN_SV_TILED;
-        else fail(STN_E_UNSUPPORTED, "no lowering for this circuit: " + why);
+        if (n <= lds_max) {
+            kind = STN_PLAN_SV_LDS;
+        } else if (dense_out) {
+            fail(STN_E_UNSUPPORTED, "density-matrix / state outputs need n <= " + std::to_string(lds_max));
+        } else {
+            // statevector passes vs lightcone networks: estimated seconds per trajectory
+            // (HBM-bound passes at ~4 TB/s; LDS-resident contraction at ~1e12 complex MACs/s)
+            double sv_t = -1, tn_t = -1;
+            if (n >= 14 && p->opts.precision == 64 && build_tiled(p, why)) {
+                schedule_tiled(p, 14, 2);
+                double bytes = 0;
+                for (auto& ps : p->passes) bytes += std::ldexp(8.0, (int)n) * ((ps.init ? 0 : 1) + (ps.last ? 0 : 1));
+                sv_t = bytes / 4e12;
+            }
+            try {
+                build_lightcone(p);
+                tn_t = p->flops_per_traj / 8.0 / 1e12;
+            } catch (const Error& e) {
+                if (e.status != STN_E_UNSUPPORTED) throw;
+                if (why.empty()) why = e.msg;
+                else why += "; " + e.msg;
+            }
+            if (tn_t >= 0 && (sv_t < 0 || tn_t < sv_t)) kind = STN_PLAN_LIGHTCONE;
+            else if (sv_t >= 0) kind = STN_PLAN_SV_TILED;
+            else fail(STN_E_UNSUPPORTED, "no lowering for this circuit: " + why);
+            if (kind != STN_PLAN_LIGHTCONE && p->lc && p->lc_free) {
+                p->lc_free(p->lc);
+                p->lc = nullptr;
+            }
+            if (kind == STN_PLAN_LIGHTCONE) {
+                // the networks use the gates as given: undo the tiled rewrite
+                for (auto& g : p->gates) {
+                    g.det_x = 0;
+                    g.theta_eff = g.theta;
+                }
+                p->passes.clear();
+            }
+        }
     }
     if (kind == STN_PLAN_SV_LDS) {
         if (n > lds_max) fail(STN_E_UNSUPPORTED, "whole-state-in-LDS lowering needs n <= " + std::to_string(lds_max));
@@ -532,7 +566,8 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
         if (p->opts.precision == 128) fail(STN_E_UNSUPPORTED, "the tiled lowering is complex64 only");
         schedule_tiled(p, 14, 2);
     } else if (kind == STN_PLAN_LIGHTCONE) {
-        fail(STN_E_UNSUPPORTED, "lightcone lowering not available");
+        if (dense_out) fail(STN_E_UNSUPPORTED, "the lightcone lowering produces energies only");
+        if (!p->lc) build_lightcone(p);
     } else {
         fail(STN_E_INVALID, "unknown plan kind");
     }
@@ -550,6 +585,10 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
         const double budget = p->opts.hbm_budget ? (double)p->opts.hbm_budget : 64.0 * (1ull << 30);
         p->max_batch = p->opts.max_batch ? p->opts.max_batch : (uint32_t)std::min(65535.0, std::max(1.0, budget / per));
         p->peak_bytes = per * p->max_batch;
+    } else if (kind == STN_PLAN_LIGHTCONE) {
+        // width / steps / flops / bytes set by build_lightcone
+        p->max_batch = p->opts.max_batch ? p->opts.max_batch : 65535;
+        p->peak_bytes = (double)p->max_batch * (p->obs_u.size() * 8.0 + 64.0 + p->sites.size());
     } else {
         p->width = n;
         p->n_passes = (uint32_t)p->passes.size();

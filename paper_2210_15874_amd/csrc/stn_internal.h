@@ -242,4 +242,7 @@ void launch_energy_stats(stn_accum* a, uint64_t K, hipStream_t s);
 // rho_out = mirror(rho)/K, diag_out = diag/K, stats[2] = trace
 void launch_finish_dense(stn_accum* a, hipStream_t s);
 void launch_lightcone(stn_plan* p, stn_batch* b, hipStream_t s);
+// lightcone lowering (kernels_tn.hip): networks of every observable term
+void build_lightcone(stn_plan* p);
+void upload_lightcone(stn_plan* p, hipStream_t s);
 }  // namespace stn

@@ -10,6 +10,8 @@ states only up to a global phase (the Pauli-frame rewrite and the dropped
 phase of Y change it), via |<a|b>|.
 """
 import itertools
+import os
+import sys
 import math
 
 import numpy as np
@@ -18,6 +20,7 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -223,3 +226,102 @@ def test_reduce_same_range_twice_rejected():
     with pytest.raises(stn.StnError, match="already reduced"):
         pl.reduce(b, acc)
     assert acc.read()["k_done"] == 10
+
+
+# ----------------------------------------------------------------------------- lightcone networks
+
+@pytest.mark.parametrize("precision,tol", [(64, 1e-5), (128, 1e-11)])
+@pytest.mark.parametrize("n,p,K,lam", [(14, 1, 24, (0.05, 0.2)), (16, 2, 12, (0.02, 0.1)), (15, 2, 16, (1e-3, 1e-2))])
+def test_lightcone_energies_same_draws(n, p, K, lam, precision, tol):
+    """Per-edge lightcone networks (min-fill bucket elimination, Pauli frame)
+    against the full-statevector oracle with literal Kraus insertion."""
+    from oracle import simulate as sim
+    from workloads import erdos_renyi_graph, make_problem, uniform_angles
+    stn = stn_mod()
+    if n == 15:
+        edges = erdos_renyi_graph(n, 3.0 / (n - 1), 77)
+        g, b = uniform_angles(p, 78)
+        pr = make_problem(n, edges, g, b, lam[0], lam[1], K, 79)
+    else:
+        pr = qaoa(n, p, 300 + n + p, lam[0], lam[1], K)
+    pl = stn.Plan(pr, plan_kind=stn.PLAN_LIGHTCONE, precision=precision)
+    info = pl.info()
+    assert info["plan_name"] == "lightcone" and info["width"] <= 14
+    b = pl.sample(pr.seed, 0, K)
+    pl.contract(b)
+    got = b.energies()
+    ens = sim.ensemble(pr, pr.seed, 0, K, want_states=False)
+    m = max(1, len(pr.edges))
+    np.testing.assert_allclose(got / m, ens["energies"] / m, atol=tol)
+
+
+def test_lightcone_matches_tiled_statevector():
+    stn = stn_mod()
+    pr = qaoa(20, 2, 41, 0.01, 0.05, 32)
+    res = {}
+    for kind in (stn.PLAN_LIGHTCONE, stn.PLAN_SV_TILED):
+        pl = stn.Plan(pr, plan_kind=kind)
+        b = pl.sample(pr.seed, 0, pr.K)
+        pl.contract(b)
+        res[kind] = b.energies()
+    np.testing.assert_allclose(res[stn.PLAN_LIGHTCONE] / len(pr.edges), res[stn.PLAN_SV_TILED] / len(pr.edges),
+                               atol=2e-5)
+
+
+@pytest.mark.parametrize("n,precision,tol", [(40, 64, 1e-5), (64, 128, 1e-10)])
+def test_lightcone_noiseless_p1_closed_form_large_n(n, precision, tol):
+    """n beyond any statevector: the noiseless p=1 energy against the closed
+    form of Wang, Hadfield, Jiang and Rieffel (PRA 97, 022304)."""
+    from test_oracle_density import closed_form_energy
+    from workloads import make_problem, random_regular_graph
+    stn = stn_mod()
+    edges = random_regular_graph(n, 3, 500 + n)
+    gamma, beta = 0.83, 2.41
+    pr = make_problem(n, edges, [gamma], [beta], 0.0, 0.0, 4, 1)
+    pl = stn.Plan(pr, precision=precision)
+    assert pl.info()["plan_name"] == "lightcone"
+    acc = pl.accum()
+    b = pl.sample(pr.seed, 0, 4)
+    pl.contract(b)
+    pl.reduce(b, acc)
+    r = acc.read()
+    exact = closed_form_energy(n, pr.edges, gamma, beta)
+    assert abs(r["energy_mean"] - exact) / len(pr.edges) < tol
+    assert r["energy_se"] < 1e-9
+
+
+# ----------------------------------------------------------------------------- full-size workload
+
+def test_full_size_workload_sampled_trajectories():
+    """n=26, p=4, K=4096 in the launch configuration the benchmark times
+    (trajectories per launch from a 160 GiB budget): sampled trajectories
+    against stored oracle values (complex128, literal Kraus insertion, same
+    draws), plus properties that hold at any size."""
+    import json
+    from workloads import config_problem
+    stn = stn_mod()
+    here = os.path.dirname(os.path.abspath(__file__))
+    with open(os.path.join(here, "golden", "config2_sampled.json")) as f:
+        gold = json.load(f)
+    pr = config_problem(2)
+    assert [list(e) for e in pr.edges] == gold["edges"]
+    m = len(pr.edges)
+    pl = stn.Plan(pr, outputs=stn.OUT_ENERGY, precision=64, hbm_budget=160 << 30)
+    info = pl.info()
+    assert info["plan_name"] == "sv_tiled"
+    B = info["max_batch"]
+    acc = pl.accum()
+    for k0 in range(0, pr.K, B):
+        b = pl.sample(pr.seed, k0, min(B, pr.K - k0))
+        pl.contract(b)
+        pl.reduce(b, acc)
+        b.close()
+    r = acc.read()
+    e = np.asarray(r["energies"])
+    assert e.shape == (pr.K,)
+    for row in gold["trajectories"]:
+        assert abs(e[row["k"]] - row["energy"]) / m < 1e-5, row["k"]
+    # any trajectory: 0 <= <C>_k <= m; the mean is the mean of the samples
+    assert np.all(e >= -1e-4) and np.all(e <= m + 1e-4)
+    assert abs(r["energy_mean"] - e.mean()) < 1e-9 * m
+    assert abs(r["energy_se"] - e.std(ddof=1) / math.sqrt(pr.K)) < 1e-9 * m
