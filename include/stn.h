@@ -268,6 +268,88 @@ stn_status stn_reduce(stn_plan* plan, stn_batch* batch, stn_accum* acc, void* st
 stn_status stn_accum_read(stn_accum* acc, stn_result* out, void* stream);
 void stn_accum_destroy(stn_accum* acc);
 
+/* ---------------------------------------------------------------- job server
+ * Many ensemble jobs (Sec. III-G, each one circuit + noise model + K) of
+ * different sizes on one device at once.  A planner thread plans submitted
+ * jobs on the host (reusing cached plans of identical inputs); a device
+ * thread admits planned jobs in arrival order while their estimated device
+ * memory fits hbm_budget (a job of at most 1/32 of the budget may go ahead of
+ * a larger one that does not fit yet), gives each a stream, and issues their
+ * trajectories in chunks (sample -> contract -> reduce), round-robin over the
+ * admitted jobs, so that jobs arriving while others run share the device
+ * with them.  A job's result depends only on its inputs, seed and K: it is
+ * the same (bit for bit) alone and in any mix.
+ *
+ * Device memory is taken from a caching pool over hipMalloc, bounded by
+ * hbm_budget; plans and accumulators stay on the device while their job runs.
+ * Only <C> jobs (an observable, ENERGY output) are served.
+ */
+typedef struct stn_server stn_server;
+
+typedef struct {
+    uint64_t hbm_budget;     /* device bytes the server may hold (>= 64 MiB) */
+    double job_share;        /* largest fraction of the budget one job's chunk may use, (0, 1] */
+    uint32_t n_streams;      /* device streams jobs are spread over, 1..8 */
+    uint32_t max_active;     /* jobs admitted at once, 1..64 */
+    uint32_t plan_cache;     /* idle plans kept for jobs with identical inputs (0: none) */
+    uint32_t precision;      /* 64 (complex64) or 128 (complex128) for every job */
+    uint32_t chunk_max;      /* trajectories per chunk cap (0: the plan's max batch) */
+    uint32_t drain_on_destroy; /* 1: stn_server_destroy waits for every submitted job */
+} stn_server_opts;
+
+typedef struct {
+    uint64_t job_id;         /* as returned by stn_server_submit */
+    uint64_t tag;            /* the caller's tag */
+    uint32_t status;         /* stn_status of the job (planning or device failure) */
+    uint32_t plan_kind;      /* lowering used */
+    uint32_t width;          /* its contraction width */
+    uint32_t chunk;          /* trajectories per chunk */
+    uint64_t K, k_done;
+    uint64_t chunks;         /* chunks issued */
+    double energy_mean;      /* <C>_hat over k = 0 .. K-1 */
+    double energy_se;        /* std(<C>_k, ddof=1)/sqrt(K) */
+    double t_submit;         /* seconds on the server clock (stn_server_clock) */
+    double t_admit;
+    double t_done;
+    char error[96];          /* message when status != STN_OK */
+} stn_job_result;
+
+typedef struct {
+    uint64_t submitted, completed, failed;
+    uint64_t active;         /* jobs admitted and not finished */
+    uint64_t waiting;        /* jobs submitted and not admitted */
+    uint64_t trajectories;   /* trajectories of completed jobs */
+    uint64_t chunks;         /* chunks issued */
+    uint64_t max_active_jobs;/* most jobs admitted at the same time */
+    uint64_t plan_cache_hits, plan_cache_misses, plans_cached;
+    uint64_t bytes_in_use, bytes_cached, bytes_peak;   /* device pool */
+    double clock;            /* server clock when read */
+} stn_server_stats;
+
+/* Defaults: 64 GiB budget, job_share 0.5, 4 streams, 16 active jobs, 64
+ * cached plans, complex64, drain on destroy. */
+void stn_server_opts_default(stn_server_opts* opts);
+/* Starts the server's threads on the calling thread's current device. */
+stn_status stn_server_create(const stn_server_opts* opts, stn_server** out);
+/* Queues a job (inputs are copied; returns at once).  The job's draws are
+ * those of stn_sample(plan, seed, 0, K).  observable is required. */
+stn_status stn_server_submit(stn_server* server, const stn_circuit* circuit, const stn_noise_model* noise,
+                             const stn_observable* observable, uint64_t seed, uint64_t K, uint64_t tag,
+                             uint64_t* job_id);
+/* Moves up to cap finished jobs' results to out (completion order), waiting
+ * up to wait_s seconds for the first one when none is ready. */
+stn_status stn_server_poll(stn_server* server, stn_job_result* out, uint32_t cap, uint32_t* n_out, double wait_s);
+/* Waits until every submitted job has finished (STN_E_STATE on timeout). */
+stn_status stn_server_drain(stn_server* server, double timeout_s);
+stn_status stn_server_stats_read(stn_server* server, stn_server_stats* out);
+/* Seconds since the server was created (the clock of t_submit / t_done). */
+double stn_server_clock(const stn_server* server);
+/* Message of the last non-OK status of a stn_server_* call on this thread. */
+const char* stn_server_last_error(void);
+/* Stops the threads (after draining, when drain_on_destroy) and frees the
+ * server, its cached plans and its device pool. */
+void stn_server_destroy(stn_server* server);
+
 #ifdef __cplusplus
 }
 #endif

@@ -86,6 +86,28 @@ class Result(C.Structure):
                 ("energies", C.POINTER(C.c_double))]
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("hbm_budget", C.c_uint64), ("job_share", C.c_double), ("n_streams", C.c_uint32),
+                ("max_active", C.c_uint32), ("plan_cache", C.c_uint32), ("precision", C.c_uint32),
+                ("chunk_max", C.c_uint32), ("drain_on_destroy", C.c_uint32)]
+
+
+class JobResult(C.Structure):
+    _fields_ = [("job_id", C.c_uint64), ("tag", C.c_uint64), ("status", C.c_uint32), ("plan_kind", C.c_uint32),
+                ("width", C.c_uint32), ("chunk", C.c_uint32), ("K", C.c_uint64), ("k_done", C.c_uint64),
+                ("chunks", C.c_uint64), ("energy_mean", C.c_double), ("energy_se", C.c_double),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+                ("error", C.c_char * 96)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("failed", C.c_uint64),
+                ("active", C.c_uint64), ("waiting", C.c_uint64), ("trajectories", C.c_uint64),
+                ("chunks", C.c_uint64), ("max_active_jobs", C.c_uint64), ("plan_cache_hits", C.c_uint64),
+                ("plan_cache_misses", C.c_uint64), ("plans_cached", C.c_uint64), ("bytes_in_use", C.c_uint64),
+                ("bytes_cached", C.c_uint64), ("bytes_peak", C.c_uint64), ("clock", C.c_double)]
+
+
 EXPORTS = {
     "stn_version": (C.c_char_p, []),
     "stn_last_error": (C.c_char_p, []),
@@ -109,6 +131,16 @@ EXPORTS = {
     "stn_reduce": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "stn_accum_read": (C.c_int, [C.c_void_p, C.POINTER(Result), C.c_void_p]),
     "stn_accum_destroy": (None, [C.c_void_p]),
+    "stn_server_opts_default": (None, [C.POINTER(ServerOpts)]),
+    "stn_server_create": (C.c_int, [C.POINTER(ServerOpts), C.POINTER(C.c_void_p)]),
+    "stn_server_submit": (C.c_int, [C.c_void_p, C.POINTER(Circuit), C.POINTER(NoiseModel), C.POINTER(Observable),
+                                    C.c_uint64, C.c_uint64, C.c_uint64, C.POINTER(C.c_uint64)]),
+    "stn_server_poll": (C.c_int, [C.c_void_p, C.POINTER(JobResult), C.c_uint32, C.POINTER(C.c_uint32), C.c_double]),
+    "stn_server_drain": (C.c_int, [C.c_void_p, C.c_double]),
+    "stn_server_stats_read": (C.c_int, [C.c_void_p, C.POINTER(ServerStats)]),
+    "stn_server_clock": (C.c_double, [C.c_void_p]),
+    "stn_server_last_error": (C.c_char_p, []),
+    "stn_server_destroy": (None, [C.c_void_p]),
 }
 
 _lib = None
@@ -368,3 +400,81 @@ def simulate_batch_ensemble(problem, K=None, seed=None, outputs=OUT_ENERGY, prec
     res = acc.read()
     acc.close()
     return res
+
+
+def _check_srv(st):
+    if st != 0:
+        raise StnError(st, _lib.stn_server_last_error().decode())
+
+
+class Server:
+    """stn_server_*: many <C> jobs of different circuits on one device, with
+    continuous batching (jobs are admitted as device memory frees up and their
+    chunks interleave).  Device memory comes from the server's own pool, not
+    PyTorch's allocator; hbm_budget bounds it."""
+
+    def __init__(self, hbm_budget=64 << 30, job_share=0.5, n_streams=4, max_active=16, plan_cache=64,
+                 precision=64, chunk_max=0, drain_on_destroy=True):
+        self.lib = load()
+        o = ServerOpts()
+        self.lib.stn_server_opts_default(C.byref(o))
+        o.hbm_budget = int(hbm_budget)
+        o.job_share = float(job_share)
+        o.n_streams = n_streams
+        o.max_active = max_active
+        o.plan_cache = plan_cache
+        o.precision = precision
+        o.chunk_max = chunk_max
+        o.drain_on_destroy = 1 if drain_on_destroy else 0
+        h = C.c_void_p()
+        _check_srv(self.lib.stn_server_create(C.byref(o), C.byref(h)))
+        self.h = h
+
+    def submit(self, problem, seed=None, K=None, tag=0):
+        circ, noise, obs, keep = _problem_structs(problem, True)
+        jid = C.c_uint64()
+        _check_srv(self.lib.stn_server_submit(self.h, C.byref(circ), C.byref(noise), C.byref(obs),
+                                              int(problem.seed if seed is None else seed),
+                                              int(problem.K if K is None else K), int(tag), C.byref(jid)))
+        return jid.value
+
+    def poll(self, wait=0.0, cap=256):
+        arr = (JobResult * cap)()
+        n = C.c_uint32()
+        _check_srv(self.lib.stn_server_poll(self.h, arr, cap, C.byref(n), float(wait)))
+        out = []
+        for i in range(n.value):
+            r = arr[i]
+            d = {f: getattr(r, f) for f, _ in JobResult._fields_ if f != "error"}
+            d["error"] = r.error.decode(errors="replace")
+            d["plan_name"] = PLAN_NAMES.get(d["plan_kind"], "?")
+            out.append(d)
+        return out
+
+    def drain(self, timeout=3600.0):
+        _check_srv(self.lib.stn_server_drain(self.h, float(timeout)))
+
+    def stats(self):
+        s = ServerStats()
+        _check_srv(self.lib.stn_server_stats_read(self.h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def clock(self):
+        return self.lib.stn_server_clock(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.stn_server_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

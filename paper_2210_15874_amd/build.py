@@ -32,9 +32,11 @@ SOURCES = {
     "kernels_sample.hip": "device",
     "kernels_sv_lds.hip": "device",
     "kernels_sv_tiled.hip": "device",
+    "kernels_sv_tiled128.hip": "device",
     "kernels_reduce.hip": "device",
     "kernels_tn.hip": "device",
     "lightcone.cpp": "host",
+    "server.cpp": "host",
 }
 
 
@@ -69,7 +71,7 @@ def build_library(verbose=False):
             if msg:
                 print(f"[{src}]\n{msg}", file=sys.stderr)
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-pthread", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -124,12 +124,58 @@ void prof_clear(stn_plan* p) {
 }  // namespace stn
 
 stn_plan::~stn_plan() {
+    // device buffers may still be read by enqueued kernels unless the owner
+    // has already waited for them (the job server does)
+    if (sync_on_destroy) (void)hipDeviceSynchronize();
     if (lc && lc_free) lc_free(lc);
     if (tiled && tiled_free) tiled_free(tiled);
-    (void)hipDeviceSynchronize();
     stn::prof_clear(this);
     for (auto e : ev_pool) (void)hipEventDestroy(e);
 }
+
+namespace stn {
+
+// Stream-ordered end of a job's energy reduction: the per-trajectory
+// energies gathered in trajectory order, then the fixed-order mean and
+// standard error into d_stats[0..1].  Enqueues only.
+void accum_finish_energy(stn_accum* a, hipStream_t s) {
+    stn_plan* p = a->plan;
+    a->d_stats.ensure(&p->alloc, 4 * 8);
+    STN_HIP(hipMemsetAsync(a->d_stats.p, 0, 4 * 8, s));
+    if (!(p->opts.outputs & STN_OUT_ENERGY) || !a->k_done) return;
+    a->d_egather.ensure(&p->alloc, a->k_done * 8);
+    std::sort(a->ranges.begin(), a->ranges.end());
+    uint64_t pos = 0;
+    for (auto& r : a->ranges) {
+        uint64_t k = r.first;
+        while (k < r.second) {
+            const uint64_t c = k / kEnergyChunk, stop = std::min<uint64_t>(r.second, (c + 1) * kEnergyChunk);
+            STN_HIP(hipMemcpyAsync(a->d_egather.as<double>() + pos, a->e_chunks[c].as<double>() + (k % kEnergyChunk),
+                                   (stop - k) * 8, hipMemcpyDeviceToDevice, s));
+            pos += stop - k;
+            k = stop;
+        }
+    }
+    launch_energy_stats(a, a->k_done, s);
+}
+
+// (Re)shapes a batch for trajectories k0 .. k0+K-1 of plan p; buffers only grow.
+void batch_prepare(stn_plan* p, stn_batch* b, uint64_t k0, uint32_t K) {
+    const size_t S = p->sites.size();
+    b->plan = p;
+    b->k0 = k0;
+    b->K = K;
+    b->contracted = false;
+    b->words = (uint32_t)((p->gates.size() + 31) / 32);
+    b->d_idx.ensure(&p->alloc, (size_t)K * S);
+    if (p->kind != STN_PLAN_SV_LDS) {
+        b->d_signs.ensure(&p->alloc, (size_t)K * std::max<uint32_t>(b->words, 1) * 4);
+        b->d_frame.ensure(&p->alloc, (size_t)K * 16);
+    }
+    b->d_energy.ensure(&p->alloc, (size_t)K * 8);
+}
+
+}  // namespace stn
 
 extern "C" {
 
@@ -228,19 +274,6 @@ stn_status stn_plan_site(const stn_plan* p, uint32_t site, uint32_t* n_ops, uint
     return STN_OK;
 }
 
-static void batch_alloc(stn_plan* p, stn_batch* b, uint32_t K) {
-    const size_t S = p->sites.size();
-    b->plan = p;
-    b->K = K;
-    b->words = (uint32_t)((p->gates.size() + 31) / 32);
-    b->d_idx.ensure(&p->alloc, (size_t)K * S);
-    if (p->kind != STN_PLAN_SV_LDS) {
-        b->d_signs.ensure(&p->alloc, (size_t)K * std::max<uint32_t>(b->words, 1) * 4);
-        b->d_frame.ensure(&p->alloc, (size_t)K * 16);
-    }
-    b->d_energy.ensure(&p->alloc, (size_t)K * 8);
-}
-
 stn_status stn_sample(stn_plan* p, uint64_t seed, uint64_t k0, uint32_t K, stn_batch** out, void* stream) {
     if (!p || !out) return set_error(STN_E_INVALID, "NULL argument");
     *out = nullptr;
@@ -248,8 +281,7 @@ stn_status stn_sample(stn_plan* p, uint64_t seed, uint64_t k0, uint32_t K, stn_b
     stn_batch* b = nullptr;
     stn_status st = guarded([&] {
         b = new stn_batch();
-        b->k0 = k0;
-        batch_alloc(p, b, K);
+        batch_prepare(p, b, k0, K);
         hipStream_t s = (hipStream_t)stream;
         ensure_uploaded(p, s);
         launch_sample(p, b, seed, s);
@@ -279,8 +311,7 @@ stn_status stn_batch_from_indices(stn_plan* p, const uint8_t* idx, uint64_t k0, 
         hipStream_t s = (hipStream_t)stream;
         ensure_uploaded(p, s);
         b = new stn_batch();
-        b->k0 = k0;
-        batch_alloc(p, b, K);
+        batch_prepare(p, b, k0, K);
         if (S) STN_HIP(hipMemcpyAsync(b->d_idx.p, idx, (size_t)K * S, hipMemcpyHostToDevice, s));
         if (p->kind != STN_PLAN_SV_LDS) launch_frame(p, b, s);
         STN_HIP(hipStreamSynchronize(s));
@@ -310,7 +341,10 @@ stn_status stn_contract(stn_plan* p, stn_batch* b, void* stream) {
         ensure_uploaded(p, s);
         switch (p->kind) {
             case STN_PLAN_SV_LDS: launch_sv_lds(p, b, s); break;
-            case STN_PLAN_SV_TILED: launch_sv_tiled(p, b, s); break;
+            case STN_PLAN_SV_TILED:
+                if (p->opts.precision == 128) launch_sv_tiled128(p, b, s);
+                else launch_sv_tiled(p, b, s);
+                break;
             case STN_PLAN_LIGHTCONE: launch_lightcone(p, b, s); break;
             default: fail(STN_E_STATE, "plan has no lowering");
         }
@@ -404,24 +438,8 @@ stn_status stn_accum_read(stn_accum* a, stn_result* out, void* stream) {
         const size_t N = (size_t)1 << p->n;
         out->k_done = a->k_done;
         double st[4] = {0, 0, 0, 0};
-        a->d_stats.ensure(&p->alloc, 4 * 8);
-        STN_HIP(hipMemsetAsync(a->d_stats.p, 0, 4 * 8, s));
+        accum_finish_energy(a, s);
         if ((p->opts.outputs & STN_OUT_ENERGY) && a->k_done) {
-            // gather the energies in trajectory order, then fixed-order statistics
-            a->d_egather.ensure(&p->alloc, a->k_done * 8);
-            std::sort(a->ranges.begin(), a->ranges.end());
-            uint64_t pos = 0;
-            for (auto& r : a->ranges) {
-                uint64_t k = r.first;
-                while (k < r.second) {
-                    const uint64_t c = k / kEnergyChunk, stop = std::min<uint64_t>(r.second, (c + 1) * kEnergyChunk);
-                    STN_HIP(hipMemcpyAsync(a->d_egather.as<double>() + pos, a->e_chunks[c].as<double>() + (k % kEnergyChunk),
-                                           (stop - k) * 8, hipMemcpyDeviceToDevice, s));
-                    pos += stop - k;
-                    k = stop;
-                }
-            }
-            launch_energy_stats(a, a->k_done, s);
             a->h_energies.resize(a->k_done);
             STN_HIP(hipMemcpyAsync(a->h_energies.data(), a->d_egather.p, a->k_done * 8, hipMemcpyDeviceToHost, s));
             out->energies = a->h_energies.data();

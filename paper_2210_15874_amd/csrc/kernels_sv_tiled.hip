@@ -592,6 +592,25 @@ struct TiledDevice {
 
 }  // namespace
 
+void upload_tiled(stn_plan* p, hipStream_t s) {
+    if (p->tiled) return;
+    auto* d = new TiledDevice();
+    p->tiled = d;
+    p->tiled_free = [](void* v) { delete static_cast<TiledDevice*>(v); };
+    d->t = build_tables(p);
+    std::vector<float2> ph32;
+    for (auto& c : d->t.phase) ph32.push_back(make_float2((float)c.real(), (float)c.imag()));
+    if (d->t.dedges.empty()) d->t.dedges.push_back(int4{0, 0, 0, 0});
+    if (ph32.empty()) ph32.push_back(make_float2(0.f, 0.f));
+    if (d->t.eedges.empty()) d->t.eedges.push_back(int2{0, 0});
+    if (d->t.ew.empty()) d->t.ew.push_back(0.0);
+    upload(d->dedges, &p->alloc, d->t.dedges.data(), d->t.dedges.size() * sizeof(int4), s);
+    upload(d->phase, &p->alloc, ph32.data(), ph32.size() * sizeof(float2), s);
+    upload(d->eedges, &p->alloc, d->t.eedges.data(), d->t.eedges.size() * sizeof(int2), s);
+    upload(d->ew, &p->alloc, d->t.ew.data(), d->t.ew.size() * sizeof(double), s);
+    STN_HIP(hipStreamSynchronize(s));
+}
+
 void launch_sv_tiled(stn_plan* p, stn_batch* b, hipStream_t s) {
     const uint32_t n = p->n;
     const uint64_t N = 1ull << n;
@@ -600,23 +619,7 @@ void launch_sv_tiled(stn_plan* p, stn_batch* b, hipStream_t s) {
     const uint32_t B = std::min(p->max_batch, b->K);
     if (b->words > 64) fail(STN_E_UNSUPPORTED, "tiled lowering supports at most 2048 gates");
     if ((uint64_t)B * tiles > 0x7fffffffull) fail(STN_E_UNSUPPORTED, "batch slice too large");
-    if (!p->tiled) {
-        auto* d = new TiledDevice();
-        p->tiled = d;
-        p->tiled_free = [](void* v) { delete static_cast<TiledDevice*>(v); };
-        d->t = build_tables(p);
-        std::vector<float2> ph32;
-        for (auto& c : d->t.phase) ph32.push_back(make_float2((float)c.real(), (float)c.imag()));
-        if (d->t.dedges.empty()) d->t.dedges.push_back(int4{0, 0, 0, 0});
-        if (ph32.empty()) ph32.push_back(make_float2(0.f, 0.f));
-        if (d->t.eedges.empty()) d->t.eedges.push_back(int2{0, 0});
-        if (d->t.ew.empty()) d->t.ew.push_back(0.0);
-        upload(d->dedges, &p->alloc, d->t.dedges.data(), d->t.dedges.size() * sizeof(int4), s);
-        upload(d->phase, &p->alloc, ph32.data(), ph32.size() * sizeof(float2), s);
-        upload(d->eedges, &p->alloc, d->t.eedges.data(), d->t.eedges.size() * sizeof(int2), s);
-        upload(d->ew, &p->alloc, d->t.ew.data(), d->t.ew.size() * sizeof(double), s);
-        STN_HIP(hipStreamSynchronize(s));
-    }
+    if (!p->tiled) upload_tiled(p, s);
     auto* d = static_cast<TiledDevice*>(p->tiled);
     p->d_work.ensure(&p->alloc, (size_t)B * N * 8);
     p->d_partials.ensure(&p->alloc, (size_t)B * tiles * 8);

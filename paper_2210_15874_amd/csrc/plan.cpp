@@ -525,10 +525,13 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
             // statevector passes vs lightcone networks: estimated seconds per trajectory
             // (HBM-bound passes at ~4 TB/s; LDS-resident contraction at ~1e12 complex MACs/s)
             double sv_t = -1, tn_t = -1;
-            if (n >= 14 && p->opts.precision == 64 && build_tiled(p, why)) {
-                schedule_tiled(p, 14, 2);
+            const bool c128 = p->opts.precision == 128;
+            if (n >= (c128 ? 13u : 14u) && build_tiled(p, why)) {
+                if (c128) schedule_tiled(p, tiled128_tile_bits(), 3);
+                else schedule_tiled(p, 14, 2);
                 double bytes = 0;
-                for (auto& ps : p->passes) bytes += std::ldexp(8.0, (int)n) * ((ps.init ? 0 : 1) + (ps.last ? 0 : 1));
+                for (auto& ps : p->passes)
+                    bytes += std::ldexp(c128 ? 16.0 : 8.0, (int)n) * ((ps.init ? 0 : 1) + (ps.last ? 0 : 1));
                 sv_t = bytes / 4e12;
             }
             try {
@@ -561,10 +564,20 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
         build_lds_program(p);
     } else if (kind == STN_PLAN_SV_TILED) {
         if (dense_out) fail(STN_E_UNSUPPORTED, "the tiled lowering produces energies only");
-        if (n < 14) fail(STN_E_UNSUPPORTED, "the tiled lowering needs n >= 14");
+        const bool c128 = p->opts.precision == 128;
+        if (n < (c128 ? tiled128_tile_bits() : 14u))
+            fail(STN_E_UNSUPPORTED, std::string("the tiled lowering needs n >= ") + (c128 ? "12" : "14"));
         if (p->layers.empty() && !build_tiled(p, why)) fail(STN_E_UNSUPPORTED, "tiled lowering: " + why);
-        if (p->opts.precision == 128) fail(STN_E_UNSUPPORTED, "the tiled lowering is complex64 only");
-        schedule_tiled(p, 14, 2);
+        if (c128) {
+            // the complex128 kernels apply every rx as given
+            for (auto& g : p->gates) {
+                g.det_x = 0;
+                g.theta_eff = g.theta;
+            }
+            schedule_tiled(p, tiled128_tile_bits(), 3);
+        } else {
+            schedule_tiled(p, 14, 2);
+        }
     } else if (kind == STN_PLAN_LIGHTCONE) {
         if (dense_out) fail(STN_E_UNSUPPORTED, "the lightcone lowering produces energies only");
         if (!p->lc) build_lightcone(p);

@@ -1,0 +1,757 @@
+// Job server: a native request loop that runs many trajectory-ensemble jobs
+// (different circuits, sizes, noise rates and trajectory counts) on one
+// device at once.
+//
+//   caller threads   stn_server_submit copies the job's inputs and returns.
+//   planner thread   builds (or takes from the plan cache) the job's plan on
+//                    the host and estimates its device memory.
+//   device thread    the only thread that calls HIP.  Admits planned jobs in
+//                    arrival order while their estimated memory fits the
+//                    budget, gives each admitted job a stream, and issues the
+//                    jobs' work in chunks of trajectories (sample -> contract
+//                    -> reduce), round-robin over the admitted jobs, so that
+//                    chunks of jobs that arrived while others were running
+//                    interleave with theirs on the device (continuous
+//                    batching).  A job's draws depend only on (its seed, k,
+//                    site), and its reduction is in trajectory order, so its
+//                    result does not depend on what else ran beside it.
+//
+// Device memory comes from a caching pool bounded by the byte budget:
+// workspaces freed by finished jobs are handed to the next ones without
+// hipFree (which would wait for the whole device).
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <list>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+#include "stn_internal.h"
+
+namespace stn {
+namespace {
+
+constexpr uint32_t kMaxStreams = 8;
+constexpr uint32_t kMaxActive = 64;
+constexpr uint32_t kChunksInFlight = 2;   // per job
+
+// ---------------------------------------------------------------- device pool
+class DevicePool {
+public:
+    explicit DevicePool(uint64_t budget) : budget_(budget) {}
+    ~DevicePool() { trim_locked(UINT64_MAX); }
+
+    static size_t rounded(size_t b) {
+        if (b <= (size_t(1) << 20)) {
+            size_t r = 256;
+            while (r < b) r <<= 1;
+            return r;
+        }
+        const size_t g = size_t(2) << 20;
+        return (b + g - 1) / g * g;
+    }
+
+    void* alloc(size_t bytes) {
+        std::lock_guard<std::mutex> lk(m_);
+        const size_t r = rounded(bytes);
+        auto it = free_.find(r);
+        if (it != free_.end() && !it->second.empty()) {
+            void* p = it->second.back();
+            it->second.pop_back();
+            cached_ -= r;
+            take(p, r);
+            return p;
+        }
+        if (in_use_ + r > budget_) return nullptr;
+        if (in_use_ + cached_ + r > budget_) trim_locked(in_use_ + cached_ + r - budget_);
+        void* p = nullptr;
+        if (hipMalloc(&p, r) != hipSuccess) {
+            (void)hipGetLastError();
+            trim_locked(UINT64_MAX);
+            if (hipMalloc(&p, r) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+        }
+        take(p, r);
+        return p;
+    }
+
+    void release(void* p) {
+        std::lock_guard<std::mutex> lk(m_);
+        auto it = size_.find(p);
+        if (it == size_.end()) return;
+        const size_t r = it->second;
+        size_.erase(it);
+        in_use_ -= r;
+        free_[r].push_back(p);
+        cached_ += r;
+    }
+
+    uint64_t in_use() const { std::lock_guard<std::mutex> lk(m_); return in_use_; }
+    uint64_t cached() const { std::lock_guard<std::mutex> lk(m_); return cached_; }
+    uint64_t peak() const { std::lock_guard<std::mutex> lk(m_); return peak_; }
+
+private:
+    void take(void* p, size_t r) {
+        size_[p] = r;
+        in_use_ += r;
+        peak_ = std::max(peak_, in_use_);
+    }
+    // frees cached blocks, largest first, until `need` bytes are released
+    void trim_locked(uint64_t need) {
+        uint64_t got = 0;
+        for (auto it = free_.rbegin(); it != free_.rend() && got < need; ++it) {
+            while (!it->second.empty() && got < need) {
+                (void)hipFree(it->second.back());
+                it->second.pop_back();
+                cached_ -= it->first;
+                got += it->first;
+            }
+        }
+    }
+
+    mutable std::mutex m_;
+    uint64_t budget_, in_use_ = 0, cached_ = 0, peak_ = 0;
+    std::map<size_t, std::vector<void*>> free_;
+    std::unordered_map<void*, size_t> size_;
+};
+
+void* pool_alloc(size_t bytes, void* ctx) { return static_cast<DevicePool*>(ctx)->alloc(bytes); }
+void pool_free(void* p, void* ctx) { static_cast<DevicePool*>(ctx)->release(p); }
+
+// ---------------------------------------------------------------- job inputs
+// Deep copy of (circuit, noise model, observable); `key` is their byte image,
+// which identifies a plan in the cache.
+struct Inputs {
+    uint32_t n = 0;
+    std::vector<stn_gate> gates;
+    std::vector<double> gate_mats;
+    std::vector<size_t> gate_mat_off;
+    std::vector<stn_channel> chans;
+    std::vector<double> kraus;
+    std::vector<size_t> kraus_off;
+    std::vector<uint32_t> uv;
+    std::vector<double> w;
+    std::string key;
+
+    template <class T> static void put(std::string& k, const T& v) { k.append(reinterpret_cast<const char*>(&v), sizeof(T)); }
+
+    void copy(const stn_circuit* c, const stn_noise_model* nm, const stn_observable* ob, uint32_t precision) {
+        if (!c || (c->n_gates && !c->gates)) fail(STN_E_INVALID, "circuit is NULL");
+        n = c->n_qubits;
+        put(key, n);
+        put(key, precision);
+        gates.assign(c->gates, c->gates + c->n_gates);
+        for (auto& g : gates) {
+            put(key, g.kind); put(key, g.q0); put(key, g.q1); put(key, g.theta);
+            const size_t cnt = g.kind == STN_G_U1 ? 8 : g.kind == STN_G_U2 ? 32 : 0;
+            gate_mat_off.push_back(gate_mats.size());
+            if (cnt) {
+                if (!g.mat) fail(STN_E_INVALID, "explicit gate without a matrix");
+                gate_mats.insert(gate_mats.end(), g.mat, g.mat + cnt);
+                for (size_t i = 0; i < cnt; ++i) put(key, g.mat[i]);
+            }
+        }
+        if (nm && nm->n_channels) {
+            if (!nm->channels) fail(STN_E_INVALID, "noise model channels are NULL");
+            chans.assign(nm->channels, nm->channels + nm->n_channels);
+        }
+        for (auto& ch : chans) {
+            put(key, ch.after_gate); put(key, ch.kind); put(key, ch.n_qubits); put(key, ch.q0); put(key, ch.q1);
+            put(key, ch.param); put(key, ch.n_kraus);
+            kraus_off.push_back(kraus.size());
+            if (ch.kind == STN_CH_KRAUS) {
+                const size_t d = ch.n_qubits == 2 ? 4 : 2, cnt = (size_t)ch.n_kraus * d * d * 2;
+                if (!ch.kraus || cnt == 0) fail(STN_E_INVALID, "explicit channel without operators");
+                kraus.insert(kraus.end(), ch.kraus, ch.kraus + cnt);
+                for (size_t i = 0; i < cnt; ++i) put(key, ch.kraus[i]);
+            }
+        }
+        if (ob && ob->n_terms) {
+            if (!ob->uv || !ob->w) fail(STN_E_INVALID, "observable arrays are NULL");
+            uv.assign(ob->uv, ob->uv + 2 * (size_t)ob->n_terms);
+            w.assign(ob->w, ob->w + ob->n_terms);
+            for (auto x : uv) put(key, x);
+            for (auto x : w) put(key, x);
+        }
+        // pointers into the owned copies
+        for (size_t i = 0; i < gates.size(); ++i)
+            gates[i].mat = (gates[i].kind == STN_G_U1 || gates[i].kind == STN_G_U2) ? gate_mats.data() + gate_mat_off[i] : nullptr;
+        for (size_t i = 0; i < chans.size(); ++i)
+            chans[i].kraus = chans[i].kind == STN_CH_KRAUS ? kraus.data() + kraus_off[i] : nullptr;
+    }
+};
+
+// ---------------------------------------------------------------- jobs
+enum class JobState { Planning, Ready, Active, Finishing, Done };
+
+struct Job {
+    uint64_t id = 0, tag = 0, seed = 0, K = 0;
+    Inputs in;
+    stn_plan* plan = nullptr;
+    stn_status status = STN_OK;
+    std::string err;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    uint64_t est_bytes = 0;
+    uint32_t B = 0;                    // trajectories per chunk
+    // device-side state (device thread only)
+    int stream = -1;
+    stn_accum* acc = nullptr;
+    stn_batch* batch[kChunksInFlight] = {};
+    hipEvent_t ev[kChunksInFlight] = {};
+    bool ev_live[kChunksInFlight] = {};
+    hipEvent_t done_ev = nullptr;
+    uint64_t k_issued = 0;
+    uint32_t next = 0;
+    uint32_t slot = 0;                 // pinned result slot
+    uint64_t chunks = 0;
+    bool finishing = false;
+};
+
+}  // namespace
+}  // namespace stn
+
+struct stn_server {
+    stn_server_opts opts{};
+    std::chrono::steady_clock::time_point t0;
+    std::unique_ptr<stn::DevicePool> pool;
+    int device = 0;
+
+    std::mutex m;                          // guards the queues, cache, results and stats below
+    std::condition_variable cv_plan, cv_ready, cv_done;
+    std::deque<std::shared_ptr<stn::Job>> to_plan, ready;
+    std::deque<stn_job_result> results;
+    std::list<std::pair<std::string, stn_plan*>> cache;   // idle plans, most recent first
+    uint64_t next_id = 1;
+    uint64_t submitted = 0, completed = 0, planned = 0, inflight_jobs = 0;
+    stn_server_stats st{};
+    bool stop = false;
+    std::string fatal;
+
+    std::thread planner, worker;
+
+    double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+};
+
+namespace stn {
+namespace {
+
+// ---------------------------------------------------------------- planner
+uint64_t estimate_bytes(const stn_plan* p, uint32_t B, uint64_t K) {
+    const double S = (double)p->sites.size();
+    const double words = std::max<double>(1.0, std::ceil(p->gates.size() / 32.0));
+    double b = 0;
+    const double N = std::ldexp(1.0, (int)p->n);
+    const double elem = p->opts.precision == 128 ? 16.0 : 8.0;
+    if (p->kind == STN_PLAN_SV_TILED) b += (double)B * N * elem + (double)B * std::ldexp(1.0, (int)p->n - 14) * 8.0;
+    if (p->kind == STN_PLAN_LIGHTCONE) b += (double)B * p->obs_u.size() * 8.0;
+    b += kChunksInFlight * (double)B * (S + 4.0 * words + 16.0 + 8.0);     // batches
+    b += std::ceil((double)K / kEnergyChunk) * kEnergyChunk * 8.0 + 2.0 * K * 8.0;  // accumulator
+    b += 8.0 * (1 << 20);                                                  // tables and rounding
+    return (uint64_t)b;
+}
+
+void plan_job(stn_server* sv, Job& j) {
+    stn_plan* p = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(sv->m);
+        for (auto it = sv->cache.begin(); it != sv->cache.end(); ++it)
+            if (it->first == j.in.key) {
+                p = it->second;
+                sv->cache.erase(it);
+                sv->st.plan_cache_hits++;
+                break;
+            }
+        if (!p) sv->st.plan_cache_misses++;
+    }
+    if (!p) {
+        stn_plan_opts o;
+        stn_plan_opts_default(&o);
+        o.precision = sv->opts.precision;
+        o.outputs = STN_OUT_ENERGY;
+        o.plan_kind = STN_PLAN_AUTO;
+        o.hbm_budget = (uint64_t)(sv->opts.job_share * (double)sv->opts.hbm_budget);
+        o.max_batch = sv->opts.chunk_max;
+        o.dev_alloc = pool_alloc;
+        o.dev_free = pool_free;
+        o.alloc_ctx = sv->pool.get();
+        const stn_circuit c{j.in.n, (uint32_t)j.in.gates.size(), j.in.gates.data()};
+        const stn_noise_model nm{(uint32_t)j.in.chans.size(), j.in.chans.data()};
+        const stn_observable ob{(uint32_t)j.in.w.size(), j.in.uv.data(), j.in.w.data()};
+        const stn_status s = stn_plan_create(&c, &nm, ob.n_terms ? &ob : nullptr, &o, &p);
+        if (s != STN_OK) {
+            j.status = s;
+            j.err = stn_last_error();
+            return;
+        }
+        p->sync_on_destroy = false;
+    }
+    j.plan = p;
+    j.B = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(p->max_batch, j.K));
+    j.est_bytes = estimate_bytes(p, j.B, j.K);
+    if (j.est_bytes > sv->opts.hbm_budget) {
+        j.status = STN_E_OOM;
+        j.err = "job needs more device memory than the server budget";
+    }
+}
+
+void planner_loop(stn_server* sv) {
+    for (;;) {
+        std::shared_ptr<Job> j;
+        {
+            std::unique_lock<std::mutex> lk(sv->m);
+            sv->cv_plan.wait(lk, [&] { return sv->stop || !sv->to_plan.empty(); });
+            if (sv->to_plan.empty() || (sv->stop && !sv->opts.drain_on_destroy)) return;
+            j = sv->to_plan.front();
+            sv->to_plan.pop_front();
+        }
+        try {
+            plan_job(sv, *j);
+        } catch (const Error& e) {
+            j->status = e.status;
+            j->err = e.msg;
+        } catch (const std::exception& e) {
+            j->status = STN_E_INVALID;
+            j->err = e.what();
+        }
+        {
+            std::lock_guard<std::mutex> lk(sv->m);
+            sv->ready.push_back(j);
+            sv->planned++;
+        }
+        sv->cv_ready.notify_one();
+    }
+}
+
+// ---------------------------------------------------------------- device thread
+struct Device {
+    stn_server* sv;
+    hipStream_t streams[kMaxStreams] = {};
+    hipStream_t upload = nullptr;
+    uint32_t stream_jobs[kMaxStreams] = {};
+    double* pinned = nullptr;              // kMaxActive x 2 doubles: mean, SE
+    std::vector<uint32_t> free_slots;
+    std::vector<std::shared_ptr<Job>> active;
+    std::vector<hipEvent_t> ev_pool;
+    uint64_t bytes_admitted = 0;
+    size_t rr = 0;
+
+    hipEvent_t event() {
+        if (!ev_pool.empty()) {
+            hipEvent_t e = ev_pool.back();
+            ev_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        STN_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        return e;
+    }
+
+    void init() {
+        STN_HIP(hipSetDevice(sv->device));
+        for (uint32_t i = 0; i < sv->opts.n_streams; ++i) STN_HIP(hipStreamCreateWithFlags(&streams[i], hipStreamNonBlocking));
+        STN_HIP(hipStreamCreateWithFlags(&upload, hipStreamNonBlocking));
+        STN_HIP(hipHostMalloc((void**)&pinned, kMaxActive * 2 * sizeof(double), hipHostMallocDefault));
+        for (uint32_t i = 0; i < kMaxActive; ++i) free_slots.push_back(kMaxActive - 1 - i);
+    }
+
+    void shutdown() {
+        for (auto& j : active) (void)hipStreamSynchronize(streams[j->stream]);
+        for (auto& j : active) release(*j);
+        active.clear();
+        for (uint32_t i = 0; i < sv->opts.n_streams; ++i)
+            if (streams[i]) (void)hipStreamDestroy(streams[i]);
+        if (upload) (void)hipStreamDestroy(upload);
+        for (auto e : ev_pool) (void)hipEventDestroy(e);
+        ev_pool.clear();
+        if (pinned) (void)hipHostFree(pinned);
+    }
+
+    // frees the job's device state (its work has completed) and returns the
+    // plan to the cache
+    void release(Job& j) {
+        for (uint32_t c = 0; c < kChunksInFlight; ++c) {
+            delete j.batch[c];
+            j.batch[c] = nullptr;
+            if (j.ev[c]) ev_pool.push_back(j.ev[c]);
+            j.ev[c] = nullptr;
+            j.ev_live[c] = false;
+        }
+        if (j.done_ev) ev_pool.push_back(j.done_ev);
+        j.done_ev = nullptr;
+        delete j.acc;
+        j.acc = nullptr;
+        if (j.stream >= 0) stream_jobs[j.stream]--;
+        free_slots.push_back(j.slot);
+        bytes_admitted -= j.est_bytes;
+        if (j.plan) {
+            j.plan->d_work.reset();
+            j.plan->d_partials.reset();
+            stn_plan* drop = nullptr;
+            {
+                std::lock_guard<std::mutex> lk(sv->m);
+                if (sv->opts.plan_cache) {
+                    sv->cache.push_front({j.in.key, j.plan});
+                    if (sv->cache.size() > sv->opts.plan_cache) {
+                        drop = sv->cache.back().second;
+                        sv->cache.pop_back();
+                    }
+                } else {
+                    drop = j.plan;
+                }
+            }
+            delete drop;
+            j.plan = nullptr;
+        }
+    }
+
+    stn_job_result record(const Job& j, stn_status s, const std::string& err) {
+        stn_job_result r{};
+        r.job_id = j.id;
+        r.tag = j.tag;
+        r.status = (uint32_t)s;
+        r.plan_kind = j.plan ? j.plan->kind : 0;
+        r.width = j.plan ? j.plan->width : 0;
+        r.K = j.K;
+        r.k_done = s == STN_OK ? j.K : 0;
+        r.chunk = j.B;
+        r.chunks = j.chunks;
+        r.t_submit = j.t_submit;
+        r.t_admit = j.t_admit;
+        r.t_done = sv->now();
+        if (s == STN_OK) {
+            r.energy_mean = pinned[2 * j.slot];
+            r.energy_se = pinned[2 * j.slot + 1];
+        }
+        std::snprintf(r.error, sizeof(r.error), "%s", err.c_str());
+        return r;
+    }
+
+    // results are published after the job's resources (and its plan, to the
+    // cache) have been released, so a caller that saw the result finds them free
+    void publish(const stn_job_result& r) {
+        {
+            std::lock_guard<std::mutex> lk(sv->m);
+            sv->results.push_back(r);
+            sv->completed++;
+            if (r.status == STN_OK) sv->st.trajectories += r.K;
+            else sv->st.failed++;
+        }
+        sv->cv_done.notify_all();
+    }
+
+    // Arrival order; when the oldest waiting job does not fit, a later job of
+    // at most 1/32 of the budget that fits may go ahead of it (small jobs
+    // barely delay the large one and are not held behind it).
+    bool admit() {
+        std::shared_ptr<Job> j;
+        {
+            std::lock_guard<std::mutex> lk(sv->m);
+            if (sv->ready.empty()) return false;
+            const bool room = active.size() < sv->opts.max_active && !free_slots.empty();
+            const uint64_t left = sv->opts.hbm_budget - bytes_admitted;
+            size_t pick = SIZE_MAX;
+            for (size_t i = 0; i < sv->ready.size(); ++i) {
+                const auto& c = sv->ready[i];
+                if (c->status != STN_OK) { pick = i; break; }       // failed planning: report now
+                if (!room) continue;
+                if (i == 0 && c->est_bytes <= left) { pick = 0; break; }
+                if (i > 0 && c->est_bytes <= left && c->est_bytes <= sv->opts.hbm_budget / 32) { pick = i; break; }
+            }
+            if (pick == SIZE_MAX) return false;
+            j = sv->ready[pick];
+            sv->ready.erase(sv->ready.begin() + (ptrdiff_t)pick);
+        }
+        if (j->status != STN_OK) {   // planning failed: report at once
+            const stn_job_result r = record(*j, j->status, j->err);
+            delete j->plan;
+            j->plan = nullptr;
+            publish(r);
+            return true;
+        }
+        j->t_admit = sv->now();
+        j->slot = free_slots.back();
+        free_slots.pop_back();
+        bytes_admitted += j->est_bytes;
+        // least-loaded stream
+        uint32_t best = 0;
+        for (uint32_t i = 1; i < sv->opts.n_streams; ++i)
+            if (stream_jobs[i] < stream_jobs[best]) best = i;
+        j->stream = (int)best;
+        stream_jobs[best]++;
+        try {
+            ensure_uploaded(j->plan, upload);
+            j->acc = new stn_accum();
+            j->acc->plan = j->plan;
+            for (uint32_t c = 0; c < kChunksInFlight; ++c) {
+                j->batch[c] = new stn_batch();
+                j->ev[c] = event();
+            }
+            j->done_ev = event();
+        } catch (const Error& e) {
+            fail_job(*j, e);
+            return true;
+        }
+        active.push_back(j);
+        std::lock_guard<std::mutex> lk(sv->m);
+        sv->st.max_active_jobs = std::max<uint64_t>(sv->st.max_active_jobs, active.size());
+        return true;
+    }
+
+    void fail_job(Job& j, const Error& e) {
+        if (j.stream >= 0) (void)hipStreamSynchronize(streams[j.stream]);
+        const stn_job_result r = record(j, e.status, e.msg);
+        release(j);
+        publish(r);
+    }
+
+    // one chunk of j onto its stream; false when nothing could be issued
+    bool issue(Job& j) {
+        if (j.k_issued >= j.K) return false;
+        const uint32_t c = j.next;
+        if (j.ev_live[c]) {
+            if (hipEventQuery(j.ev[c]) == hipErrorNotReady) return false;
+            j.ev_live[c] = false;
+        }
+        hipStream_t s = streams[j.stream];
+        const uint32_t K = (uint32_t)std::min<uint64_t>(j.B, j.K - j.k_issued);
+        stn_batch* b = j.batch[c];
+        batch_prepare(j.plan, b, j.k_issued, K);
+        launch_sample(j.plan, b, j.seed, s);
+        if (j.plan->kind != STN_PLAN_SV_LDS) launch_frame(j.plan, b, s);
+        const stn_status st1 = stn_contract(j.plan, b, s);
+        if (st1 != STN_OK) throw Error{st1, stn_last_error()};
+        const stn_status st2 = stn_reduce(j.plan, b, j.acc, s);
+        if (st2 != STN_OK) throw Error{st2, stn_last_error()};
+        STN_HIP(hipEventRecord(j.ev[c], s));
+        j.ev_live[c] = true;
+        j.next = (c + 1) % kChunksInFlight;
+        j.k_issued += K;
+        j.chunks++;
+        std::lock_guard<std::mutex> lk(sv->m);
+        sv->st.chunks++;
+        return true;
+    }
+
+    // true when j made progress (chunk issued, finishing enqueued, or done)
+    bool step(Job& j, bool& done) {
+        done = false;
+        if (j.k_issued < j.K) return issue(j);
+        if (!j.finishing) {
+            // all chunks enqueued: statistics in trajectory order, copied to the pinned slot
+            hipStream_t s = streams[j.stream];
+            accum_finish_energy(j.acc, s);
+            STN_HIP(hipMemcpyAsync(pinned + 2 * j.slot, j.acc->d_stats.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+            STN_HIP(hipEventRecord(j.done_ev, s));
+            j.finishing = true;
+            return true;
+        }
+        const hipError_t q = hipEventQuery(j.done_ev);
+        if (q == hipErrorNotReady) return false;
+        if (q != hipSuccess) throw Error{STN_E_DEVICE, std::string("job stream: ") + hipGetErrorString(q)};
+        const stn_job_result r = record(j, STN_OK, "");
+        release(j);
+        publish(r);
+        done = true;
+        return true;
+    }
+
+    void loop() {
+        for (;;) {
+            bool progress = false;
+            while (admit()) progress = true;
+            // round-robin over the admitted jobs, one chunk each per round
+            for (size_t i = 0; i < active.size();) {
+                auto j = active[(rr + i) % active.size()];
+                bool done = false;
+                try {
+                    progress |= step(*j, done);
+                } catch (const Error& e) {
+                    fail_job(*j, e);
+                    done = true;
+                    progress = true;
+                }
+                if (done) {
+                    active.erase(std::find(active.begin(), active.end(), j));
+                    continue;
+                }
+                ++i;
+            }
+            rr = active.empty() ? 0 : (rr + 1) % active.size();
+            {
+                std::unique_lock<std::mutex> lk(sv->m);
+                sv->inflight_jobs = active.size();
+                if (sv->stop && (!sv->opts.drain_on_destroy || (active.empty() && sv->completed == sv->submitted)))
+                    return;
+                if (!progress) {
+                    if (active.empty()) sv->cv_ready.wait_for(lk, std::chrono::milliseconds(5));
+                    else sv->cv_ready.wait_for(lk, std::chrono::microseconds(50));
+                }
+            }
+        }
+    }
+};
+
+void worker_main(stn_server* sv) {
+    Device d;
+    d.sv = sv;
+    try {
+        d.init();
+        d.loop();
+    } catch (const Error& e) {
+        std::lock_guard<std::mutex> lk(sv->m);
+        sv->fatal = e.msg;
+    }
+    d.shutdown();
+}
+
+thread_local std::string g_srv_err;
+stn_status srv_error(stn_status s, const std::string& m) {
+    g_srv_err = m;
+    return s;
+}
+
+}  // namespace
+}  // namespace stn
+
+using namespace stn;
+
+extern "C" {
+
+void stn_server_opts_default(stn_server_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->hbm_budget = 64ull << 30;
+    o->job_share = 0.5;
+    o->n_streams = 4;
+    o->max_active = 16;
+    o->plan_cache = 64;
+    o->precision = 64;
+    o->drain_on_destroy = 1;
+}
+
+stn_status stn_server_create(const stn_server_opts* opts, stn_server** out) {
+    if (!out) return STN_E_INVALID;
+    *out = nullptr;
+    stn_server_opts o;
+    if (opts) o = *opts;
+    else stn_server_opts_default(&o);
+    if (o.n_streams < 1 || o.n_streams > kMaxStreams || o.max_active < 1 || o.max_active > kMaxActive ||
+        !(o.job_share > 0 && o.job_share <= 1) || o.hbm_budget < (64ull << 20) ||
+        (o.precision != 64 && o.precision != 128))
+        return srv_error(STN_E_INVALID, "server options out of range");
+    auto* sv = new stn_server();
+    sv->opts = o;
+    sv->t0 = std::chrono::steady_clock::now();
+    sv->pool = std::make_unique<DevicePool>(o.hbm_budget);
+    if (hipGetDevice(&sv->device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete sv;
+        return srv_error(STN_E_DEVICE, "no HIP device");
+    }
+    sv->planner = std::thread(planner_loop, sv);
+    sv->worker = std::thread(worker_main, sv);
+    *out = sv;
+    return STN_OK;
+}
+
+stn_status stn_server_submit(stn_server* sv, const stn_circuit* circuit, const stn_noise_model* noise,
+                             const stn_observable* observable, uint64_t seed, uint64_t K, uint64_t tag,
+                             uint64_t* job_id) {
+    if (!sv || !circuit || !observable) return srv_error(STN_E_INVALID, "NULL argument");
+    if (K == 0) return srv_error(STN_E_INVALID, "K must be positive");
+    auto j = std::make_shared<Job>();
+    try {
+        j->in.copy(circuit, noise, observable, sv->opts.precision);
+    } catch (const Error& e) {
+        return srv_error(e.status, e.msg);
+    } catch (const std::bad_alloc&) {
+        return srv_error(STN_E_OOM, "host allocation failed");
+    }
+    j->seed = seed;
+    j->K = K;
+    j->tag = tag;
+    {
+        std::lock_guard<std::mutex> lk(sv->m);
+        if (!sv->fatal.empty()) return srv_error(STN_E_DEVICE, "server stopped: " + sv->fatal);
+        j->t_submit = sv->now();
+        j->id = sv->next_id++;
+        sv->submitted++;
+        sv->to_plan.push_back(j);
+    }
+    sv->cv_plan.notify_one();
+    if (job_id) *job_id = j->id;
+    return STN_OK;
+}
+
+stn_status stn_server_poll(stn_server* sv, stn_job_result* out, uint32_t cap, uint32_t* n_out, double wait_s) {
+    if (!sv || !n_out || (cap && !out)) return srv_error(STN_E_INVALID, "NULL argument");
+    *n_out = 0;
+    std::unique_lock<std::mutex> lk(sv->m);
+    if (sv->results.empty() && wait_s > 0)
+        sv->cv_done.wait_for(lk, std::chrono::duration<double>(wait_s), [&] { return !sv->results.empty() || !sv->fatal.empty(); });
+    uint32_t n = 0;
+    while (n < cap && !sv->results.empty()) {
+        out[n++] = sv->results.front();
+        sv->results.pop_front();
+    }
+    *n_out = n;
+    if (!sv->fatal.empty() && n == 0) return srv_error(STN_E_DEVICE, "server stopped: " + sv->fatal);
+    return STN_OK;
+}
+
+stn_status stn_server_drain(stn_server* sv, double timeout_s) {
+    if (!sv) return srv_error(STN_E_INVALID, "NULL argument");
+    std::unique_lock<std::mutex> lk(sv->m);
+    const bool ok = sv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s),
+                                         [&] { return sv->completed == sv->submitted || !sv->fatal.empty(); });
+    if (!sv->fatal.empty()) return srv_error(STN_E_DEVICE, "server stopped: " + sv->fatal);
+    return ok ? STN_OK : srv_error(STN_E_STATE, "drain timed out");
+}
+
+stn_status stn_server_stats_read(stn_server* sv, stn_server_stats* out) {
+    if (!sv || !out) return srv_error(STN_E_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(sv->m);
+    *out = sv->st;
+    out->submitted = sv->submitted;
+    out->completed = sv->completed;
+    out->active = sv->inflight_jobs;
+    out->waiting = sv->to_plan.size() + sv->ready.size();
+    out->bytes_in_use = sv->pool->in_use();
+    out->bytes_cached = sv->pool->cached();
+    out->bytes_peak = sv->pool->peak();
+    out->plans_cached = sv->cache.size();
+    out->clock = sv->now();
+    return STN_OK;
+}
+
+double stn_server_clock(const stn_server* sv) { return sv ? sv->now() : 0.0; }
+
+const char* stn_server_last_error(void) { return g_srv_err.c_str(); }
+
+void stn_server_destroy(stn_server* sv) {
+    if (!sv) return;
+    if (sv->opts.drain_on_destroy) (void)stn_server_drain(sv, 1e9);
+    {
+        std::lock_guard<std::mutex> lk(sv->m);
+        sv->stop = true;
+    }
+    sv->cv_plan.notify_all();
+    sv->cv_ready.notify_all();
+    if (sv->planner.joinable()) sv->planner.join();
+    if (sv->worker.joinable()) sv->worker.join();
+    // jobs planned but never admitted
+    for (auto& j : sv->ready) delete j->plan;
+    for (auto& e : sv->cache) delete e.second;
+    sv->cache.clear();
+    delete sv;
+}
+
+}  // extern "C"

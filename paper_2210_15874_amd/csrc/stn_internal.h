@@ -189,6 +189,7 @@ struct stn_plan {
     void* lc = nullptr;
     void (*lc_free)(void*) = nullptr;
 
+    bool sync_on_destroy = true;            // false: the owner has waited for every enqueued use
     ~stn_plan();
 };
 
@@ -228,6 +229,13 @@ void prof_begin(stn_plan* p, int cls, hipStream_t s);
 void prof_end(stn_plan* p, int cls, hipStream_t s, double bytes, double flops);
 void prof_clear(stn_plan* p);
 
+// device tables of a plan, uploaded on first device use (synchronises s)
+void ensure_uploaded(stn_plan* p, hipStream_t s);
+// (re)shapes a batch for trajectories k0 .. k0+K-1; buffers only grow
+void batch_prepare(stn_plan* p, stn_batch* b, uint64_t k0, uint32_t K);
+// enqueues the gather of per-trajectory energies and their statistics into d_stats
+void accum_finish_energy(stn_accum* a, hipStream_t s);
+
 // planner (plan.cpp)
 void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, const stn_observable* ob);
 
@@ -245,4 +253,10 @@ void launch_lightcone(stn_plan* p, stn_batch* b, hipStream_t s);
 // lightcone lowering (kernels_tn.hip): networks of every observable term
 void build_lightcone(stn_plan* p);
 void upload_lightcone(stn_plan* p, hipStream_t s);
+// tiled lowering (kernels_sv_tiled.hip): pass tables
+void upload_tiled(stn_plan* p, hipStream_t s);
+// complex128 tiled lowering (kernels_sv_tiled128.hip)
+uint32_t tiled128_tile_bits();
+void upload_tiled128(stn_plan* p, hipStream_t s);
+void launch_sv_tiled128(stn_plan* p, stn_batch* b, hipStream_t s);
 }  // namespace stn

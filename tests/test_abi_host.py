@@ -95,3 +95,47 @@ def test_validation_errors():
         plan(config_problem(2), outputs=OUT_RHO)
     with pytest.raises(StnError, match="INVALID"):
         plan(bad_q)  # ENERGY without edges is fine, bad qubit is not
+
+
+def test_complex128_tiled_plan():
+    from workloads import config_problem
+    pr = config_problem(2)
+    i = plan(pr, precision=128).info()
+    assert i["plan_name"] == "sv_tiled"
+    # 12-qubit tiles: 3 tiles per layer, alternating order merges layer
+    # boundaries, so p = 4 layers cost 4 * (3 - 1) + 1 passes of 2^26 * 16 B
+    assert i["n_passes"] == 9
+    assert i["bytes_per_traj"] == (2 * 9 - 2) * 2 ** 26 * 16
+
+
+def test_lightcone_plans_and_auto_choice():
+    from workloads import make_problem, random_regular_graph, uniform_angles
+    from paper_2210_15874_amd import PLAN_LIGHTCONE, StnError
+    g, b = uniform_angles(1, 5)
+    pr = make_problem(40, random_regular_graph(40, 3, 4), g, b, 1e-3, 1e-2, 16, 6)
+    i = plan(pr).info()
+    # p = 1 on a 3-regular graph: each edge's lightcone touches at most 6 qubits
+    assert i["plan_name"] == "lightcone" and i["width"] <= 8 and i["n_steps"] > 0
+    g, b = uniform_angles(4, 5)
+    pr = make_problem(26, random_regular_graph(26, 3, 7), g, b, 1e-3, 1e-2, 16, 6)
+    assert plan(pr).info()["plan_name"] == "sv_tiled"
+    with pytest.raises(StnError, match="UNSUPPORTED"):
+        plan(pr, plan_kind=PLAN_LIGHTCONE)
+
+
+def test_server_needs_a_device_and_valid_options():
+    from paper_2210_15874_amd import Server, StnError
+    with pytest.raises(StnError, match="INVALID"):
+        Server(n_streams=0)
+    with pytest.raises(StnError, match="INVALID"):
+        Server(job_share=0.0)
+    with pytest.raises(StnError, match="INVALID"):
+        Server(precision=32)
+    try:
+        import torch
+        has_gpu = torch.cuda.is_available()
+    except ImportError:
+        has_gpu = False
+    if not has_gpu:
+        with pytest.raises(StnError, match="DEVICE"):
+            Server()

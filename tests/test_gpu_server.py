@@ -1,0 +1,180 @@
+"""Job server (continuous batching of many <C> jobs on one device): results
+of served jobs against the same jobs run alone through the plan API (bit
+for bit), against the oracle, and the admission / failure behaviour."""
+import math
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2210_15874_amd as stn
+    stn.load()
+    torch.cuda.set_device(0)
+
+
+def stn_mod():
+    import paper_2210_15874_amd as stn
+    return stn
+
+
+def mixed_jobs():
+    """Small jobs covering the three lowerings (whole state in LDS, tiled
+    HBM statevector, lightcone networks)."""
+    from workloads import erdos_renyi_graph, make_problem, random_regular_graph, uniform_angles
+    jobs = []
+    for i, (n, p, K, lam) in enumerate([(10, 3, 700, (1e-3, 1e-2)), (16, 2, 300, (2e-3, 2e-2)),
+                                        (22, 1, 500, (1e-3, 1e-2)), (12, 4, 1200, (1e-4, 5e-3)),
+                                        (18, 3, 96, (5e-3, 1e-2)), (20, 1, 64, (1e-2, 1e-2))]):
+        if i % 2:
+            edges = random_regular_graph(n, 3, 900 + i)
+        else:
+            edges = erdos_renyi_graph(n, 3.0 / (n - 1), 900 + i)
+        g, b = uniform_angles(p, 950 + i)
+        jobs.append(make_problem(n, edges, g, b, lam[0], lam[1], K, 7000 + i, name=f"mix{i}"))
+    return jobs
+
+
+def alone(pr, precision=64):
+    stn = stn_mod()
+    return stn.simulate_batch_ensemble(pr, precision=precision)
+
+
+def test_served_jobs_equal_plan_api_bit_for_bit():
+    stn = stn_mod()
+    jobs = mixed_jobs()
+    ref = [alone(pr) for pr in jobs]
+    with stn.Server(hbm_budget=8 << 30, n_streams=4, max_active=8) as sv:
+        ids = [sv.submit(pr, tag=i) for i, pr in enumerate(jobs)]
+        sv.drain(300)
+        res = {r["tag"]: r for r in sv.poll(cap=64)}
+        st = sv.stats()
+    assert sorted(res) == list(range(len(jobs)))
+    kinds = set()
+    for i, pr in enumerate(jobs):
+        r = res[i]
+        assert r["status"] == 0, r["error"]
+        assert r["k_done"] == pr.K
+        kinds.add(r["plan_name"])
+        assert r["energy_mean"] == ref[i]["energy_mean"], (i, r["energy_mean"], ref[i]["energy_mean"])
+        assert r["energy_se"] == ref[i]["energy_se"]
+        assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
+    assert kinds == {"sv_lds", "sv_tiled", "lightcone"}
+    assert st["completed"] == len(jobs) and st["failed"] == 0
+    assert st["trajectories"] == sum(pr.K for pr in jobs)
+    assert len(set(ids)) == len(ids)
+
+
+def test_same_result_alone_and_in_mix():
+    """A job's result does not depend on what else the server runs."""
+    stn = stn_mod()
+    jobs = mixed_jobs()
+    probe = jobs[1]
+    with stn.Server(hbm_budget=8 << 30) as sv:
+        sv.submit(probe, tag=99)
+        sv.drain(120)
+        solo = sv.poll(cap=4)[0]
+    with stn.Server(hbm_budget=8 << 30, n_streams=3, max_active=6, chunk_max=64) as sv:
+        for i, pr in enumerate(jobs):
+            sv.submit(pr, tag=i)
+            if i == 2:
+                sv.submit(probe, tag=99)
+        sv.drain(300)
+        mixed = [r for r in sv.poll(cap=64) if r["tag"] == 99][0]
+    assert mixed["status"] == 0 and solo["status"] == 0
+    assert mixed["chunks"] > solo["chunks"]      # smaller chunks in the mix
+    assert mixed["energy_mean"] == solo["energy_mean"]
+    assert mixed["energy_se"] == solo["energy_se"]
+
+
+def test_served_job_against_oracle():
+    from oracle import simulate as sim
+    from workloads import make_problem, random_regular_graph, uniform_angles
+    stn = stn_mod()
+    n, p, K = 10, 2, 48
+    g, b = uniform_angles(p, 31)
+    pr = make_problem(n, random_regular_graph(n, 3, 30), g, b, 5e-3, 3e-2, K, 32)
+    ens = sim.ensemble(pr, pr.seed, 0, K, want_states=False)
+    e = np.asarray(ens["energies"])
+    for precision, tol in [(64, 1e-5), (128, 1e-11)]:
+        with stn.Server(hbm_budget=1 << 30, precision=precision) as sv:
+            sv.submit(pr)
+            sv.drain(60)
+            r = sv.poll(cap=4)[0]
+        assert r["status"] == 0, r["error"]
+        m = len(pr.edges)
+        assert abs(r["energy_mean"] - e.mean()) / m < tol
+        assert abs(r["energy_se"] - e.std(ddof=1) / math.sqrt(K)) / m < tol
+
+
+def test_small_jobs_overtake_a_long_one():
+    """Continuous batching: jobs submitted after a long job has started run
+    beside it and finish before it."""
+    from workloads import make_problem, random_regular_graph, uniform_angles
+    stn = stn_mod()
+    g, b = uniform_angles(4, 61)
+    big = make_problem(24, random_regular_graph(24, 3, 60), g, b, 1e-3, 1e-2, 6144, 62, name="big")
+    smalls = mixed_jobs()
+    with stn.Server(hbm_budget=48 << 30, job_share=0.5, n_streams=4, max_active=8) as sv:
+        sv.submit(big, tag=1000)
+        t_wait = time.time() + 30
+        while sv.stats()["active"] == 0 and time.time() < t_wait:
+            time.sleep(0.01)
+        time.sleep(0.2)
+        for i, pr in enumerate(smalls):
+            sv.submit(pr, tag=i)
+        sv.drain(600)
+        res = {r["tag"]: r for r in sv.poll(cap=64)}
+        st = sv.stats()
+    assert all(r["status"] == 0 for r in res.values())
+    assert st["max_active_jobs"] >= 2
+    tb = res[1000]
+    assert tb["chunks"] > 1
+    done_first = [i for i in range(len(smalls)) if res[i]["t_done"] < tb["t_done"]]
+    assert len(done_first) >= len(smalls) - 1, (done_first, tb)
+
+
+def test_failed_jobs_reported_and_others_unaffected():
+    from workloads import Gate, Problem
+    stn = stn_mod()
+    jobs = mixed_jobs()[:2]
+    bad = Problem(4, [Gate("h", (7,))], [], [(0, 1)], [1.0], [], [], 16, 5, "bad")   # qubit out of range
+    with stn.Server(hbm_budget=1 << 30) as sv:
+        sv.submit(jobs[0], tag=0)
+        sv.submit(bad, tag=1)
+        sv.submit(jobs[1], tag=2)
+        # larger than the whole budget: rejected, not admitted
+        from workloads import make_problem, random_regular_graph, uniform_angles
+        g, b = uniform_angles(2, 3)
+        huge = make_problem(28, random_regular_graph(28, 3, 4), g, b, 1e-3, 1e-2, 64, 5)
+        sv.submit(huge, tag=3)
+        sv.drain(120)
+        res = {r["tag"]: r for r in sv.poll(cap=8)}
+    assert res[1]["status"] == 1 and "qubit" in res[1]["error"]
+    assert res[3]["status"] == 3
+    ref0, ref2 = alone(jobs[0]), alone(jobs[1])
+    assert res[0]["status"] == 0 and res[0]["energy_mean"] == ref0["energy_mean"]
+    assert res[2]["status"] == 0 and res[2]["energy_mean"] == ref2["energy_mean"]
+
+
+def test_plan_cache_reuses_plans():
+    stn = stn_mod()
+    pr = mixed_jobs()[0]
+    with stn.Server(hbm_budget=2 << 30, plan_cache=4) as sv:
+        for s in range(3):
+            sv.submit(pr, seed=100 + s, K=128, tag=s)
+            sv.drain(60)
+        res = {r["tag"]: r for r in sv.poll(cap=8)}
+        st = sv.stats()
+    assert st["plan_cache_hits"] == 2 and st["plan_cache_misses"] == 1
+    for s in range(3):
+        ref = stn.simulate_batch_ensemble(pr, K=128, seed=100 + s)
+        assert res[s]["energy_mean"] == ref["energy_mean"]
