@@ -10,6 +10,15 @@ lowering) is built once outside the timed region and reported separately.
 Prints one JSON line (value = trajectories/s over the timed steps) with the
 dominant kernel's roofline (algorithmic bytes per launch / HIP-event launch
 time, against 8 TB/s HBM) and the CPU FP64 oracle timed on a bounded sample.
+Untimed legs beside it:
+  fp64       the complex128 path on a prefix of the same job: per-trajectory
+             and mean error of the complex64 result, and of both against
+             stored oracle values;
+  plain_loop the same kernels one trajectory per launch, sequentially;
+  serving    the job server on the first arrivals of a Poisson stream (mean
+             200 jobs/s; n 10..30, p 1..6, K 256..8192, depolarizing rates
+             log-uniform in 1e-4..1e-2): p50/p99 latency, trajectories/s, and
+             the <C> error of sampled jobs against the complex128 path.
 """
 import argparse
 import json
@@ -45,6 +54,22 @@ def cpu_baseline(problem, sample_gates):
                       f"n={problem.n_qubits}, complex128, {dt:.1f} s, scaled by {G}/{sample_gates}"}
 
 
+def measured_traffic(kernel_source):
+    """HBM bytes per launch of the tiled pass from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None if the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "sv_pass_qaoa_n26_p4_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    with open(os.path.join(ROOT, kernel_source), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t["source_sha256"]:
+            return None
+    return t["traffic_bytes_per_launch"] / 1e9
+
+
 def fp64_check(energies_by_k, problem):
     """Largest |<C>_k - <C>_k(oracle, FP64)| / m over the stored oracle samples."""
     path = os.path.join(ROOT, "tests", "golden", "config2_sampled.json")
@@ -68,6 +93,13 @@ def main():
     ap.add_argument("--hbm-budget-gib", type=float, default=160.0)
     ap.add_argument("--cpu-sample-gates", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--fp64-prefix", type=int, default=1024,
+                    help="trajectories of the job also run in complex128 (0: skip)")
+    ap.add_argument("--plain-traj", type=int, default=16, help="trajectories of the one-per-launch loop (0: skip)")
+    ap.add_argument("--serve-jobs", type=int, default=16, help="arrivals of the serving stream (0: skip)")
+    ap.add_argument("--serve-window", type=float, default=40.0, help="seconds the serving leg runs")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="mean arrivals per second")
+    ap.add_argument("--serve-check-every", type=int, default=4, help="complex128 check of every k-th served job")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="copy a buffer of this size once before the timed region (a known-size reference "
                          "for hardware byte counters)")
@@ -137,6 +169,15 @@ def main():
     achieved = kern["bytes"] / (kern["ms"] * 1e-3) / 1e9 if kern["ms"] else None
     energies = {k: float(e) for k, e in enumerate(res["energies"])}
     times.sort()
+
+    plan.close()                    # release the headline workspace before the other legs
+    torch.cuda.empty_cache()
+    fp64 = fp64_leg(stn, problem, res["energies"], args.fp64_prefix) if args.fp64_prefix > 0 else None
+    torch.cuda.empty_cache()
+    plain = plain_loop(stn, problem, args.plain_traj, value) if args.plain_traj > 0 else None
+    torch.cuda.empty_cache()
+    serving = serving_leg(stn, args) if args.serve_jobs > 0 else None
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -156,16 +197,137 @@ def main():
                    "trajectories_per_launch": B, "passes_per_trajectory": info["n_passes"],
                    "plan_ms": plan_ms},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS if achieved else None,
+                     "traffic": measured_traffic("paper_2210_15874_amd/csrc/kernels_sv_tiled.hip")
+                     if kname == "sv_pass" and B == 319 else None, "traffic_unit": "GB per launch",
                      "launches": kern["launches"], "avg_launch_ms": kern["ms"] / max(1, kern["launches"]),
                      "bytes_per_launch": kern["bytes"] / max(1, kern["launches"])},
         "kernels": {k: {"launches": v["launches"], "ms": v["ms"]} for k, v in prof.items() if v["launches"]},
         "result": {"energy_mean": res["energy_mean"], "energy_se": res["energy_se"],
-                   "fp64_check": fp64_check(energies, problem)},
+                   "fp64_check": fp64_check(energies, problem), "fp64": fp64},
         "job_latency_ms": {"p50": times[len(times) // 2] * 1e3, "max": times[-1] * 1e3},
+        "plain_loop": plain,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def fp64_leg(stn, problem, e64, prefix):
+    """The complex128 tiled path on trajectories 0 .. prefix-1 of the job:
+    error of the complex64 energies against it (per trajectory and of the
+    mean), and of the complex128 energies against the stored oracle values."""
+    import numpy as np
+    prefix = min(prefix, problem.K)
+    pl = stn.Plan(problem, outputs=stn.OUT_ENERGY, precision=128, hbm_budget=160 << 30)
+    t0 = time.perf_counter()
+    e128 = stn.simulate_batch_ensemble(problem, K=prefix, plan=pl)["energies"]
+    dt = time.perf_counter() - t0
+    m = len(problem.edges)
+    e64 = np.asarray(e64[:prefix])
+    d = np.abs(e64 - e128) / m
+    out = {"trajectories": prefix, "plan": pl.info()["plan_name"], "seconds": dt,
+           "c64_vs_c128_max_abs_err_per_edge": float(d.max()),
+           "c64_vs_c128_mean_abs_err_per_edge": float(abs(e64.mean() - e128.mean()) / m),
+           "stochastic_se_per_edge": float(e128.std(ddof=1) / math.sqrt(prefix) / m)}
+    path = os.path.join(ROOT, "tests", "golden", "config2_sampled.json")
+    if os.path.exists(path):
+        with open(path) as f:
+            g = json.load(f)
+        errs = [abs(e128[r["k"]] - r["energy"]) / m for r in g["trajectories"] if r["k"] < prefix]
+        out["c128_vs_oracle_max_abs_err_per_edge"] = max(errs) if errs else None
+        out["oracle_trajectories"] = len(errs)
+    pl.close()
+    return out
+
+
+def plain_loop(stn, problem, n_traj, batched_value):
+    """Plain per-trajectory loop: the same kernels, one trajectory per launch,
+    sequential (sample, contract, reduce, synchronise)."""
+    import torch
+    pl = stn.Plan(problem, outputs=stn.OUT_ENERGY, precision=64, max_batch=1)
+    acc = pl.accum()
+    b = pl.sample(problem.seed, 0, 1)   # warm: tables, workspace
+    pl.contract(b)
+    torch.cuda.synchronize()
+    b.close()
+    t0 = time.perf_counter()
+    for k in range(n_traj):
+        b = pl.sample(problem.seed, k, 1)
+        pl.contract(b)
+        pl.reduce(b, acc)
+        torch.cuda.synchronize()
+        b.close()
+    dt = time.perf_counter() - t0
+    acc.close()
+    pl.close()
+    v = n_traj / dt
+    return {"value": v, "unit": "trajectories/s", "trajectories": n_traj, "batched_over_plain": batched_value / v}
+
+
+def serving_leg(stn, args):
+    """The first `serve_jobs` arrivals of the Poisson stream through the job
+    server at their arrival times, for a window of `serve_window` seconds from
+    the first arrival; latency = completion - arrival.  Jobs still running at
+    the end of the window are counted as censored (latency > window) and
+    abandoned; a percentile that falls on a censored job is reported as None."""
+    import numpy as np
+    import torch
+    from workloads import poisson_stream
+    arrivals, jobs = poisson_stream(args.serve_jobs, rate_per_s=args.serve_rate)
+    res = {}
+    sv = stn.Server(hbm_budget=int(args.hbm_budget_gib * (1 << 30)), job_share=0.5, n_streams=4, max_active=16,
+                    drain_on_destroy=False)
+    t0 = sv.clock()
+    for i, (ta, pr) in enumerate(zip(arrivals, jobs)):
+        while sv.clock() - t0 < ta:
+            time.sleep(min(1e-3, max(0.0, ta - (sv.clock() - t0))))
+        sv.submit(pr, tag=i)
+    while sv.clock() - t0 < args.serve_window and len(res) < len(jobs):
+        for r in sv.poll(wait=0.5, cap=4096):
+            res[r["tag"]] = r
+    t_end = min(sv.clock() - t0, args.serve_window)
+    st = sv.stats()
+    sv.close()                      # abandons unfinished jobs
+    lat = np.array([res[i]["t_done"] - t0 - arrivals[i] if i in res else np.inf for i in range(len(jobs))])
+    done = [i for i in res if res[i]["status"] == 0]
+    traj = sum(res[i]["K"] for i in done)
+
+    def pct(q):
+        v = float(np.percentile(lat, q, method="higher"))
+        return v if math.isfinite(v) else None
+
+    checks = []
+    # every k-th finished job up to n = 24 (the complex128 path costs ~3x the complex64 one)
+    chk = [i for i in range(0, len(jobs), max(1, args.serve_check_every)) if i in done and jobs[i].n_qubits <= 24]
+    if chk:
+        with stn.Server(hbm_budget=int(args.hbm_budget_gib * (1 << 30)), precision=128) as sv2:
+            for i in chk:
+                sv2.submit(jobs[i], tag=i)
+            sv2.drain(3600)
+            ref = {r["tag"]: r for r in sv2.poll(cap=4096)}
+        for i in chk:
+            m = max(1, len(jobs[i].edges))
+            checks.append({"job": i, "n": jobs[i].n_qubits, "p": jobs[i].p, "K": jobs[i].K,
+                           "plan": res[i]["plan_name"],
+                           "abs_err_per_edge": abs(res[i]["energy_mean"] - ref[i]["energy_mean"]) / m,
+                           "se_per_edge": res[i]["energy_se"] / m})
+    torch.cuda.synchronize()
+    return {
+        "jobs": len(jobs), "rate_per_s": args.serve_rate, "window_s": args.serve_window,
+        "completed": len(done), "censored": len(jobs) - len(res),
+        "failed": int(sum(r["status"] != 0 for r in res.values())),
+        "latency_s": {"p50": pct(50), "p99": pct(99), "max_completed": float(lat[np.isfinite(lat)].max())
+                      if np.isfinite(lat).any() else None},
+        "trajectories_per_s": traj / t_end if t_end > 0 else None, "arrivals_span_s": arrivals[-1],
+        "max_concurrent_jobs": st["max_active_jobs"],
+        "plans": {k: sum(1 for r in res.values() if r["plan_name"] == k) for k in ("sv_lds", "sv_tiled", "lightcone")},
+        "jobs_detail": [{"n": jobs[i].n_qubits, "p": jobs[i].p, "K": jobs[i].K,
+                         "latency_s": None if not math.isfinite(lat[i]) else float(lat[i]),
+                         "plan": res[i]["plan_name"] if i in res else None} for i in range(len(jobs))],
+        "offered": "arrival rate far above one GPU's capacity: latency is mostly queueing behind n >= 26 jobs",
+        "fp64_checks": checks,
+    }
 
 
 if __name__ == "__main__":

@@ -220,10 +220,12 @@ def poisson_stream(n_jobs: int, rate_per_s: float = 200.0, seed: int = 1004, n_r
     """Arrival times (s) and jobs of a Poisson stream of noisy-QAOA energy jobs;
     depolarizing rates are drawn log-uniformly and independently for 1q / 2q."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    t = np.cumsum(rng.exponential(1.0 / rate_per_s, n_jobs))
-    jobs = []
+    t, jobs = [], []
+    now = 0.0
     lo, hi = math.log(lam_range[0]), math.log(lam_range[1])
-    for j in range(n_jobs):
+    for j in range(n_jobs):   # one job at a time: the first m arrivals do not depend on n_jobs
+        now += float(rng.exponential(1.0 / rate_per_s))
+        t.append(now)
         n = int(rng.integers(n_range[0], n_range[1] + 1))
         p = int(rng.integers(p_range[0], p_range[1] + 1))
         K = int(rng.integers(K_range[0], K_range[1] + 1))
@@ -232,4 +234,4 @@ def poisson_stream(n_jobs: int, rate_per_s: float = 200.0, seed: int = 1004, n_r
         g, b = uniform_angles(p, int(rng.integers(1 << 31)))
         jobs.append(make_problem(n, edges, g, b, l1, l2, K, int(rng.integers(1 << 62)),
                                  name=f"stream-n{n}-p{p}-K{K}-j{j}"))
-    return [float(x) for x in t], jobs
+    return t, jobs
