@@ -279,6 +279,26 @@ def test_tiled_complex64_against_complex128_n22():
     assert np.abs(res[64] - res[128]).max() > 0     # two different arithmetics
 
 
+@pytest.mark.parametrize("n,p", [(30, 2), (18, 3), (28, 1)])
+def test_tiled_tile_counts_complex64_against_complex128(n, p):
+    """Tiles of 3 (n=28, 30) and 2 (n=18) per layer, merged layer
+    boundaries: energies of the same draws against the complex128 passes
+    (12-qubit tiles, another schedule)."""
+    stn = stn_mod()
+    pr = qaoa(n, p, 60 + n, 2e-3, 2e-2, 6)
+    res = {}
+    for precision in (64, 128):
+        pl = stn.Plan(pr, plan_kind=stn.PLAN_SV_TILED, precision=precision, hbm_budget=64 << 30)
+        b = pl.sample(pr.seed, 0, pr.K)
+        pl.contract(b)
+        res[precision] = b.energies()
+        b.close()
+        pl.close()
+        torch.cuda.empty_cache()
+    m = len(pr.edges)
+    np.testing.assert_allclose(res[64] / m, res[128] / m, atol=1e-5)
+
+
 def test_lightcone_matches_tiled_statevector():
     stn = stn_mod()
     pr = qaoa(20, 2, 44, 0.01, 0.05, 32)
