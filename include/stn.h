@@ -158,6 +158,8 @@ typedef struct {
     double bytes_per_traj;  /* algorithmic HBM bytes per trajectory (cost model) */
     double flops_per_traj;  /* algorithmic flops per trajectory (cost model) */
     double peak_bytes;      /* device working memory at max_batch */
+    uint32_t lc_width;      /* lightcone networks' width when the planner built them (0: not built) */
+    double lc_flops_per_traj; /* their flops per trajectory */
 } stn_plan_stats;
 
 typedef struct {

@@ -70,7 +70,8 @@ class PlanStats(C.Structure):
     _fields_ = [("plan_kind", C.c_uint32), ("n_qubits", C.c_uint32), ("n_gates", C.c_uint32),
                 ("n_sites", C.c_uint32), ("max_batch", C.c_uint32), ("width", C.c_uint32),
                 ("n_passes", C.c_uint32), ("n_steps", C.c_uint32), ("bytes_per_traj", C.c_double),
-                ("flops_per_traj", C.c_double), ("peak_bytes", C.c_double)]
+                ("flops_per_traj", C.c_double), ("peak_bytes", C.c_double), ("lc_width", C.c_uint32),
+                ("lc_flops_per_traj", C.c_double)]
 
 
 class KernelStats(C.Structure):

@@ -230,6 +230,8 @@ stn_status stn_plan_info(const stn_plan* p, stn_plan_stats* o) {
     o->bytes_per_traj = p->bytes_per_traj;
     o->flops_per_traj = p->flops_per_traj;
     o->peak_bytes = p->peak_bytes;
+    o->lc_width = p->lc_width;
+    o->lc_flops_per_traj = p->lc_flops_per_traj;
     return STN_OK;
 }
 

@@ -175,16 +175,20 @@ void build_lightcone(stn_plan* p) {
     const size_t elem = p->opts.precision == 128 ? 16 : 8;
     double cost = 0;
     int width = 0;
+    int max_rank = 0;
     for (size_t t = 0; t < p->obs_u.size(); ++t) {
         d->nets.push_back(build_term(p, p->obs_u[t], p->obs_v[t], p->opts.order_restarts, p->opts.order_seed));
         const TnNetwork& net = d->nets.back();
         for (auto& st : net.steps)
-            for (auto& in : st.inputs)
-                if ((int)in.pos.size() > kMaxPos) fail(STN_E_UNSUPPORTED, "lightcone step rank above 14");
+            for (auto& in : st.inputs) max_rank = std::max(max_rank, (int)in.pos.size());
         d->arena = std::max(d->arena, net.arena);
         width = std::max(width, net.width);
         cost += net.cost;
     }
+    // the networks' size is known even where this lowering cannot run them
+    p->lc_width = (uint32_t)width;
+    p->lc_flops_per_traj = 8.0 * cost;
+    if (max_rank > kMaxPos) fail(STN_E_UNSUPPORTED, "lightcone step rank above 14 (width " + std::to_string(width) + ")");
     if ((size_t)d->arena * elem > (size_t)kLdsBytes)
         fail(STN_E_UNSUPPORTED, "lightcone intermediates exceed the LDS arena (width " + std::to_string(width) + ")");
     p->width = (uint32_t)width;

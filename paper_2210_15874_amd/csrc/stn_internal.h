@@ -154,6 +154,8 @@ struct stn_plan {
     // cost model
     double bytes_per_traj = 0, flops_per_traj = 0, peak_bytes = 0;
     uint32_t width = 0, n_passes = 0, n_steps = 0;
+    uint32_t lc_width = 0;                  // lightcone networks: width and flops, when they were built
+    double lc_flops_per_traj = 0;
 
     // device tables shared by every lowering
     stn::DevBuf d_site_T;            // uint64 thresholds, flattened
