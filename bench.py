@@ -100,6 +100,10 @@ def main():
     ap.add_argument("--serve-window", type=float, default=40.0, help="seconds the serving leg runs")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean arrivals per second")
     ap.add_argument("--serve-check-every", type=int, default=4, help="complex128 check of every k-th served job")
+    ap.add_argument("--rho-leg", type=int, default=1, help="n=12 rho_hat workload leg (0: skip)")
+    ap.add_argument("--ksweep", action="store_true",
+                    help="rho_hat leg: fidelity / trace distance vs the exact density matrix for K = 16..1024 "
+                         "(adds minutes of CPU work)")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="copy a buffer of this size once before the timed region (a known-size reference "
                          "for hardware byte counters)")
@@ -176,6 +180,8 @@ def main():
     torch.cuda.empty_cache()
     plain = plain_loop(stn, problem, args.plain_traj, value) if args.plain_traj > 0 else None
     torch.cuda.empty_cache()
+    rho_leg = rho_hat_leg(stn, args.ksweep) if args.rho_leg else None
+    torch.cuda.empty_cache()
     serving = serving_leg(stn, args) if args.serve_jobs > 0 else None
 
     out = {
@@ -207,6 +213,7 @@ def main():
                    "fp64_check": fp64_check(energies, problem), "fp64": fp64},
         "job_latency_ms": {"p50": times[len(times) // 2] * 1e3, "max": times[-1] * 1e3},
         "plain_loop": plain,
+        "rho_hat": rho_leg,
         "serving": serving,
         "cpu_baseline": cpu,
     }
@@ -263,6 +270,64 @@ def plain_loop(stn, problem, n_traj, batched_value):
     pl.close()
     v = n_traj / dt
     return {"value": v, "unit": "trajectories/s", "trajectories": n_traj, "batched_over_plain": batched_value / v}
+
+
+def rho_hat_leg(stn, ksweep):
+    """n=12 QAOA p=2, 3-regular, depolarizing + amplitude damping, K=1024 in
+    one launch: complex64 contraction, FP64 rho_hat (4096 x 4096).  Times the
+    job and its FP64 matrix-core rank-K update; with ksweep, the fidelity and
+    trace distance of nested prefixes K = 16 .. 1024 against the exact
+    density matrix (oracle, CPU)."""
+    import numpy as np
+    import torch
+    from workloads import config_problem
+    pr = config_problem(1)
+    pl = stn.Plan(pr, outputs=stn.OUT_RHO | stn.OUT_ENERGY, precision=64)
+    stn.simulate_batch_ensemble(pr, plan=pl)            # warm
+    torch.cuda.synchronize()
+    pl.profile(True)
+    t0 = time.perf_counter()
+    res = stn.simulate_batch_ensemble(pr, plan=pl)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = pl.profile_read()
+    pl.profile(False)
+    herk = prof["herk"]
+    out = {"workload": pr.name, "K": pr.K, "seconds": dt, "trajectories_per_s": pr.K / dt,
+           "kernels_ms": {k: v["ms"] for k, v in prof.items() if v["launches"]},
+           "herk_fp64_tflops": herk["flops"] / (herk["ms"] * 1e-3) / 1e12 if herk["ms"] else None,
+           "herk_peak_tflops": 78.6, "trace": res["trace"]}
+    if ksweep:
+        from oracle import metrics, simulate as sim
+        t1 = time.perf_counter()
+        print("rho_hat leg: exact density matrix (oracle, CPU) ...", file=sys.stderr, flush=True)
+        rho = sim.density_matrix(pr)
+        N = rho.shape[0]
+        rho = rho.reshape(N, N)
+        out["dm_oracle_seconds"] = time.perf_counter() - t1
+        edges = [0, 16, 32, 64, 128, 256, 512, 1024]
+        acc_sum = np.zeros((N, N), dtype=np.complex128)
+        rows = []
+        for a, b in zip(edges[:-1], edges[1:]):
+            acc = pl.accum()
+            bt = pl.sample(pr.seed, a, b - a)
+            pl.contract(bt)
+            pl.reduce(bt, acc)
+            r = acc.read()
+            acc_sum += r["rho"] * r["k_done"]
+            acc.close()
+            bt.close()
+            est = acc_sum / b
+            est_n = est / np.trace(est).real
+            rows.append({"K": b, "trace": float(np.trace(est).real),
+                         "fidelity": metrics.uhlmann_fidelity(rho, est_n),
+                         "trace_distance": metrics.trace_distance(rho, est_n),
+                         "frobenius": metrics.frobenius(rho, est_n),
+                         "eq2_error": metrics.paper_error(np.diag(est_n).real, np.diag(rho).real)})
+            print(f"rho_hat leg: K={b} {rows[-1]}", file=sys.stderr, flush=True)
+        out["ksweep"] = rows
+    pl.close()
+    return out
 
 
 def serving_leg(stn, args):

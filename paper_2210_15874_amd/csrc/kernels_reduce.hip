@@ -3,9 +3,14 @@
 // energy <C>).
 //
 // k_herk:     rho += Psi^T conj(Psi) over a batch of B statevectors, only the
-//             tiles on or above the diagonal (I <= J); products of complex64
-//             amplitudes are formed in binary64.  Every element has a single
-//             writer per launch and the batch is summed in trajectory order.
+//             64x64 tiles on or above the diagonal (I <= J), on the FP64
+//             matrix cores.  With X = [Re Psi^T | Im Psi^T] and
+//             Y = [Im Psi^T | -Re Psi^T] (N x 2B, the two parts of each
+//             trajectory interleaved), Re rho = X X^T and Im rho = Y X^T: two
+//             real rank-2B updates of 16x16 blocks by v_mfma_f64_16x16x4
+//             (k = 4: two trajectories per step).  Amplitudes are widened to
+//             binary64 before the products; every element has a single writer
+//             per launch.
 // k_diag:     diag += sum_b |psi_b|^2 in trajectory order.
 // k_stats:    mean and standard error of the per-trajectory energies, summed
 //             in a fixed order (strided per thread, then a fixed tree), two
@@ -23,6 +28,12 @@ template <class V> __device__ __forceinline__ double2 widen(V v) { return make_d
 constexpr int kTile = 64;   // output tile edge
 constexpr int kChunk = 16;  // trajectories per LDS stage
 
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+// Operand and result layout of v_mfma_f64_16x16x4_f64 (64 lanes, measured on
+// gfx950 with one-hot operands): A (16x4) lane l holds A[l % 16][l / 16];
+// B (4x16) lane l holds B[l / 16][l % 16]; D (16x16) lane l, component v
+// holds D[l / 16 + 4 v][l % 16].
 template <class V>
 __global__ __launch_bounds__(256) void k_herk(const V* __restrict__ Psi, uint32_t B, uint32_t N, uint32_t tiles,
                                               double2* __restrict__ rho) {
@@ -33,14 +44,20 @@ __global__ __launch_bounds__(256) void k_herk(const V* __restrict__ Psi, uint32_
         ++I;
     }
     const uint32_t J = I + t;
-    __shared__ double2 A[kChunk][kTile];
-    __shared__ double2 C[kChunk][kTile];
-    const uint32_t tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    double2 acc[4][4];
+    __shared__ double2 A[kChunk][kTile];   // rows i0.., widened amplitudes
+    __shared__ double2 C[kChunk][kTile];   // cols j0..
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t rw = (wave >> 1) * 32, cw = (wave & 1) * 32;   // this wave's 32x32 sub-block
+    const uint32_t l16 = lane & 15, k4 = lane >> 4;               // row/col in block, k index
+    const uint32_t kb = k4 >> 1, part = k4 & 1;                    // trajectory within the step, re/im
+    d4_t re[2][2], im[2][2];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = make_double2(0.0, 0.0);
+        for (int c = 0; c < 2; ++c) {
+            re[r][c] = d4_t{0.0, 0.0, 0.0, 0.0};
+            im[r][c] = d4_t{0.0, 0.0, 0.0, 0.0};
+        }
     const uint32_t i0 = I * kTile, j0 = J * kTile;
     for (uint32_t b0 = 0; b0 < B; b0 += kChunk) {
         for (uint32_t e = threadIdx.x; e < kChunk * kTile; e += 256) {
@@ -50,37 +67,45 @@ __global__ __launch_bounds__(256) void k_herk(const V* __restrict__ Psi, uint32_
             C[bb][x] = (ok && j0 + x < N) ? widen(Psi[(size_t)(b0 + bb) * N + j0 + x]) : make_double2(0.0, 0.0);
         }
         __syncthreads();
-#pragma unroll 4
-        for (int bb = 0; bb < kChunk; ++bb) {
-            double2 a[4], c[4];
+#pragma unroll 2
+        for (int bb = 0; bb < kChunk; bb += 2) {
+            double ax[2], ay[2], bx[2];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) a[r] = A[bb][ty + 16 * r];
+            for (int r = 0; r < 2; ++r) {
+                const double2 a = A[bb + kb][rw + 16 * r + l16];
+                ax[r] = part ? a.y : a.x;      // X[i][k]
+                ay[r] = part ? -a.x : a.y;     // Y[i][k]
+            }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) c[q] = C[bb][tx + 16 * q];
+            for (int c = 0; c < 2; ++c) {
+                const double2 v = C[bb + kb][cw + 16 * c + l16];
+                bx[c] = part ? v.y : v.x;      // X[j][k] as B[k][j]
+            }
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int r = 0; r < 2; ++r)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    // a * conj(c)
-                    acc[r][q].x = fma(a[r].x, c[q].x, fma(a[r].y, c[q].y, acc[r][q].x));
-                    acc[r][q].y = fma(a[r].y, c[q].x, fma(-a[r].x, c[q].y, acc[r][q].y));
+                for (int c = 0; c < 2; ++c) {
+                    re[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax[r], bx[c], re[r][c], 0, 0, 0);
+                    im[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ay[r], bx[c], im[r][c], 0, 0, 0);
                 }
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t i = i0 + ty + 16 * r, j = j0 + tx + 16 * q;
-            if (i < N && j < N && i <= j) {
-                double2* d = rho + (size_t)i * N + j;
-                double2 v = *d;
-                v.x += acc[r][q].x;
-                v.y += acc[r][q].y;
-                *d = v;
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const uint32_t i = i0 + rw + 16 * r + k4 + 4 * v, j = j0 + cw + 16 * c + l16;
+                if (i < N && j < N && i <= j) {
+                    double2* d = rho + (size_t)i * N + j;
+                    double2 o = *d;
+                    o.x += re[r][c][v];
+                    o.y += im[r][c][v];
+                    *d = o;
+                }
             }
-        }
 }
 
 template <class V>
