@@ -160,7 +160,15 @@ typedef struct {
     double peak_bytes;      /* device working memory at max_batch */
     uint32_t lc_width;      /* lightcone networks' width when the planner built them (0: not built) */
     double lc_flops_per_traj; /* their flops per trajectory */
+    uint32_t variant;       /* launch shape of the contraction kernels (stn_plan_autotune) */
+    uint32_t tuned;         /* 1 after stn_plan_autotune or stn_plan_set_variant */
 } stn_plan_stats;
+
+typedef struct {
+    uint32_t n_variants;    /* launch shapes of this plan's lowering */
+    uint32_t chosen;        /* the fastest, now the plan's */
+    double ms[8];           /* per variant: mean event time of one contraction of the batch */
+} stn_tune_result;
 
 typedef struct {
     uint64_t k_done;        /* trajectories reduced so far */
@@ -258,6 +266,17 @@ stn_status stn_profile(stn_plan* plan, int enable);
 /* Fills out[0 .. STN_K_COUNT) with the timings since enabling. Syncs. */
 stn_status stn_profile_read(stn_plan* plan, stn_kernel_stats* out);
 
+/* Launch-shape autotuning: contracts `batch` (a sampled batch of this plan)
+ * `reps` times with every launch shape of the plan's lowering (threads per
+ * workgroup of the LDS and lightcone kernels, persistent grid of the tiled
+ * one), timed with HIP events on `stream`, and keeps the fastest.  Results do
+ * not depend on the shape (each output has one writer in a fixed order), so
+ * the batch is left contracted.  Synchronises the stream. */
+stn_status stn_plan_autotune(stn_plan* plan, stn_batch* batch, uint32_t reps, stn_tune_result* out, void* stream);
+/* Sets the launch shape directly (a cached tuning result); out of range:
+ * STN_E_INVALID. */
+stn_status stn_plan_set_variant(stn_plan* plan, uint32_t variant);
+
 /* Accumulator of one job's ensemble sums (FP64, device-resident). */
 stn_status stn_accum_create(stn_plan* plan, stn_accum** out);
 
@@ -297,6 +316,7 @@ typedef struct {
     uint32_t precision;      /* 64 (complex64) or 128 (complex128) for every job */
     uint32_t chunk_max;      /* trajectories per chunk cap (0: the plan's max batch) */
     uint32_t drain_on_destroy; /* 1: stn_server_destroy waits for every submitted job */
+    uint32_t reserve_cus;    /* CUs the persistent (tiled) kernels leave free for other jobs' kernels */
 } stn_server_opts;
 
 typedef struct {
@@ -324,12 +344,13 @@ typedef struct {
     uint64_t chunks;         /* chunks issued */
     uint64_t max_active_jobs;/* most jobs admitted at the same time */
     uint64_t plan_cache_hits, plan_cache_misses, plans_cached;
+    uint64_t autotuned;      /* plan shapes whose launch shape was timed (then reused for the shape) */
     uint64_t bytes_in_use, bytes_cached, bytes_peak;   /* device pool */
     double clock;            /* server clock when read */
 } stn_server_stats;
 
 /* Defaults: 64 GiB budget, job_share 0.5, 4 streams, 16 active jobs, 64
- * cached plans, complex64, drain on destroy. */
+ * cached plans, complex64, drain on destroy, 32 reserved CUs. */
 void stn_server_opts_default(stn_server_opts* opts);
 /* Starts the server's threads on the calling thread's current device. */
 stn_status stn_server_create(const stn_server_opts* opts, stn_server** out);

@@ -71,7 +71,11 @@ class PlanStats(C.Structure):
                 ("n_sites", C.c_uint32), ("max_batch", C.c_uint32), ("width", C.c_uint32),
                 ("n_passes", C.c_uint32), ("n_steps", C.c_uint32), ("bytes_per_traj", C.c_double),
                 ("flops_per_traj", C.c_double), ("peak_bytes", C.c_double), ("lc_width", C.c_uint32),
-                ("lc_flops_per_traj", C.c_double)]
+                ("lc_flops_per_traj", C.c_double), ("variant", C.c_uint32), ("tuned", C.c_uint32)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("n_variants", C.c_uint32), ("chosen", C.c_uint32), ("ms", C.c_double * 8)]
 
 
 class KernelStats(C.Structure):
@@ -90,7 +94,7 @@ class Result(C.Structure):
 class ServerOpts(C.Structure):
     _fields_ = [("hbm_budget", C.c_uint64), ("job_share", C.c_double), ("n_streams", C.c_uint32),
                 ("max_active", C.c_uint32), ("plan_cache", C.c_uint32), ("precision", C.c_uint32),
-                ("chunk_max", C.c_uint32), ("drain_on_destroy", C.c_uint32)]
+                ("chunk_max", C.c_uint32), ("drain_on_destroy", C.c_uint32), ("reserve_cus", C.c_uint32)]
 
 
 class JobResult(C.Structure):
@@ -105,7 +109,8 @@ class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("failed", C.c_uint64),
                 ("active", C.c_uint64), ("waiting", C.c_uint64), ("trajectories", C.c_uint64),
                 ("chunks", C.c_uint64), ("max_active_jobs", C.c_uint64), ("plan_cache_hits", C.c_uint64),
-                ("plan_cache_misses", C.c_uint64), ("plans_cached", C.c_uint64), ("bytes_in_use", C.c_uint64),
+                ("plan_cache_misses", C.c_uint64), ("plans_cached", C.c_uint64), ("autotuned", C.c_uint64),
+                ("bytes_in_use", C.c_uint64),
                 ("bytes_cached", C.c_uint64), ("bytes_peak", C.c_uint64), ("clock", C.c_double)]
 
 
@@ -124,6 +129,8 @@ EXPORTS = {
     "stn_batch_indices": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint8)]),
     "stn_contract": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "stn_batch_results": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "stn_plan_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(TuneResult), C.c_void_p]),
+    "stn_plan_set_variant": (C.c_int, [C.c_void_p, C.c_uint32]),
     "stn_batch_size": (C.c_uint32, [C.c_void_p]),
     "stn_batch_destroy": (None, [C.c_void_p]),
     "stn_profile": (C.c_int, [C.c_void_p, C.c_int]),
@@ -292,6 +299,17 @@ class Plan:
     def contract(self, batch, stream=None):
         _check(self.lib.stn_contract(self.h, batch.h, stream if stream is not None else current_stream()))
 
+    def autotune(self, batch, reps=2, stream=None):
+        """Times every launch shape of this plan's contraction on `batch` and
+        keeps the fastest; returns {"chosen": v, "ms": [...]}."""
+        r = TuneResult()
+        _check(self.lib.stn_plan_autotune(self.h, batch.h, int(reps), C.byref(r),
+                                          stream if stream is not None else current_stream()))
+        return {"chosen": r.chosen, "ms": [r.ms[i] for i in range(r.n_variants)]}
+
+    def set_variant(self, v):
+        _check(self.lib.stn_plan_set_variant(self.h, int(v)))
+
     def profile(self, enable=True):
         _check(self.lib.stn_profile(self.h, 1 if enable else 0))
 
@@ -415,7 +433,7 @@ class Server:
     PyTorch's allocator; hbm_budget bounds it."""
 
     def __init__(self, hbm_budget=64 << 30, job_share=0.5, n_streams=4, max_active=16, plan_cache=64,
-                 precision=64, chunk_max=0, drain_on_destroy=True):
+                 precision=64, chunk_max=0, drain_on_destroy=True, reserve_cus=32):
         self.lib = load()
         o = ServerOpts()
         self.lib.stn_server_opts_default(C.byref(o))
@@ -427,6 +445,7 @@ class Server:
         o.precision = precision
         o.chunk_max = chunk_max
         o.drain_on_destroy = 1 if drain_on_destroy else 0
+        o.reserve_cus = int(reserve_cus)
         h = C.c_void_p()
         _check_srv(self.lib.stn_server_create(C.byref(o), C.byref(h)))
         self.h = h

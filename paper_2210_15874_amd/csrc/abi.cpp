@@ -232,6 +232,8 @@ stn_status stn_plan_info(const stn_plan* p, stn_plan_stats* o) {
     o->peak_bytes = p->peak_bytes;
     o->lc_width = p->lc_width;
     o->lc_flops_per_traj = p->lc_flops_per_traj;
+    o->variant = p->variant;
+    o->tuned = p->tuned ? 1 : 0;
     return STN_OK;
 }
 
@@ -335,23 +337,90 @@ stn_status stn_batch_indices(const stn_batch* b, uint8_t* host_out) {
     });
 }
 
+static uint32_t plan_variants(const stn_plan* p) {
+    switch (p->kind) {
+        case STN_PLAN_SV_LDS: return lds_variants();
+        case STN_PLAN_SV_TILED: return tiled_variants(p);
+        case STN_PLAN_LIGHTCONE: return tn_variants();
+        default: return 1;
+    }
+}
+
+static void contract_launch(stn_plan* p, stn_batch* b, hipStream_t s) {
+    switch (p->kind) {
+        case STN_PLAN_SV_LDS: launch_sv_lds(p, b, s); break;
+        case STN_PLAN_SV_TILED:
+            if (p->opts.precision == 128) launch_sv_tiled128(p, b, s);
+            else launch_sv_tiled(p, b, s);
+            break;
+        case STN_PLAN_LIGHTCONE: launch_lightcone(p, b, s); break;
+        default: fail(STN_E_STATE, "plan has no lowering");
+    }
+}
+
 stn_status stn_contract(stn_plan* p, stn_batch* b, void* stream) {
     if (!p || !b) return set_error(STN_E_INVALID, "NULL argument");
     if (b->plan != p) return set_error(STN_E_INVALID, "batch belongs to another plan");
     return guarded([&] {
         hipStream_t s = (hipStream_t)stream;
         ensure_uploaded(p, s);
-        switch (p->kind) {
-            case STN_PLAN_SV_LDS: launch_sv_lds(p, b, s); break;
-            case STN_PLAN_SV_TILED:
-                if (p->opts.precision == 128) launch_sv_tiled128(p, b, s);
-                else launch_sv_tiled(p, b, s);
-                break;
-            case STN_PLAN_LIGHTCONE: launch_lightcone(p, b, s); break;
-            default: fail(STN_E_STATE, "plan has no lowering");
-        }
+        contract_launch(p, b, s);
         b->contracted = true;
     });
+}
+
+stn_status stn_plan_autotune(stn_plan* p, stn_batch* b, uint32_t reps, stn_tune_result* out, void* stream) {
+    if (!p || !b) return set_error(STN_E_INVALID, "NULL argument");
+    if (b->plan != p) return set_error(STN_E_INVALID, "batch belongs to another plan");
+    if (reps == 0) reps = 1;
+    return guarded([&] {
+        hipStream_t s = (hipStream_t)stream;
+        ensure_uploaded(p, s);
+        const uint32_t nv = std::min<uint32_t>(plan_variants(p), 8);
+        hipEvent_t e0, e1;
+        STN_HIP(hipEventCreate(&e0));
+        STN_HIP(hipEventCreate(&e1));
+        double ms[8] = {0};
+        uint32_t best = 0;
+        try {
+            for (uint32_t v = 0; v < nv; ++v) {
+                p->variant = v;
+                contract_launch(p, b, s);   // warm (code object, attributes)
+                STN_HIP(hipEventRecord(e0, s));
+                for (uint32_t r = 0; r < reps; ++r) contract_launch(p, b, s);
+                STN_HIP(hipEventRecord(e1, s));
+                STN_HIP(hipEventSynchronize(e1));
+                float t = 0;
+                STN_HIP(hipEventElapsedTime(&t, e0, e1));
+                ms[v] = t / reps;
+                if (ms[v] < ms[best]) best = v;
+            }
+        } catch (...) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            p->variant = 0;
+            throw;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        p->variant = best;
+        p->tuned = true;
+        b->contracted = true;
+        if (out) {
+            std::memset(out, 0, sizeof(*out));
+            out->n_variants = nv;
+            out->chosen = best;
+            for (uint32_t v = 0; v < nv; ++v) out->ms[v] = ms[v];
+        }
+    });
+}
+
+stn_status stn_plan_set_variant(stn_plan* p, uint32_t variant) {
+    if (!p) return set_error(STN_E_INVALID, "NULL argument");
+    if (variant >= plan_variants(p)) return set_error(STN_E_INVALID, "launch-shape variant out of range");
+    p->variant = variant;
+    p->tuned = true;
+    return STN_OK;
 }
 
 stn_status stn_batch_results(const stn_batch* b, double* energies, double* states) {

@@ -8,9 +8,10 @@
 // the dense K_j / sqrt(q_j)).  The trajectory index is the grid dimension, so
 // every launch contracts the whole batch.
 //
-// Epilogue: the energy <psi|C|psi> of C = sum_t w_t [z_u != z_v], summed in
-// binary64 per thread and reduced over the workgroup in a fixed order, and
-// optionally the final statevector.
+// Epilogue: optionally the final statevector, then the energy <psi|C|psi> of
+// C = sum_t w_t [z_u != z_v]: each amplitude's term in binary64 into LDS, and
+// a pairwise tree over the 2^n terms, so the result does not depend on the
+// workgroup size (a launch shape the autotuner picks).
 #include "stn_internal.h"
 
 namespace stn {
@@ -43,9 +44,7 @@ __device__ __forceinline__ uint32_t ins0(uint32_t p, uint32_t q) {
     return ((p ^ lo) << 1) | lo;
 }
 
-constexpr int kThreads = 256;
-
-template <class R>
+template <class R, int kThreads>
 __global__ __launch_bounds__(kThreads) void k_sv_lds(uint32_t n, const LdsOp* __restrict__ ops, uint32_t n_ops,
                                                     const typename Cx<R>::T* __restrict__ vals,
                                                     const LdsOp* __restrict__ site_ops,
@@ -58,7 +57,6 @@ __global__ __launch_bounds__(kThreads) void k_sv_lds(uint32_t n, const LdsOp* __
     using V = typename Cx<R>::T;
     extern __shared__ char smem_raw[];
     V* psi = reinterpret_cast<V*>(smem_raw);
-    __shared__ double red[kThreads];
     const uint32_t b = blockIdx.x;
     const uint32_t tid = threadIdx.x;
     const uint32_t N = 1u << n;
@@ -136,24 +134,46 @@ __global__ __launch_bounds__(kThreads) void k_sv_lds(uint32_t n, const LdsOp* __
         }
         __syncthreads();
     }
-    // energy <psi|C|psi> in binary64
-    double acc = 0.0;
+    // energy <psi|C|psi> in binary64: per-amplitude terms, then a fixed tree
+    if (states)
+        for (uint32_t i = tid; i < N; i += kThreads) states[(size_t)b * N + i] = psi[i];
+    double* e = reinterpret_cast<double*>(smem_raw) + (sizeof(V) == 8 ? 0 : 2 * (size_t)N);
     for (uint32_t i = tid; i < N; i += kThreads) {
-        const V v = psi[i];
+        const V v = psi[i];   // complex64: e[i] takes psi[i]'s own 8 bytes
         const double pr = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
         double c = 0.0;
         for (uint32_t t = 0; t < n_terms; ++t)
             c += ((i >> obs_uv[2 * t]) ^ (i >> obs_uv[2 * t + 1])) & 1 ? obs_w[t] : 0.0;
-        acc += pr * c;
-        if (states) states[(size_t)b * N + i] = v;
+        e[i] = pr * c;
     }
-    red[tid] = acc;
     __syncthreads();
-    for (uint32_t w = kThreads / 2; w > 0; w >>= 1) {
-        if (tid < w) red[tid] += red[tid + w];
+    for (uint32_t h = N / 2; h > 0; h >>= 1) {
+        for (uint32_t i = tid; i < h; i += kThreads) e[i] += e[i + h];
         __syncthreads();
     }
-    if (tid == 0) energy[b] = red[0];
+    if (tid == 0) energy[b] = e[0];
+}
+
+template <class R>
+using LdsFn = void (*)(uint32_t, const LdsOp*, uint32_t, const typename Cx<R>::T*, const LdsOp*, const uint32_t*,
+                       const uint8_t*, uint32_t, const uint32_t*, const double*, uint32_t, double*,
+                       typename Cx<R>::T*);
+
+struct LdsKernel {
+    void* f;
+    uint32_t threads;
+};
+
+// launch shapes the autotuner chooses from (variant 0 is the default)
+constexpr uint32_t kLdsVariants = 4;
+template <class R>
+LdsKernel lds_kernel(uint32_t v) {
+    switch (v) {
+        case 1: return {(void*)k_sv_lds<R, 128>, 128};
+        case 2: return {(void*)k_sv_lds<R, 512>, 512};
+        case 3: return {(void*)k_sv_lds<R, 1024>, 1024};
+        default: return {(void*)k_sv_lds<R, 256>, 256};
+    }
 }
 
 }  // namespace
@@ -168,37 +188,41 @@ void launch_sv_lds(stn_plan* p, stn_batch* b, hipStream_t s) {
         b->d_states.ensure(&p->alloc, N * b->K * elem);
         b->has_states = true;
     }
-    const size_t lds = N * elem;
-    static bool attr_set[2] = {false, false};
-    if (!attr_set[dbl]) {
-        if (dbl) STN_HIP(hipFuncSetAttribute((const void*)k_sv_lds<double>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536));
-        else STN_HIP(hipFuncSetAttribute((const void*)k_sv_lds<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536));
-        attr_set[dbl] = true;
-    }
+    // complex128 needs room for the binary64 terms beside the state
+    const size_t lds = N * elem + (dbl ? N * 8 : 0);
     const uint32_t S = (uint32_t)p->sites.size();
     const uint32_t T = (uint32_t)p->obs_u.size();
+    const uint32_t v = std::min<uint32_t>(p->variant, kLdsVariants - 1);
+    const LdsKernel ker = dbl ? lds_kernel<double>(v) : lds_kernel<float>(v);
+    static bool attr_set[2][kLdsVariants] = {};
+    if (!attr_set[dbl][v]) {
+        STN_HIP(hipFuncSetAttribute((const void*)ker.f, hipFuncAttributeMaxDynamicSharedMemorySize, 98304));
+        attr_set[dbl][v] = true;
+    }
     // the grid dimension is capped; larger batches run in slices
     for (uint32_t k0 = 0; k0 < b->K; k0 += 65535) {
         const uint32_t nb = std::min<uint32_t>(65535, b->K - k0);
         prof_begin(p, STN_K_SV_LDS, s);
         if (dbl) {
-            hipLaunchKernelGGL(k_sv_lds<double>, dim3(nb), dim3(kThreads), lds, s, n, p->d_lds_ops.as<LdsOp>(),
-                               (uint32_t)p->lds_ops.size(), p->d_lds_vals64.as<double2>(), p->d_site_ops.as<LdsOp>(),
-                               p->d_site_op_off.as<uint32_t>(), b->d_idx.as<uint8_t>() + (size_t)k0 * S, S,
-                               p->d_obs.as<uint32_t>(), p->d_obs_w.as<double>(), T,
-                               b->d_energy.as<double>() + k0,
+            hipLaunchKernelGGL(reinterpret_cast<LdsFn<double>>(ker.f), dim3(nb), dim3(ker.threads), lds, s, n,
+                               p->d_lds_ops.as<LdsOp>(), (uint32_t)p->lds_ops.size(), p->d_lds_vals64.as<double2>(),
+                               p->d_site_ops.as<LdsOp>(), p->d_site_op_off.as<uint32_t>(),
+                               b->d_idx.as<uint8_t>() + (size_t)k0 * S, S, p->d_obs.as<uint32_t>(),
+                               p->d_obs_w.as<double>(), T, b->d_energy.as<double>() + k0,
                                dense ? b->d_states.as<double2>() + (size_t)k0 * N : nullptr);
         } else {
-            hipLaunchKernelGGL(k_sv_lds<float>, dim3(nb), dim3(kThreads), lds, s, n, p->d_lds_ops.as<LdsOp>(),
-                               (uint32_t)p->lds_ops.size(), p->d_lds_vals32.as<float2>(), p->d_site_ops.as<LdsOp>(),
-                               p->d_site_op_off.as<uint32_t>(), b->d_idx.as<uint8_t>() + (size_t)k0 * S, S,
-                               p->d_obs.as<uint32_t>(), p->d_obs_w.as<double>(), T,
-                               b->d_energy.as<double>() + k0,
+            hipLaunchKernelGGL(reinterpret_cast<LdsFn<float>>(ker.f), dim3(nb), dim3(ker.threads), lds, s, n,
+                               p->d_lds_ops.as<LdsOp>(), (uint32_t)p->lds_ops.size(), p->d_lds_vals32.as<float2>(),
+                               p->d_site_ops.as<LdsOp>(), p->d_site_op_off.as<uint32_t>(),
+                               b->d_idx.as<uint8_t>() + (size_t)k0 * S, S, p->d_obs.as<uint32_t>(),
+                               p->d_obs_w.as<double>(), T, b->d_energy.as<double>() + k0,
                                dense ? b->d_states.as<float2>() + (size_t)k0 * N : nullptr);
         }
         STN_HIP(hipGetLastError());
         prof_end(p, STN_K_SV_LDS, s, (double)nb * ((dense ? N * elem : 0) + S + 8.0), (double)nb * p->flops_per_traj);
     }
 }
+
+uint32_t lds_variants() { return kLdsVariants; }
 
 }  // namespace stn

@@ -626,8 +626,11 @@ void launch_sv_tiled(stn_plan* p, stn_batch* b, hipStream_t s) {
     int dev = 0, cus = 0;
     STN_HIP(hipGetDevice(&dev));
     STN_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    // one resident workgroup per CU, a multiple of 32 (XCD rounds of line groups)
-    const uint32_t grid_max = std::max(32u, (uint32_t)cus / 32u * 32u);
+    // one resident workgroup per CU (variant 1: two per CU, the second queued), a
+    // multiple of 32 (XCD rounds of line groups)
+    uint32_t grid_max = std::max(32u, (uint32_t)cus / 32u * 32u) * (p->variant == 1 ? 2u : 1u);
+    // a job server may keep some CUs free for other jobs' kernels
+    if (p->grid_cap) grid_max = std::min(grid_max, std::max(32u, p->grid_cap / 32u * 32u));
     for (uint32_t c0 = 0; c0 < b->K; c0 += B) {
         const uint32_t nb = std::min(B, b->K - c0);
         const uint32_t blocks = nb * tiles;
@@ -654,5 +657,7 @@ void launch_sv_tiled(stn_plan* p, stn_batch* b, hipStream_t s) {
         prof_end(p, STN_K_TILE_SUM, s, (double)nb * tiles * 8.0 + nb * 8.0, (double)nb * tiles);
     }
 }
+
+uint32_t tiled_variants(const stn_plan* p) { return p->opts.precision == 128 ? 1u : 2u; }
 
 }  // namespace stn

@@ -19,7 +19,6 @@ namespace stn {
 
 namespace {
 
-constexpr int kTnThreads = 256;
 constexpr int kMaxPos = 14;
 constexpr int kLdsBytes = 64 * 1024;
 
@@ -47,7 +46,9 @@ template <class V> __device__ __forceinline__ V cmul(V a, V b) {
     return r;
 }
 
-template <class R>
+// One workgroup per (term, trajectory); each output element of a step is one
+// thread's sum, so the result does not depend on the workgroup size.
+template <class R, int kTnThreads>
 __global__ __launch_bounds__(kTnThreads) void k_tn(const TnTerm* __restrict__ terms, const TnStep* __restrict__ steps,
                                                    const TnIn* __restrict__ ins,
                                                    const typename Cx<R>::T* __restrict__ gtab,
@@ -115,6 +116,26 @@ __global__ __launch_bounds__(64) void k_tn_energy(const double* __restrict__ zz,
         e += w[t] * (1.0 - f * zz[(size_t)b * T + t]) * 0.5;
     }
     energy[b] = e;
+}
+
+template <class R>
+using TnFn = void (*)(const TnTerm*, const TnStep*, const TnIn*, const typename Cx<R>::T*, const uint32_t*,
+                      uint32_t, double*, uint32_t);
+
+struct TnKernel {
+    void* f;
+    uint32_t threads;
+};
+
+// launch shapes the autotuner chooses from (variant 0 is the default)
+constexpr uint32_t kTnVariants = 3;
+template <class R>
+TnKernel tn_kernel(uint32_t v) {
+    switch (v) {
+        case 1: return {(void*)k_tn<R, 64>, 64};
+        case 2: return {(void*)k_tn<R, 128>, 128};
+        default: return {(void*)k_tn<R, 256>, 256};
+    }
 }
 
 struct TnDevice {
@@ -249,11 +270,12 @@ void launch_lightcone(stn_plan* p, stn_batch* b, hipStream_t s) {
     const size_t lds = (size_t)d->arena * (dbl ? 16 : 8);
     const uint32_t B = std::min<uint32_t>(b->K, 65535);
     d->zz.ensure(&p->alloc, (size_t)B * T * 8);
-    static bool attr[2] = {false, false};
-    if (!attr[dbl]) {
-        if (dbl) STN_HIP(hipFuncSetAttribute((const void*)k_tn<double>, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes));
-        else STN_HIP(hipFuncSetAttribute((const void*)k_tn<float>, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes));
-        attr[dbl] = true;
+    const uint32_t v = std::min<uint32_t>(p->variant, kTnVariants - 1);
+    const TnKernel ker = dbl ? tn_kernel<double>(v) : tn_kernel<float>(v);
+    static bool attr[2][kTnVariants] = {};
+    if (!attr[dbl][v]) {
+        STN_HIP(hipFuncSetAttribute(ker.f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes));
+        attr[dbl][v] = true;
     }
     double cost = 0;
     for (auto& net : d->nets) cost += net.cost;
@@ -261,13 +283,15 @@ void launch_lightcone(stn_plan* p, stn_batch* b, hipStream_t s) {
         const uint32_t nb = std::min(B, b->K - c0);
         prof_begin(p, STN_K_TN_STEP, s);
         if (dbl)
-            hipLaunchKernelGGL(k_tn<double>, dim3(T, nb), dim3(kTnThreads), lds, s, d->terms.as<TnTerm>(),
-                               d->steps.as<TnStep>(), d->ins.as<TnIn>(), d->gtab64.as<double2>(),
-                               b->d_signs.as<uint32_t>() + (size_t)c0 * b->words, b->words, d->zz.as<double>(), T);
+            hipLaunchKernelGGL(reinterpret_cast<TnFn<double>>(ker.f), dim3(T, nb), dim3(ker.threads), lds, s,
+                               d->terms.as<TnTerm>(), d->steps.as<TnStep>(), d->ins.as<TnIn>(),
+                               d->gtab64.as<double2>(), b->d_signs.as<uint32_t>() + (size_t)c0 * b->words, b->words,
+                               d->zz.as<double>(), T);
         else
-            hipLaunchKernelGGL(k_tn<float>, dim3(T, nb), dim3(kTnThreads), lds, s, d->terms.as<TnTerm>(),
-                               d->steps.as<TnStep>(), d->ins.as<TnIn>(), d->gtab32.as<float2>(),
-                               b->d_signs.as<uint32_t>() + (size_t)c0 * b->words, b->words, d->zz.as<double>(), T);
+            hipLaunchKernelGGL(reinterpret_cast<TnFn<float>>(ker.f), dim3(T, nb), dim3(ker.threads), lds, s,
+                               d->terms.as<TnTerm>(), d->steps.as<TnStep>(), d->ins.as<TnIn>(),
+                               d->gtab32.as<float2>(), b->d_signs.as<uint32_t>() + (size_t)c0 * b->words, b->words,
+                               d->zz.as<double>(), T);
         STN_HIP(hipGetLastError());
         prof_end(p, STN_K_TN_STEP, s, (double)nb * T * 8.0, (double)nb * 8.0 * cost);
         hipLaunchKernelGGL(k_tn_energy, dim3((nb + 63) / 64), dim3(64), 0, s, d->zz.as<double>(), T,
@@ -276,5 +300,7 @@ void launch_lightcone(stn_plan* p, stn_batch* b, hipStream_t s) {
         STN_HIP(hipGetLastError());
     }
 }
+
+uint32_t tn_variants() { return kTnVariants; }
 
 }  // namespace stn

@@ -213,6 +213,8 @@ struct Job {
     uint32_t slot = 0;                 // pinned result slot
     uint64_t chunks = 0;
     bool finishing = false;
+    bool tune = false;                 // autotune the launch shape on the first chunk
+    uint64_t shape = 0;                // tuning cache key
 };
 
 }  // namespace
@@ -339,9 +341,11 @@ struct Device {
     double* pinned = nullptr;              // kMaxActive x 2 doubles: mean, SE
     std::vector<uint32_t> free_slots;
     std::vector<std::shared_ptr<Job>> active;
+    std::unordered_map<uint64_t, uint32_t> tuned;   // shape key -> launch-shape variant
     std::vector<hipEvent_t> ev_pool;
     uint64_t bytes_admitted = 0;
     size_t rr = 0;
+    uint32_t cus = 0;
 
     hipEvent_t event() {
         if (!ev_pool.empty()) {
@@ -356,6 +360,9 @@ struct Device {
 
     void init() {
         STN_HIP(hipSetDevice(sv->device));
+        int c = 0;
+        STN_HIP(hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, sv->device));
+        cus = (uint32_t)c;
         for (uint32_t i = 0; i < sv->opts.n_streams; ++i) STN_HIP(hipStreamCreateWithFlags(&streams[i], hipStreamNonBlocking));
         STN_HIP(hipStreamCreateWithFlags(&upload, hipStreamNonBlocking));
         STN_HIP(hipHostMalloc((void**)&pinned, kMaxActive * 2 * sizeof(double), hipHostMallocDefault));
@@ -488,6 +495,9 @@ struct Device {
         stream_jobs[best]++;
         try {
             ensure_uploaded(j->plan, upload);
+            // persistent kernels leave reserve_cus CUs to the other jobs
+            if (sv->opts.reserve_cus && cus > sv->opts.reserve_cus) j->plan->grid_cap = cus - sv->opts.reserve_cus;
+            choose_shape(*j);
             j->acc = new stn_accum();
             j->acc->plan = j->plan;
             for (uint32_t c = 0; c < kChunksInFlight; ++c) {
@@ -503,6 +513,24 @@ struct Device {
         std::lock_guard<std::mutex> lk(sv->m);
         sv->st.max_active_jobs = std::max<uint64_t>(sv->st.max_active_jobs, active.size());
         return true;
+    }
+
+    // Launch shape of the job's contraction: a cached choice for its shape, or
+    // autotuning on its first chunk when that chunk is cheap (the device thread
+    // waits for it); otherwise the default.
+    void choose_shape(Job& j) {
+        stn_plan* p = j.plan;
+        if (p->tuned) return;
+        const uint32_t lg = 32 - __builtin_clz(std::max<uint32_t>(j.B, 1));
+        j.shape = (uint64_t)p->kind | ((uint64_t)p->opts.precision << 8) | ((uint64_t)p->n << 16) |
+                  ((uint64_t)p->width << 24) | ((uint64_t)lg << 32);
+        auto it = tuned.find(j.shape);
+        if (it != tuned.end()) {
+            if (stn_plan_set_variant(p, it->second) != STN_OK) throw Error{STN_E_STATE, stn_last_error()};
+            return;
+        }
+        const double est = (p->bytes_per_traj / 4e12 + p->flops_per_traj / 8e12) * j.B;
+        j.tune = est < 0.01;
     }
 
     void fail_job(Job& j, const Error& e) {
@@ -524,10 +552,24 @@ struct Device {
         const uint32_t K = (uint32_t)std::min<uint64_t>(j.B, j.K - j.k_issued);
         stn_batch* b = j.batch[c];
         batch_prepare(j.plan, b, j.k_issued, K);
-        launch_sample(j.plan, b, j.seed, s);
-        if (j.plan->kind != STN_PLAN_SV_LDS) launch_frame(j.plan, b, s);
-        const stn_status st1 = stn_contract(j.plan, b, s);
-        if (st1 != STN_OK) throw Error{st1, stn_last_error()};
+        if (j.tune) {
+            // on the private stream: sample, time every launch shape (this
+            // leaves the batch contracted), keep the fastest for the shape
+            launch_sample(j.plan, b, j.seed, upload);
+            if (j.plan->kind != STN_PLAN_SV_LDS) launch_frame(j.plan, b, upload);
+            stn_tune_result tr{};
+            const stn_status st0 = stn_plan_autotune(j.plan, b, 1, &tr, upload);
+            if (st0 != STN_OK) throw Error{st0, stn_last_error()};
+            tuned[j.shape] = tr.chosen;
+            j.tune = false;
+            std::lock_guard<std::mutex> lk(sv->m);
+            sv->st.autotuned++;
+        } else {
+            launch_sample(j.plan, b, j.seed, s);
+            if (j.plan->kind != STN_PLAN_SV_LDS) launch_frame(j.plan, b, s);
+            const stn_status st1 = stn_contract(j.plan, b, s);
+            if (st1 != STN_OK) throw Error{st1, stn_last_error()};
+        }
         const stn_status st2 = stn_reduce(j.plan, b, j.acc, s);
         if (st2 != STN_OK) throw Error{st2, stn_last_error()};
         STN_HIP(hipEventRecord(j.ev[c], s));
@@ -635,6 +677,7 @@ void stn_server_opts_default(stn_server_opts* o) {
     o->plan_cache = 64;
     o->precision = 64;
     o->drain_on_destroy = 1;
+    o->reserve_cus = 32;
 }
 
 stn_status stn_server_create(const stn_server_opts* opts, stn_server** out) {

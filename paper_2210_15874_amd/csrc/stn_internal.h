@@ -192,6 +192,9 @@ struct stn_plan {
     void (*lc_free)(void*) = nullptr;
 
     bool sync_on_destroy = true;            // false: the owner has waited for every enqueued use
+    uint32_t variant = 0;                   // launch shape of the contraction kernels (autotuner)
+    uint32_t grid_cap = 0;                  // persistent kernels use at most this many workgroups (0: all CUs)
+    bool tuned = false;
     ~stn_plan();
 };
 
@@ -237,6 +240,11 @@ void ensure_uploaded(stn_plan* p, hipStream_t s);
 void batch_prepare(stn_plan* p, stn_batch* b, uint64_t k0, uint32_t K);
 // enqueues the gather of per-trajectory energies and their statistics into d_stats
 void accum_finish_energy(stn_accum* a, hipStream_t s);
+
+// launch-shape variants of each lowering's contraction (results do not depend on them)
+uint32_t lds_variants();
+uint32_t tn_variants();
+uint32_t tiled_variants(const stn_plan* p);
 
 // planner (plan.cpp)
 void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, const stn_observable* ob);

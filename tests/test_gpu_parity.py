@@ -369,3 +369,31 @@ def test_full_size_workload_sampled_trajectories():
     assert np.all(e >= -1e-4) and np.all(e <= m + 1e-4)
     assert abs(r["energy_mean"] - e.mean()) < 1e-9 * m
     assert abs(r["energy_se"] - e.std(ddof=1) / math.sqrt(pr.K)) < 1e-9 * m
+
+
+# ----------------------------------------------------------------------------- launch shapes
+
+@pytest.mark.parametrize("kind,n,p,precision", [("sv_lds", 10, 3, 64), ("sv_lds", 12, 2, 128),
+                                                ("lightcone", 20, 1, 64), ("lightcone", 16, 1, 128),
+                                                ("sv_tiled", 18, 2, 64)])
+def test_launch_shapes_give_identical_results(kind, n, p, precision):
+    """Every launch shape the autotuner may pick gives the same energies, bit
+    for bit, and autotune keeps the fastest."""
+    stn = stn_mod()
+    kinds = {"sv_lds": stn.PLAN_SV_LDS, "lightcone": stn.PLAN_LIGHTCONE, "sv_tiled": stn.PLAN_SV_TILED}
+    pr = qaoa(n, p, 700 + n, 5e-3, 2e-2, 96)
+    pl = stn.Plan(pr, plan_kind=kinds[kind], precision=precision)
+    b = pl.sample(pr.seed, 0, pr.K)
+    tune = pl.autotune(b, reps=1)
+    assert len(tune["ms"]) >= 2 and tune["chosen"] == int(np.argmin(tune["ms"]))
+    assert pl.info()["variant"] == tune["chosen"] and pl.info()["tuned"] == 1
+    ref = None
+    for v in range(len(tune["ms"])):
+        pl.set_variant(v)
+        pl.contract(b)
+        e = b.energies()
+        if ref is None:
+            ref = e
+        np.testing.assert_array_equal(e, ref)
+    with pytest.raises(stn.StnError, match="INVALID"):
+        pl.set_variant(len(tune["ms"]))
