@@ -389,6 +389,8 @@ def serving_leg(stn, args):
         "plans": {k: sum(1 for r in res.values() if r["plan_name"] == k) for k in ("sv_lds", "sv_tiled", "lightcone")},
         "jobs_detail": [{"n": jobs[i].n_qubits, "p": jobs[i].p, "K": jobs[i].K,
                          "latency_s": None if not math.isfinite(lat[i]) else float(lat[i]),
+                         "admit_wait_s": res[i]["t_admit"] - t0 - arrivals[i] if i in res else None,
+                         "chunks": res[i]["chunks"] if i in res else None,
                          "plan": res[i]["plan_name"] if i in res else None} for i in range(len(jobs))],
         "offered": "arrival rate far above one GPU's capacity: latency is mostly queueing behind n >= 26 jobs",
         "fp64_checks": checks,

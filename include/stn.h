@@ -158,7 +158,8 @@ typedef struct {
     double bytes_per_traj;  /* algorithmic HBM bytes per trajectory (cost model) */
     double flops_per_traj;  /* algorithmic flops per trajectory (cost model) */
     double peak_bytes;      /* device working memory at max_batch */
-    uint32_t lc_width;      /* lightcone networks' width when the planner built them (0: not built) */
+    uint32_t lc_width;      /* lightcone networks' width when the planner built them (0: not built); a lower bound when
+                               above the rank the lightcone lowering runs (its flops are then infinite) */
     double lc_flops_per_traj; /* their flops per trajectory */
     uint32_t variant;       /* launch shape of the contraction kernels (stn_plan_autotune) */
     uint32_t tuned;         /* 1 after stn_plan_autotune or stn_plan_set_variant */
@@ -291,11 +292,12 @@ void stn_accum_destroy(stn_accum* acc);
 
 /* ---------------------------------------------------------------- job server
  * Many ensemble jobs (Sec. III-G, each one circuit + noise model + K) of
- * different sizes on one device at once.  A planner thread plans submitted
+ * different sizes on one device at once.  Planner threads plan submitted
  * jobs on the host (reusing cached plans of identical inputs); a device
  * thread admits planned jobs in arrival order while their estimated device
  * memory fits hbm_budget (a job of at most 1/32 of the budget may go ahead of
- * a larger one that does not fit yet), gives each a stream, and issues their
+ * a larger one that does not fit yet; larger jobs fill at most 15/16 of the
+ * budget, so small ones always find room), gives each a stream, and issues their
  * trajectories in chunks (sample -> contract -> reduce), round-robin over the
  * admitted jobs, so that jobs arriving while others run share the device
  * with them.  A job's result depends only on its inputs, seed and K: it is

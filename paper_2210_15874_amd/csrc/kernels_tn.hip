@@ -198,8 +198,15 @@ void build_lightcone(stn_plan* p) {
     int width = 0;
     int max_rank = 0;
     for (size_t t = 0; t < p->obs_u.size(); ++t) {
-        d->nets.push_back(build_term(p, p->obs_u[t], p->obs_v[t], p->opts.order_restarts, p->opts.order_seed));
+        d->nets.push_back(
+            build_term(p, p->obs_u[t], p->obs_v[t], p->opts.order_restarts, p->opts.order_seed, kMaxPos));
         const TnNetwork& net = d->nets.back();
+        if (net.steps.empty() && !std::isfinite(net.cost)) {
+            max_rank = std::max(max_rank, net.width);   // stopped early: too wide for this lowering
+            width = std::max(width, net.width);
+            cost = HUGE_VAL;
+            break;
+        }
         for (auto& st : net.steps)
             for (auto& in : st.inputs) max_rank = std::max(max_rank, (int)in.pos.size());
         d->arena = std::max(d->arena, net.arena);

@@ -40,8 +40,12 @@ struct Tensor {
 
 bool diagonal_kind(uint32_t k) { return k == STN_G_RZ || k == STN_G_Z || k == STN_G_ZZ; }
 
-// min-fill order of the interaction graph; ties broken by degree, then randomly
-std::vector<int> minfill_order(int nv, const std::vector<std::vector<int>>& tensors, std::mt19937_64* rng) {
+// min-fill order of the interaction graph; ties broken by degree, then randomly.
+// Stops (returning an empty order) as soon as the variable to eliminate has
+// more than max_deg neighbours, i.e. a step of that rank would be needed;
+// *deg_seen receives the largest degree met.
+std::vector<int> minfill_order(int nv, const std::vector<std::vector<int>>& tensors, std::mt19937_64* rng,
+                               int max_deg, int* deg_seen) {
     std::vector<std::set<int>> adj(nv);
     for (auto& t : tensors)
         for (int a : t)
@@ -71,6 +75,8 @@ std::vector<int> minfill_order(int nv, const std::vector<std::vector<int>>& tens
         }
         int v = cands[0];
         if (rng && cands.size() > 1) v = cands[(*rng)() % cands.size()];
+        *deg_seen = std::max(*deg_seen, best_deg);
+        if (best_deg > max_deg) return {};
         done[v] = 1;
         order.push_back(v);
         const std::vector<int> nb(adj[v].begin(), adj[v].end());
@@ -182,7 +188,7 @@ Lowered lower(const std::vector<Tensor>& base, int nv, const std::vector<int>& o
 
 // Network of one term: lightcone gates on the ket, the observable, the
 // conjugate gates on the bra, |0> at both ends of every chain.
-TnNetwork build_term(const stn_plan* p, uint32_t u, uint32_t v, uint32_t restarts, uint64_t seed) {
+TnNetwork build_term(const stn_plan* p, uint32_t u, uint32_t v, uint32_t restarts, uint64_t seed, int max_rank) {
     const uint32_t n = p->n;
     // backward lightcone of {u, v}
     std::vector<char> in_cone(p->gates.size(), 0);
@@ -299,13 +305,24 @@ TnNetwork build_term(const stn_plan* p, uint32_t u, uint32_t v, uint32_t restart
     Lowered best;
     bool have = false;
     std::mt19937_64 rng(seed ^ (0x9E3779B97F4A7C15ull * (u * 131 + v)));
+    int deg_lb = 0;
     for (uint32_t r = 0; r <= restarts; ++r) {
-        const std::vector<int> order = minfill_order(nv, tv, r == 0 ? nullptr : &rng);
+        int deg = 0;
+        const std::vector<int> order = minfill_order(nv, tv, r == 0 ? nullptr : &rng, max_rank, &deg);
+        if (order.empty() && nv > 0) {   // this order needs a step above max_rank
+            deg_lb = deg_lb ? std::min(deg_lb, deg) : deg;
+            continue;
+        }
         Lowered L = lower(ts, nv, order);
         if (!have || L.width < best.width || (L.width == best.width && L.cost < best.cost)) {
             best = std::move(L);
             have = true;
         }
+    }
+    if (!have) {   // no order within max_rank: width is at least deg_lb + 1
+        net.width = deg_lb + 1;
+        net.cost = HUGE_VAL;
+        return net;
     }
     net.steps = std::move(best.steps);
     net.width = best.width;

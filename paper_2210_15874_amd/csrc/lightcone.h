@@ -38,6 +38,8 @@ struct TnNetwork {
     std::vector<TnStepRec> steps;
 };
 
-TnNetwork build_term(const stn_plan* p, uint32_t u, uint32_t v, uint32_t restarts, uint64_t seed);
+// Networks whose elimination order would need a step of rank above max_rank
+// come back without steps, width = a lower bound, cost = infinity.
+TnNetwork build_term(const stn_plan* p, uint32_t u, uint32_t v, uint32_t restarts, uint64_t seed, int max_rank);
 
 }  // namespace stn

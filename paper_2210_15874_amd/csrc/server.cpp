@@ -3,8 +3,9 @@
 // device at once.
 //
 //   caller threads   stn_server_submit copies the job's inputs and returns.
-//   planner thread   builds (or takes from the plan cache) the job's plan on
-//                    the host and estimates its device memory.
+//   planner threads  build (or take from the plan cache) the job's plan on
+//                    the host and estimate its device memory; the device
+//                    thread sees planned jobs in arrival order.
 //   device thread    the only thread that calls HIP.  Admits planned jobs in
 //                    arrival order while their estimated memory fits the
 //                    budget, gives each admitted job a stream, and issues the
@@ -40,6 +41,7 @@ namespace {
 constexpr uint32_t kMaxStreams = 8;
 constexpr uint32_t kMaxActive = 64;
 constexpr uint32_t kChunksInFlight = 2;   // per job
+constexpr int kPlanners = 4;              // host planning threads (a slow plan does not hold up the others)
 
 // ---------------------------------------------------------------- device pool
 class DevicePool {
@@ -237,7 +239,8 @@ struct stn_server {
     bool stop = false;
     std::string fatal;
 
-    std::thread planner, worker;
+    std::vector<std::thread> planners;
+    std::thread worker;
 
     double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
 };
@@ -279,7 +282,8 @@ void plan_job(stn_server* sv, Job& j) {
         o.precision = sv->opts.precision;
         o.outputs = STN_OUT_ENERGY;
         o.plan_kind = STN_PLAN_AUTO;
-        o.hbm_budget = (uint64_t)(sv->opts.job_share * (double)sv->opts.hbm_budget);
+        // large jobs may fill at most 15/16 of the budget (the rest is for small ones)
+        o.hbm_budget = (uint64_t)(std::min(sv->opts.job_share, 15.0 / 16.0) * (double)sv->opts.hbm_budget);
         o.max_batch = sv->opts.chunk_max;
         o.dev_alloc = pool_alloc;
         o.dev_free = pool_free;
@@ -298,7 +302,8 @@ void plan_job(stn_server* sv, Job& j) {
     j.plan = p;
     j.B = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(p->max_batch, j.K));
     j.est_bytes = estimate_bytes(p, j.B, j.K);
-    if (j.est_bytes > sv->opts.hbm_budget) {
+    const uint64_t budget = sv->opts.hbm_budget;
+    if (j.est_bytes > budget / 32 && j.est_bytes > budget - budget / 16) {
         j.status = STN_E_OOM;
         j.err = "job needs more device memory than the server budget";
     }
@@ -324,8 +329,13 @@ void planner_loop(stn_server* sv) {
             j->err = e.what();
         }
         {
+            // admission sees planned jobs in arrival order
             std::lock_guard<std::mutex> lk(sv->m);
-            sv->ready.push_back(j);
+            auto pos = std::upper_bound(sv->ready.begin(), sv->ready.end(), j,
+                                        [](const std::shared_ptr<Job>& a, const std::shared_ptr<Job>& b) {
+                                            return a->id < b->id;
+                                        });
+            sv->ready.insert(pos, j);
             sv->planned++;
         }
         sv->cv_ready.notify_one();
@@ -456,21 +466,26 @@ struct Device {
 
     // Arrival order; when the oldest waiting job does not fit, a later job of
     // at most 1/32 of the budget that fits may go ahead of it (small jobs
-    // barely delay the large one and are not held behind it).
+    // barely delay the large one and are not held behind it).  Jobs above
+    // that size may fill only 15/16 of the budget, so small jobs always find
+    // room.
     bool admit() {
         std::shared_ptr<Job> j;
         {
             std::lock_guard<std::mutex> lk(sv->m);
             if (sv->ready.empty()) return false;
             const bool room = active.size() < sv->opts.max_active && !free_slots.empty();
-            const uint64_t left = sv->opts.hbm_budget - bytes_admitted;
+            const uint64_t budget = sv->opts.hbm_budget, small = budget / 32;
+            const uint64_t left = budget - std::min(budget, bytes_admitted);
+            const uint64_t left_big = (budget - budget / 16) - std::min(budget - budget / 16, bytes_admitted);
             size_t pick = SIZE_MAX;
             for (size_t i = 0; i < sv->ready.size(); ++i) {
                 const auto& c = sv->ready[i];
                 if (c->status != STN_OK) { pick = i; break; }       // failed planning: report now
                 if (!room) continue;
-                if (i == 0 && c->est_bytes <= left) { pick = 0; break; }
-                if (i > 0 && c->est_bytes <= left && c->est_bytes <= sv->opts.hbm_budget / 32) { pick = i; break; }
+                const bool is_small = c->est_bytes <= small;
+                if (i == 0 && c->est_bytes <= (is_small ? left : left_big)) { pick = 0; break; }
+                if (i > 0 && is_small && c->est_bytes <= left) { pick = i; break; }
             }
             if (pick == SIZE_MAX) return false;
             j = sv->ready[pick];
@@ -699,7 +714,7 @@ stn_status stn_server_create(const stn_server_opts* opts, stn_server** out) {
         delete sv;
         return srv_error(STN_E_DEVICE, "no HIP device");
     }
-    sv->planner = std::thread(planner_loop, sv);
+    for (int i = 0; i < kPlanners; ++i) sv->planners.emplace_back(planner_loop, sv);
     sv->worker = std::thread(worker_main, sv);
     *out = sv;
     return STN_OK;
@@ -788,7 +803,8 @@ void stn_server_destroy(stn_server* sv) {
     }
     sv->cv_plan.notify_all();
     sv->cv_ready.notify_all();
-    if (sv->planner.joinable()) sv->planner.join();
+    for (auto& t : sv->planners)
+        if (t.joinable()) t.join();
     if (sv->worker.joinable()) sv->worker.join();
     // jobs planned but never admitted
     for (auto& j : sv->ready) delete j->plan;
