@@ -19,8 +19,8 @@ namespace stn {
 
 namespace {
 
-constexpr int kMaxPos = 14;
-constexpr int kLdsBytes = 64 * 1024;
+constexpr int kMaxPos = 24;              // largest step input rank (HBM tier)
+constexpr int kLdsBytes = 64 * 1024;     // LDS tier: the whole arena in LDS
 
 struct TnIn {
     int32_t kind, gate, conj, arena, npos;
@@ -46,20 +46,16 @@ template <class V> __device__ __forceinline__ V cmul(V a, V b) {
     return r;
 }
 
-// One workgroup per (term, trajectory); each output element of a step is one
-// thread's sum, so the result does not depend on the workgroup size.
+// The steps of term t for trajectory b with intermediates in `arena` (LDS or
+// this workgroup's slice of global memory).  Each output element of a step
+// is one thread's sum over the eliminated variable, so the result does not
+// depend on the workgroup size.  __syncthreads() orders the steps (its
+// workgroup-scope fences cover global memory too).
 template <class R, int kTnThreads>
-__global__ __launch_bounds__(kTnThreads) void k_tn(const TnTerm* __restrict__ terms, const TnStep* __restrict__ steps,
-                                                   const TnIn* __restrict__ ins,
-                                                   const typename Cx<R>::T* __restrict__ gtab,
-                                                   const uint32_t* __restrict__ signs, uint32_t words,
-                                                   double* __restrict__ zz, uint32_t T) {
+__device__ __forceinline__ double run_term(typename Cx<R>::T* arena, const TnTerm tm,
+                                           const TnStep* __restrict__ steps, const TnIn* __restrict__ ins,
+                                           const typename Cx<R>::T* __restrict__ gtab, const uint32_t* sg) {
     using V = typename Cx<R>::T;
-    extern __shared__ char smem[];
-    V* arena = reinterpret_cast<V*>(smem);
-    const uint32_t t = blockIdx.x, b = blockIdx.y;
-    const TnTerm tm = terms[t];
-    const uint32_t* sg = signs + (size_t)b * words;
     for (int s = 0; s < tm.n_steps; ++s) {
         const TnStep st = steps[tm.step_off + s];
         const uint32_t nout = 1u << st.out_bits;
@@ -99,7 +95,43 @@ __global__ __launch_bounds__(kTnThreads) void k_tn(const TnTerm* __restrict__ te
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) zz[(size_t)b * T + t] = (double)arena[tm.result].x;
+    const double r = (double)arena[tm.result].x;
+    __syncthreads();   // the arena is reused by the next work item
+    return r;
+}
+
+// LDS tier: one workgroup per (term, trajectory), the arena in LDS.
+template <class R, int kTnThreads>
+__global__ __launch_bounds__(kTnThreads) void k_tn(const TnTerm* __restrict__ terms, const TnStep* __restrict__ steps,
+                                                   const TnIn* __restrict__ ins,
+                                                   const typename Cx<R>::T* __restrict__ gtab,
+                                                   const uint32_t* __restrict__ signs, uint32_t words,
+                                                   double* __restrict__ zz, uint32_t T) {
+    using V = typename Cx<R>::T;
+    extern __shared__ char smem[];
+    const uint32_t t = blockIdx.x, b = blockIdx.y;
+    const double r = run_term<R, kTnThreads>(reinterpret_cast<V*>(smem), terms[t], steps, ins, gtab,
+                                             signs + (size_t)b * words);
+    if (threadIdx.x == 0) zz[(size_t)b * T + t] = r;
+}
+
+// HBM tier: persistent workgroups, each with a private arena of `stride`
+// slots in global memory, take work items (term, trajectory) in turn.
+template <class R, int kTnThreads>
+__global__ __launch_bounds__(kTnThreads) void k_tn_hbm(const TnTerm* __restrict__ terms,
+                                                       const TnStep* __restrict__ steps,
+                                                       const TnIn* __restrict__ ins,
+                                                       const typename Cx<R>::T* __restrict__ gtab,
+                                                       const uint32_t* __restrict__ signs, uint32_t words,
+                                                       double* __restrict__ zz, uint32_t T, uint32_t nb,
+                                                       typename Cx<R>::T* __restrict__ garena, uint32_t stride) {
+    typename Cx<R>::T* arena = garena + (size_t)blockIdx.x * stride;
+    const uint32_t items = T * nb;
+    for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
+        const uint32_t t = item % T, b = item / T;
+        const double r = run_term<R, kTnThreads>(arena, terms[t], steps, ins, gtab, signs + (size_t)b * words);
+        if (threadIdx.x == 0) zz[(size_t)b * T + t] = r;
+    }
 }
 
 // energy[b] = sum_t w_t (1 - f_t zz[b][t]) / 2, f_t = (-1)^(F_x[u] xor F_x[v])
@@ -138,10 +170,26 @@ TnKernel tn_kernel(uint32_t v) {
     }
 }
 
+template <class R>
+using TnHbmFn = void (*)(const TnTerm*, const TnStep*, const TnIn*, const typename Cx<R>::T*, const uint32_t*,
+                         uint32_t, double*, uint32_t, uint32_t, typename Cx<R>::T*, uint32_t);
+
+template <class R>
+TnKernel tn_hbm_kernel(uint32_t v) {
+    switch (v) {
+        case 1: return {(void*)k_tn_hbm<R, 128>, 128};
+        case 2: return {(void*)k_tn_hbm<R, 512>, 512};
+        default: return {(void*)k_tn_hbm<R, 256>, 256};
+    }
+}
+
 struct TnDevice {
     std::vector<TnNetwork> nets;
     int arena = 0;
-    DevBuf terms, steps, ins, gtab32, gtab64, zz;
+    bool hbm = false;           // intermediates in global memory (persistent workgroups)
+    uint32_t stride = 0;        // HBM tier: arena slots per workgroup
+    uint32_t grid = 0;          // HBM tier: persistent workgroups
+    DevBuf terms, steps, ins, gtab32, gtab64, zz, garena;
 };
 
 // tensor values of gate g over its local index, for sign s (0: theta, 1: -theta)
@@ -199,7 +247,7 @@ void build_lightcone(stn_plan* p) {
     int max_rank = 0;
     for (size_t t = 0; t < p->obs_u.size(); ++t) {
         d->nets.push_back(
-            build_term(p, p->obs_u[t], p->obs_v[t], p->opts.order_restarts, p->opts.order_seed, kMaxPos));
+            build_term(p, p->obs_u[t], p->obs_v[t], p->opts.order_restarts, p->opts.order_seed, kMaxPos - 1));
         const TnNetwork& net = d->nets.back();
         if (net.steps.empty() && !std::isfinite(net.cost)) {
             max_rank = std::max(max_rank, net.width);   // stopped early: too wide for this lowering
@@ -216,15 +264,39 @@ void build_lightcone(stn_plan* p) {
     // the networks' size is known even where this lowering cannot run them
     p->lc_width = (uint32_t)width;
     p->lc_flops_per_traj = 8.0 * cost;
-    if (max_rank > kMaxPos) fail(STN_E_UNSUPPORTED, "lightcone step rank above 14 (width " + std::to_string(width) + ")");
-    if ((size_t)d->arena * elem > (size_t)kLdsBytes)
-        fail(STN_E_UNSUPPORTED, "lightcone intermediates exceed the LDS arena (width " + std::to_string(width) + ")");
+    if (max_rank > kMaxPos)
+        fail(STN_E_UNSUPPORTED, "lightcone step rank above " + std::to_string(kMaxPos) + " (width " +
+                                    std::to_string(width) + ")");
     p->width = (uint32_t)width;
     size_t steps = 0;
-    for (auto& net : d->nets) steps += net.steps.size();
+    double inter_bytes = 0;   // intermediates read and written per trajectory
+    for (auto& net : d->nets) {
+        steps += net.steps.size();
+        for (auto& st : net.steps) {
+            inter_bytes += std::ldexp((double)elem, (int)st.out_vars.size());
+            for (auto& in : st.inputs)
+                if (in.kind == TN_INTER) inter_bytes += std::ldexp((double)elem, (int)in.pos.size());
+        }
+    }
     p->n_steps = (uint32_t)steps;
     p->flops_per_traj = 8.0 * cost;             // one complex multiply-add per input per index
-    p->bytes_per_traj = 8.0 * p->obs_u.size();  // per-term result; everything else stays in LDS
+    if ((size_t)d->arena * elem <= (size_t)kLdsBytes) {
+        d->hbm = false;
+        p->bytes_per_traj = 8.0 * p->obs_u.size();  // per-term result; everything else stays in LDS
+        p->lc_est_s = p->flops_per_traj / 8e12;
+    } else {
+        // HBM tier: persistent workgroups with private arenas within the budget
+        d->hbm = true;
+        d->stride = (uint32_t)((d->arena + 63) / 64 * 64);
+        const double budget = p->opts.hbm_budget ? (double)p->opts.hbm_budget : 64.0 * (1ull << 30);
+        const double per_wg = (double)d->stride * elem;
+        d->grid = (uint32_t)std::min(512.0, std::floor(budget / 2 / per_wg));
+        if (d->grid < 32) fail(STN_E_UNSUPPORTED, "lightcone intermediates exceed the memory budget (width " +
+                                                      std::to_string(width) + ")");
+        p->bytes_per_traj = inter_bytes + 8.0 * p->obs_u.size();
+        p->lc_est_s = inter_bytes / 1.5e12 + p->flops_per_traj / 4e12;
+        p->lc_arena_bytes = (double)d->grid * per_wg;
+    }
 }
 
 void upload_lightcone(stn_plan* p, hipStream_t s) {
@@ -274,33 +346,48 @@ void launch_lightcone(stn_plan* p, stn_batch* b, hipStream_t s) {
     auto* d = static_cast<TnDevice*>(p->lc);
     const uint32_t T = (uint32_t)d->nets.size();
     const bool dbl = p->opts.precision == 128;
-    const size_t lds = (size_t)d->arena * (dbl ? 16 : 8);
+    const size_t elem = dbl ? 16 : 8;
+    const size_t lds = (size_t)d->arena * elem;
     const uint32_t B = std::min<uint32_t>(b->K, 65535);
     d->zz.ensure(&p->alloc, (size_t)B * T * 8);
     const uint32_t v = std::min<uint32_t>(p->variant, kTnVariants - 1);
-    const TnKernel ker = dbl ? tn_kernel<double>(v) : tn_kernel<float>(v);
+    const TnKernel ker = d->hbm ? (dbl ? tn_hbm_kernel<double>(v) : tn_hbm_kernel<float>(v))
+                                : (dbl ? tn_kernel<double>(v) : tn_kernel<float>(v));
     static bool attr[2][kTnVariants] = {};
-    if (!attr[dbl][v]) {
+    if (!d->hbm && !attr[dbl][v]) {
         STN_HIP(hipFuncSetAttribute(ker.f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes));
         attr[dbl][v] = true;
     }
+    if (d->hbm) d->garena.ensure(&p->alloc, (size_t)d->grid * d->stride * elem);
     double cost = 0;
     for (auto& net : d->nets) cost += net.cost;
     for (uint32_t c0 = 0; c0 < b->K; c0 += B) {
         const uint32_t nb = std::min(B, b->K - c0);
+        const uint32_t* sg = b->d_signs.as<uint32_t>() + (size_t)c0 * b->words;
         prof_begin(p, STN_K_TN_STEP, s);
-        if (dbl)
+        if (d->hbm) {
+            const uint32_t grid = std::min<uint32_t>(d->grid, T * nb);
+            if (dbl)
+                hipLaunchKernelGGL(reinterpret_cast<TnHbmFn<double>>(ker.f), dim3(grid), dim3(ker.threads), 0, s,
+                                   d->terms.as<TnTerm>(), d->steps.as<TnStep>(), d->ins.as<TnIn>(),
+                                   d->gtab64.as<double2>(), sg, b->words, d->zz.as<double>(), T, nb,
+                                   d->garena.as<double2>(), d->stride);
+            else
+                hipLaunchKernelGGL(reinterpret_cast<TnHbmFn<float>>(ker.f), dim3(grid), dim3(ker.threads), 0, s,
+                                   d->terms.as<TnTerm>(), d->steps.as<TnStep>(), d->ins.as<TnIn>(),
+                                   d->gtab32.as<float2>(), sg, b->words, d->zz.as<double>(), T, nb,
+                                   d->garena.as<float2>(), d->stride);
+        } else if (dbl) {
             hipLaunchKernelGGL(reinterpret_cast<TnFn<double>>(ker.f), dim3(T, nb), dim3(ker.threads), lds, s,
                                d->terms.as<TnTerm>(), d->steps.as<TnStep>(), d->ins.as<TnIn>(),
-                               d->gtab64.as<double2>(), b->d_signs.as<uint32_t>() + (size_t)c0 * b->words, b->words,
-                               d->zz.as<double>(), T);
-        else
+                               d->gtab64.as<double2>(), sg, b->words, d->zz.as<double>(), T);
+        } else {
             hipLaunchKernelGGL(reinterpret_cast<TnFn<float>>(ker.f), dim3(T, nb), dim3(ker.threads), lds, s,
                                d->terms.as<TnTerm>(), d->steps.as<TnStep>(), d->ins.as<TnIn>(),
-                               d->gtab32.as<float2>(), b->d_signs.as<uint32_t>() + (size_t)c0 * b->words, b->words,
-                               d->zz.as<double>(), T);
+                               d->gtab32.as<float2>(), sg, b->words, d->zz.as<double>(), T);
+        }
         STN_HIP(hipGetLastError());
-        prof_end(p, STN_K_TN_STEP, s, (double)nb * T * 8.0, (double)nb * 8.0 * cost);
+        prof_end(p, STN_K_TN_STEP, s, (double)nb * p->bytes_per_traj, (double)nb * 8.0 * cost);
         hipLaunchKernelGGL(k_tn_energy, dim3((nb + 63) / 64), dim3(64), 0, s, d->zz.as<double>(), T,
                            p->d_obs.as<uint32_t>(), p->d_obs_w.as<double>(),
                            b->d_frame.as<uint64_t>() + 2 * (size_t)c0, nb, b->d_energy.as<double>() + c0);

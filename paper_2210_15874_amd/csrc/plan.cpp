@@ -523,7 +523,7 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
             fail(STN_E_UNSUPPORTED, "density-matrix / state outputs need n <= " + std::to_string(lds_max));
         } else {
             // statevector passes vs lightcone networks: estimated seconds per trajectory
-            // (HBM-bound passes at ~4 TB/s; LDS-resident contraction at ~1e12 complex MACs/s)
+            // (HBM-bound passes at ~4 TB/s; lightcone networks: their own estimate)
             double sv_t = -1, tn_t = -1;
             const bool c128 = p->opts.precision == 128;
             if (n >= (c128 ? 13u : 14u) && build_tiled(p, why)) {
@@ -536,7 +536,7 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
             }
             try {
                 build_lightcone(p);
-                tn_t = p->flops_per_traj / 8.0 / 1e12;
+                tn_t = p->lc_est_s;
             } catch (const Error& e) {
                 if (e.status != STN_E_UNSUPPORTED) throw;
                 if (why.empty()) why = e.msg;
@@ -601,7 +601,7 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
     } else if (kind == STN_PLAN_LIGHTCONE) {
         // width / steps / flops / bytes set by build_lightcone
         p->max_batch = p->opts.max_batch ? p->opts.max_batch : 65535;
-        p->peak_bytes = (double)p->max_batch * (p->obs_u.size() * 8.0 + 64.0 + p->sites.size());
+        p->peak_bytes = (double)p->max_batch * (p->obs_u.size() * 8.0 + 64.0 + p->sites.size()) + p->lc_arena_bytes;
     } else {
         p->width = n;
         p->n_passes = (uint32_t)p->passes.size();

@@ -256,7 +256,7 @@ uint64_t estimate_bytes(const stn_plan* p, uint32_t B, uint64_t K) {
     const double N = std::ldexp(1.0, (int)p->n);
     const double elem = p->opts.precision == 128 ? 16.0 : 8.0;
     if (p->kind == STN_PLAN_SV_TILED) b += (double)B * N * elem + (double)B * std::ldexp(1.0, (int)p->n - 14) * 8.0;
-    if (p->kind == STN_PLAN_LIGHTCONE) b += (double)B * p->obs_u.size() * 8.0;
+    if (p->kind == STN_PLAN_LIGHTCONE) b += (double)B * p->obs_u.size() * 8.0 + p->lc_arena_bytes;
     b += kChunksInFlight * (double)B * (S + 4.0 * words + 16.0 + 8.0);     // batches
     b += std::ceil((double)K / kEnergyChunk) * kEnergyChunk * 8.0 + 2.0 * K * 8.0;  // accumulator
     b += 8.0 * (1 << 20);                                                  // tables and rounding

@@ -156,6 +156,8 @@ struct stn_plan {
     uint32_t width = 0, n_passes = 0, n_steps = 0;
     uint32_t lc_width = 0;                  // lightcone networks: width and flops, when they were built
     double lc_flops_per_traj = 0;
+    double lc_est_s = 0;                    // their estimated seconds per trajectory
+    double lc_arena_bytes = 0;              // HBM tier: global-memory arenas of the persistent workgroups
 
     // device tables shared by every lowering
     stn::DevBuf d_site_T;            // uint64 thresholds, flattened

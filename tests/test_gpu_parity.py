@@ -375,7 +375,7 @@ def test_full_size_workload_sampled_trajectories():
 
 @pytest.mark.parametrize("kind,n,p,precision", [("sv_lds", 10, 3, 64), ("sv_lds", 12, 2, 128),
                                                 ("lightcone", 20, 1, 64), ("lightcone", 16, 1, 128),
-                                                ("sv_tiled", 18, 2, 64)])
+                                                ("lightcone", 22, 2, 64), ("sv_tiled", 18, 2, 64)])
 def test_launch_shapes_give_identical_results(kind, n, p, precision):
     """Every launch shape the autotuner may pick gives the same energies, bit
     for bit, and autotune keeps the fastest."""
@@ -397,3 +397,40 @@ def test_launch_shapes_give_identical_results(kind, n, p, precision):
         np.testing.assert_array_equal(e, ref)
     with pytest.raises(stn.StnError, match="INVALID"):
         pl.set_variant(len(tune["ms"]))
+
+
+# ----------------------------------------------------------------------------- lightcone networks in HBM
+
+@pytest.mark.parametrize("precision,tol", [(64, 1e-5), (128, 1e-11)])
+def test_lightcone_hbm_tier_against_oracle(precision, tol):
+    """Networks of width 20 (intermediates in global-memory arenas of
+    persistent workgroups) against literal Kraus insertion."""
+    from oracle import simulate as sim
+    stn = stn_mod()
+    pr = qaoa(14, 3, 903, 5e-3, 2e-2, 6)
+    pl = stn.Plan(pr, plan_kind=stn.PLAN_LIGHTCONE, precision=precision)
+    assert pl.info()["width"] == 20
+    b = pl.sample(pr.seed, 0, pr.K)
+    pl.contract(b)
+    got = b.energies()
+    ens = sim.ensemble(pr, pr.seed, 0, pr.K, want_states=False)
+    m = len(pr.edges)
+    np.testing.assert_allclose(got / m, ens["energies"] / m, atol=tol)
+
+
+@pytest.mark.parametrize("n,seed,precision,tol", [(22, 904, 64, 2e-5), (22, 904, 128, 1e-11), (24, 907, 64, 2e-5)])
+def test_lightcone_hbm_tier_against_statevector(n, seed, precision, tol):
+    stn = stn_mod()
+    pr = qaoa(n, 2, seed, 5e-3, 2e-2, 24)
+    res = {}
+    for kind in (stn.PLAN_LIGHTCONE, stn.PLAN_SV_TILED):
+        pl = stn.Plan(pr, plan_kind=kind, precision=precision)
+        if kind == stn.PLAN_LIGHTCONE:
+            assert pl.info()["width"] >= 17
+        b = pl.sample(pr.seed, 0, pr.K)
+        pl.contract(b)
+        res[kind] = b.energies()
+        b.close()
+        pl.close()
+    m = len(pr.edges)
+    np.testing.assert_allclose(res[stn.PLAN_LIGHTCONE] / m, res[stn.PLAN_SV_TILED] / m, atol=tol)

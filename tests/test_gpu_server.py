@@ -153,7 +153,7 @@ def test_failed_jobs_reported_and_others_unaffected():
         sv.submit(jobs[1], tag=2)
         # larger than the whole budget: rejected, not admitted
         from workloads import make_problem, random_regular_graph, uniform_angles
-        g, b = uniform_angles(2, 3)
+        g, b = uniform_angles(4, 3)   # p = 4: statevector only, 2 GiB per trajectory
         huge = make_problem(28, random_regular_graph(28, 3, 4), g, b, 1e-3, 1e-2, 64, 5)
         sv.submit(huge, tag=3)
         sv.drain(120)
