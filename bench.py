@@ -341,7 +341,7 @@ def serving_leg(stn, args):
     from workloads import poisson_stream
     arrivals, jobs = poisson_stream(args.serve_jobs, rate_per_s=args.serve_rate)
     res = {}
-    sv = stn.Server(hbm_budget=int(args.hbm_budget_gib * (1 << 30)), job_share=0.5, n_streams=4, max_active=16,
+    sv = stn.Server(hbm_budget=int(args.hbm_budget_gib * (1 << 30)), job_share=0.5, n_streams=3, max_active=16,
                     drain_on_destroy=False)
     t0 = sv.clock()
     for i, (ta, pr) in enumerate(zip(arrivals, jobs)):

@@ -303,8 +303,9 @@ void stn_accum_destroy(stn_accum* acc);
  * with them.  A job's result depends only on its inputs, seed and K: it is
  * the same (bit for bit) alone and in any mix.
  *
- * Device memory is taken from a caching pool over hipMalloc, bounded by
- * hbm_budget; plans and accumulators stay on the device while their job runs.
+ * Device memory: hbm_budget bytes are reserved with one hipMalloc when the
+ * server starts (stn_server_create returns once they are) and handed out
+ * first-fit; plans and accumulators stay on the device while their job runs.
  * Only <C> jobs (an observable, ENERGY output) are served.
  */
 typedef struct stn_server stn_server;
@@ -312,13 +313,15 @@ typedef struct stn_server stn_server;
 typedef struct {
     uint64_t hbm_budget;     /* device bytes the server may hold (>= 64 MiB) */
     double job_share;        /* largest fraction of the budget one job's chunk may use, (0, 1] */
-    uint32_t n_streams;      /* device streams jobs are spread over, 1..8 */
+    uint32_t n_streams;      /* device streams, 1..8: stream 0 for small jobs, the others for large ones;
+                                keep it within the process's hardware queues (GPU_MAX_HW_QUEUES) */
     uint32_t max_active;     /* jobs admitted at once, 1..64 */
     uint32_t plan_cache;     /* idle plans kept for jobs with identical inputs (0: none) */
     uint32_t precision;      /* 64 (complex64) or 128 (complex128) for every job */
     uint32_t chunk_max;      /* trajectories per chunk cap (0: the plan's max batch) */
     uint32_t drain_on_destroy; /* 1: stn_server_destroy waits for every submitted job */
-    uint32_t reserve_cus;    /* CUs the persistent (tiled) kernels leave free for other jobs' kernels */
+    uint32_t reserve_cus;    /* CUs the persistent kernels (tiled statevector, lightcone networks in
+                                HBM) leave free for other jobs' kernels */
 } stn_server_opts;
 
 typedef struct {
@@ -347,11 +350,11 @@ typedef struct {
     uint64_t max_active_jobs;/* most jobs admitted at the same time */
     uint64_t plan_cache_hits, plan_cache_misses, plans_cached;
     uint64_t autotuned;      /* plan shapes whose launch shape was timed (then reused for the shape) */
-    uint64_t bytes_in_use, bytes_cached, bytes_peak;   /* device pool */
+    uint64_t bytes_in_use, bytes_cached, bytes_peak;   /* device memory reserved at create: in use, free, peak in use */
     double clock;            /* server clock when read */
 } stn_server_stats;
 
-/* Defaults: 64 GiB budget, job_share 0.5, 4 streams, 16 active jobs, 64
+/* Defaults: 64 GiB budget, job_share 0.5, 3 streams, 16 active jobs, 64
  * cached plans, complex64, drain on destroy, 32 reserved CUs. */
 void stn_server_opts_default(stn_server_opts* opts);
 /* Starts the server's threads on the calling thread's current device. */

@@ -366,7 +366,9 @@ void launch_lightcone(stn_plan* p, stn_batch* b, hipStream_t s) {
         const uint32_t* sg = b->d_signs.as<uint32_t>() + (size_t)c0 * b->words;
         prof_begin(p, STN_K_TN_STEP, s);
         if (d->hbm) {
-            const uint32_t grid = std::min<uint32_t>(d->grid, T * nb);
+            // a job server may keep some CUs free for other jobs' kernels
+            uint32_t grid = std::min<uint32_t>(d->grid, T * nb);
+            if (p->grid_cap) grid = std::min(grid, p->grid_cap);
             if (dbl)
                 hipLaunchKernelGGL(reinterpret_cast<TnHbmFn<double>>(ker.f), dim3(grid), dim3(ker.threads), 0, s,
                                    d->terms.as<TnTerm>(), d->steps.as<TnStep>(), d->ins.as<TnIn>(),

@@ -17,9 +17,9 @@
 //                    site), and its reduction is in trajectory order, so its
 //                    result does not depend on what else ran beside it.
 //
-// Device memory comes from a caching pool bounded by the byte budget:
-// workspaces freed by finished jobs are handed to the next ones without
-// hipFree (which would wait for the whole device).
+// Device memory: the whole byte budget is reserved once when the server
+// starts and carved into blocks for plans, workspaces, batches and
+// accumulators; blocks freed by finished jobs go to the next ones.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -42,87 +42,79 @@ constexpr uint32_t kMaxStreams = 8;
 constexpr uint32_t kMaxActive = 64;
 constexpr uint32_t kChunksInFlight = 2;   // per job
 constexpr int kPlanners = 4;              // host planning threads (a slow plan does not hold up the others)
+constexpr uint32_t kTuneSample = 64;      // trajectories the autotuner times the launch shapes on
+constexpr double kChunkTiles = 32768;     // statevector tiles per launch a chunk aims at
 
 // ---------------------------------------------------------------- device pool
+// One hipMalloc of the whole budget when the server starts; blocks are carved
+// from it first-fit (256-byte aligned) and returned with their neighbours
+// merged, so serving never calls hipMalloc / hipFree (which map and unmap
+// memory and may wait for the device).
 class DevicePool {
 public:
-    explicit DevicePool(uint64_t budget) : budget_(budget) {}
-    ~DevicePool() { trim_locked(UINT64_MAX); }
+    explicit DevicePool(uint64_t budget) : size_(budget / 256 * 256) {}
+    ~DevicePool() {
+        if (base_) (void)hipFree(base_);
+    }
 
-    static size_t rounded(size_t b) {
-        if (b <= (size_t(1) << 20)) {
-            size_t r = 256;
-            while (r < b) r <<= 1;
-            return r;
+    // on the device thread, with the device current
+    void init() {
+        if (hipMalloc((void**)&base_, size_) != hipSuccess) {
+            (void)hipGetLastError();
+            base_ = nullptr;
+            fail(STN_E_OOM, "could not reserve the server's device memory (" + std::to_string(size_) + " bytes)");
         }
-        const size_t g = size_t(2) << 20;
-        return (b + g - 1) / g * g;
+        free_[0] = size_;
     }
 
     void* alloc(size_t bytes) {
         std::lock_guard<std::mutex> lk(m_);
-        const size_t r = rounded(bytes);
-        auto it = free_.find(r);
-        if (it != free_.end() && !it->second.empty()) {
-            void* p = it->second.back();
-            it->second.pop_back();
-            cached_ -= r;
-            take(p, r);
-            return p;
+        const uint64_t r = (std::max<uint64_t>(bytes, 1) + 255) / 256 * 256;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < r) continue;
+            const uint64_t off = it->first, sz = it->second;
+            free_.erase(it);
+            if (sz > r) free_[off + r] = sz - r;
+            used_[base_ + off] = r;
+            in_use_ += r;
+            peak_ = std::max(peak_, in_use_);
+            return base_ + off;
         }
-        if (in_use_ + r > budget_) return nullptr;
-        if (in_use_ + cached_ + r > budget_) trim_locked(in_use_ + cached_ + r - budget_);
-        void* p = nullptr;
-        if (hipMalloc(&p, r) != hipSuccess) {
-            (void)hipGetLastError();
-            trim_locked(UINT64_MAX);
-            if (hipMalloc(&p, r) != hipSuccess) {
-                (void)hipGetLastError();
-                return nullptr;
-            }
-        }
-        take(p, r);
-        return p;
+        return nullptr;
     }
 
     void release(void* p) {
         std::lock_guard<std::mutex> lk(m_);
-        auto it = size_.find(p);
-        if (it == size_.end()) return;
-        const size_t r = it->second;
-        size_.erase(it);
-        in_use_ -= r;
-        free_[r].push_back(p);
-        cached_ += r;
+        auto u = used_.find(static_cast<char*>(p));
+        if (u == used_.end()) return;
+        uint64_t off = (uint64_t)(u->first - base_), sz = u->second;
+        used_.erase(u);
+        in_use_ -= sz;
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && next->first == off + sz) {
+            sz += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) {
+                prev->second += sz;
+                return;
+            }
+        }
+        free_[off] = sz;
     }
 
     uint64_t in_use() const { std::lock_guard<std::mutex> lk(m_); return in_use_; }
-    uint64_t cached() const { std::lock_guard<std::mutex> lk(m_); return cached_; }
+    uint64_t cached() const { std::lock_guard<std::mutex> lk(m_); return size_ - in_use_; }
     uint64_t peak() const { std::lock_guard<std::mutex> lk(m_); return peak_; }
 
 private:
-    void take(void* p, size_t r) {
-        size_[p] = r;
-        in_use_ += r;
-        peak_ = std::max(peak_, in_use_);
-    }
-    // frees cached blocks, largest first, until `need` bytes are released
-    void trim_locked(uint64_t need) {
-        uint64_t got = 0;
-        for (auto it = free_.rbegin(); it != free_.rend() && got < need; ++it) {
-            while (!it->second.empty() && got < need) {
-                (void)hipFree(it->second.back());
-                it->second.pop_back();
-                cached_ -= it->first;
-                got += it->first;
-            }
-        }
-    }
-
     mutable std::mutex m_;
-    uint64_t budget_, in_use_ = 0, cached_ = 0, peak_ = 0;
-    std::map<size_t, std::vector<void*>> free_;
-    std::unordered_map<void*, size_t> size_;
+    char* base_ = nullptr;
+    uint64_t size_, in_use_ = 0, peak_ = 0;
+    std::map<uint64_t, uint64_t> free_;           // offset -> size
+    std::unordered_map<char*, uint64_t> used_;    // block -> size
 };
 
 void* pool_alloc(size_t bytes, void* ctx) { return static_cast<DevicePool*>(ctx)->alloc(bytes); }
@@ -215,7 +207,7 @@ struct Job {
     uint32_t slot = 0;                 // pinned result slot
     uint64_t chunks = 0;
     bool finishing = false;
-    bool tune = false;                 // autotune the launch shape on the first chunk
+    bool tune = false;                 // autotune the launch shape on a sample of the first chunk
     uint64_t shape = 0;                // tuning cache key
 };
 
@@ -237,6 +229,7 @@ struct stn_server {
     uint64_t submitted = 0, completed = 0, planned = 0, inflight_jobs = 0;
     stn_server_stats st{};
     bool stop = false;
+    bool started = false;                  // device thread initialised (memory reserved)
     std::string fatal;
 
     std::vector<std::thread> planners;
@@ -301,6 +294,13 @@ void plan_job(stn_server* sv, Job& j) {
     }
     j.plan = p;
     j.B = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(p->max_batch, j.K));
+    // statevector chunks only as large as it takes to fill the device
+    // (~32k tiles per launch): the rest of the memory serves other jobs
+    if (p->kind == STN_PLAN_SV_TILED) {
+        const int tile_bits = p->opts.precision == 128 ? (int)tiled128_tile_bits() : 14;
+        const double tiles = std::ldexp(1.0, std::max(0, (int)p->n - tile_bits));
+        j.B = (uint32_t)std::max(1.0, std::min((double)j.B, std::ceil(kChunkTiles / tiles)));
+    }
     j.est_bytes = estimate_bytes(p, j.B, j.K);
     const uint64_t budget = sv->opts.hbm_budget;
     if (j.est_bytes > budget / 32 && j.est_bytes > budget - budget / 16) {
@@ -370,11 +370,12 @@ struct Device {
 
     void init() {
         STN_HIP(hipSetDevice(sv->device));
+        sv->pool->init();
         int c = 0;
         STN_HIP(hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, sv->device));
         cus = (uint32_t)c;
         for (uint32_t i = 0; i < sv->opts.n_streams; ++i) STN_HIP(hipStreamCreateWithFlags(&streams[i], hipStreamNonBlocking));
-        STN_HIP(hipStreamCreateWithFlags(&upload, hipStreamNonBlocking));
+        upload = streams[0];
         STN_HIP(hipHostMalloc((void**)&pinned, kMaxActive * 2 * sizeof(double), hipHostMallocDefault));
         for (uint32_t i = 0; i < kMaxActive; ++i) free_slots.push_back(kMaxActive - 1 - i);
     }
@@ -385,7 +386,6 @@ struct Device {
         active.clear();
         for (uint32_t i = 0; i < sv->opts.n_streams; ++i)
             if (streams[i]) (void)hipStreamDestroy(streams[i]);
-        if (upload) (void)hipStreamDestroy(upload);
         for (auto e : ev_pool) (void)hipEventDestroy(e);
         ev_pool.clear();
         if (pinned) (void)hipHostFree(pinned);
@@ -502,10 +502,20 @@ struct Device {
         j->slot = free_slots.back();
         free_slots.pop_back();
         bytes_admitted += j->est_bytes;
-        // least-loaded stream
+        // Streams that share a hardware queue run one after the other, so the
+        // server keeps few: stream 0 carries table uploads, autotuning and the
+        // small jobs (estimated under 50 ms of device time), so that they never
+        // wait behind a large job's chunks; large jobs take the least-loaded of
+        // the others.
         uint32_t best = 0;
-        for (uint32_t i = 1; i < sv->opts.n_streams; ++i)
-            if (stream_jobs[i] < stream_jobs[best]) best = i;
+        const stn_plan* pl = j->plan;
+        const double per = pl->kind == STN_PLAN_LIGHTCONE ? 2.0 * pl->lc_est_s
+                                                          : pl->bytes_per_traj / 2e12 + pl->flops_per_traj / 2e12;
+        if (sv->opts.n_streams > 1 && per * (double)j->K > 0.05) {
+            best = 1;
+            for (uint32_t i = 2; i < sv->opts.n_streams; ++i)
+                if (stream_jobs[i] < stream_jobs[best]) best = i;
+        }
         j->stream = (int)best;
         stream_jobs[best]++;
         try {
@@ -544,8 +554,14 @@ struct Device {
             if (stn_plan_set_variant(p, it->second) != STN_OK) throw Error{STN_E_STATE, stn_last_error()};
             return;
         }
-        const double est = (p->bytes_per_traj / 4e12 + p->flops_per_traj / 8e12) * j.B;
-        j.tune = est < 0.01;
+        // estimated seconds for the tuning sample (all shapes, warm and timed)
+        const double per = p->kind == STN_PLAN_LIGHTCONE ? 2.0 * p->lc_est_s
+                                                         : p->bytes_per_traj / 2e12 + p->flops_per_traj / 2e12;
+        // networks in HBM run long per work item: their default shape is kept.
+        // The device thread waits for the tuning runs, so they are done only
+        // while no other job occupies the device.
+        const bool hbm_tier = p->kind == STN_PLAN_LIGHTCONE && p->lc_arena_bytes > 0;
+        j.tune = !hbm_tier && active.empty() && per * std::min<uint32_t>(j.B, kTuneSample) * 8.0 < 0.005;
     }
 
     void fail_job(Job& j, const Error& e) {
@@ -568,23 +584,24 @@ struct Device {
         stn_batch* b = j.batch[c];
         batch_prepare(j.plan, b, j.k_issued, K);
         if (j.tune) {
-            // on the private stream: sample, time every launch shape (this
-            // leaves the batch contracted), keep the fastest for the shape
-            launch_sample(j.plan, b, j.seed, upload);
-            if (j.plan->kind != STN_PLAN_SV_LDS) launch_frame(j.plan, b, upload);
+            // on the private stream: sample the first trajectories, time every
+            // launch shape on them, keep the fastest for the shape
+            stn_batch probe;
+            batch_prepare(j.plan, &probe, 0, std::min<uint32_t>(K, kTuneSample));
+            launch_sample(j.plan, &probe, j.seed, upload);
+            if (j.plan->kind != STN_PLAN_SV_LDS) launch_frame(j.plan, &probe, upload);
             stn_tune_result tr{};
-            const stn_status st0 = stn_plan_autotune(j.plan, b, 1, &tr, upload);
+            const stn_status st0 = stn_plan_autotune(j.plan, &probe, 1, &tr, upload);
             if (st0 != STN_OK) throw Error{st0, stn_last_error()};
             tuned[j.shape] = tr.chosen;
             j.tune = false;
             std::lock_guard<std::mutex> lk(sv->m);
             sv->st.autotuned++;
-        } else {
-            launch_sample(j.plan, b, j.seed, s);
-            if (j.plan->kind != STN_PLAN_SV_LDS) launch_frame(j.plan, b, s);
-            const stn_status st1 = stn_contract(j.plan, b, s);
-            if (st1 != STN_OK) throw Error{st1, stn_last_error()};
         }
+        launch_sample(j.plan, b, j.seed, s);
+        if (j.plan->kind != STN_PLAN_SV_LDS) launch_frame(j.plan, b, s);
+        const stn_status st1 = stn_contract(j.plan, b, s);
+        if (st1 != STN_OK) throw Error{st1, stn_last_error()};
         const stn_status st2 = stn_reduce(j.plan, b, j.acc, s);
         if (st2 != STN_OK) throw Error{st2, stn_last_error()};
         STN_HIP(hipEventRecord(j.ev[c], s));
@@ -661,11 +678,18 @@ void worker_main(stn_server* sv) {
     d.sv = sv;
     try {
         d.init();
+        {
+            std::lock_guard<std::mutex> lk(sv->m);
+            sv->started = true;
+        }
+        sv->cv_done.notify_all();
         d.loop();
     } catch (const Error& e) {
         std::lock_guard<std::mutex> lk(sv->m);
         sv->fatal = e.msg;
+        sv->started = true;
     }
+    sv->cv_done.notify_all();
     d.shutdown();
 }
 
@@ -687,7 +711,7 @@ void stn_server_opts_default(stn_server_opts* o) {
     std::memset(o, 0, sizeof(*o));
     o->hbm_budget = 64ull << 30;
     o->job_share = 0.5;
-    o->n_streams = 4;
+    o->n_streams = 3;
     o->max_active = 16;
     o->plan_cache = 64;
     o->precision = 64;
@@ -716,6 +740,18 @@ stn_status stn_server_create(const stn_server_opts* opts, stn_server** out) {
     }
     for (int i = 0; i < kPlanners; ++i) sv->planners.emplace_back(planner_loop, sv);
     sv->worker = std::thread(worker_main, sv);
+    // the server's clock and memory are ready when create returns
+    std::string fatal;
+    {
+        std::unique_lock<std::mutex> lk(sv->m);
+        sv->cv_done.wait(lk, [&] { return sv->started; });
+        fatal = sv->fatal;
+        sv->t0 = std::chrono::steady_clock::now();
+    }
+    if (!fatal.empty()) {
+        stn_server_destroy(sv);
+        return srv_error(STN_E_OOM, fatal);
+    }
     *out = sv;
     return STN_OK;
 }
