@@ -104,6 +104,10 @@ def main():
     ap.add_argument("--ksweep", action="store_true",
                     help="rho_hat leg: fidelity / trace distance vs the exact density matrix for K = 16..1024 "
                          "(adds minutes of CPU work)")
+    ap.add_argument("--uneven", action="store_true",
+                    help="only the uneven-batch leg: 64 jobs (n 10..30, p 1..6, K 256..8192) submitted at once to "
+                         "the job server, for --uneven-window seconds")
+    ap.add_argument("--uneven-window", type=float, default=900.0)
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="copy a buffer of this size once before the timed region (a known-size reference "
                          "for hardware byte counters)")
@@ -114,6 +118,11 @@ def main():
               "with one FP64 all-reduce of the partial sums (not built in this repository); run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.uneven:
+        import paper_2210_15874_amd as stn
+        print(json.dumps({"uneven_batch": uneven_leg(stn, args)}))
+        return
 
     from workloads import config_problem
     problem = config_problem(2, K=args.K)
@@ -328,6 +337,49 @@ def rho_hat_leg(stn, ksweep):
         out["ksweep"] = rows
     pl.close()
     return out
+
+
+def uneven_leg(stn, args):
+    """64 QAOA jobs, n ~ U{10..30}, p ~ U{1..6}, Erdos-Renyi p_edge = 3/(n-1),
+    K ~ U{256..8192}, submitted at once to the job server; runs until all are
+    done or the window ends (jobs still running then are censored)."""
+    import numpy as np
+    import torch
+    from workloads import uneven_batch
+    torch.cuda.set_device(0)
+    jobs = uneven_batch()
+    res = {}
+    sv = stn.Server(hbm_budget=int(args.hbm_budget_gib * (1 << 30)), job_share=0.5, n_streams=3, max_active=32,
+                    drain_on_destroy=False)
+    t0 = sv.clock()
+    for i, pr in enumerate(jobs):
+        sv.submit(pr, tag=i)
+    while sv.clock() - t0 < args.uneven_window and len(res) < len(jobs):
+        for r in sv.poll(wait=1.0, cap=4096):
+            res[r["tag"]] = r
+            print(f"uneven: job {r['tag']} n={jobs[r['tag']].n_qubits} p={jobs[r['tag']].p} K={r['K']} "
+                  f"{r['plan_name']} done at {r['t_done'] - t0:.2f} s", file=sys.stderr, flush=True)
+    t_end = min(sv.clock() - t0, args.uneven_window)
+    st = sv.stats()
+    sv.close()
+    done = [i for i in res if res[i]["status"] == 0]
+    traj = sum(res[i]["K"] for i in done)
+    lat = np.array([res[i]["t_done"] - t0 if i in res else np.inf for i in range(len(jobs))])
+    by_plan = {}
+    for i in done:
+        d = by_plan.setdefault(res[i]["plan_name"], {"jobs": 0, "trajectories": 0})
+        d["jobs"] += 1
+        d["trajectories"] += res[i]["K"]
+    censored = [{"n": jobs[i].n_qubits, "p": jobs[i].p, "K": jobs[i].K} for i in range(len(jobs)) if i not in res]
+    torch.cuda.synchronize()
+    return {"jobs": len(jobs), "window_s": args.uneven_window, "completed": len(done),
+            "failed": int(sum(r["status"] != 0 for r in res.values())), "censored": censored,
+            "makespan_s": t_end, "trajectories": traj, "trajectories_per_s": traj / t_end if t_end > 0 else None,
+            "completion_s": {"p50": float(np.percentile(lat, 50, method="higher"))
+                             if np.isfinite(np.percentile(lat, 50, method="higher")) else None,
+                             "max_completed": float(lat[np.isfinite(lat)].max()) if np.isfinite(lat).any() else None},
+            "by_plan": by_plan, "max_concurrent_jobs": st["max_active_jobs"], "autotuned_shapes": st["autotuned"],
+            "plan_cache_hits": st["plan_cache_hits"], "device_bytes_peak": st["bytes_peak"]}
 
 
 def serving_leg(stn, args):
