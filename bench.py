@@ -108,6 +108,9 @@ def main():
                     help="only the uneven-batch leg: 64 jobs (n 10..30, p 1..6, K 256..8192) submitted at once to "
                          "the job server, for --uneven-window seconds")
     ap.add_argument("--uneven-window", type=float, default=900.0)
+    ap.add_argument("--job", type=str, default=None,
+                    help="only one job n,p,K[,precision] (QAOA on an Erdos-Renyi graph, p_edge 3/(n-1), "
+                         "depolarizing 1e-3/1e-2) through the plan API with the planner's choice of lowering")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="copy a buffer of this size once before the timed region (a known-size reference "
                          "for hardware byte counters)")
@@ -122,6 +125,10 @@ def main():
     if args.uneven:
         import paper_2210_15874_amd as stn
         print(json.dumps({"uneven_batch": uneven_leg(stn, args)}))
+        return
+    if args.job:
+        import paper_2210_15874_amd as stn
+        print(json.dumps({"job": one_job_leg(stn, args)}))
         return
 
     from workloads import config_problem
@@ -302,7 +309,20 @@ def rho_hat_leg(stn, ksweep):
     prof = pl.profile_read()
     pl.profile(False)
     herk = prof["herk"]
+    # the same kernels one trajectory per launch, sequential (plain loop)
+    n_plain = 64
+    acc = pl.accum()
+    t1 = time.perf_counter()
+    for k in range(n_plain):
+        bt = pl.sample(pr.seed, k, 1)
+        pl.contract(bt)
+        pl.reduce(bt, acc)
+        torch.cuda.synchronize()
+        bt.close()
+    plain = n_plain / (time.perf_counter() - t1)
+    acc.close()
     out = {"workload": pr.name, "K": pr.K, "seconds": dt, "trajectories_per_s": pr.K / dt,
+           "plain_loop_trajectories_per_s": plain, "batched_over_plain": pr.K / dt / plain,
            "kernels_ms": {k: v["ms"] for k, v in prof.items() if v["launches"]},
            "herk_fp64_tflops": herk["flops"] / (herk["ms"] * 1e-3) / 1e12 if herk["ms"] else None,
            "herk_peak_tflops": 78.6, "trace": res["trace"]}
@@ -339,6 +359,53 @@ def rho_hat_leg(stn, ksweep):
     return out
 
 
+def one_job_leg(stn, args):
+    """One QAOA job (n, p, K[, precision]) on a seeded Erdos-Renyi graph:
+    plan, then sample / contract / reduce in the planner's chunks, timed warm;
+    per-kernel event times."""
+    import torch
+    from workloads import erdos_renyi_graph, make_problem, uniform_angles
+    f = [int(x) for x in args.job.split(",")]
+    n, p, K = f[:3]
+    precision = f[3] if len(f) > 3 else 64
+    torch.cuda.set_device(0)
+    g, b = uniform_angles(p, 5000 + n)
+    pr = make_problem(n, erdos_renyi_graph(n, 3.0 / (n - 1), 4000 + n), g, b, 1e-3, 1e-2, K, 6000 + n,
+                      name=f"er-n{n}-p{p}-K{K}")
+    t0 = time.perf_counter()
+    pl = stn.Plan(pr, outputs=stn.OUT_ENERGY, precision=precision, hbm_budget=int(args.hbm_budget_gib * (1 << 30)))
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    info = pl.info()
+    B = info["max_batch"]
+
+    def run():
+        acc = pl.accum()
+        for k0 in range(0, K, B):
+            bt = pl.sample(pr.seed, k0, min(B, K - k0))
+            pl.contract(bt)
+            pl.reduce(bt, acc)
+            bt.close()
+        r = acc.read()
+        acc.close()
+        return r
+
+    run()
+    torch.cuda.synchronize()
+    pl.profile(True)
+    t1 = time.perf_counter()
+    r = run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    prof = pl.profile_read()
+    pl.close()
+    return {"workload": pr.name, "precision": precision, "plan": info["plan_name"], "width": info["width"],
+            "steps": info["n_steps"], "passes": info["n_passes"], "trajectories_per_launch": B, "plan_ms": plan_ms,
+            "seconds": dt, "trajectories_per_s": K / dt, "energy_mean": r["energy_mean"], "energy_se": r["energy_se"],
+            "kernels": {k: {"launches": v["launches"], "ms": v["ms"],
+                            "gbps": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] else None}
+                        for k, v in prof.items() if v["launches"]}}
+
+
 def uneven_leg(stn, args):
     """64 QAOA jobs, n ~ U{10..30}, p ~ U{1..6}, Erdos-Renyi p_edge = 3/(n-1),
     K ~ U{256..8192}, submitted at once to the job server; runs until all are
@@ -354,11 +421,18 @@ def uneven_leg(stn, args):
     t0 = sv.clock()
     for i, pr in enumerate(jobs):
         sv.submit(pr, tag=i)
+    last_chunks, last_print = 0, 0.0
     while sv.clock() - t0 < args.uneven_window and len(res) < len(jobs):
         for r in sv.poll(wait=1.0, cap=4096):
             res[r["tag"]] = r
             print(f"uneven: job {r['tag']} n={jobs[r['tag']].n_qubits} p={jobs[r['tag']].p} K={r['K']} "
                   f"{r['plan_name']} done at {r['t_done'] - t0:.2f} s", file=sys.stderr, flush=True)
+        # chunks issued since the last line (long jobs complete rarely)
+        st = sv.stats()
+        if st["chunks"] > last_chunks and st["clock"] - last_print >= 20.0:
+            print(f"uneven: {st['clock'] - t0:.0f} s, {st['completed']} jobs done, {st['chunks']} chunks issued",
+                  file=sys.stderr, flush=True)
+            last_chunks, last_print = st["chunks"], st["clock"]
     t_end = min(sv.clock() - t0, args.uneven_window)
     st = sv.stats()
     sv.close()
