@@ -22,9 +22,11 @@ namespace {
 constexpr int kMaxPos = 24;              // largest step input rank (HBM tier)
 constexpr int kLdsBytes = 64 * 1024;     // LDS tier: the whole arena in LDS
 
+// An input's local index from the step index: its bits come in runs of
+// consecutive positions, loc |= ((full >> src) & (2^len - 1)) << dst.
 struct TnIn {
-    int32_t kind, gate, conj, arena, npos;
-    int32_t pos[kMaxPos];
+    int32_t kind, gate, conj, arena, nrun;
+    uint8_t src[kMaxPos], dst[kMaxPos], len[kMaxPos];
 };
 
 struct TnStep {
@@ -71,7 +73,8 @@ __device__ __forceinline__ double run_term(typename Cx<R>::T* arena, const TnTer
                 for (int i = 0; i < st.n_in; ++i) {
                     const TnIn& in = ins[st.in_off + i];
                     uint32_t loc = 0;
-                    for (int k = 0; k < in.npos; ++k) loc |= ((full >> in.pos[k]) & 1u) << k;
+                    for (int r = 0; r < in.nrun; ++r)
+                        loc |= ((full >> in.src[r]) & ((1u << in.len[r]) - 1u)) << in.dst[r];
                     V val;
                     if (in.kind == TN_INTER) {
                         val = arena[in.arena + loc];
@@ -174,12 +177,13 @@ template <class R>
 using TnHbmFn = void (*)(const TnTerm*, const TnStep*, const TnIn*, const typename Cx<R>::T*, const uint32_t*,
                          uint32_t, double*, uint32_t, uint32_t, typename Cx<R>::T*, uint32_t);
 
+// one persistent workgroup per free CU: the default is the widest
 template <class R>
 TnKernel tn_hbm_kernel(uint32_t v) {
     switch (v) {
-        case 1: return {(void*)k_tn_hbm<R, 128>, 128};
+        case 1: return {(void*)k_tn_hbm<R, 256>, 256};
         case 2: return {(void*)k_tn_hbm<R, 512>, 512};
-        default: return {(void*)k_tn_hbm<R, 256>, 256};
+        default: return {(void*)k_tn_hbm<R, 1024>, 1024};
     }
 }
 
@@ -315,8 +319,16 @@ void upload_lightcone(stn_plan* p, hipStream_t s) {
                 di.gate = in.gate;
                 di.conj = in.conj;
                 di.arena = in.arena;
-                di.npos = (int32_t)in.pos.size();
-                for (size_t k = 0; k < in.pos.size(); ++k) di.pos[k] = in.pos[k];
+                di.nrun = 0;
+                for (size_t k = 0; k < in.pos.size();) {
+                    size_t e = k + 1;
+                    while (e < in.pos.size() && in.pos[e] == in.pos[e - 1] + 1) ++e;
+                    di.src[di.nrun] = (uint8_t)in.pos[k];
+                    di.dst[di.nrun] = (uint8_t)k;
+                    di.len[di.nrun] = (uint8_t)(e - k);
+                    di.nrun++;
+                    k = e;
+                }
                 ins.push_back(di);
             }
             steps.push_back(ds);
