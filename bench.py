@@ -148,6 +148,10 @@ def main():
     plan_ms = (time.perf_counter() - t0) * 1e3
     info = plan.info()
     B = info["max_batch"]
+    # launch shape from the autotuner (untimed; results do not depend on it)
+    tb = plan.sample(problem.seed, 0, B)
+    tune = plan.autotune(tb, reps=1)
+    tb.close()
 
     def job():
         acc = plan.accum()
@@ -217,6 +221,7 @@ def main():
                    "graph": "random 3-regular (seed 1002)", "K": K, "lambda1": 1e-3, "lambda2": 1e-2,
                    "contraction": "complex64 (FP32), FP64 reductions", "plan": info["plan_name"],
                    "trajectories_per_launch": B, "passes_per_trajectory": info["n_passes"],
+                   "launch_shape": {"chosen": tune["chosen"], "ms_per_variant": tune["ms"]},
                    "plan_ms": plan_ms},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None,
