@@ -33,8 +33,9 @@
 // Tiles that hold only two low storage bits read 32-byte runs; the four
 // workgroups that share each 128-byte line get tile indices x, x+8, x+16,
 // x+24, which the dispatcher places on the same XCD at the same time, so each
-// line comes from HBM once.  Workgroups are persistent (one per CU) and
-// prefetch the next tile into registers while working on the current one.
+// line comes from HBM once.  Workgroups are persistent: either one per CU,
+// prefetching the next tile into registers while working on the current one,
+// or two per CU with the exchange buffer halved (the launch-shape variants).
 #include <cmath>
 
 #include "stn_internal.h"
@@ -85,6 +86,13 @@ struct Pass2 {
 // so a thread's 32 slots are one base address plus immediate offsets.
 constexpr int kLdsSlots = 16894;  // pad(2^14 - 1) + 1
 __host__ __device__ constexpr uint32_t pad(uint32_t t) { return t + 2u * ((t >> 6) & 7u) + 16u * (t >> 9); }
+
+// The same for the exchange in two halves (real parts, then imaginary parts;
+// 4-byte slots), which halves the buffer so that two workgroups fit on a CU.
+// In every layout the 32 lanes of a half-wave see tile-bit offsets of
+// 2-adic valuations 0..4, i.e. 32 distinct banks of 32.
+constexpr int kLdsSlots4 = 16895;  // pad4(2^14 - 1) + 1
+__host__ __device__ constexpr uint32_t pad4(uint32_t t) { return t + ((t >> 5) & 1u) + 2u * (t >> 6); }
 
 template <const int* T>
 __device__ __forceinline__ uint32_t thread_part(uint32_t tid) {
@@ -147,23 +155,50 @@ __device__ __forceinline__ void mix(float2 (&v)[kRegs], const float* tt) {
     }
 }
 
-// write registers in layout A, read them back in layout B
-template <const int* AR, const int* AT, const int* BR, const int* BT>
-__device__ __forceinline__ void exchange(float2 (&v)[kRegs], float2* lds, uint32_t tid) {
-    float2* wa = lds + pad(thread_part<AT>(tid));
+// write registers in layout A, read them back in layout B; TWO: through a
+// buffer of 4-byte slots, real parts first
+template <bool TWO, const int* AR, const int* AT, const int* BR, const int* BT>
+__device__ __forceinline__ void exchange(float2 (&v)[kRegs], float* ldsf, uint32_t tid) {
+    if constexpr (!TWO) {
+        float2* lds = reinterpret_cast<float2*>(ldsf);
+        float2* wa = lds + pad(thread_part<AT>(tid));
 #pragma unroll
-    for (int j = 0; j < kRegs; ++j) wa[pad(reg_part<AR>(j))] = v[j];
-    __syncthreads();
-    const float2* rb = lds + pad(thread_part<BT>(tid));
+        for (int j = 0; j < kRegs; ++j) wa[pad(reg_part<AR>(j))] = v[j];
+        __syncthreads();
+        const float2* rb = lds + pad(thread_part<BT>(tid));
 #pragma unroll
-    for (int j = 0; j < kRegs; ++j) v[j] = rb[pad(reg_part<BR>(j))];
-    __syncthreads();
+        for (int j = 0; j < kRegs; ++j) v[j] = rb[pad(reg_part<BR>(j))];
+        __syncthreads();
+    } else {
+        // the bases are recomputed here rather than kept live across the
+        // pass (register budget of two workgroups per CU)
+        uint32_t ta = pad4(thread_part<AT>(tid)), tb = pad4(thread_part<BT>(tid));
+        asm volatile("" : "+v"(ta), "+v"(tb));
+        float* wa = ldsf + ta;
+        const float* rb = ldsf + tb;
+        // the real parts are replaced while the imaginary parts still hold
+        // layout A
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) wa[pad4(reg_part<AR>(j))] = v[j].x;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) v[j].x = rb[pad4(reg_part<BR>(j))];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) wa[pad4(reg_part<AR>(j))] = v[j].y;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) v[j].y = rb[pad4(reg_part<BR>(j))];
+        __syncthreads();
+    }
 }
 
 // Diagonal exp(-i base m(z)) on the registers of the layout whose register
-// bits sit at storage bits rs[] and whose other bits form z0.
+// bits sit at storage bits rs[] and whose other bits form z0.  m6[j] is the
+// part of m from zz gates with both qubits on register bits (the same for
+// every thread, tabulated once per trajectory by reg_pair_table).
 __device__ __forceinline__ void diag(float2 (&v)[kRegs], const DiagTab& D, uint64_t z0, const int4* dedges,
-                                     const int* wt, uint32_t w_base, const float2* ph) {
+                                     const int* wt, uint32_t w_base, const float2* ph, const int* m6) {
     int C = 0, h[5] = {0, 0, 0, 0, 0};
     for (uint32_t e = 0; e < D.n[0]; ++e) {
         const int4 E = dedges[D.off[0] + e];
@@ -191,20 +226,25 @@ __device__ __forceinline__ void diag(float2 (&v)[kRegs], const DiagTab& D, uint6
                 if (j & (1 << r)) a += h[r];
             m[jj] = a;
         }
-        for (uint32_t e = 0; e < D.n[6]; ++e) {
-            const int4 E = dedges[D.off[6] + e];
-            const int w = wt[D.off[6] + e - w_base];
-#pragma unroll
-            for (int jj = 0; jj < 8; ++jj) m[jj] += ((((j0 + jj) >> E.x) ^ ((j0 + jj) >> E.y)) & 1) ? w : 0;
-        }
 #pragma unroll
         for (int jj = 0; jj < 8; ++jj) {
-            const float2 p = ph[D.ph_mid + m[jj]];
+            const float2 p = ph[D.ph_mid + m[jj] + m6[j0 + jj]];
             const float2 a = v[j0 + jj];
             v[j0 + jj] = make_float2(p.x * a.x - p.y * a.y, fmaf(p.x, a.y, p.y * a.x));
         }
         __builtin_amdgcn_sched_barrier(0);
     }
+}
+
+// m6[j] of diagonal D for register index j (threads j = 0..31 of the caller)
+__device__ __forceinline__ int reg_pair_table(const DiagTab& D, const int4* dedges, const int* wt, uint32_t w_base,
+                                              int j) {
+    int a = 0;
+    for (uint32_t e = 0; e < D.n[6]; ++e) {
+        const int4 E = dedges[D.off[6] + e];
+        a += (((j >> E.x) ^ (j >> E.y)) & 1) ? wt[D.off[6] + e - w_base] : 0;
+    }
+    return a;
 }
 
 __device__ __forceinline__ uint32_t tile_of(uint32_t x, uint32_t share) {
@@ -297,8 +337,11 @@ __device__ __forceinline__ float energy_part(const float2 (&v)[kRegs], const Pas
 // 8 = last pass (energy instead of store).
 // Workgroup w processes tiles w, w + G, ... (G = grid, a multiple of 32 so
 // every workgroup keeps its XCD's share of line-sharing tiles).
-template <int FL>
-__global__ __launch_bounds__(kThreads) void k_sv_pass(float2* __restrict__ psi, const Pass2 P, uint32_t n,
+// TWO: two resident workgroups per CU (half the LDS, at most 128 registers,
+// no prefetch): one workgroup's loads and stores overlap the other's
+// arithmetic and exchanges.
+template <int FL, bool TWO>
+__global__ __launch_bounds__(kThreads, TWO ? 4 : 1) void k_sv_pass(float2* __restrict__ psi, const Pass2 P, uint32_t n,
                                                       uint32_t tiles_log2, uint32_t total,
                                                       const uint32_t* __restrict__ signs, uint32_t words,
                                                       const uint64_t* __restrict__ frame,
@@ -307,16 +350,17 @@ __global__ __launch_bounds__(kThreads) void k_sv_pass(float2* __restrict__ psi, 
                                                       const int2* __restrict__ eedges,
                                                       const double* __restrict__ ew,
                                                       double* __restrict__ partials) {
-    __shared__ float2 lds[kLdsSlots];
+    __shared__ __align__(16) float lds[TWO ? kLdsSlots4 : 2 * kLdsSlots];
     __shared__ uint32_t sg[64];
     __shared__ float2 pha[kMaxPhase], phb[kMaxPhase];
     __shared__ double red[kThreads / 64];
     __shared__ int wt[kMaxEdges];  // this trajectory's signed multiplicities of the pass's zz gates
     __shared__ float tt[32];       // this trajectory's signed rotation coefficients [segment][layout][r]
+    __shared__ int m6[2][kRegs];   // register-pair parts of the two diagonals' m (see diag)
     constexpr bool kInit = FL & 1, kDiagA = FL & 2, kSeg2 = FL & 4, kLast = FL & 8;
     // the next tile is prefetched into registers when they allow it (one
     // segment); two-segment passes load it after finishing the current one
-    constexpr bool kPrefetch = !kSeg2;
+    constexpr bool kPrefetch = !kSeg2 && !TWO;
     const uint32_t tid = threadIdx.x;
     const uint64_t zt0 = storage_thread<L0T>(P, tid), zt2 = storage_thread<L2T>(P, tid);
     const uint32_t tmask = (1u << tiles_log2) - 1u;
@@ -366,22 +410,32 @@ __global__ __launch_bounds__(kThreads) void k_sv_pass(float2* __restrict__ psi, 
                 tt[tid] = (g >= 0 && sign_bit(sg, g)) ? -c0 : c0;
             }
             __syncthreads();
+            if (tid < 2 * kRegs) {
+                const bool second = tid >= kRegs;
+                if (second ? kSeg2 : kDiagA)
+                    m6[second][tid % kRegs] =
+                        reg_pair_table(second ? P.db : P.da, dedges, wt, P.w_off, (int)(tid % kRegs));
+            }
+            __syncthreads();
             sb = b;
         }
         float2* st = psi + ((size_t)b << n);
 
-        if (kDiagA) diag(v, P.da, base | zt0, dedges, wt, P.w_off, pha);
+        if (kDiagA) diag(v, P.da, base | zt0, dedges, wt, P.w_off, pha, m6[0]);
+        if constexpr (TWO) __builtin_amdgcn_sched_barrier(0);
         mix<0, 0, 5>(v, tt);
-        exchange<L0R, L0T, L1R, L1T>(v, lds, tid);
+        exchange<TWO, L0R, L0T, L1R, L1T>(v, lds, tid);
         mix<0, 1, 5>(v, tt);
-        exchange<L1R, L1T, L2R, L2T>(v, lds, tid);
+        exchange<TWO, L1R, L1T, L2R, L2T>(v, lds, tid);
         mix<0, 2, 0>(v, tt);
         if (kSeg2) {
-            diag(v, P.db, base | zt2, dedges, wt, P.w_off, phb);
+            if constexpr (TWO) __builtin_amdgcn_sched_barrier(0);
+            diag(v, P.db, base | zt2, dedges, wt, P.w_off, phb, m6[1]);
+            if constexpr (TWO) __builtin_amdgcn_sched_barrier(0);
             mix<1, 2, 5>(v, tt);
-            exchange<L2R, L2T, L1R, L1T>(v, lds, tid);
+            exchange<TWO, L2R, L2T, L1R, L1T>(v, lds, tid);
             mix<1, 1, 5>(v, tt);
-            exchange<L1R, L1T, L0R, L0T>(v, lds, tid);
+            exchange<TWO, L1R, L1T, L0R, L0T>(v, lds, tid);
             mix<1, 0, 0>(v, tt);
         }
 
@@ -439,13 +493,17 @@ __global__ __launch_bounds__(256) void k_tile_sum(const double* __restrict__ par
 typedef void (*PassKernel)(float2*, const Pass2, uint32_t, uint32_t, uint32_t, const uint32_t*, uint32_t,
                            const uint64_t*, const int4*, const float2*, const int2*, const double*, double*);
 
-PassKernel pass_kernel(int fl) {
+template <bool TWO>
+PassKernel pass_kernel_of(int fl) {
     static const PassKernel tab[16] = {
-        k_sv_pass<0>,  k_sv_pass<1>,  k_sv_pass<2>,  k_sv_pass<3>,  k_sv_pass<4>,  k_sv_pass<5>,
-        k_sv_pass<6>,  k_sv_pass<7>,  k_sv_pass<8>,  k_sv_pass<9>,  k_sv_pass<10>, k_sv_pass<11>,
-        k_sv_pass<12>, k_sv_pass<13>, k_sv_pass<14>, k_sv_pass<15>};
+        k_sv_pass<0, TWO>,  k_sv_pass<1, TWO>,  k_sv_pass<2, TWO>,  k_sv_pass<3, TWO>,
+        k_sv_pass<4, TWO>,  k_sv_pass<5, TWO>,  k_sv_pass<6, TWO>,  k_sv_pass<7, TWO>,
+        k_sv_pass<8, TWO>,  k_sv_pass<9, TWO>,  k_sv_pass<10, TWO>, k_sv_pass<11, TWO>,
+        k_sv_pass<12, TWO>, k_sv_pass<13, TWO>, k_sv_pass<14, TWO>, k_sv_pass<15, TWO>};
     return tab[fl & 15];
 }
+
+PassKernel pass_kernel(int fl, bool two) { return two ? pass_kernel_of<true>(fl) : pass_kernel_of<false>(fl); }
 
 struct TiledTables {
     std::vector<Pass2> passes;
@@ -626,11 +684,14 @@ void launch_sv_tiled(stn_plan* p, stn_batch* b, hipStream_t s) {
     int dev = 0, cus = 0;
     STN_HIP(hipGetDevice(&dev));
     STN_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    // one resident workgroup per CU (variant 1: two per CU, the second queued), a
-    // multiple of 32 (XCD rounds of line groups)
-    uint32_t grid_max = std::max(32u, (uint32_t)cus / 32u * 32u) * (p->variant == 1 ? 2u : 1u);
+    // variant 0: one workgroup per CU; 1: two per CU, the second queued behind
+    // the first; 2: two resident per CU (the half-buffer kernels).  The grid is
+    // a multiple of 32 (XCD rounds of line groups).
+    const bool two = p->variant == 2;
+    const uint32_t per_cu = p->variant == 0 ? 1u : 2u;
+    uint32_t grid_max = std::max(32u, (uint32_t)cus / 32u * 32u) * per_cu;
     // a job server may keep some CUs free for other jobs' kernels
-    if (p->grid_cap) grid_max = std::min(grid_max, std::max(32u, p->grid_cap / 32u * 32u));
+    if (p->grid_cap) grid_max = std::min(grid_max, std::max(32u, p->grid_cap * (two ? 2u : 1u) / 32u * 32u));
     for (uint32_t c0 = 0; c0 < b->K; c0 += B) {
         const uint32_t nb = std::min(B, b->K - c0);
         const uint32_t blocks = nb * tiles;
@@ -641,7 +702,7 @@ void launch_sv_tiled(stn_plan* p, stn_batch* b, hipStream_t s) {
             if (blocks % (8u << P.share) || grid % 32) P.share = 0;  // grouping needs whole XCD rounds
             const double elems = (double)nb * (double)N;
             prof_begin(p, STN_K_SV_PASS, s);
-            hipLaunchKernelGGL(pass_kernel(fl), dim3(grid), dim3(kThreads), 0, s, p->d_work.as<float2>(), P, n,
+            hipLaunchKernelGGL(pass_kernel(fl, two), dim3(grid), dim3(kThreads), 0, s, p->d_work.as<float2>(), P, n,
                                tiles_log2, blocks, b->d_signs.as<uint32_t>() + (size_t)c0 * b->words, b->words,
                                b->d_frame.as<uint64_t>() + 2 * (size_t)c0, d->dedges.as<int4>(),
                                d->phase.as<float2>(), d->eedges.as<int2>(), d->ew.as<double>(),
@@ -658,6 +719,6 @@ void launch_sv_tiled(stn_plan* p, stn_batch* b, hipStream_t s) {
     }
 }
 
-uint32_t tiled_variants(const stn_plan* p) { return p->opts.precision == 128 ? 1u : 2u; }
+uint32_t tiled_variants(const stn_plan* p) { return p->opts.precision == 128 ? 1u : 3u; }
 
 }  // namespace stn

@@ -336,11 +336,13 @@ def test_lightcone_noiseless_p1_closed_form_large_n(n, precision, tol):
 
 # ----------------------------------------------------------------------------- full-size workload
 
-def test_full_size_workload_sampled_trajectories():
-    """n=26, p=4, K=4096 in the launch configuration the benchmark times
-    (trajectories per launch from a 160 GiB budget): sampled trajectories
-    against stored oracle values (complex128, literal Kraus insertion, same
-    draws), plus properties that hold at any size."""
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_full_size_workload_sampled_trajectories(variant):
+    """n=26, p=4, K=4096 in the launch configurations the benchmark times
+    (trajectories per launch from a 160 GiB budget, each launch shape the
+    autotuner may pick): sampled trajectories against stored oracle values
+    (complex128, literal Kraus insertion, same draws), plus properties that
+    hold at any size."""
     import json
     from workloads import config_problem
     stn = stn_mod()
@@ -351,8 +353,9 @@ def test_full_size_workload_sampled_trajectories():
     assert [list(e) for e in pr.edges] == gold["edges"]
     m = len(pr.edges)
     pl = stn.Plan(pr, outputs=stn.OUT_ENERGY, precision=64, hbm_budget=160 << 30)
+    pl.set_variant(variant)
     info = pl.info()
-    assert info["plan_name"] == "sv_tiled"
+    assert info["plan_name"] == "sv_tiled" and info["variant"] == variant
     B = info["max_batch"]
     acc = pl.accum()
     for k0 in range(0, pr.K, B):
