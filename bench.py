@@ -54,10 +54,11 @@ def cpu_baseline(problem, sample_gates):
                       f"n={problem.n_qubits}, complex128, {dt:.1f} s, scaled by {G}/{sample_gates}"}
 
 
-def measured_traffic(kernel_source):
+def measured_traffic(kernel_source, launch_shape):
     """HBM bytes per launch of the tiled pass from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary, or None if the kernel source has changed
-    since the counters were taken."""
+    since the counters were taken or they were taken with another launch
+    shape."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "sv_pass_qaoa_n26_p4_traffic.json")
     if not os.path.exists(path):
@@ -67,6 +68,8 @@ def measured_traffic(kernel_source):
     with open(os.path.join(ROOT, kernel_source), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != t["source_sha256"]:
             return None
+    if t.get("launch_shape") != launch_shape:
+        return None
     return t["traffic_bytes_per_launch"] / 1e9
 
 
@@ -225,7 +228,7 @@ def main():
                    "plan_ms": plan_ms},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None,
-                     "traffic": measured_traffic("paper_2210_15874_amd/csrc/kernels_sv_tiled.hip")
+                     "traffic": measured_traffic("paper_2210_15874_amd/csrc/kernels_sv_tiled.hip", tune["chosen"])
                      if kname == "sv_pass" and B == 319 else None, "traffic_unit": "GB per launch",
                      "launches": kern["launches"], "avg_launch_ms": kern["ms"] / max(1, kern["launches"]),
                      "bytes_per_launch": kern["bytes"] / max(1, kern["launches"])},
