@@ -201,7 +201,7 @@ def main():
     torch.cuda.empty_cache()
     fp64 = fp64_leg(stn, problem, res["energies"], args.fp64_prefix) if args.fp64_prefix > 0 else None
     torch.cuda.empty_cache()
-    plain = plain_loop(stn, problem, args.plain_traj, value) if args.plain_traj > 0 else None
+    plain = plain_loop(stn, problem, args.plain_traj, value, tune["chosen"]) if args.plain_traj > 0 else None
     torch.cuda.empty_cache()
     rho_leg = rho_hat_leg(stn, args.ksweep) if args.rho_leg else None
     torch.cuda.empty_cache()
@@ -272,11 +272,14 @@ def fp64_leg(stn, problem, e64, prefix):
     return out
 
 
-def plain_loop(stn, problem, n_traj, batched_value):
-    """Plain per-trajectory loop: the same kernels, one trajectory per launch,
-    sequential (sample, contract, reduce, synchronise)."""
+def plain_loop(stn, problem, n_traj, batched_value, variant=None):
+    """Plain per-trajectory loop: the same kernels (and launch shape),
+    one trajectory per launch, sequential (sample, contract, reduce,
+    synchronise)."""
     import torch
     pl = stn.Plan(problem, outputs=stn.OUT_ENERGY, precision=64, max_batch=1)
+    if variant is not None:
+        pl.set_variant(variant)
     acc = pl.accum()
     b = pl.sample(problem.seed, 0, 1)   # warm: tables, workspace
     pl.contract(b)
