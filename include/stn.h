@@ -163,6 +163,9 @@ typedef struct {
     double lc_flops_per_traj; /* their flops per trajectory */
     uint32_t variant;       /* launch shape of the contraction kernels (stn_plan_autotune) */
     uint32_t tuned;         /* 1 after stn_plan_autotune or stn_plan_set_variant */
+    uint32_t graphs;        /* 1 while stn_contract uses HIP graphs (stn_plan_set_graphs) */
+    uint64_t graph_captures;/* contraction graphs captured so far */
+    uint64_t graph_replays; /* contractions run by replaying a captured graph */
 } stn_plan_stats;
 
 typedef struct {
@@ -218,6 +221,13 @@ stn_status stn_plan_site(const stn_plan* plan, uint32_t site, uint32_t* n_ops, u
  * (seed, k, site).  K may exceed max_batch: contract splits it. */
 stn_status stn_sample(stn_plan* plan, uint64_t seed, uint64_t k0, uint32_t K,
                       stn_batch** out, void* stream);
+
+/* Draws trajectories k0 .. k0+K-1 of job `seed` into an existing batch of
+ * its plan, replacing its contents (the same draws as stn_sample).  Device
+ * buffers are kept when large enough, so a caller running many chunks
+ * allocates once; work already enqueued on the batch must be ordered before
+ * this call (same stream). */
+stn_status stn_resample(stn_batch* batch, uint64_t seed, uint64_t k0, uint32_t K, void* stream);
 
 /* Batch from caller-chosen Kraus indices: idx is a host array [K x n_sites]
  * of uint8 (index j of each site's operator, < the channel's operator count).
@@ -278,6 +288,18 @@ stn_status stn_plan_autotune(stn_plan* plan, stn_batch* batch, uint32_t reps, st
  * STN_E_INVALID. */
 stn_status stn_plan_set_variant(stn_plan* plan, uint32_t variant);
 
+/* HIP graphs for the contraction (on: 1, off: 0; off by default).  With
+ * graphs on, stn_contract runs a batch's launches eagerly the first time it
+ * sees that batch with a given K, launch shape, CU cap and device workspace,
+ * captures them into a HIP graph the second time and replays the graph on
+ * later calls (a caller that refills one batch with stn_resample for every
+ * chunk pays the launch sequence once).  A change of any of these (for
+ * example a reallocation by the plan's allocator) starts over.  Results are
+ * those of eager launches, bit for bit.  Graphs are not used while profiling
+ * is on, on the NULL stream, or when the caller is already capturing the
+ * stream.  The graph belongs to the batch and is freed with it. */
+stn_status stn_plan_set_graphs(stn_plan* plan, uint32_t on);
+
 /* Accumulator of one job's ensemble sums (FP64, device-resident). */
 stn_status stn_accum_create(stn_plan* plan, stn_accum** out);
 
@@ -322,6 +344,7 @@ typedef struct {
     uint32_t drain_on_destroy; /* 1: stn_server_destroy waits for every submitted job */
     uint32_t reserve_cus;    /* CUs the persistent kernels (tiled statevector, lightcone networks in
                                 HBM) leave free for other jobs' kernels */
+    uint32_t graphs;         /* 1: chunk contractions replay HIP graphs (stn_plan_set_graphs) */
 } stn_server_opts;
 
 typedef struct {
@@ -355,7 +378,7 @@ typedef struct {
 } stn_server_stats;
 
 /* Defaults: 64 GiB budget, job_share 0.5, 3 streams, 16 active jobs, 64
- * cached plans, complex64, drain on destroy, 32 reserved CUs. */
+ * cached plans, complex64, drain on destroy, 32 reserved CUs, graphs on. */
 void stn_server_opts_default(stn_server_opts* opts);
 /* Starts the server's threads on the calling thread's current device. */
 stn_status stn_server_create(const stn_server_opts* opts, stn_server** out);

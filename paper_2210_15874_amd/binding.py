@@ -71,7 +71,8 @@ class PlanStats(C.Structure):
                 ("n_sites", C.c_uint32), ("max_batch", C.c_uint32), ("width", C.c_uint32),
                 ("n_passes", C.c_uint32), ("n_steps", C.c_uint32), ("bytes_per_traj", C.c_double),
                 ("flops_per_traj", C.c_double), ("peak_bytes", C.c_double), ("lc_width", C.c_uint32),
-                ("lc_flops_per_traj", C.c_double), ("variant", C.c_uint32), ("tuned", C.c_uint32)]
+                ("lc_flops_per_traj", C.c_double), ("variant", C.c_uint32), ("tuned", C.c_uint32),
+                ("graphs", C.c_uint32), ("graph_captures", C.c_uint64), ("graph_replays", C.c_uint64)]
 
 
 class TuneResult(C.Structure):
@@ -94,7 +95,8 @@ class Result(C.Structure):
 class ServerOpts(C.Structure):
     _fields_ = [("hbm_budget", C.c_uint64), ("job_share", C.c_double), ("n_streams", C.c_uint32),
                 ("max_active", C.c_uint32), ("plan_cache", C.c_uint32), ("precision", C.c_uint32),
-                ("chunk_max", C.c_uint32), ("drain_on_destroy", C.c_uint32), ("reserve_cus", C.c_uint32)]
+                ("chunk_max", C.c_uint32), ("drain_on_destroy", C.c_uint32), ("reserve_cus", C.c_uint32),
+                ("graphs", C.c_uint32)]
 
 
 class JobResult(C.Structure):
@@ -131,6 +133,8 @@ EXPORTS = {
     "stn_batch_results": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "stn_plan_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(TuneResult), C.c_void_p]),
     "stn_plan_set_variant": (C.c_int, [C.c_void_p, C.c_uint32]),
+    "stn_plan_set_graphs": (C.c_int, [C.c_void_p, C.c_uint32]),
+    "stn_resample": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint32, C.c_void_p]),
     "stn_batch_size": (C.c_uint32, [C.c_void_p]),
     "stn_batch_destroy": (None, [C.c_void_p]),
     "stn_profile": (C.c_int, [C.c_void_p, C.c_int]),
@@ -310,6 +314,17 @@ class Plan:
     def set_variant(self, v):
         _check(self.lib.stn_plan_set_variant(self.h, int(v)))
 
+    def set_graphs(self, on=True):
+        """Contractions of a reused batch replay a captured HIP graph."""
+        _check(self.lib.stn_plan_set_graphs(self.h, 1 if on else 0))
+
+    def resample(self, batch, seed, k0, K, stream=None):
+        """Refills `batch` with trajectories k0 .. k0+K-1 (buffers reused)."""
+        _check(self.lib.stn_resample(batch.h, int(seed), int(k0), int(K),
+                                     stream if stream is not None else current_stream()))
+        batch.K = int(K)
+        return batch
+
     def profile(self, enable=True):
         _check(self.lib.stn_profile(self.h, 1 if enable else 0))
 
@@ -433,7 +448,7 @@ class Server:
     PyTorch's allocator; hbm_budget bounds it."""
 
     def __init__(self, hbm_budget=64 << 30, job_share=0.5, n_streams=3, max_active=16, plan_cache=64,
-                 precision=64, chunk_max=0, drain_on_destroy=True, reserve_cus=32):
+                 precision=64, chunk_max=0, drain_on_destroy=True, reserve_cus=32, graphs=True):
         self.lib = load()
         o = ServerOpts()
         self.lib.stn_server_opts_default(C.byref(o))
@@ -446,6 +461,7 @@ class Server:
         o.chunk_max = chunk_max
         o.drain_on_destroy = 1 if drain_on_destroy else 0
         o.reserve_cus = int(reserve_cus)
+        o.graphs = 1 if graphs else 0
         h = C.c_void_p()
         _check_srv(self.lib.stn_server_create(C.byref(o), C.byref(h)))
         self.h = h

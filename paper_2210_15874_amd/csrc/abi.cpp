@@ -28,6 +28,7 @@ void hip_check(hipError_t e, const char* what) {
 
 void* Allocator::alloc(size_t bytes) const {
     void* p = nullptr;
+    ++gen;
     if (fn) {
         p = fn(bytes, ctx);
         if (!p) fail(STN_E_OOM, "device allocator returned NULL for " + std::to_string(bytes) + " bytes");
@@ -234,6 +235,9 @@ stn_status stn_plan_info(const stn_plan* p, stn_plan_stats* o) {
     o->lc_flops_per_traj = p->lc_flops_per_traj;
     o->variant = p->variant;
     o->tuned = p->tuned ? 1 : 0;
+    o->graphs = p->graphs ? 1 : 0;
+    o->graph_captures = p->graph_captures;
+    o->graph_replays = p->graph_replays;
     return STN_OK;
 }
 
@@ -299,6 +303,20 @@ stn_status stn_sample(stn_plan* p, uint64_t seed, uint64_t k0, uint32_t K, stn_b
     return STN_OK;
 }
 
+stn_status stn_resample(stn_batch* b, uint64_t seed, uint64_t k0, uint32_t K, void* stream) {
+    if (!b || !b->plan) return set_error(STN_E_INVALID, "NULL argument");
+    if (K == 0) return set_error(STN_E_INVALID, "K must be positive");
+    stn_plan* p = b->plan;
+    return guarded([&] {
+        batch_prepare(p, b, k0, K);
+        b->has_states = false;
+        hipStream_t s = (hipStream_t)stream;
+        ensure_uploaded(p, s);
+        launch_sample(p, b, seed, s);
+        if (p->kind != STN_PLAN_SV_LDS) launch_frame(p, b, s);
+    });
+}
+
 stn_status stn_batch_from_indices(stn_plan* p, const uint8_t* idx, uint64_t k0, uint32_t K, stn_batch** out,
                                   void* stream) {
     if (!p || !out || (!idx && K && !p->sites.empty())) return set_error(STN_E_INVALID, "NULL argument");
@@ -358,15 +376,79 @@ static void contract_launch(stn_plan* p, stn_batch* b, hipStream_t s) {
     }
 }
 
+// Contraction through a HIP graph per (batch, K, launch shape, CU cap,
+// workspace): eager the first time, captured the second, replayed after.
+static void contract_graph(stn_plan* p, stn_batch* b, hipStream_t s) {
+    const uint64_t key[4] = {b->K, p->variant, p->grid_cap, p->alloc.gen};
+    const bool same = std::equal(key, key + 4, b->gkey);
+    if (b->gstate == 2 && same) {
+        STN_HIP(hipGraphLaunch(b->gexec, s));
+        p->graph_replays++;
+        return;
+    }
+    if (b->gstate == 1 && same) {
+        hipGraph_t g = nullptr;
+        STN_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        try {
+            contract_launch(p, b, s);
+        } catch (...) {
+            (void)hipStreamEndCapture(s, &g);
+            if (g) (void)hipGraphDestroy(g);
+            b->gstate = 0;
+            throw;
+        }
+        STN_HIP(hipStreamEndCapture(s, &g));
+        if (p->alloc.gen != key[3]) {   // the eager run allocated everything; nothing may move now
+            (void)hipGraphDestroy(g);
+            b->gstate = 0;
+            fail(STN_E_STATE, "device memory allocated during graph capture");
+        }
+        if (b->gexec) {
+            (void)hipGraphExecDestroy(b->gexec);
+            b->gexec = nullptr;
+        }
+        const hipError_t e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            b->gexec = nullptr;
+            b->gstate = 0;
+            STN_HIP(e);
+        }
+        b->gstate = 2;
+        p->graph_captures++;
+        STN_HIP(hipGraphLaunch(b->gexec, s));
+        return;
+    }
+    contract_launch(p, b, s);
+    b->gkey[0] = b->K;
+    b->gkey[1] = p->variant;
+    b->gkey[2] = p->grid_cap;
+    b->gkey[3] = p->alloc.gen;
+    b->gstate = 1;
+}
+
 stn_status stn_contract(stn_plan* p, stn_batch* b, void* stream) {
     if (!p || !b) return set_error(STN_E_INVALID, "NULL argument");
     if (b->plan != p) return set_error(STN_E_INVALID, "batch belongs to another plan");
     return guarded([&] {
         hipStream_t s = (hipStream_t)stream;
         ensure_uploaded(p, s);
-        contract_launch(p, b, s);
+        bool use_graph = p->graphs && !p->prof && s != nullptr;
+        if (use_graph) {
+            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+            STN_HIP(hipStreamIsCapturing(s, &cs));
+            use_graph = cs == hipStreamCaptureStatusNone;
+        }
+        if (use_graph) contract_graph(p, b, s);
+        else contract_launch(p, b, s);
         b->contracted = true;
     });
+}
+
+stn_status stn_plan_set_graphs(stn_plan* p, uint32_t on) {
+    if (!p) return set_error(STN_E_INVALID, "NULL argument");
+    p->graphs = on != 0;
+    return STN_OK;
 }
 
 stn_status stn_plan_autotune(stn_plan* p, stn_batch* b, uint32_t reps, stn_tune_result* out, void* stream) {

@@ -522,6 +522,7 @@ struct Device {
             ensure_uploaded(j->plan, upload);
             // persistent kernels leave reserve_cus CUs to the other jobs
             if (sv->opts.reserve_cus && cus > sv->opts.reserve_cus) j->plan->grid_cap = cus - sv->opts.reserve_cus;
+            j->plan->graphs = sv->opts.graphs != 0;
             choose_shape(*j);
             j->acc = new stn_accum();
             j->acc->plan = j->plan;
@@ -717,6 +718,7 @@ void stn_server_opts_default(stn_server_opts* o) {
     o->precision = 64;
     o->drain_on_destroy = 1;
     o->reserve_cus = 32;
+    o->graphs = 1;
 }
 
 stn_status stn_server_create(const stn_server_opts* opts, stn_server** out) {
@@ -727,7 +729,7 @@ stn_status stn_server_create(const stn_server_opts* opts, stn_server** out) {
     else stn_server_opts_default(&o);
     if (o.n_streams < 1 || o.n_streams > kMaxStreams || o.max_active < 1 || o.max_active > kMaxActive ||
         !(o.job_share > 0 && o.job_share <= 1) || o.hbm_budget < (64ull << 20) ||
-        (o.precision != 64 && o.precision != 128))
+        (o.precision != 64 && o.precision != 128) || o.graphs > 1)
         return srv_error(STN_E_INVALID, "server options out of range");
     auto* sv = new stn_server();
     sv->opts = o;

@@ -30,6 +30,7 @@ struct Allocator {
     stn_alloc_fn fn = nullptr;
     stn_free_fn ffn = nullptr;
     void* ctx = nullptr;
+    mutable uint64_t gen = 0;    // allocations made so far (a captured graph is valid while unchanged)
     void* alloc(size_t bytes) const;
     void release(void* p) const;
 };
@@ -196,6 +197,8 @@ struct stn_plan {
     bool sync_on_destroy = true;            // false: the owner has waited for every enqueued use
     uint32_t variant = 0;                   // launch shape of the contraction kernels (autotuner)
     uint32_t grid_cap = 0;                  // persistent kernels use at most this many workgroups (0: all CUs)
+    bool graphs = false;                    // stn_contract replays HIP graphs (stn_plan_set_graphs)
+    uint64_t graph_captures = 0, graph_replays = 0;
     bool tuned = false;
     ~stn_plan();
 };
@@ -212,6 +215,17 @@ struct stn_batch {
     stn::DevBuf d_states;            // complex [K x 2^n] (float2 or double2)
     bool contracted = false;
     bool has_states = false;
+    // contraction graph of this batch: 0 none, 1 eager run done with gkey,
+    // 2 captured with gkey (K, launch shape, CU cap, allocator generation)
+    int gstate = 0;
+    uint64_t gkey[4] = {0, 0, 0, 0};
+    hipGraphExec_t gexec = nullptr;
+    stn_batch() = default;
+    stn_batch(const stn_batch&) = delete;
+    stn_batch& operator=(const stn_batch&) = delete;
+    ~stn_batch() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+    }
 };
 
 struct stn_accum {

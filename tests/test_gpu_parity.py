@@ -9,10 +9,11 @@ several draws could produce are compared by what is unique: per-trajectory
 states only up to a global phase (the Pauli-frame rewrite and the dropped
 phase of Y change it), via |<a|b>|.
 """
+import ctypes
 import itertools
+import math
 import os
 import sys
-import math
 
 import numpy as np
 import pytest
@@ -400,6 +401,70 @@ def test_launch_shapes_give_identical_results(kind, n, p, precision):
         np.testing.assert_array_equal(e, ref)
     with pytest.raises(stn.StnError, match="INVALID"):
         pl.set_variant(len(tune["ms"]))
+
+
+# ----------------------------------------------------------------------------- contraction graphs
+
+@pytest.mark.parametrize("kind,n,p,precision", [("sv_lds", 10, 2, 64), ("sv_lds", 12, 2, 128),
+                                                ("sv_tiled", 18, 2, 64), ("sv_tiled", 16, 2, 128),
+                                                ("lightcone", 20, 1, 64), ("lightcone", 22, 2, 64)])
+def test_contraction_graph_replays_match_eager(kind, n, p, precision):
+    """One batch refilled chunk after chunk and contracted through a HIP
+    graph (eager, captured, then replayed) against a plan launching eagerly,
+    bit for bit, with unrelated eager work and synchronisation between the
+    replays; then a change of K and of launch shape, which start over."""
+    stn = stn_mod()
+    kinds = {"sv_lds": stn.PLAN_SV_LDS, "lightcone": stn.PLAN_LIGHTCONE, "sv_tiled": stn.PLAN_SV_TILED}
+    pr = qaoa(n, p, 800 + n, 5e-3, 2e-2, 96)
+    ref = stn.Plan(pr, plan_kind=kinds[kind], precision=precision)
+    pl = stn.Plan(pr, plan_kind=kinds[kind], precision=precision)
+    pl.set_graphs(True)
+    stream = torch.cuda.Stream()
+    K, chunks = 48, 6
+
+    def check(b, k0, K):
+        got = b.energies()
+        rb = ref.sample(pr.seed, k0, K)
+        ref.contract(rb)
+        want = rb.energies()
+        rb.close()
+        np.testing.assert_array_equal(got, want)
+
+    with torch.cuda.stream(stream):
+        b = pl.sample(pr.seed, 0, K)
+        for c in range(chunks):
+            if c:
+                pl.resample(b, pr.seed, c * K, K)
+            pl.contract(b)
+            check(b, c * K, K)
+            x = torch.arange(1 << 20, device="cuda", dtype=torch.float32)
+            assert float((x * 2).sum().item()) == float(2 * sum(range(1 << 20)))
+        info = pl.info()
+        assert info["graphs"] == 1 and info["graph_captures"] == 1 and info["graph_replays"] == chunks - 2
+        # a different K: eager, captured, replayed again
+        for c in range(3):
+            pl.resample(b, pr.seed, 1000 + c * 17, 17)
+            pl.contract(b)
+            check(b, 1000 + c * 17, 17)
+        info = pl.info()
+        assert info["graph_captures"] == 2 and info["graph_replays"] == chunks - 1
+        if kind != "sv_tiled" or precision == 64:
+            pl.set_variant(1)
+            for c in range(3):
+                pl.resample(b, pr.seed, 2000 + c * 17, 17)
+                pl.contract(b)
+                check(b, 2000 + c * 17, 17)
+            assert pl.info()["graph_captures"] == 3
+        b.close()
+    # the NULL stream never captures
+    pl2 = stn.Plan(pr, plan_kind=kinds[kind], precision=precision)
+    pl2.set_graphs(True)
+    b2 = pl2.sample(pr.seed, 0, K, stream=ctypes.c_void_p(0))
+    for c in range(3):
+        pl2.contract(b2, stream=ctypes.c_void_p(0))
+    assert pl2.info()["graph_captures"] == 0
+    check(b2, 0, K)
+    b2.close()
 
 
 # ----------------------------------------------------------------------------- lightcone networks in HBM

@@ -95,6 +95,25 @@ def test_same_result_alone_and_in_mix():
     assert mixed["energy_se"] == solo["energy_se"]
 
 
+def test_graphs_on_and_off_give_the_same_results():
+    """Chunk contractions replayed from HIP graphs (the default) against
+    eager launches: the same jobs, many chunks each, bit for bit."""
+    stn = stn_mod()
+    jobs = mixed_jobs()
+    out = {}
+    for graphs in (False, True):
+        with stn.Server(hbm_budget=8 << 30, n_streams=3, max_active=6, chunk_max=64, graphs=graphs) as sv:
+            for i, pr in enumerate(jobs):
+                sv.submit(pr, tag=i)
+            sv.drain(300)
+            out[graphs] = {r["tag"]: r for r in sv.poll(cap=64)}
+    for i, pr in enumerate(jobs):
+        a, b = out[False][i], out[True][i]
+        assert a["status"] == 0 and b["status"] == 0, (a["error"], b["error"])
+        assert b["chunks"] == a["chunks"] and b["k_done"] == pr.K
+        assert b["energy_mean"] == a["energy_mean"] and b["energy_se"] == a["energy_se"]
+
+
 def test_served_job_against_oracle():
     from oracle import simulate as sim
     from workloads import make_problem, random_regular_graph, uniform_angles
