@@ -114,6 +114,9 @@ def main():
     ap.add_argument("--job", type=str, default=None,
                     help="only one job n,p,K[,precision] (QAOA on an Erdos-Renyi graph, p_edge 3/(n-1), "
                          "depolarizing 1e-3/1e-2) through the plan API with the planner's choice of lowering")
+    ap.add_argument("--graph-leg", action="store_true",
+                    help="only the contraction-graph leg: many small chunks refilled into one batch, eager "
+                         "launches against replayed HIP graphs")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="copy a buffer of this size once before the timed region (a known-size reference "
                          "for hardware byte counters)")
@@ -132,6 +135,10 @@ def main():
     if args.job:
         import paper_2210_15874_amd as stn
         print(json.dumps({"job": one_job_leg(stn, args)}))
+        return
+    if args.graph_leg:
+        import paper_2210_15874_amd as stn
+        print(json.dumps({"graphs": graph_leg(stn)}))
         return
 
     from workloads import config_problem
@@ -415,6 +422,58 @@ def one_job_leg(stn, args):
             "kernels": {k: {"launches": v["launches"], "ms": v["ms"],
                             "gbps": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] else None}
                         for k, v in prof.items() if v["launches"]}}
+
+
+def graph_leg(stn, chunks=400):
+    """Chunks of small jobs (one batch refilled with stn_resample, then
+    contracted) on a side stream, eager against replayed HIP graphs: wall
+    time per chunk with the device kept busy, and with a synchronisation
+    after every chunk (latency)."""
+    import torch
+    from workloads import make_problem, random_regular_graph, uniform_angles
+    torch.cuda.set_device(0)
+    out = {}
+    for name, n, p, K in [("sv_lds", 10, 2, 64), ("lightcone", 20, 1, 64), ("sv_tiled", 16, 2, 8)]:
+        g, b = uniform_angles(p, 70 + n)
+        pr = make_problem(n, random_regular_graph(n, 3, 60 + n), g, b, 1e-3, 1e-2, K, 80 + n)
+        row = {"n": n, "p": p, "K": K}
+        energies = {}
+        for graphs in (False, True):
+            pl = stn.Plan(pr, outputs=stn.OUT_ENERGY)
+            pl.set_graphs(graphs)
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                bt = pl.sample(pr.seed, 0, K)
+                for c in range(3):            # eager, capture, first replay
+                    pl.resample(bt, pr.seed, c * K, K)
+                    pl.contract(bt)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for c in range(chunks):
+                    pl.resample(bt, pr.seed, c * K, K)
+                    pl.contract(bt)
+                torch.cuda.synchronize()
+                busy = (time.perf_counter() - t0) / chunks
+                t0 = time.perf_counter()
+                for c in range(chunks // 4):
+                    pl.resample(bt, pr.seed, c * K, K)
+                    pl.contract(bt)
+                    s.synchronize()
+                lat = (time.perf_counter() - t0) / (chunks // 4)
+                energies[graphs] = bt.energies()
+            info = pl.info()
+            key = "graph" if graphs else "eager"
+            row[key + "_us_per_chunk"] = busy * 1e6
+            row[key + "_us_per_chunk_synced"] = lat * 1e6
+            if graphs:
+                row["captures"] = info["graph_captures"]
+                row["replays"] = info["graph_replays"]
+            row["plan"] = info["plan_name"]
+            bt.close()
+            pl.close()
+        row["identical"] = bool((energies[False] == energies[True]).all())
+        out[name] = row
+    return out
 
 
 def uneven_leg(stn, args):

@@ -344,7 +344,9 @@ typedef struct {
     uint32_t drain_on_destroy; /* 1: stn_server_destroy waits for every submitted job */
     uint32_t reserve_cus;    /* CUs the persistent kernels (tiled statevector, lightcone networks in
                                 HBM) leave free for other jobs' kernels */
-    uint32_t graphs;         /* 1: chunk contractions replay HIP graphs (stn_plan_set_graphs) */
+    uint32_t graphs;         /* 1: chunk contractions replay HIP graphs (stn_plan_set_graphs); off by
+                                default, since a graph launch costs more host time than the one to six
+                                kernel launches of a contraction it replaces */
 } stn_server_opts;
 
 typedef struct {
@@ -378,7 +380,7 @@ typedef struct {
 } stn_server_stats;
 
 /* Defaults: 64 GiB budget, job_share 0.5, 3 streams, 16 active jobs, 64
- * cached plans, complex64, drain on destroy, 32 reserved CUs, graphs on. */
+ * cached plans, complex64, drain on destroy, 32 reserved CUs, graphs off. */
 void stn_server_opts_default(stn_server_opts* opts);
 /* Starts the server's threads on the calling thread's current device. */
 stn_status stn_server_create(const stn_server_opts* opts, stn_server** out);

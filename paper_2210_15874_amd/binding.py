@@ -448,7 +448,7 @@ class Server:
     PyTorch's allocator; hbm_budget bounds it."""
 
     def __init__(self, hbm_budget=64 << 30, job_share=0.5, n_streams=3, max_active=16, plan_cache=64,
-                 precision=64, chunk_max=0, drain_on_destroy=True, reserve_cus=32, graphs=True):
+                 precision=64, chunk_max=0, drain_on_destroy=True, reserve_cus=32, graphs=False):
         self.lib = load()
         o = ServerOpts()
         self.lib.stn_server_opts_default(C.byref(o))

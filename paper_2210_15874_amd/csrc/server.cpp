@@ -718,7 +718,7 @@ void stn_server_opts_default(stn_server_opts* o) {
     o->precision = 64;
     o->drain_on_destroy = 1;
     o->reserve_cus = 32;
-    o->graphs = 1;
+    o->graphs = 0;
 }
 
 stn_status stn_server_create(const stn_server_opts* opts, stn_server** out) {

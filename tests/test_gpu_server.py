@@ -96,8 +96,8 @@ def test_same_result_alone_and_in_mix():
 
 
 def test_graphs_on_and_off_give_the_same_results():
-    """Chunk contractions replayed from HIP graphs (the default) against
-    eager launches: the same jobs, many chunks each, bit for bit."""
+    """Chunk contractions replayed from HIP graphs against eager launches
+    (the default): the same jobs, many chunks each, bit for bit."""
     stn = stn_mod()
     jobs = mixed_jobs()
     out = {}
