@@ -117,6 +117,9 @@ def main():
     ap.add_argument("--graph-leg", action="store_true",
                     help="only the contraction-graph leg: many small chunks refilled into one batch, eager "
                          "launches against replayed HIP graphs")
+    ap.add_argument("--queue-leg", action="store_true",
+                    help="only the multi-batch leg: 64 small jobs (n 6..12, p 1..4, K 16..256) contracted one "
+                         "launch per job against one launch draining a device-side queue of all their trajectories")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="copy a buffer of this size once before the timed region (a known-size reference "
                          "for hardware byte counters)")
@@ -135,6 +138,10 @@ def main():
     if args.job:
         import paper_2210_15874_amd as stn
         print(json.dumps({"job": one_job_leg(stn, args)}))
+        return
+    if args.queue_leg:
+        import paper_2210_15874_amd as stn
+        print(json.dumps({"queue": queue_leg(stn)}))
         return
     if args.graph_leg:
         import paper_2210_15874_amd as stn
@@ -422,6 +429,55 @@ def one_job_leg(stn, args):
             "kernels": {k: {"launches": v["launches"], "ms": v["ms"],
                             "gbps": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] else None}
                         for k, v in prof.items() if v["launches"]}}
+
+
+def queue_leg(stn, jobs=64, reps=5):
+    """Many small jobs (whole state in LDS) on one stream: one launch per job
+    against one launch whose persistent workgroups drain a device-side queue
+    of every job's trajectories.  Same results, bit for bit."""
+    import numpy as np
+    import torch
+    from workloads import make_problem, random_regular_graph, uniform_angles
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng(2024)
+    probs = []
+    for i in range(jobs):
+        n = 2 * int(rng.integers(3, 7))
+        p = int(rng.integers(1, 5))
+        K = int(rng.integers(16, 257))
+        g, b = uniform_angles(p, 300 + i)
+        probs.append(make_problem(n, random_regular_graph(n, 3, 400 + i), g, b, 1e-3, 1e-2, K, 500 + i,
+                                  name=f"small{i}"))
+    plans = [stn.Plan(pr, plan_kind=stn.PLAN_SV_LDS, outputs=stn.OUT_ENERGY) for pr in probs]
+    batches = [pl.sample(pr.seed, 0, pr.K) for pl, pr in zip(plans, probs)]
+    for pl, bt in zip(plans, batches):
+        pl.contract(bt)
+    alone = [bt.energies() for bt in batches]
+    stn.contract_many(plans, batches)
+    torch.cuda.synchronize()
+    same = all((bt.energies() == e).all() for bt, e in zip(batches, alone))
+
+    def timed(fn):
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        return best
+
+    t_each = timed(lambda: [pl.contract(bt) for pl, bt in zip(plans, batches)])
+    t_queue = timed(lambda: stn.contract_many(plans, batches))
+    traj = sum(pr.K for pr in probs)
+    for bt in batches:
+        bt.close()
+    return {"jobs": jobs, "trajectories": traj, "n_range": [min(pr.n_qubits for pr in probs),
+                                                              max(pr.n_qubits for pr in probs)],
+            "one_launch_per_job_ms": t_each * 1e3, "queue_launch_ms": t_queue * 1e3,
+            "one_launch_per_job_traj_per_s": traj / t_each, "queue_traj_per_s": traj / t_queue,
+            "speedup": t_each / t_queue, "identical": bool(same)}
 
 
 def graph_leg(stn, chunks=400):

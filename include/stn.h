@@ -277,6 +277,17 @@ stn_status stn_profile(stn_plan* plan, int enable);
 /* Fills out[0 .. STN_K_COUNT) with the timings since enabling. Syncs. */
 stn_status stn_profile_read(stn_plan* plan, stn_kernel_stats* out);
 
+/* Contracts the batches of several whole-state-in-LDS plans (n <= 13 in
+ * complex64, n <= 12 in complex128; all of one precision) in one launch:
+ * persistent workgroups take (batch, trajectory) items from a device-side
+ * queue (an atomic counter over the items of all batches, batch after batch)
+ * until it is empty, so many small jobs fill the device together.  Results
+ * equal stn_contract of each batch, bit for bit.  The launch shape is that of
+ * plans[0]; the queue's descriptors live with batches[0], so a batch must not
+ * lead two multi-batch launches that may overlap.  Other lowerings:
+ * STN_E_UNSUPPORTED; mixed precision or a repeated batch: STN_E_INVALID. */
+stn_status stn_contract_many(stn_plan* const* plans, stn_batch* const* batches, uint32_t count, void* stream);
+
 /* Launch-shape autotuning: contracts `batch` (a sampled batch of this plan)
  * `reps` times with every launch shape of the plan's lowering (threads per
  * workgroup of the LDS and lightcone kernels, persistent grid of the tiled

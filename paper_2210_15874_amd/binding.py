@@ -134,6 +134,7 @@ EXPORTS = {
     "stn_plan_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(TuneResult), C.c_void_p]),
     "stn_plan_set_variant": (C.c_int, [C.c_void_p, C.c_uint32]),
     "stn_plan_set_graphs": (C.c_int, [C.c_void_p, C.c_uint32]),
+    "stn_contract_many": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_uint32, C.c_void_p]),
     "stn_resample": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint32, C.c_void_p]),
     "stn_batch_size": (C.c_uint32, [C.c_void_p]),
     "stn_batch_destroy": (None, [C.c_void_p]),
@@ -352,6 +353,17 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def contract_many(plans, batches, stream=None):
+    """Contracts batches of several whole-state-in-LDS plans in one launch
+    (a device-side queue of (batch, trajectory) items)."""
+    assert len(plans) == len(batches) and plans
+    lib = plans[0].lib
+    n = len(plans)
+    ph = (C.c_void_p * n)(*[p.h for p in plans])
+    bh = (C.c_void_p * n)(*[b.h for b in batches])
+    _check(lib.stn_contract_many(ph, bh, n, stream if stream is not None else current_stream()))
 
 
 class Batch:

@@ -445,6 +445,27 @@ stn_status stn_contract(stn_plan* p, stn_batch* b, void* stream) {
     });
 }
 
+stn_status stn_contract_many(stn_plan* const* plans, stn_batch* const* batches, uint32_t count, void* stream) {
+    if (count == 0) return STN_OK;
+    if (!plans || !batches) return set_error(STN_E_INVALID, "NULL argument");
+    for (uint32_t i = 0; i < count; ++i) {
+        if (!plans[i] || !batches[i]) return set_error(STN_E_INVALID, "NULL plan or batch");
+        if (batches[i]->plan != plans[i]) return set_error(STN_E_INVALID, "batch belongs to another plan");
+        if (plans[i]->kind != STN_PLAN_SV_LDS)
+            return set_error(STN_E_UNSUPPORTED, "multi-batch launches take whole-state-in-LDS plans only");
+        if (plans[i]->opts.precision != plans[0]->opts.precision)
+            return set_error(STN_E_INVALID, "all plans of a multi-batch launch need the same precision");
+        for (uint32_t j = 0; j < i; ++j)
+            if (batches[j] == batches[i]) return set_error(STN_E_INVALID, "a batch appears twice");
+    }
+    return guarded([&] {
+        hipStream_t s = (hipStream_t)stream;
+        for (uint32_t i = 0; i < count; ++i) ensure_uploaded(plans[i], s);
+        launch_sv_lds_many(plans, batches, count, s);
+        for (uint32_t i = 0; i < count; ++i) batches[i]->contracted = true;
+    });
+}
+
 stn_status stn_plan_set_graphs(stn_plan* p, uint32_t on) {
     if (!p) return set_error(STN_E_INVALID, "NULL argument");
     p->graphs = on != 0;

@@ -44,20 +44,19 @@ __device__ __forceinline__ uint32_t ins0(uint32_t p, uint32_t q) {
     return ((p ^ lo) << 1) | lo;
 }
 
+// One trajectory of one plan in the workgroup's LDS (psi: 2^n amplitudes,
+// plus 2^n binary64 terms for complex128): the gate list with the picked
+// Kraus operators of `row`, then the optional state and the energy.
 template <class R, int kThreads>
-__global__ __launch_bounds__(kThreads) void k_sv_lds(uint32_t n, const LdsOp* __restrict__ ops, uint32_t n_ops,
-                                                    const typename Cx<R>::T* __restrict__ vals,
-                                                    const LdsOp* __restrict__ site_ops,
-                                                    const uint32_t* __restrict__ site_off,
-                                                    const uint8_t* __restrict__ idx, uint32_t S,
-                                                    const uint32_t* __restrict__ obs_uv,
-                                                    const double* __restrict__ obs_w, uint32_t n_terms,
-                                                    double* __restrict__ energy,
-                                                    typename Cx<R>::T* __restrict__ states) {
+__device__ __forceinline__ void lds_trajectory(typename Cx<R>::T* psi, uint32_t n, const LdsOp* __restrict__ ops,
+                                               uint32_t n_ops, const typename Cx<R>::T* __restrict__ vals,
+                                               const LdsOp* __restrict__ site_ops,
+                                               const uint32_t* __restrict__ site_off,
+                                               const uint8_t* __restrict__ row,
+                                               const uint32_t* __restrict__ obs_uv,
+                                               const double* __restrict__ obs_w, uint32_t n_terms,
+                                               double* __restrict__ energy, typename Cx<R>::T* __restrict__ state) {
     using V = typename Cx<R>::T;
-    extern __shared__ char smem_raw[];
-    V* psi = reinterpret_cast<V*>(smem_raw);
-    const uint32_t b = blockIdx.x;
     const uint32_t tid = threadIdx.x;
     const uint32_t N = 1u << n;
     for (uint32_t i = tid; i < N; i += kThreads) {
@@ -67,7 +66,6 @@ __global__ __launch_bounds__(kThreads) void k_sv_lds(uint32_t n, const LdsOp* __
         psi[i] = v;
     }
     __syncthreads();
-    const uint8_t* row = idx + (size_t)b * S;
     for (uint32_t oi = 0; oi < n_ops; ++oi) {
         LdsOp o = ops[oi];
         if (o.kind == OP_SITE) o = site_ops[site_off[o.site] + row[o.site]];
@@ -135,9 +133,9 @@ __global__ __launch_bounds__(kThreads) void k_sv_lds(uint32_t n, const LdsOp* __
         __syncthreads();
     }
     // energy <psi|C|psi> in binary64: per-amplitude terms, then a fixed tree
-    if (states)
-        for (uint32_t i = tid; i < N; i += kThreads) states[(size_t)b * N + i] = psi[i];
-    double* e = reinterpret_cast<double*>(smem_raw) + (sizeof(V) == 8 ? 0 : 2 * (size_t)N);
+    if (state)
+        for (uint32_t i = tid; i < N; i += kThreads) state[i] = psi[i];
+    double* e = reinterpret_cast<double*>(psi) + (sizeof(V) == 8 ? 0 : 2 * (size_t)N);
     for (uint32_t i = tid; i < N; i += kThreads) {
         const V v = psi[i];   // complex64: e[i] takes psi[i]'s own 8 bytes
         const double pr = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
@@ -151,8 +149,76 @@ __global__ __launch_bounds__(kThreads) void k_sv_lds(uint32_t n, const LdsOp* __
         for (uint32_t i = tid; i < h; i += kThreads) e[i] += e[i + h];
         __syncthreads();
     }
-    if (tid == 0) energy[b] = e[0];
+    if (tid == 0) *energy = e[0];
 }
+
+template <class R, int kThreads>
+__global__ __launch_bounds__(kThreads) void k_sv_lds(uint32_t n, const LdsOp* __restrict__ ops, uint32_t n_ops,
+                                                    const typename Cx<R>::T* __restrict__ vals,
+                                                    const LdsOp* __restrict__ site_ops,
+                                                    const uint32_t* __restrict__ site_off,
+                                                    const uint8_t* __restrict__ idx, uint32_t S,
+                                                    const uint32_t* __restrict__ obs_uv,
+                                                    const double* __restrict__ obs_w, uint32_t n_terms,
+                                                    double* __restrict__ energy,
+                                                    typename Cx<R>::T* __restrict__ states) {
+    using V = typename Cx<R>::T;
+    extern __shared__ char smem_raw[];
+    const uint32_t b = blockIdx.x;
+    lds_trajectory<R, kThreads>(reinterpret_cast<V*>(smem_raw), n, ops, n_ops, vals, site_ops, site_off,
+                                idx + (size_t)b * S, obs_uv, obs_w, n_terms, energy + b,
+                                states ? states + ((size_t)b << n) : nullptr);
+}
+
+// Several plans' batches in one launch: a queue of (batch, trajectory) items,
+// numbered batch after batch (batch j owns items [item0_j, item0_j + K_j)).
+// Persistent workgroups take the next item from an atomic counter until it
+// passes the total, so every workgroup exits once the queue is empty.
+template <class R, int kThreads>
+__global__ __launch_bounds__(kThreads) void k_sv_lds_queue(const LdsJob* __restrict__ jobs, uint32_t n_jobs,
+                                                          unsigned long long total,
+                                                          unsigned long long* __restrict__ counter) {
+    using V = typename Cx<R>::T;
+    extern __shared__ __align__(16) char smem_raw[];
+    __shared__ unsigned long long s_item;
+    __shared__ uint32_t s_job;
+    while (true) {
+        // a barrier first: the previous item is finished everywhere (its LDS
+        // and s_item reads), and nothing the fetching thread does below is
+        // next to the same thread's energy store of that item without a
+        // barrier between them (the compiler could otherwise route that
+        // thread around a different loop than the others)
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned long long it = atomicAdd(counter, 1ull);
+            uint32_t lo = 0, hi = n_jobs - 1;   // last job with item0 <= it
+            if (it < total)
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi + 1) / 2;
+                    if (jobs[mid].item0 <= it) lo = mid;
+                    else hi = mid - 1;
+                }
+            s_item = it;
+            s_job = lo;
+        }
+        __syncthreads();
+        // the same item for the whole workgroup, read as a uniform (scalar)
+        // value so that the loop exit is a uniform branch
+        const uint32_t ilo = __builtin_amdgcn_readfirstlane((uint32_t)s_item);
+        const uint32_t ihi = __builtin_amdgcn_readfirstlane((uint32_t)(s_item >> 32));
+        const uint32_t j = __builtin_amdgcn_readfirstlane(s_job);
+        const unsigned long long it = ((unsigned long long)ihi << 32) | ilo;
+        if (it >= total) break;
+        const LdsJob& J = jobs[j];
+        const uint64_t b = it - J.item0;
+        V* st = static_cast<V*>(J.states);
+        lds_trajectory<R, kThreads>(reinterpret_cast<V*>(smem_raw), J.n, J.ops, J.n_ops,
+                                    static_cast<const V*>(J.vals), J.site_ops, J.site_off, J.idx + b * J.S,
+                                    J.obs_uv, J.obs_w, J.n_terms, J.energy + b, st ? st + (b << J.n) : nullptr);
+    }
+}
+
+__global__ void k_zero_counter(unsigned long long* c) { *c = 0ull; }
 
 template <class R>
 using LdsFn = void (*)(uint32_t, const LdsOp*, uint32_t, const typename Cx<R>::T*, const LdsOp*, const uint32_t*,
@@ -224,5 +290,71 @@ void launch_sv_lds(stn_plan* p, stn_batch* b, hipStream_t s) {
 }
 
 uint32_t lds_variants() { return kLdsVariants; }
+
+void launch_sv_lds_many(stn_plan* const* plans, stn_batch* const* batches, uint32_t count, hipStream_t s) {
+    if (count == 0) return;
+    const bool dbl = plans[0]->opts.precision == 128;
+    const size_t elem = dbl ? 16 : 8;
+    std::vector<LdsJob> jobs(count);
+    uint64_t total = 0;
+    size_t lds = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+        stn_plan* p = plans[i];
+        stn_batch* b = batches[i];
+        const size_t N = (size_t)1 << p->n;
+        const bool dense = p->opts.outputs & (STN_OUT_RHO | STN_OUT_DIAG | STN_OUT_STATES);
+        if (dense) {
+            b->d_states.ensure(&p->alloc, N * b->K * elem);
+            b->has_states = true;
+        }
+        LdsJob& J = jobs[i];
+        J.ops = p->d_lds_ops.as<LdsOp>();
+        J.vals = dbl ? (const void*)p->d_lds_vals64.p : (const void*)p->d_lds_vals32.p;
+        J.site_ops = p->d_site_ops.as<LdsOp>();
+        J.site_off = p->d_site_op_off.as<uint32_t>();
+        J.idx = b->d_idx.as<uint8_t>();
+        J.obs_uv = p->d_obs.as<uint32_t>();
+        J.obs_w = p->d_obs_w.as<double>();
+        J.energy = b->d_energy.as<double>();
+        J.states = dense ? b->d_states.p : nullptr;
+        J.item0 = total;
+        J.n = p->n;
+        J.n_ops = (uint32_t)p->lds_ops.size();
+        J.S = (uint32_t)p->sites.size();
+        J.n_terms = (uint32_t)p->obs_u.size();
+        total += b->K;
+        lds = std::max(lds, N * elem + (dbl ? N * 8 : 0));
+    }
+    // the descriptors and the counter live with the first batch
+    stn_batch* owner = batches[0];
+    const size_t desc = (count * sizeof(LdsJob) + 255) / 256 * 256;
+    owner->d_queue.ensure(&plans[0]->alloc, desc + 256);
+    STN_HIP(hipMemcpyAsync(owner->d_queue.p, jobs.data(), count * sizeof(LdsJob), hipMemcpyHostToDevice, s));
+    auto* counter = reinterpret_cast<unsigned long long*>(static_cast<char*>(owner->d_queue.p) + desc);
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, counter);
+    STN_HIP(hipGetLastError());
+    const uint32_t v = std::min<uint32_t>(plans[0]->variant, kLdsVariants - 1);
+    const uint32_t threads = v == 1 ? 128 : v == 2 ? 512 : v == 3 ? 1024 : 256;
+    using QFn = void (*)(const LdsJob*, uint32_t, unsigned long long, unsigned long long*);
+    QFn f;
+    if (dbl) f = v == 1 ? k_sv_lds_queue<double, 128> : v == 2 ? k_sv_lds_queue<double, 512>
+               : v == 3 ? k_sv_lds_queue<double, 1024> : k_sv_lds_queue<double, 256>;
+    else f = v == 1 ? k_sv_lds_queue<float, 128> : v == 2 ? k_sv_lds_queue<float, 512>
+             : v == 3 ? k_sv_lds_queue<float, 1024> : k_sv_lds_queue<float, 256>;
+    static bool attr_set[2][kLdsVariants] = {};
+    if (!attr_set[dbl][v]) {
+        STN_HIP(hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, 98304));
+        attr_set[dbl][v] = true;
+    }
+    // workgroups resident at once: LDS (160 KiB per CU) and at most 8 per CU
+    int dev = 0, cus = 0;
+    STN_HIP(hipGetDevice(&dev));
+    STN_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const uint64_t per_cu = std::max<uint64_t>(1, std::min<uint64_t>(8, (160u << 10) / (lds + 1024)));
+    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(total, per_cu * (uint64_t)cus));
+    hipLaunchKernelGGL(f, dim3(grid), dim3(threads), lds, s, reinterpret_cast<const LdsJob*>(owner->d_queue.p),
+                       count, (unsigned long long)total, counter);
+    STN_HIP(hipGetLastError());
+}
 
 }  // namespace stn

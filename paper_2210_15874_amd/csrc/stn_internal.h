@@ -213,6 +213,7 @@ struct stn_batch {
     stn::DevBuf d_frame;             // uint64 [K x 2]: final frame x mask, z mask
     stn::DevBuf d_energy;            // double [K]
     stn::DevBuf d_states;            // complex [K x 2^n] (float2 or double2)
+    stn::DevBuf d_queue;             // multi-batch launches led by this batch: descriptors, counter
     bool contracted = false;
     bool has_states = false;
     // contraction graph of this batch: 0 none, 1 eager run done with gkey,
@@ -259,6 +260,21 @@ void accum_finish_energy(stn_accum* a, hipStream_t s);
 
 // launch-shape variants of each lowering's contraction (results do not depend on them)
 uint32_t lds_variants();
+// one batch of a whole-state-in-LDS plan, as seen by the multi-batch kernel
+struct LdsJob {
+    const LdsOp* ops;
+    const void* vals;
+    const LdsOp* site_ops;
+    const uint32_t* site_off;
+    const uint8_t* idx;
+    const uint32_t* obs_uv;
+    const double* obs_w;
+    double* energy;
+    void* states;
+    uint64_t item0;
+    uint32_t n, n_ops, S, n_terms;
+};
+void launch_sv_lds_many(stn_plan* const* plans, stn_batch* const* batches, uint32_t count, hipStream_t s);
 uint32_t tn_variants();
 uint32_t tiled_variants(const stn_plan* p);
 

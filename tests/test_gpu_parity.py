@@ -403,6 +403,56 @@ def test_launch_shapes_give_identical_results(kind, n, p, precision):
         pl.set_variant(len(tune["ms"]))
 
 
+# ----------------------------------------------------------------------------- multi-batch queue launch
+
+@pytest.mark.parametrize("precision", [64, 128])
+def test_contract_many_matches_per_batch(precision):
+    """Batches of several whole-state-in-LDS plans (different n, depth,
+    noise, outputs and K, one of them with amplitude damping) contracted by
+    one launch that drains a device-side queue of (batch, trajectory) items,
+    against each batch contracted alone: energies and states bit for bit, for
+    two launch shapes and a repeated launch."""
+    from workloads import config_problem
+    stn = stn_mod()
+    probs = [qaoa(n, p, 850 + n, lam, 2 * lam, K) for n, p, K, lam in
+             [(6, 1, 5, 1e-2), (8, 2, 40, 5e-3), (10, 3, 200, 2e-3), (12, 2, 77, 1e-2), (4, 1, 1, 0.1)]]
+    probs.append(config_problem(1, K=64))
+    outs = [stn.OUT_ENERGY] * 3 + [stn.OUT_ENERGY | stn.OUT_RHO] + [stn.OUT_ENERGY] + [stn.OUT_ENERGY | stn.OUT_RHO]
+    want = []
+    for pr, o in zip(probs, outs):
+        pl = stn.Plan(pr, plan_kind=stn.PLAN_SV_LDS, outputs=o, precision=precision)
+        b = pl.sample(pr.seed, 3, pr.K)
+        pl.contract(b)
+        want.append((b.energies(), b.states() if o & stn.OUT_RHO else None))
+        b.close()
+        pl.close()
+    plans = [stn.Plan(pr, plan_kind=stn.PLAN_SV_LDS, outputs=o, precision=precision) for pr, o in zip(probs, outs)]
+    batches = [pl.sample(pr.seed, 3, pr.K) for pl, pr in zip(plans, probs)]
+    for variant in (0, 2, 2):
+        plans[0].set_variant(variant)
+        stn.contract_many(plans, batches)
+        for i, (b, (e, st)) in enumerate(zip(batches, want)):
+            np.testing.assert_array_equal(b.energies(), e, err_msg=str(i))
+            if st is not None:
+                np.testing.assert_array_equal(b.states(), st, err_msg=str(i))
+    # one batch alone through the queue
+    stn.contract_many(plans[2:3], batches[2:3])
+    np.testing.assert_array_equal(batches[2].energies(), want[2][0])
+    other = 64 if precision == 128 else 128
+    mixed = stn.Plan(probs[1], plan_kind=stn.PLAN_SV_LDS, precision=other)
+    mb = mixed.sample(probs[1].seed, 0, 4)
+    with pytest.raises(stn.StnError, match="INVALID"):
+        stn.contract_many([plans[0], mixed], [batches[0], mb])
+    with pytest.raises(stn.StnError, match="INVALID"):
+        stn.contract_many([plans[0], plans[0]], [batches[0], batches[0]])
+    tiled = stn.Plan(qaoa(16, 1, 870, 1e-3, 1e-2, 4), plan_kind=stn.PLAN_SV_TILED, precision=precision)
+    tb = tiled.sample(870, 0, 4)
+    with pytest.raises(stn.StnError, match="UNSUPPORTED"):
+        stn.contract_many([plans[0], tiled], [batches[0], tb])
+    for b in batches + [mb, tb]:
+        b.close()
+
+
 # ----------------------------------------------------------------------------- contraction graphs
 
 @pytest.mark.parametrize("kind,n,p,precision", [("sv_lds", 10, 2, 64), ("sv_lds", 12, 2, 128),
