@@ -358,6 +358,8 @@ typedef struct {
     uint32_t graphs;         /* 1: chunk contractions replay HIP graphs (stn_plan_set_graphs); off by
                                 default, since a graph launch costs more host time than the one to six
                                 kernel launches of a contraction it replaces */
+    uint32_t gang;           /* 1: ready chunks of whole-state-in-LDS jobs on the shared stream are
+                                contracted together by one multi-batch launch (stn_contract_many) */
 } stn_server_opts;
 
 typedef struct {
@@ -388,10 +390,13 @@ typedef struct {
     uint64_t autotuned;      /* plan shapes whose launch shape was timed (then reused for the shape) */
     uint64_t bytes_in_use, bytes_cached, bytes_peak;   /* device memory reserved at create: in use, free, peak in use */
     double clock;            /* server clock when read */
+    uint64_t gang_launches;  /* multi-batch launches (stn_contract_many) of several jobs' chunks */
+    uint64_t gang_chunks;    /* chunks contracted by them */
 } stn_server_stats;
 
 /* Defaults: 64 GiB budget, job_share 0.5, 3 streams, 16 active jobs, 64
- * cached plans, complex64, drain on destroy, 32 reserved CUs, graphs off. */
+ * cached plans, complex64, drain on destroy, 32 reserved CUs, graphs off,
+ * multi-batch launches on. */
 void stn_server_opts_default(stn_server_opts* opts);
 /* Starts the server's threads on the calling thread's current device. */
 stn_status stn_server_create(const stn_server_opts* opts, stn_server** out);

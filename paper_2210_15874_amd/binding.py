@@ -96,7 +96,7 @@ class ServerOpts(C.Structure):
     _fields_ = [("hbm_budget", C.c_uint64), ("job_share", C.c_double), ("n_streams", C.c_uint32),
                 ("max_active", C.c_uint32), ("plan_cache", C.c_uint32), ("precision", C.c_uint32),
                 ("chunk_max", C.c_uint32), ("drain_on_destroy", C.c_uint32), ("reserve_cus", C.c_uint32),
-                ("graphs", C.c_uint32)]
+                ("graphs", C.c_uint32), ("gang", C.c_uint32)]
 
 
 class JobResult(C.Structure):
@@ -113,7 +113,8 @@ class ServerStats(C.Structure):
                 ("chunks", C.c_uint64), ("max_active_jobs", C.c_uint64), ("plan_cache_hits", C.c_uint64),
                 ("plan_cache_misses", C.c_uint64), ("plans_cached", C.c_uint64), ("autotuned", C.c_uint64),
                 ("bytes_in_use", C.c_uint64),
-                ("bytes_cached", C.c_uint64), ("bytes_peak", C.c_uint64), ("clock", C.c_double)]
+                ("bytes_cached", C.c_uint64), ("bytes_peak", C.c_uint64), ("clock", C.c_double),
+                ("gang_launches", C.c_uint64), ("gang_chunks", C.c_uint64)]
 
 
 EXPORTS = {
@@ -460,7 +461,7 @@ class Server:
     PyTorch's allocator; hbm_budget bounds it."""
 
     def __init__(self, hbm_budget=64 << 30, job_share=0.5, n_streams=3, max_active=16, plan_cache=64,
-                 precision=64, chunk_max=0, drain_on_destroy=True, reserve_cus=32, graphs=False):
+                 precision=64, chunk_max=0, drain_on_destroy=True, reserve_cus=32, graphs=False, gang=True):
         self.lib = load()
         o = ServerOpts()
         self.lib.stn_server_opts_default(C.byref(o))
@@ -474,6 +475,7 @@ class Server:
         o.drain_on_destroy = 1 if drain_on_destroy else 0
         o.reserve_cus = int(reserve_cus)
         o.graphs = 1 if graphs else 0
+        o.gang = 1 if gang else 0
         h = C.c_void_p()
         _check_srv(self.lib.stn_server_create(C.byref(o), C.byref(h)))
         self.h = h

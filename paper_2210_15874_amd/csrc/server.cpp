@@ -615,6 +615,62 @@ struct Device {
         return true;
     }
 
+    // the chunk slot of j is free (its previous use has finished)
+    bool slot_free(Job& j) {
+        const uint32_t c = j.next;
+        if (!j.ev_live[c]) return true;
+        if (hipEventQuery(j.ev[c]) == hipErrorNotReady) return false;
+        j.ev_live[c] = false;
+        return true;
+    }
+
+    // Whole-state-in-LDS jobs on the shared stream with a chunk ready: their
+    // chunks go out together, one multi-batch launch draining a device-side
+    // queue of all their trajectories (each job's results are those of its own
+    // launches, bit for bit).  True when something was issued.
+    bool gang() {
+        if (!sv->opts.gang) return false;
+        std::vector<Job*> g;
+        for (auto& jp : active) {
+            Job& j = *jp;
+            if (j.stream != 0 || !j.plan || j.plan->kind != STN_PLAN_SV_LDS || j.tune || j.k_issued >= j.K)
+                continue;
+            if (slot_free(j)) g.push_back(&j);
+        }
+        if (g.size() < 2) return false;
+        hipStream_t s = streams[0];
+        std::vector<stn_plan*> plans;
+        std::vector<stn_batch*> batches;
+        std::vector<uint32_t> ks;
+        for (Job* j : g) {
+            const uint32_t K = (uint32_t)std::min<uint64_t>(j->B, j->K - j->k_issued);
+            stn_batch* b = j->batch[j->next];
+            batch_prepare(j->plan, b, j->k_issued, K);
+            launch_sample(j->plan, b, j->seed, s);
+            plans.push_back(j->plan);
+            batches.push_back(b);
+            ks.push_back(K);
+        }
+        const stn_status st = stn_contract_many(plans.data(), batches.data(), (uint32_t)g.size(), s);
+        if (st != STN_OK) throw Error{st, stn_last_error()};
+        for (size_t i = 0; i < g.size(); ++i) {
+            Job& j = *g[i];
+            const uint32_t c = j.next;
+            const stn_status st2 = stn_reduce(j.plan, batches[i], j.acc, s);
+            if (st2 != STN_OK) throw Error{st2, stn_last_error()};
+            STN_HIP(hipEventRecord(j.ev[c], s));
+            j.ev_live[c] = true;
+            j.next = (c + 1) % kChunksInFlight;
+            j.k_issued += ks[i];
+            j.chunks++;
+        }
+        std::lock_guard<std::mutex> lk(sv->m);
+        sv->st.chunks += g.size();
+        sv->st.gang_launches++;
+        sv->st.gang_chunks += g.size();
+        return true;
+    }
+
     // true when j made progress (chunk issued, finishing enqueued, or done)
     bool step(Job& j, bool& done) {
         done = false;
@@ -642,6 +698,21 @@ struct Device {
         for (;;) {
             bool progress = false;
             while (admit()) progress = true;
+            try {
+                progress |= gang();
+            } catch (const Error& e) {
+                // a failed multi-batch launch fails every whole-state-in-LDS job on the shared stream
+                for (size_t i = 0; i < active.size();) {
+                    Job& j = *active[i];
+                    if (j.stream == 0 && j.plan && j.plan->kind == STN_PLAN_SV_LDS) {
+                        fail_job(j, e);
+                        active.erase(active.begin() + i);
+                        continue;
+                    }
+                    ++i;
+                }
+                progress = true;
+            }
             // round-robin over the admitted jobs, one chunk each per round
             for (size_t i = 0; i < active.size();) {
                 auto j = active[(rr + i) % active.size()];
@@ -719,6 +790,7 @@ void stn_server_opts_default(stn_server_opts* o) {
     o->drain_on_destroy = 1;
     o->reserve_cus = 32;
     o->graphs = 0;
+    o->gang = 1;
 }
 
 stn_status stn_server_create(const stn_server_opts* opts, stn_server** out) {
@@ -729,7 +801,7 @@ stn_status stn_server_create(const stn_server_opts* opts, stn_server** out) {
     else stn_server_opts_default(&o);
     if (o.n_streams < 1 || o.n_streams > kMaxStreams || o.max_active < 1 || o.max_active > kMaxActive ||
         !(o.job_share > 0 && o.job_share <= 1) || o.hbm_budget < (64ull << 20) ||
-        (o.precision != 64 && o.precision != 128) || o.graphs > 1)
+        (o.precision != 64 && o.precision != 128) || o.graphs > 1 || o.gang > 1)
         return srv_error(STN_E_INVALID, "server options out of range");
     auto* sv = new stn_server();
     sv->opts = o;

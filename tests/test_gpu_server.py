@@ -114,6 +114,35 @@ def test_graphs_on_and_off_give_the_same_results():
         assert b["energy_mean"] == a["energy_mean"] and b["energy_se"] == a["energy_se"]
 
 
+def test_multi_batch_launches_give_the_same_results():
+    """Ready chunks of whole-state-in-LDS jobs gathered into multi-batch
+    launches (the default) against one launch per chunk: bit for bit."""
+    from workloads import make_problem, random_regular_graph, uniform_angles
+    stn = stn_mod()
+    jobs = []
+    for i in range(12):
+        n, p, K = 6 + 2 * (i % 4), 1 + i % 3, 100 + 37 * i
+        g, b = uniform_angles(p, 600 + i)
+        jobs.append(make_problem(n, random_regular_graph(n, 3, 610 + i), g, b, 2e-3, 1e-2, K, 620 + i,
+                                 name=f"lds{i}"))
+    out, stats = {}, {}
+    for gang in (False, True):
+        with stn.Server(hbm_budget=4 << 30, n_streams=3, max_active=16, chunk_max=64, gang=gang) as sv:
+            for i, pr in enumerate(jobs):
+                sv.submit(pr, tag=i)
+            sv.drain(120)
+            out[gang] = {r["tag"]: r for r in sv.poll(cap=64)}
+            stats[gang] = sv.stats()
+    assert stats[False]["gang_launches"] == 0
+    assert stats[True]["gang_launches"] > 0 and stats[True]["gang_chunks"] >= 2 * stats[True]["gang_launches"]
+    for i, pr in enumerate(jobs):
+        a, b = out[False][i], out[True][i]
+        assert a["status"] == 0 and b["status"] == 0, (a["error"], b["error"])
+        assert a["plan_name"] == b["plan_name"] == "sv_lds"
+        assert b["k_done"] == pr.K and b["chunks"] == a["chunks"]
+        assert b["energy_mean"] == a["energy_mean"] and b["energy_se"] == a["energy_se"]
+
+
 def test_served_job_against_oracle():
     from oracle import simulate as sim
     from workloads import make_problem, random_regular_graph, uniform_angles
