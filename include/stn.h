@@ -283,8 +283,10 @@ stn_status stn_profile_read(stn_plan* plan, stn_kernel_stats* out);
  * queue (an atomic counter over the items of all batches, batch after batch)
  * until it is empty, so many small jobs fill the device together.  Results
  * equal stn_contract of each batch, bit for bit.  The launch shape is that of
- * plans[0]; the queue's descriptors live with batches[0], so a batch must not
- * lead two multi-batch launches that may overlap.  Other lowerings:
+ * plans[0]; the queue's item counter lives with batches[0], so a batch must
+ * not lead two multi-batch launches that may overlap (on two streams).  Up to
+ * 32 batches go into one launch (more: several launches).  The call copies
+ * nothing from the host and never waits for the stream.  Other lowerings:
  * STN_E_UNSUPPORTED; mixed precision or a repeated batch: STN_E_INVALID. */
 stn_status stn_contract_many(stn_plan* const* plans, stn_batch* const* batches, uint32_t count, void* stream);
 

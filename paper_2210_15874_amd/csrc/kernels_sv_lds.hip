@@ -175,9 +175,10 @@ __global__ __launch_bounds__(kThreads) void k_sv_lds(uint32_t n, const LdsOp* __
 // Persistent workgroups take the next item from an atomic counter until it
 // passes the total, so every workgroup exits once the queue is empty.
 template <class R, int kThreads>
-__global__ __launch_bounds__(kThreads) void k_sv_lds_queue(const LdsJob* __restrict__ jobs, uint32_t n_jobs,
-                                                          unsigned long long total,
-                                                          unsigned long long* __restrict__ counter) {
+__global__ __launch_bounds__(kThreads) void k_sv_lds_queue(const LdsQueue q, unsigned long long* __restrict__ counter) {
+    const LdsJob* jobs = q.job;
+    const uint32_t n_jobs = q.n_jobs;
+    const unsigned long long total = q.total;
     using V = typename Cx<R>::T;
     extern __shared__ __align__(16) char smem_raw[];
     __shared__ unsigned long long s_item;
@@ -296,8 +297,6 @@ void launch_sv_lds_many(stn_plan* const* plans, stn_batch* const* batches, uint3
     const bool dbl = plans[0]->opts.precision == 128;
     const size_t elem = dbl ? 16 : 8;
     std::vector<LdsJob> jobs(count);
-    uint64_t total = 0;
-    size_t lds = 0;
     for (uint32_t i = 0; i < count; ++i) {
         stn_plan* p = plans[i];
         stn_batch* b = batches[i];
@@ -317,25 +316,21 @@ void launch_sv_lds_many(stn_plan* const* plans, stn_batch* const* batches, uint3
         J.obs_w = p->d_obs_w.as<double>();
         J.energy = b->d_energy.as<double>();
         J.states = dense ? b->d_states.p : nullptr;
-        J.item0 = total;
+        J.item0 = 0;
         J.n = p->n;
         J.n_ops = (uint32_t)p->lds_ops.size();
         J.S = (uint32_t)p->sites.size();
         J.n_terms = (uint32_t)p->obs_u.size();
-        total += b->K;
-        lds = std::max(lds, N * elem + (dbl ? N * 8 : 0));
     }
-    // the descriptors and the counter live with the first batch
+    // the counter lives with the first batch; the descriptors travel as
+    // kernel arguments, kLdsQueueJobs batches per launch (no host copy, so
+    // the call does not wait for earlier work on the stream)
     stn_batch* owner = batches[0];
-    const size_t desc = (count * sizeof(LdsJob) + 255) / 256 * 256;
-    owner->d_queue.ensure(&plans[0]->alloc, desc + 256);
-    STN_HIP(hipMemcpyAsync(owner->d_queue.p, jobs.data(), count * sizeof(LdsJob), hipMemcpyHostToDevice, s));
-    auto* counter = reinterpret_cast<unsigned long long*>(static_cast<char*>(owner->d_queue.p) + desc);
-    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, counter);
-    STN_HIP(hipGetLastError());
+    owner->d_queue.ensure(&plans[0]->alloc, 256);
+    auto* counter = static_cast<unsigned long long*>(owner->d_queue.p);
     const uint32_t v = std::min<uint32_t>(plans[0]->variant, kLdsVariants - 1);
     const uint32_t threads = v == 1 ? 128 : v == 2 ? 512 : v == 3 ? 1024 : 256;
-    using QFn = void (*)(const LdsJob*, uint32_t, unsigned long long, unsigned long long*);
+    using QFn = void (*)(const LdsQueue, unsigned long long*);
     QFn f;
     if (dbl) f = v == 1 ? k_sv_lds_queue<double, 128> : v == 2 ? k_sv_lds_queue<double, 512>
                : v == 3 ? k_sv_lds_queue<double, 1024> : k_sv_lds_queue<double, 256>;
@@ -346,15 +341,30 @@ void launch_sv_lds_many(stn_plan* const* plans, stn_batch* const* batches, uint3
         STN_HIP(hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, 98304));
         attr_set[dbl][v] = true;
     }
-    // workgroups resident at once: LDS (160 KiB per CU) and at most 8 per CU
     int dev = 0, cus = 0;
     STN_HIP(hipGetDevice(&dev));
     STN_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const uint64_t per_cu = std::max<uint64_t>(1, std::min<uint64_t>(8, (160u << 10) / (lds + 1024)));
-    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(total, per_cu * (uint64_t)cus));
-    hipLaunchKernelGGL(f, dim3(grid), dim3(threads), lds, s, reinterpret_cast<const LdsJob*>(owner->d_queue.p),
-                       count, (unsigned long long)total, counter);
-    STN_HIP(hipGetLastError());
+    for (uint32_t g0 = 0; g0 < count; g0 += kLdsQueueJobs) {
+        const uint32_t ng = std::min<uint32_t>(kLdsQueueJobs, count - g0);
+        LdsQueue q{};
+        uint64_t tot = 0;
+        size_t lds = 0;
+        for (uint32_t i = 0; i < ng; ++i) {
+            q.job[i] = jobs[g0 + i];
+            q.job[i].item0 = tot;
+            tot += batches[g0 + i]->K;
+            lds = std::max(lds, ((size_t)1 << jobs[g0 + i].n) * elem + (dbl ? ((size_t)8 << jobs[g0 + i].n) : 0));
+        }
+        q.n_jobs = ng;
+        q.total = tot;
+        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, counter);
+        STN_HIP(hipGetLastError());
+        // workgroups resident at once: LDS (160 KiB per CU) and at most 8 per CU
+        const uint64_t per_cu = std::max<uint64_t>(1, std::min<uint64_t>(8, (160u << 10) / (lds + 1024)));
+        const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tot, per_cu * (uint64_t)cus));
+        hipLaunchKernelGGL(f, dim3(grid), dim3(threads), lds, s, q, counter);
+        STN_HIP(hipGetLastError());
+    }
 }
 
 }  // namespace stn

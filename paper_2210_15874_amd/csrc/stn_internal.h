@@ -213,7 +213,7 @@ struct stn_batch {
     stn::DevBuf d_frame;             // uint64 [K x 2]: final frame x mask, z mask
     stn::DevBuf d_energy;            // double [K]
     stn::DevBuf d_states;            // complex [K x 2^n] (float2 or double2)
-    stn::DevBuf d_queue;             // multi-batch launches led by this batch: descriptors, counter
+    stn::DevBuf d_queue;             // multi-batch launches led by this batch: their item counter
     bool contracted = false;
     bool has_states = false;
     // contraction graph of this batch: 0 none, 1 eager run done with gkey,
@@ -273,6 +273,13 @@ struct LdsJob {
     void* states;
     uint64_t item0;
     uint32_t n, n_ops, S, n_terms;
+};
+// batches per multi-batch launch (the descriptors are kernel arguments)
+constexpr uint32_t kLdsQueueJobs = 32;
+struct LdsQueue {
+    LdsJob job[kLdsQueueJobs];
+    uint64_t total;     // items of all batches
+    uint32_t n_jobs;
 };
 void launch_sv_lds_many(stn_plan* const* plans, stn_batch* const* batches, uint32_t count, hipStream_t s);
 uint32_t tn_variants();
