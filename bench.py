@@ -112,8 +112,9 @@ def main():
                          "the job server, for --uneven-window seconds")
     ap.add_argument("--uneven-window", type=float, default=900.0)
     ap.add_argument("--job", type=str, default=None,
-                    help="only one job n,p,K[,precision] (QAOA on an Erdos-Renyi graph, p_edge 3/(n-1), "
-                         "depolarizing 1e-3/1e-2) through the plan API with the planner's choice of lowering")
+                    help="only one job n,p,K[,precision[,lc_max_rank,lc_slice_bits]] (QAOA on an Erdos-Renyi graph, "
+                         "p_edge 3/(n-1), depolarizing 1e-3/1e-2) through the plan API with the planner's choice of "
+                         "lowering, or sliced lightcone networks when slice bits are given")
     ap.add_argument("--graph-leg", action="store_true",
                     help="only the contraction-graph leg: many small chunks refilled into one batch, eager "
                          "launches against replayed HIP graphs")
@@ -393,12 +394,15 @@ def one_job_leg(stn, args):
     f = [int(x) for x in args.job.split(",")]
     n, p, K = f[:3]
     precision = f[3] if len(f) > 3 else 64
+    lc_max_rank, lc_slice_bits = (f[4], f[5]) if len(f) > 5 else (0, 0)
     torch.cuda.set_device(0)
     g, b = uniform_angles(p, 5000 + n)
     pr = make_problem(n, erdos_renyi_graph(n, 3.0 / (n - 1), 4000 + n), g, b, 1e-3, 1e-2, K, 6000 + n,
                       name=f"er-n{n}-p{p}-K{K}")
     t0 = time.perf_counter()
-    pl = stn.Plan(pr, outputs=stn.OUT_ENERGY, precision=precision, hbm_budget=int(args.hbm_budget_gib * (1 << 30)))
+    pl = stn.Plan(pr, outputs=stn.OUT_ENERGY, precision=precision, hbm_budget=int(args.hbm_budget_gib * (1 << 30)),
+                  plan_kind=stn.PLAN_LIGHTCONE if lc_slice_bits else stn.PLAN_AUTO, lc_max_rank=lc_max_rank,
+                  lc_slice_bits=lc_slice_bits)
     plan_ms = (time.perf_counter() - t0) * 1e3
     info = pl.info()
     B = info["max_batch"]
@@ -424,6 +428,7 @@ def one_job_leg(stn, args):
     prof = pl.profile_read()
     pl.close()
     return {"workload": pr.name, "precision": precision, "plan": info["plan_name"], "width": info["width"],
+            "lc_slices": info["lc_slices"], "lc_slice_bits": info["lc_slice_bits"],
             "steps": info["n_steps"], "passes": info["n_passes"], "trajectories_per_launch": B, "plan_ms": plan_ms,
             "seconds": dt, "trajectories_per_s": K / dt, "energy_mean": r["energy_mean"], "energy_se": r["energy_se"],
             "kernels": {k: {"launches": v["launches"], "ms": v["ms"],

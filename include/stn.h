@@ -146,6 +146,11 @@ typedef struct {
     stn_alloc_fn dev_alloc; /* optional device allocator (e.g. a caching allocator) */
     stn_free_fn dev_free;
     void* alloc_ctx;
+    uint32_t lc_max_rank;   /* lightcone plans: largest step rank (summed variable included: rank + 1
+                               index bits); 0 = 23, the most the kernels take */
+    uint32_t lc_slice_bits; /* lightcone plans: a network needing larger steps is sliced (Sec. III-C:
+                               up to this many variables fixed to each value, the 2^bits results
+                               summed); 0 = no slicing, at most 16 */
 } stn_plan_opts;
 
 typedef struct {
@@ -166,6 +171,8 @@ typedef struct {
     uint32_t graphs;        /* 1 while stn_contract uses HIP graphs (stn_plan_set_graphs) */
     uint64_t graph_captures;/* contraction graphs captured so far */
     uint64_t graph_replays; /* contractions run by replaying a captured graph */
+    uint32_t lc_slices;     /* lightcone plans: networks contracted per trajectory (terms x slices) */
+    uint32_t lc_slice_bits; /* largest number of sliced variables of one term */
 } stn_plan_stats;
 
 typedef struct {

@@ -63,7 +63,7 @@ class PlanOpts(C.Structure):
     _fields_ = [("precision", C.c_uint32), ("outputs", C.c_uint32), ("plan_kind", C.c_uint32),
                 ("max_batch", C.c_uint32), ("hbm_budget", C.c_uint64), ("order_restarts", C.c_uint32),
                 ("order_seed", C.c_uint64), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
-                ("alloc_ctx", C.c_void_p)]
+                ("alloc_ctx", C.c_void_p), ("lc_max_rank", C.c_uint32), ("lc_slice_bits", C.c_uint32)]
 
 
 class PlanStats(C.Structure):
@@ -72,7 +72,8 @@ class PlanStats(C.Structure):
                 ("n_passes", C.c_uint32), ("n_steps", C.c_uint32), ("bytes_per_traj", C.c_double),
                 ("flops_per_traj", C.c_double), ("peak_bytes", C.c_double), ("lc_width", C.c_uint32),
                 ("lc_flops_per_traj", C.c_double), ("variant", C.c_uint32), ("tuned", C.c_uint32),
-                ("graphs", C.c_uint32), ("graph_captures", C.c_uint64), ("graph_replays", C.c_uint64)]
+                ("graphs", C.c_uint32), ("graph_captures", C.c_uint64), ("graph_replays", C.c_uint64),
+                ("lc_slices", C.c_uint32), ("lc_slice_bits", C.c_uint32)]
 
 
 class TuneResult(C.Structure):
@@ -249,7 +250,7 @@ class Plan:
     """stn_plan_create for a workloads.Problem."""
 
     def __init__(self, problem, outputs=OUT_ENERGY, precision=64, plan_kind=PLAN_AUTO, max_batch=0,
-                 hbm_budget=0, torch_allocator=True, device=0):
+                 hbm_budget=0, torch_allocator=True, device=0, lc_max_rank=0, lc_slice_bits=0):
         self.lib = load()
         self.problem = problem
         self.n = problem.n_qubits
@@ -263,6 +264,8 @@ class Plan:
         opts.plan_kind = plan_kind
         opts.max_batch = max_batch
         opts.hbm_budget = hbm_budget
+        opts.lc_max_rank = lc_max_rank
+        opts.lc_slice_bits = lc_slice_bits
         self._alloc = None
         if torch_allocator:
             self._alloc = _TorchAllocator(device)

@@ -238,6 +238,8 @@ stn_status stn_plan_info(const stn_plan* p, stn_plan_stats* o) {
     o->graphs = p->graphs ? 1 : 0;
     o->graph_captures = p->graph_captures;
     o->graph_replays = p->graph_replays;
+    o->lc_slices = p->lc_slices;
+    o->lc_slice_bits = p->lc_slice_bits;
     return STN_OK;
 }
 

@@ -99,8 +99,38 @@ struct Lowered {
     int result = -1;         // final scalar tensor id
 };
 
-Lowered lower(const std::vector<Tensor>& base, int nv, const std::vector<int>& order) {
+// Variables of every step of bucket elimination along `order` (the
+// eliminated variable included), on variable lists without sliced variables.
+std::vector<std::vector<int>> step_sets(const std::vector<std::vector<int>>& tv, const std::vector<int>& order) {
+    std::vector<std::vector<int>> pool = tv, sets;
+    std::vector<char> alive(pool.size(), 1);
+    for (int v : order) {
+        std::vector<int> out;
+        bool any = false;
+        for (size_t i = 0; i < pool.size(); ++i) {
+            if (!alive[i] || std::find(pool[i].begin(), pool[i].end(), v) == pool[i].end()) continue;
+            any = true;
+            alive[i] = 0;
+            for (int x : pool[i])
+                if (x != v && std::find(out.begin(), out.end(), x) == out.end()) out.push_back(x);
+        }
+        if (!any) continue;
+        std::vector<int> st = out;
+        st.push_back(v);
+        sets.push_back(st);
+        pool.push_back(out);
+        alive.push_back(1);
+    }
+    return sets;
+}
+
+Lowered lower(const std::vector<Tensor>& base, int nv, const std::vector<int>& order,
+              const std::vector<int>& sliced) {
     Lowered L;
+    auto slice_bit = [&](int x) {
+        const auto it = std::find(sliced.begin(), sliced.end(), x);
+        return it == sliced.end() ? -1 : (int)(it - sliced.begin());
+    };
     std::vector<Tensor> pool = base;
     std::vector<char> alive(pool.size(), 1);
     // arena: first fit over [offset, size) free blocks
@@ -117,6 +147,7 @@ Lowered lower(const std::vector<Tensor>& base, int nv, const std::vector<int>& o
     };
     auto release = [&](int off) { used.erase(off); };
     for (int v : order) {
+        if (slice_bit(v) >= 0) continue;
         std::vector<int> bucket;
         for (size_t i = 0; i < pool.size(); ++i)
             if (alive[i] && std::find(pool[i].vars.begin(), pool[i].vars.end(), v) != pool[i].vars.end())
@@ -128,7 +159,8 @@ Lowered lower(const std::vector<Tensor>& base, int nv, const std::vector<int>& o
         std::vector<int> out;
         for (int i : bucket)
             for (int x : pool[i].vars)
-                if (x != v && std::find(out.begin(), out.end(), x) == out.end()) out.push_back(x);
+                if (x != v && slice_bit(x) < 0 && std::find(out.begin(), out.end(), x) == out.end())
+                    out.push_back(x);
         TnStepRec st;
         st.elim = v;
         st.out_vars = out;
@@ -142,10 +174,12 @@ Lowered lower(const std::vector<Tensor>& base, int nv, const std::vector<int>& o
             in.conj = pool[i].conj;
             in.arena = pool[i].arena;
             // position of each of the input's variables in the step's index space
-            // (output variables at bits 0..|out|-1, the summed variable at |out|)
+            // (output variables at bits 0..|out|-1, the summed variable at |out|;
+            // a sliced variable: its bit of the slice index)
             for (int x : pool[i].vars) {
                 const auto it = std::find(out.begin(), out.end(), x);
-                in.pos.push_back(x == v ? (int)out.size() : (int)(it - out.begin()));
+                const int sb = slice_bit(x);
+                in.pos.push_back(sb >= 0 ? -1 - sb : x == v ? (int)out.size() : (int)(it - out.begin()));
             }
             st.inputs.push_back(in);
             alive[i] = 0;
@@ -162,13 +196,17 @@ Lowered lower(const std::vector<Tensor>& base, int nv, const std::vector<int>& o
         alive.push_back(1);
         L.steps.push_back(st);
     }
-    // remaining scalars (no variables) multiply into the result
+    // remaining scalars (no variables but sliced ones) multiply into the result
     TnStepRec fin;
     fin.elim = -1;
     for (size_t i = 0; i < pool.size(); ++i)
         if (alive[i]) {
-            if (!pool[i].vars.empty()) fail(STN_E_INVALID, "tensor left with open indices");
             TnInputRec in;
+            for (int x : pool[i].vars) {
+                const int sb = slice_bit(x);
+                if (sb < 0) fail(STN_E_INVALID, "tensor left with open indices");
+                in.pos.push_back(-1 - sb);
+            }
             in.kind = pool[i].kind;
             in.gate = pool[i].gate;
             in.conj = pool[i].conj;
@@ -188,7 +226,8 @@ Lowered lower(const std::vector<Tensor>& base, int nv, const std::vector<int>& o
 
 // Network of one term: lightcone gates on the ket, the observable, the
 // conjugate gates on the bra, |0> at both ends of every chain.
-TnNetwork build_term(const stn_plan* p, uint32_t u, uint32_t v, uint32_t restarts, uint64_t seed, int max_rank) {
+TnNetwork build_term(const stn_plan* p, uint32_t u, uint32_t v, uint32_t restarts, uint64_t seed, int max_rank,
+                     int slice_bits) {
     const uint32_t n = p->n;
     // backward lightcone of {u, v}
     std::vector<char> in_cone(p->gates.size(), 0);
@@ -296,28 +335,52 @@ TnNetwork build_term(const stn_plan* p, uint32_t u, uint32_t v, uint32_t restart
             // qubit with no non-diagonal gate: ket and bra start share one variable
         }
     }
-    std::vector<std::vector<int>> tv;
-    for (auto& t : ts) tv.push_back(t.vars);
     TnNetwork net;
     net.u = u;
     net.v = v;
     net.n_vars = nv;
     Lowered best;
     bool have = false;
-    std::mt19937_64 rng(seed ^ (0x9E3779B97F4A7C15ull * (u * 131 + v)));
+    std::vector<int> sliced;   // slice index bit k fixes variable sliced[k]
     int deg_lb = 0;
-    for (uint32_t r = 0; r <= restarts; ++r) {
+    for (;;) {
+        // interaction graph without the sliced variables
+        std::vector<std::vector<int>> tv;
+        for (auto& t : ts) {
+            std::vector<int> r;
+            for (int x : t.vars)
+                if (std::find(sliced.begin(), sliced.end(), x) == sliced.end()) r.push_back(x);
+            tv.push_back(r);
+        }
+        std::mt19937_64 rng(seed ^ (0x9E3779B97F4A7C15ull * (u * 131 + v)));
+        deg_lb = 0;
+        for (uint32_t r = 0; r <= restarts; ++r) {
+            int deg = 0;
+            const std::vector<int> order = minfill_order(nv, tv, r == 0 ? nullptr : &rng, max_rank, &deg);
+            if (order.empty() && nv > 0) {   // this order needs a step above max_rank
+                deg_lb = deg_lb ? std::min(deg_lb, deg) : deg;
+                continue;
+            }
+            Lowered L = lower(ts, nv, order, sliced);
+            if (!have || L.width < best.width || (L.width == best.width && L.cost < best.cost)) {
+                best = std::move(L);
+                have = true;
+            }
+        }
+        if (have || (int)sliced.size() >= slice_bits) break;
+        // slice the variable that sits in the most (and widest) steps above
+        // max_rank of an unbounded-rank min-fill order, then try again
         int deg = 0;
-        const std::vector<int> order = minfill_order(nv, tv, r == 0 ? nullptr : &rng, max_rank, &deg);
-        if (order.empty() && nv > 0) {   // this order needs a step above max_rank
-            deg_lb = deg_lb ? std::min(deg_lb, deg) : deg;
-            continue;
-        }
-        Lowered L = lower(ts, nv, order);
-        if (!have || L.width < best.width || (L.width == best.width && L.cost < best.cost)) {
-            best = std::move(L);
-            have = true;
-        }
+        const std::vector<int> order = minfill_order(nv, tv, nullptr, nv, &deg);
+        std::vector<double> score(nv, 0.0);
+        for (auto& st : step_sets(tv, order))
+            if ((int)st.size() > max_rank + 1)
+                for (int x : st) score[x] += std::ldexp(1.0, (int)st.size() - max_rank - 1);
+        int pick = -1;
+        for (int x = 0; x < nv; ++x)
+            if (score[x] > 0 && (pick < 0 || score[x] > score[pick])) pick = x;
+        if (pick < 0) break;
+        sliced.push_back(pick);
     }
     if (!have) {   // no order within max_rank: width is at least deg_lb + 1
         net.width = deg_lb + 1;
@@ -326,7 +389,8 @@ TnNetwork build_term(const stn_plan* p, uint32_t u, uint32_t v, uint32_t restart
     }
     net.steps = std::move(best.steps);
     net.width = best.width;
-    net.cost = best.cost;
+    net.slice_bits = (int)sliced.size();
+    net.cost = std::ldexp(best.cost, net.slice_bits);
     net.arena = best.arena;
     net.result = best.result;
     return net;

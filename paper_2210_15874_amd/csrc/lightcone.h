@@ -18,7 +18,9 @@ struct TnInputRec {
     int gate = -1;
     int conj = 0;
     int arena = -1;
-    std::vector<int> pos;   // local index bit k of the input = bit pos[k] of the step's index
+    // local index bit k of the input = bit pos[k] of the step's index, or,
+    // where pos[k] < 0, bit -1 - pos[k] of the slice index
+    std::vector<int> pos;
 };
 
 struct TnStepRec {
@@ -31,15 +33,19 @@ struct TnStepRec {
 struct TnNetwork {
     uint32_t u = 0, v = 0;
     int n_vars = 0;
-    int width = 0;                 // largest step index space (output rank + 1)
-    double cost = 0;               // sum over steps of 2^width(step) * inputs
+    int width = 0;                 // largest step index space (output rank + 1), per slice
+    int slice_bits = 0;            // variables fixed by the slice index (2^slice_bits slices, summed)
+    double cost = 0;               // sum over steps of 2^width(step) * inputs, times the slices
     int arena = 0;                 // complex slots of intermediates
     int result = -1;               // arena slot of the final scalar
     std::vector<TnStepRec> steps;
 };
 
 // Networks whose elimination order would need a step of rank above max_rank
-// come back without steps, width = a lower bound, cost = infinity.
-TnNetwork build_term(const stn_plan* p, uint32_t u, uint32_t v, uint32_t restarts, uint64_t seed, int max_rank);
+// are sliced (Sec. III-C: variables fixed to each of their values, the
+// results summed) by up to slice_bits variables; those still too wide come
+// back without steps, width = a lower bound, cost = infinity.
+TnNetwork build_term(const stn_plan* p, uint32_t u, uint32_t v, uint32_t restarts, uint64_t seed, int max_rank,
+                     int slice_bits);
 
 }  // namespace stn

@@ -123,6 +123,24 @@ def test_lightcone_plans_and_auto_choice():
         plan(pr, plan_kind=PLAN_LIGHTCONE)
 
 
+def test_lightcone_slicing_plans():
+    """Index slicing (Sec. III-C) on the host: a width-20 network sliced to
+    steps of rank 12 and 16; without slicing a rank cap below the width is
+    rejected."""
+    from workloads import make_problem, random_regular_graph, uniform_angles
+    from paper_2210_15874_amd import PLAN_LIGHTCONE, StnError
+    g, b = uniform_angles(3, 904)
+    pr = make_problem(14, random_regular_graph(14, 3, 903), g, b, 5e-3, 2e-2, 6, 905)
+    base = plan(pr, plan_kind=PLAN_LIGHTCONE).info()
+    assert base["width"] == 20 and base["lc_slices"] == len(pr.edges) and base["lc_slice_bits"] == 0
+    for rank, bits in [(12, 10), (16, 6)]:
+        i = plan(pr, plan_kind=PLAN_LIGHTCONE, lc_max_rank=rank, lc_slice_bits=bits).info()
+        assert i["width"] <= rank + 1
+        assert 0 < i["lc_slice_bits"] <= bits and len(pr.edges) < i["lc_slices"] <= len(pr.edges) << bits
+    with pytest.raises(StnError, match="UNSUPPORTED"):
+        plan(pr, plan_kind=PLAN_LIGHTCONE, lc_max_rank=12)
+
+
 def test_server_needs_a_device_and_valid_options():
     from paper_2210_15874_amd import Server, StnError
     with pytest.raises(StnError, match="INVALID"):

@@ -517,6 +517,38 @@ def test_contraction_graph_replays_match_eager(kind, n, p, precision):
     b2.close()
 
 
+# ----------------------------------------------------------------------------- sliced lightcone networks
+
+@pytest.mark.parametrize("precision,tol", [(64, 1e-5), (128, 1e-11)])
+def test_lightcone_slicing_against_oracle_and_unsliced(precision, tol):
+    """Networks of width 20 sliced down to steps of rank 16 (intermediates in
+    HBM) and 12 (whole arena in LDS): per-trajectory energies against literal
+    Kraus insertion and against the unsliced networks."""
+    from oracle import simulate as sim
+    stn = stn_mod()
+    pr = qaoa(14, 3, 903, 5e-3, 2e-2, 6)
+    ens = sim.ensemble(pr, pr.seed, 0, pr.K, want_states=False)
+    m = len(pr.edges)
+    ref = None
+    for kw in [dict(), dict(lc_max_rank=16, lc_slice_bits=6), dict(lc_max_rank=12, lc_slice_bits=10)]:
+        pl = stn.Plan(pr, plan_kind=stn.PLAN_LIGHTCONE, precision=precision, **kw)
+        info = pl.info()
+        if kw:
+            assert info["lc_slice_bits"] > 0 and info["lc_slices"] > len(pr.edges)
+            assert info["width"] <= kw["lc_max_rank"] + 1
+        else:
+            assert info["width"] == 20 and info["lc_slices"] == len(pr.edges)
+        b = pl.sample(pr.seed, 0, pr.K)
+        pl.contract(b)
+        got = b.energies()
+        b.close()
+        np.testing.assert_allclose(got / m, ens["energies"] / m, atol=tol)
+        if ref is None:
+            ref = got
+        else:
+            np.testing.assert_allclose(got / m, ref / m, atol=tol)
+
+
 # ----------------------------------------------------------------------------- lightcone networks in HBM
 
 @pytest.mark.parametrize("precision,tol", [(64, 1e-5), (128, 1e-11)])
