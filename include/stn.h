@@ -355,8 +355,9 @@ typedef struct stn_server stn_server;
 typedef struct {
     uint64_t hbm_budget;     /* device bytes the server may hold (>= 64 MiB) */
     double job_share;        /* largest fraction of the budget one job's chunk may use, (0, 1] */
-    uint32_t n_streams;      /* device streams, 1..8: stream 0 for small jobs, the others for large ones;
-                                keep it within the process's hardware queues (GPU_MAX_HW_QUEUES) */
+    uint32_t n_streams;      /* job streams, 1..8: stream 0 for small jobs, the others for large ones; one
+                                more stream carries table uploads and tuning runs.  Keep n_streams + 1
+                                within the process's hardware queues (GPU_MAX_HW_QUEUES) */
     uint32_t max_active;     /* jobs admitted at once, 1..64 */
     uint32_t plan_cache;     /* idle plans kept for jobs with identical inputs (0: none) */
     uint32_t precision;      /* 64 (complex64) or 128 (complex128) for every job */

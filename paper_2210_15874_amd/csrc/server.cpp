@@ -42,6 +42,8 @@ constexpr uint32_t kMaxStreams = 8;
 constexpr uint32_t kMaxActive = 64;
 constexpr uint32_t kChunksInFlight = 2;   // per job
 constexpr int kPlanners = 4;              // host planning threads (a slow plan does not hold up the others)
+constexpr double kSmallJobSeconds = 0.05;  // estimated device time of a job for the small-job stream
+constexpr double kLongJobHold = 1.0;       // longest a long job waits for the small-job stream to drain
 constexpr uint32_t kTuneSample = 64;      // trajectories the autotuner times the launch shapes on
 constexpr double kChunkTiles = 32768;     // statevector tiles per launch a chunk aims at
 
@@ -193,6 +195,8 @@ struct Job {
     stn_status status = STN_OK;
     std::string err;
     double t_submit = 0, t_admit = 0, t_done = 0;
+    double t_ready = 0;                // planning finished
+    double est_s = 0;                  // estimated device seconds of the whole job
     uint64_t est_bytes = 0;
     uint32_t B = 0;                    // trajectories per chunk
     // device-side state (device thread only)
@@ -302,6 +306,9 @@ void plan_job(stn_server* sv, Job& j) {
         j.B = (uint32_t)std::max(1.0, std::min((double)j.B, std::ceil(kChunkTiles / tiles)));
     }
     j.est_bytes = estimate_bytes(p, j.B, j.K);
+    const double per = p->kind == STN_PLAN_LIGHTCONE ? 2.0 * p->lc_est_s
+                                                     : p->bytes_per_traj / 2e12 + p->flops_per_traj / 2e12;
+    j.est_s = per * (double)j.K;
     const uint64_t budget = sv->opts.hbm_budget;
     if (j.est_bytes > budget / 32 && j.est_bytes > budget - budget / 16) {
         j.status = STN_E_OOM;
@@ -335,6 +342,7 @@ void planner_loop(stn_server* sv) {
                                         [](const std::shared_ptr<Job>& a, const std::shared_ptr<Job>& b) {
                                             return a->id < b->id;
                                         });
+            j->t_ready = sv->now();
             sv->ready.insert(pos, j);
             sv->planned++;
         }
@@ -375,7 +383,9 @@ struct Device {
         STN_HIP(hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, sv->device));
         cus = (uint32_t)c;
         for (uint32_t i = 0; i < sv->opts.n_streams; ++i) STN_HIP(hipStreamCreateWithFlags(&streams[i], hipStreamNonBlocking));
-        upload = streams[0];
+        // table uploads and tuning runs get a stream of their own: the device
+        // thread waits for them, and must not wait behind the small jobs' chunks
+        STN_HIP(hipStreamCreateWithFlags(&upload, hipStreamNonBlocking));
         STN_HIP(hipHostMalloc((void**)&pinned, kMaxActive * 2 * sizeof(double), hipHostMallocDefault));
         for (uint32_t i = 0; i < kMaxActive; ++i) free_slots.push_back(kMaxActive - 1 - i);
     }
@@ -386,6 +396,10 @@ struct Device {
         active.clear();
         for (uint32_t i = 0; i < sv->opts.n_streams; ++i)
             if (streams[i]) (void)hipStreamDestroy(streams[i]);
+        if (upload) {
+            (void)hipStreamSynchronize(upload);
+            (void)hipStreamDestroy(upload);
+        }
         for (auto e : ev_pool) (void)hipEventDestroy(e);
         ev_pool.clear();
         if (pinned) (void)hipHostFree(pinned);
@@ -468,7 +482,12 @@ struct Device {
     // at most 1/32 of the budget that fits may go ahead of it (small jobs
     // barely delay the large one and are not held behind it).  Jobs above
     // that size may fill only 15/16 of the budget, so small jobs always find
-    // room.
+    // room.  A long job (estimated over kSmallJobSeconds of device time, so
+    // bound for the large-job streams) is held back while the small-job
+    // stream has work, for at most kLongJobHold seconds after its planning
+    // finished: short jobs then get the whole device first rather than the
+    // CUs a long job's persistent kernels leave free; the first job not held
+    // takes the oldest job's place in the rule above.
     bool admit() {
         std::shared_ptr<Job> j;
         {
@@ -478,14 +497,24 @@ struct Device {
             const uint64_t budget = sv->opts.hbm_budget, small = budget / 32;
             const uint64_t left = budget - std::min(budget, bytes_admitted);
             const uint64_t left_big = (budget - budget / 16) - std::min(budget - budget / 16, bytes_admitted);
+            const double now = sv->now();
+            const bool small_busy = hipStreamQuery(streams[0]) == hipErrorNotReady;
             size_t pick = SIZE_MAX;
+            bool head = true;
             for (size_t i = 0; i < sv->ready.size(); ++i) {
                 const auto& c = sv->ready[i];
                 if (c->status != STN_OK) { pick = i; break; }       // failed planning: report now
                 if (!room) continue;
+                const bool held = sv->opts.n_streams > 1 && c->est_s > kSmallJobSeconds && small_busy &&
+                                  now - c->t_ready < kLongJobHold;
+                if (held) continue;
                 const bool is_small = c->est_bytes <= small;
-                if (i == 0 && c->est_bytes <= (is_small ? left : left_big)) { pick = 0; break; }
-                if (i > 0 && is_small && c->est_bytes <= left) { pick = i; break; }
+                if (head) {
+                    head = false;
+                    if (c->est_bytes <= (is_small ? left : left_big)) { pick = i; break; }
+                    continue;
+                }
+                if (is_small && c->est_bytes <= left) { pick = i; break; }
             }
             if (pick == SIZE_MAX) return false;
             j = sv->ready[pick];
@@ -503,15 +532,13 @@ struct Device {
         free_slots.pop_back();
         bytes_admitted += j->est_bytes;
         // Streams that share a hardware queue run one after the other, so the
-        // server keeps few: stream 0 carries table uploads, autotuning and the
-        // small jobs (estimated under 50 ms of device time), so that they never
-        // wait behind a large job's chunks; large jobs take the least-loaded of
-        // the others.
+        // server keeps few (three job streams and the upload stream fill the
+        // four queues a process gets by default): stream 0 carries the small
+        // jobs (estimated under 50 ms of device time), so that they never wait
+        // behind a large job's chunks; large jobs take the least-loaded of the
+        // others.
         uint32_t best = 0;
-        const stn_plan* pl = j->plan;
-        const double per = pl->kind == STN_PLAN_LIGHTCONE ? 2.0 * pl->lc_est_s
-                                                          : pl->bytes_per_traj / 2e12 + pl->flops_per_traj / 2e12;
-        if (sv->opts.n_streams > 1 && per * (double)j->K > 0.05) {
+        if (sv->opts.n_streams > 1 && j->est_s > kSmallJobSeconds) {
             best = 1;
             for (uint32_t i = 2; i < sv->opts.n_streams; ++i)
                 if (stream_jobs[i] < stream_jobs[best]) best = i;
