@@ -123,6 +123,27 @@ def test_lightcone_plans_and_auto_choice():
         plan(pr, plan_kind=PLAN_LIGHTCONE)
 
 
+def test_new_entry_points_validate_arguments():
+    """Argument checks of the multi-batch, resample and graph entry points
+    (no device needed: they fail before any device call)."""
+    import ctypes as C
+    from paper_2210_15874_amd.binding import load
+    lib = load()
+    INVALID = 1
+    assert lib.stn_contract_many(None, None, 0, None) == 0          # nothing to do
+    assert lib.stn_contract_many(None, None, 2, None) == INVALID
+    null2 = (C.c_void_p * 2)(None, None)
+    assert lib.stn_contract_many(null2, null2, 2, None) == INVALID
+    assert lib.stn_resample(None, 1, 0, 4, None) == INVALID
+    assert lib.stn_plan_set_graphs(None, 1) == INVALID
+    from workloads import config_problem
+    pl = plan(config_problem(0))
+    assert lib.stn_plan_set_graphs(pl.h, 1) == 0
+    assert pl.info()["graphs"] == 1
+    assert lib.stn_plan_set_graphs(pl.h, 0) == 0
+    assert pl.info()["graphs"] == 0 and pl.info()["graph_captures"] == 0
+
+
 def test_lightcone_slicing_plans():
     """Index slicing (Sec. III-C) on the host: a width-20 network sliced to
     steps of rank 12 and 16; without slicing a rank cap below the width is
