@@ -44,6 +44,7 @@ constexpr uint32_t kChunksInFlight = 2;   // per job
 constexpr int kPlanners = 4;              // host planning threads (a slow plan does not hold up the others)
 constexpr double kSmallJobSeconds = 0.05;  // estimated device time of a job for the small-job stream
 constexpr double kLongJobHold = 1.0;       // longest a long job waits for the small-job stream to drain
+constexpr double kSmallChunkSeconds = 0.005;  // estimated device time of one chunk of a small job
 constexpr uint32_t kTuneSample = 64;      // trajectories the autotuner times the launch shapes on
 constexpr double kChunkTiles = 32768;     // statevector tiles per launch a chunk aims at
 
@@ -305,10 +306,17 @@ void plan_job(stn_server* sv, Job& j) {
         const double tiles = std::ldexp(1.0, std::max(0, (int)p->n - tile_bits));
         j.B = (uint32_t)std::max(1.0, std::min((double)j.B, std::ceil(kChunkTiles / tiles)));
     }
-    j.est_bytes = estimate_bytes(p, j.B, j.K);
     const double per = p->kind == STN_PLAN_LIGHTCONE ? 2.0 * p->lc_est_s
                                                      : p->bytes_per_traj / 2e12 + p->flops_per_traj / 2e12;
     j.est_s = per * (double)j.K;
+    // a job for the small-job stream runs in chunks of about kSmallChunkSeconds,
+    // so that the other small jobs' chunks are issued between its chunks
+    // instead of waiting behind all of it
+    if (j.est_s > kSmallChunkSeconds && j.est_s <= kSmallJobSeconds) {
+        const double chunks = std::ceil(j.est_s / kSmallChunkSeconds);
+        j.B = (uint32_t)std::max(1.0, std::min((double)j.B, std::ceil((double)j.K / chunks)));
+    }
+    j.est_bytes = estimate_bytes(p, j.B, j.K);
     const uint64_t budget = sv->opts.hbm_budget;
     if (j.est_bytes > budget / 32 && j.est_bytes > budget - budget / 16) {
         j.status = STN_E_OOM;
