@@ -230,7 +230,8 @@ stn_status stn_sample(stn_plan* plan, uint64_t seed, uint64_t k0, uint32_t K,
                       stn_batch** out, void* stream);
 
 /* Draws trajectories k0 .. k0+K-1 of job `seed` into an existing batch of
- * its plan, replacing its contents (the same draws as stn_sample).  Device
+ * its plan, replacing its contents (Sec. III-G selection rule: the same
+ * draws as stn_sample).  Device
  * buffers are kept when large enough, so a caller running many chunks
  * allocates once; work already enqueued on the batch must be ordered before
  * this call (same stream). */
@@ -285,7 +286,8 @@ stn_status stn_profile(stn_plan* plan, int enable);
 stn_status stn_profile_read(stn_plan* plan, stn_kernel_stats* out);
 
 /* Contracts the batches of several whole-state-in-LDS plans (n <= 13 in
- * complex64, n <= 12 in complex128; all of one precision) in one launch:
+ * complex64, n <= 12 in complex128; all of one precision) in one launch
+ * (Sec. III-D, sample parallelism: many small circuits share one GPU):
  * persistent workgroups take (batch, trajectory) items from a device-side
  * queue (an atomic counter over the items of all batches, batch after batch)
  * until it is empty, so many small jobs fill the device together.  Results
