@@ -106,11 +106,13 @@ __device__ __forceinline__ void lds_trajectory(typename Cx<R>::T* psi, uint32_t 
                 break;
             }
             case OP_DIAG2: {
-                V d[4];
-#pragma unroll
-                for (int l = 0; l < 4; ++l) d[l] = vals[o.mat + l];
-                for (uint32_t i = tid; i < N; i += kThreads)
-                    psi[i] = cmul(d[((i >> o.q0) & 1) | (((i >> o.q1) & 1) << 1)], psi[i]);
+                const V d0 = vals[o.mat], d1 = vals[o.mat + 1], d2 = vals[o.mat + 2], d3 = vals[o.mat + 3];
+                for (uint32_t i = tid; i < N; i += kThreads) {
+                    // selects, not an indexed local array (which would live in scratch)
+                    const bool a = (i >> o.q0) & 1, b = (i >> o.q1) & 1;
+                    const V lo = a ? d1 : d0, hi = a ? d3 : d2;
+                    psi[i] = cmul(b ? hi : lo, psi[i]);
+                }
                 break;
             }
             case OP_PAULI: {

@@ -585,6 +585,10 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
         fail(STN_E_INVALID, "unknown plan kind");
     }
     p->kind = kind;
+    // launch shape before any tuning: for the tiled complex64 kernels, two
+    // resident workgroups per CU (variant 2), the autotuner's choice on every
+    // size measured
+    if (kind == STN_PLAN_SV_TILED && p->opts.precision == 64) p->variant = 2;
     // cost model and batch size
     const double elem = p->opts.precision == 128 ? 16.0 : 8.0;
     const double N = std::ldexp(1.0, (int)n);

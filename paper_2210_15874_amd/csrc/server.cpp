@@ -43,7 +43,7 @@ constexpr uint32_t kMaxActive = 64;
 constexpr uint32_t kChunksInFlight = 2;   // per job
 constexpr int kPlanners = 4;              // host planning threads (a slow plan does not hold up the others)
 constexpr double kSmallJobSeconds = 0.05;  // estimated device time of a job for the small-job stream
-constexpr double kLongJobHold = 1.0;       // longest a long job waits for the small-job stream to drain
+constexpr double kLongJobHold = 0.25;      // longest a long job waits for the small-job stream to drain
 constexpr double kSmallChunkSeconds = 0.005;  // estimated device time of one chunk of a small job
 constexpr uint32_t kTuneSample = 64;      // trajectories the autotuner times the launch shapes on
 constexpr double kChunkTiles = 32768;     // statevector tiles per launch a chunk aims at
