@@ -605,9 +605,13 @@ def serving_leg(stn, args):
         while sv.clock() - t0 < ta:
             time.sleep(min(1e-3, max(0.0, ta - (sv.clock() - t0))))
         sv.submit(pr, tag=i)
+    last = sv.clock()
     while sv.clock() - t0 < args.serve_window and len(res) < len(jobs):
         for r in sv.poll(wait=0.5, cap=4096):
             res[r["tag"]] = r
+        if sv.clock() - last > 20.0:    # progress for long windows
+            last = sv.clock()
+            print(f"serving: {last - t0:.0f} s, {len(res)} of {len(jobs)} jobs done", file=sys.stderr, flush=True)
     t_end = min(sv.clock() - t0, args.serve_window)
     st = sv.stats()
     sv.close()                      # abandons unfinished jobs
