@@ -35,7 +35,7 @@ typedef double d4_t __attribute__((ext_vector_type(4)));
 // B (4x16) lane l holds B[l / 16][l % 16]; D (16x16) lane l, component v
 // holds D[l / 16 + 4 v][l % 16].
 template <class V>
-__global__ __launch_bounds__(256) void k_herk(const V* __restrict__ Psi, uint32_t B, uint32_t N, uint32_t tiles,
+__global__ __launch_bounds__(256, 4) void k_herk(const V* __restrict__ Psi, uint32_t B, uint32_t N, uint32_t tiles,
                                               double2* __restrict__ rho) {
     // upper-triangle tile pair from the linear block index
     uint32_t t = blockIdx.x, I = 0;
@@ -44,8 +44,10 @@ __global__ __launch_bounds__(256) void k_herk(const V* __restrict__ Psi, uint32_
         ++I;
     }
     const uint32_t J = I + t;
-    __shared__ double2 A[kChunk][kTile];   // rows i0.., widened amplitudes
-    __shared__ double2 C[kChunk][kTile];   // cols j0..
+    // staged in the amplitudes' own precision (half the LDS for complex64,
+    // so more workgroups fit on a CU) and widened when read
+    __shared__ V A[kChunk][kTile];   // rows i0..
+    __shared__ V C[kChunk][kTile];   // cols j0..
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t rw = (wave >> 1) * 32, cw = (wave & 1) * 32;   // this wave's 32x32 sub-block
     const uint32_t l16 = lane & 15, k4 = lane >> 4;               // row/col in block, k index
@@ -63,8 +65,11 @@ __global__ __launch_bounds__(256) void k_herk(const V* __restrict__ Psi, uint32_
         for (uint32_t e = threadIdx.x; e < kChunk * kTile; e += 256) {
             const uint32_t bb = e / kTile, x = e % kTile;
             const bool ok = b0 + bb < B;
-            A[bb][x] = (ok && i0 + x < N) ? widen(Psi[(size_t)(b0 + bb) * N + i0 + x]) : make_double2(0.0, 0.0);
-            C[bb][x] = (ok && j0 + x < N) ? widen(Psi[(size_t)(b0 + bb) * N + j0 + x]) : make_double2(0.0, 0.0);
+            V za;
+            za.x = 0;
+            za.y = 0;
+            A[bb][x] = (ok && i0 + x < N) ? Psi[(size_t)(b0 + bb) * N + i0 + x] : za;
+            C[bb][x] = (ok && j0 + x < N) ? Psi[(size_t)(b0 + bb) * N + j0 + x] : za;
         }
         __syncthreads();
 #pragma unroll 2
@@ -72,13 +77,13 @@ __global__ __launch_bounds__(256) void k_herk(const V* __restrict__ Psi, uint32_
             double ax[2], ay[2], bx[2];
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
-                const double2 a = A[bb + kb][rw + 16 * r + l16];
+                const double2 a = widen(A[bb + kb][rw + 16 * r + l16]);
                 ax[r] = part ? a.y : a.x;      // X[i][k]
                 ay[r] = part ? -a.x : a.y;     // Y[i][k]
             }
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                const double2 v = C[bb + kb][cw + 16 * c + l16];
+                const double2 v = widen(C[bb + kb][cw + 16 * c + l16]);
                 bx[c] = part ? v.y : v.x;      // X[j][k] as B[k][j]
             }
 #pragma unroll
