@@ -113,13 +113,24 @@ __global__ __launch_bounds__(256, 4) void k_herk(const V* __restrict__ Psi, uint
             }
 }
 
+// One thread per basis state (64-thread workgroups, so that small N still
+// spreads over many CUs); the sum over trajectories stays in trajectory
+// order, with the loads of 8 trajectories issued ahead of their adds.
 template <class V>
-__global__ __launch_bounds__(256) void k_diag(const V* __restrict__ Psi, uint32_t B, uint32_t N,
-                                              double* __restrict__ diag) {
-    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(64) void k_diag(const V* __restrict__ Psi, uint32_t B, uint32_t N,
+                                             double* __restrict__ diag) {
+    const uint32_t i = blockIdx.x * 64 + threadIdx.x;
     if (i >= N) return;
     double s = 0.0;
-    for (uint32_t b = 0; b < B; ++b) {
+    uint32_t b = 0;
+    for (; b + 8 <= B; b += 8) {
+        double2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = widen(Psi[(size_t)(b + u) * N + i]);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u].x * v[u].x + v[u].y * v[u].y;
+    }
+    for (; b < B; ++b) {
         const double2 v = widen(Psi[(size_t)b * N + i]);
         s += v.x * v.x + v.y * v.y;
     }
@@ -208,10 +219,10 @@ void launch_reduce(stn_plan* p, stn_batch* b, stn_accum* a, hipStream_t s) {
     if (outs & (STN_OUT_RHO | STN_OUT_DIAG)) {
         prof_begin(p, STN_K_DIAG, s);
         if (dbl)
-            hipLaunchKernelGGL(k_diag<double2>, dim3((N + 255) / 256), dim3(256), 0, s, b->d_states.as<double2>(),
+            hipLaunchKernelGGL(k_diag<double2>, dim3((N + 63) / 64), dim3(64), 0, s, b->d_states.as<double2>(),
                                b->K, N, a->d_diag.as<double>());
         else
-            hipLaunchKernelGGL(k_diag<float2>, dim3((N + 255) / 256), dim3(256), 0, s, b->d_states.as<float2>(),
+            hipLaunchKernelGGL(k_diag<float2>, dim3((N + 63) / 64), dim3(64), 0, s, b->d_states.as<float2>(),
                                b->K, N, a->d_diag.as<double>());
         STN_HIP(hipGetLastError());
         prof_end(p, STN_K_DIAG, s, (double)b->K * N * (dbl ? 16 : 8) + N * 16.0, (double)b->K * N * 4.0);
