@@ -115,6 +115,8 @@ def main():
                     help="only one job n,p,K[,precision[,lc_max_rank,lc_slice_bits]] (QAOA on an Erdos-Renyi graph, "
                          "p_edge 3/(n-1), depolarizing 1e-3/1e-2) through the plan API with the planner's choice of "
                          "lowering, or sliced lightcone networks when slice bits are given")
+    ap.add_argument("--job-tune", action="store_true",
+                    help="with --job: autotune the launch shape on 256 sampled trajectories first")
     ap.add_argument("--graph-leg", action="store_true",
                     help="only the contraction-graph leg: many small chunks refilled into one batch, eager "
                          "launches against replayed HIP graphs")
@@ -404,6 +406,11 @@ def one_job_leg(stn, args):
                   plan_kind=stn.PLAN_LIGHTCONE if lc_slice_bits else stn.PLAN_AUTO, lc_max_rank=lc_max_rank,
                   lc_slice_bits=lc_slice_bits)
     plan_ms = (time.perf_counter() - t0) * 1e3
+    tune = None
+    if args.job_tune:
+        tb = pl.sample(pr.seed, 0, min(K, 256))
+        tune = pl.autotune(tb, reps=1)
+        tb.close()
     info = pl.info()
     B = info["max_batch"]
 
@@ -428,7 +435,7 @@ def one_job_leg(stn, args):
     prof = pl.profile_read()
     pl.close()
     return {"workload": pr.name, "precision": precision, "plan": info["plan_name"], "width": info["width"],
-            "lc_slices": info["lc_slices"], "lc_slice_bits": info["lc_slice_bits"],
+            "lc_slices": info["lc_slices"], "lc_slice_bits": info["lc_slice_bits"], "launch_shape": tune,
             "steps": info["n_steps"], "passes": info["n_passes"], "trajectories_per_launch": B, "plan_ms": plan_ms,
             "seconds": dt, "trajectories_per_s": K / dt, "energy_mean": r["energy_mean"], "energy_se": r["energy_se"],
             "kernels": {k: {"launches": v["launches"], "ms": v["ms"],
