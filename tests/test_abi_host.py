@@ -29,6 +29,19 @@ def test_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+def test_header_is_plain_c():
+    """include/stn.h is a C ABI: it compiles as C99 and as C++."""
+    import shutil
+    import subprocess
+    hdr = os.path.join(ROOT, "include", "stn.h")
+    for cc, args in [("gcc", ["-x", "c", "-std=c99"]), ("g++", ["-x", "c++"])]:
+        exe = shutil.which(cc)
+        if exe is None:
+            pytest.skip(f"{cc} not found")
+        r = subprocess.run([exe, "-fsyntax-only", "-Wall", "-Werror"] + args + [hdr], capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
+
+
 def test_binding_covers_header():
     from paper_2210_15874_amd.binding import EXPORTS
     assert set(declared_functions()) == set(EXPORTS)
