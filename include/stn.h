@@ -285,6 +285,17 @@ stn_status stn_profile(stn_plan* plan, int enable);
 /* Fills out[0 .. STN_K_COUNT) with the timings since enabling. Syncs. */
 stn_status stn_profile_read(stn_plan* plan, stn_kernel_stats* out);
 
+/* Contracts each distinct trajectory of the batch once (Sec. III-G: many
+ * sampled circuits coincide, e.g. all error-free ones) and copies its energy
+ * to the trajectories that equal it.  Trajectories are equal when their
+ * Kraus indices are (whole-state-in-LDS plans) or when their gate signs and
+ * final-frame X part are (Pauli-frame plans: tiled, lightcone).  Energies are
+ * those of stn_contract, bit for bit; *n_unique (may be NULL) receives the
+ * number of distinct trajectories.  Energy outputs only (RHO / DIAG /
+ * STATES: STN_E_UNSUPPORTED).  Synchronises the stream (the keys are read on
+ * the host). */
+stn_status stn_contract_dedup(stn_plan* plan, stn_batch* batch, uint32_t* n_unique, void* stream);
+
 /* Contracts the batches of several whole-state-in-LDS plans (n <= 13 in
  * complex64, n <= 12 in complex128; all of one precision) in one launch
  * (Sec. III-D, sample parallelism: many small circuits share one GPU):

@@ -137,6 +137,7 @@ EXPORTS = {
     "stn_plan_set_variant": (C.c_int, [C.c_void_p, C.c_uint32]),
     "stn_plan_set_graphs": (C.c_int, [C.c_void_p, C.c_uint32]),
     "stn_contract_many": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_uint32, C.c_void_p]),
+    "stn_contract_dedup": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_uint32), C.c_void_p]),
     "stn_resample": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint32, C.c_void_p]),
     "stn_batch_size": (C.c_uint32, [C.c_void_p]),
     "stn_batch_destroy": (None, [C.c_void_p]),
@@ -307,6 +308,13 @@ class Plan:
 
     def contract(self, batch, stream=None):
         _check(self.lib.stn_contract(self.h, batch.h, stream if stream is not None else current_stream()))
+
+    def contract_dedup(self, batch, stream=None):
+        """Contracts each distinct trajectory once; returns their number."""
+        u = C.c_uint32()
+        _check(self.lib.stn_contract_dedup(self.h, batch.h, C.byref(u),
+                                           stream if stream is not None else current_stream()))
+        return u.value
 
     def autotune(self, batch, reps=2, stream=None):
         """Times every launch shape of this plan's contraction on `batch` and

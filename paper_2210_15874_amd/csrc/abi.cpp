@@ -1,6 +1,7 @@
 // extern "C" entry points of include/stn.h: argument checks, handle
 // lifetimes, device memory, and dispatch to the kernel launchers.
 #include <algorithm>
+#include <unordered_map>
 #include <cstring>
 #include <new>
 
@@ -465,6 +466,80 @@ stn_status stn_contract_many(stn_plan* const* plans, stn_batch* const* batches, 
         for (uint32_t i = 0; i < count; ++i) ensure_uploaded(plans[i], s);
         launch_sv_lds_many(plans, batches, count, s);
         for (uint32_t i = 0; i < count; ++i) batches[i]->contracted = true;
+    });
+}
+
+stn_status stn_contract_dedup(stn_plan* p, stn_batch* b, uint32_t* n_unique, void* stream) {
+    if (!p || !b) return set_error(STN_E_INVALID, "NULL argument");
+    if (b->plan != p) return set_error(STN_E_INVALID, "batch belongs to another plan");
+    if (p->opts.outputs & (STN_OUT_RHO | STN_OUT_DIAG | STN_OUT_STATES))
+        return set_error(STN_E_UNSUPPORTED, "de-duplicated contraction produces energies only");
+    return guarded([&] {
+        hipStream_t s = (hipStream_t)stream;
+        ensure_uploaded(p, s);
+        const uint32_t K = b->K;
+        const bool by_index = p->kind == STN_PLAN_SV_LDS;   // else: gate signs and final frame X
+        const size_t S = p->sites.size(), W = b->words;
+        // the trajectories' keys, read back once the sampling has finished
+        std::vector<uint8_t> idx;
+        std::vector<uint32_t> sg;
+        std::vector<uint64_t> fr;
+        STN_HIP(hipStreamSynchronize(s));
+        if (by_index) {
+            idx.resize((size_t)K * S);
+            if (!idx.empty()) STN_HIP(hipMemcpy(idx.data(), b->d_idx.p, idx.size(), hipMemcpyDeviceToHost));
+        } else {
+            sg.resize((size_t)K * W);
+            fr.resize((size_t)K * 2);
+            if (!sg.empty()) STN_HIP(hipMemcpy(sg.data(), b->d_signs.p, sg.size() * 4, hipMemcpyDeviceToHost));
+            STN_HIP(hipMemcpy(fr.data(), b->d_frame.p, fr.size() * 8, hipMemcpyDeviceToHost));
+        }
+        auto key = [&](uint32_t k) {
+            if (by_index) return std::string(reinterpret_cast<const char*>(idx.data() + (size_t)k * S), S);
+            std::string kk(reinterpret_cast<const char*>(sg.data() + (size_t)k * W), W * 4);
+            kk.append(reinterpret_cast<const char*>(&fr[2 * (size_t)k]), 8);   // the frame's X part signs the energy
+            return kk;
+        };
+        std::unordered_map<std::string, uint32_t> first;
+        std::vector<uint32_t> rep, map(K);
+        for (uint32_t k = 0; k < K; ++k) {
+            auto it = first.emplace(key(k), (uint32_t)rep.size());
+            if (it.second) rep.push_back(k);
+            map[k] = it.first->second;
+        }
+        if (n_unique) *n_unique = (uint32_t)rep.size();
+        if (rep.size() == K) {   // nothing to share
+            contract_launch(p, b, s);
+            b->contracted = true;
+            return;
+        }
+        // one representative per distinct key, in trajectory order
+        const uint32_t U = (uint32_t)rep.size();
+        if (!b->unique) b->unique = new stn_batch();
+        stn_batch* u = b->unique;
+        batch_prepare(p, u, b->k0, U);
+        if (by_index) {
+            std::vector<uint8_t> ui((size_t)U * S);
+            for (uint32_t r = 0; r < U; ++r)
+                std::copy_n(idx.data() + (size_t)rep[r] * S, S, ui.data() + (size_t)r * S);
+            if (!ui.empty()) STN_HIP(hipMemcpyAsync(u->d_idx.p, ui.data(), ui.size(), hipMemcpyHostToDevice, s));
+        } else {
+            std::vector<uint32_t> us((size_t)U * W);
+            std::vector<uint64_t> uf((size_t)U * 2);
+            for (uint32_t r = 0; r < U; ++r) {
+                std::copy_n(sg.data() + (size_t)rep[r] * W, W, us.data() + (size_t)r * W);
+                uf[2 * r] = fr[2 * (size_t)rep[r]];
+                uf[2 * r + 1] = fr[2 * (size_t)rep[r] + 1];
+            }
+            if (!us.empty()) STN_HIP(hipMemcpyAsync(u->d_signs.p, us.data(), us.size() * 4, hipMemcpyHostToDevice, s));
+            STN_HIP(hipMemcpyAsync(u->d_frame.p, uf.data(), uf.size() * 8, hipMemcpyHostToDevice, s));
+        }
+        b->d_map.ensure(&p->alloc, (size_t)K * 4);
+        STN_HIP(hipMemcpyAsync(b->d_map.p, map.data(), (size_t)K * 4, hipMemcpyHostToDevice, s));
+        STN_HIP(hipStreamSynchronize(s));   // the host copies above are pageable
+        contract_launch(p, u, s);
+        launch_scatter_energy(u->d_energy.as<double>(), b->d_map.as<uint32_t>(), K, b->d_energy.as<double>(), s);
+        b->contracted = true;
     });
 }
 

@@ -241,6 +241,19 @@ void launch_reduce(stn_plan* p, stn_batch* b, stn_accum* a, hipStream_t s) {
     }
 }
 
+__global__ __launch_bounds__(256) void k_scatter_energy(const double* __restrict__ src,
+                                                        const uint32_t* __restrict__ map, uint32_t K,
+                                                        double* __restrict__ dst) {
+    const uint32_t k = blockIdx.x * 256 + threadIdx.x;
+    if (k < K) dst[k] = src[map[k]];
+}
+
+void launch_scatter_energy(const double* src, const uint32_t* map, uint32_t K, double* dst, hipStream_t s) {
+    if (!K) return;
+    hipLaunchKernelGGL(k_scatter_energy, dim3((K + 255) / 256), dim3(256), 0, s, src, map, K, dst);
+    STN_HIP(hipGetLastError());
+}
+
 void launch_energy_stats(stn_accum* a, uint64_t K, hipStream_t s) {
     hipLaunchKernelGGL(k_stats, dim3(1), dim3(256), 0, s, a->d_egather.as<double>(), K, a->d_stats.as<double>());
     STN_HIP(hipGetLastError());

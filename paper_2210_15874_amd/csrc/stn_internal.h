@@ -215,6 +215,8 @@ struct stn_batch {
     stn::DevBuf d_energy;            // double [K]
     stn::DevBuf d_states;            // complex [K x 2^n] (float2 or double2)
     stn::DevBuf d_queue;             // multi-batch launches led by this batch: their item counter
+    stn::DevBuf d_map;               // stn_contract_dedup: representative of each trajectory
+    stn_batch* unique = nullptr;     // stn_contract_dedup: the distinct trajectories
     bool contracted = false;
     bool has_states = false;
     // contraction graph of this batch: 0 none, 1 eager run done with gkey,
@@ -227,6 +229,7 @@ struct stn_batch {
     stn_batch& operator=(const stn_batch&) = delete;
     ~stn_batch() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
+        delete unique;
     }
 };
 
@@ -297,6 +300,8 @@ void launch_sv_tiled(stn_plan* p, stn_batch* b, hipStream_t s);
 void launch_reduce(stn_plan* p, stn_batch* b, stn_accum* a, hipStream_t s);
 // fixed-order energy statistics over the gathered per-trajectory energies
 void launch_energy_stats(stn_accum* a, uint64_t K, hipStream_t s);
+// dst[k] = src[map[k]] for k < K
+void launch_scatter_energy(const double* src, const uint32_t* map, uint32_t K, double* dst, hipStream_t s);
 // rho_out = mirror(rho)/K, diag_out = diag/K, stats[2] = trace
 void launch_finish_dense(stn_accum* a, hipStream_t s);
 void launch_lightcone(stn_plan* p, stn_batch* b, hipStream_t s);

@@ -453,6 +453,36 @@ def test_contract_many_matches_per_batch(precision):
         b.close()
 
 
+# ----------------------------------------------------------------------------- de-duplicated contraction
+
+@pytest.mark.parametrize("kind,n,p,precision,lam", [("sv_tiled", 18, 2, 64, (1e-3, 5e-3)),
+                                                    ("sv_tiled", 16, 2, 128, (2e-3, 1e-2)),
+                                                    ("lightcone", 20, 1, 64, (1e-3, 1e-2)),
+                                                    ("sv_lds", 10, 2, 128, (1e-3, 1e-2))])
+def test_dedup_contraction_matches_plain(kind, n, p, precision, lam):
+    """Each distinct trajectory contracted once, its energy copied to the
+    equal ones: the same energies as contracting every trajectory, bit for
+    bit; the distinct count is at most the number of distinct Kraus-index
+    rows (different Pauli errors can leave the same signs and frame)."""
+    stn = stn_mod()
+    kinds = {"sv_lds": stn.PLAN_SV_LDS, "lightcone": stn.PLAN_LIGHTCONE, "sv_tiled": stn.PLAN_SV_TILED}
+    pr = qaoa(n, p, 880 + n, lam[0], lam[1], 300)
+    pl = stn.Plan(pr, plan_kind=kinds[kind], precision=precision)
+    for k0 in (0, 300):
+        b = pl.sample(pr.seed, k0, pr.K)
+        pl.contract(b)
+        want = b.energies()
+        rows = len({r.tobytes() for r in b.indices()})
+        b.close()
+        b2 = pl.sample(pr.seed, k0, pr.K) if k0 == 0 else pl.resample(b2, pr.seed, k0, pr.K)
+        u = pl.contract_dedup(b2)
+        np.testing.assert_array_equal(b2.energies(), want)
+        assert 1 <= u <= rows < pr.K
+        if kind == "sv_lds":
+            assert u == rows
+    b2.close()
+
+
 # ----------------------------------------------------------------------------- contraction graphs
 
 @pytest.mark.parametrize("kind,n,p,precision", [("sv_lds", 10, 2, 64), ("sv_lds", 12, 2, 128),
