@@ -20,12 +20,15 @@ What it computes (all complex128 / float64, plain and slow on purpose):
 * ``channels``     Kraus sets (Sec. III-F), selection probabilities and the
                    integer thresholds that turn a 32-bit draw into an index.
 * ``metrics``      Eq.(2) error, Uhlmann fidelity, trace distance, Frobenius.
+* ``sampling``     bitstrings drawn from sigma_approx by inverse-transform
+                   sampling of its running sums.
 
 Pins (tests/test_oracle_*.py, run with ``-m "not gpu"``): channel closed forms,
 trace/Hermitian/PSD invariants, the noiseless limit against the p=1 QAOA
 closed form of Wang et al., exhaustive outcome enumeration against the exact
-density matrix, the convergence law of the estimator, and Philox against the
-independent rocRAND implementation.  Parity unpinned: <C> with noise at sizes
+density matrix, the convergence law of the estimator, Philox against the
+independent rocRAND implementation, and the bitstring sampler against
+hand-computed samples, stratified counts and a chi-square bound.  Parity unpinned: <C> with noise at sizes
 where no exact density matrix fits (n > 12); there only same-draw comparison and
 the stated standard error apply.
 """
