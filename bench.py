@@ -381,9 +381,20 @@ def rho_hat_leg(stn, ksweep):
         torch.cuda.synchronize()
         bt.close()
     plain = n_plain / (time.perf_counter() - t1)
+    # bitstrings drawn from sigma_approx of those trajectories (inverse transform, 2^24 draws)
+    m = 1 << 24
+    u = torch.rand(m, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+    xs = acc.sample(u)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    xs = acc.sample(u, out=xs)
+    ev1.record()
+    torch.cuda.synchronize()
+    sample_s = ev0.elapsed_time(ev1) * 1e-3
     acc.close()
     out = {"workload": pr.name, "K": pr.K, "seconds": dt, "trajectories_per_s": pr.K / dt,
            "plain_loop_trajectories_per_s": plain, "batched_over_plain": pr.K / dt / plain,
+           "bitstring_samples_per_s": m / sample_s,
            "kernels_ms": {k: v["ms"] for k, v in prof.items() if v["launches"]},
            "herk_fp64_tflops": herk["flops"] / (herk["ms"] * 1e-3) / 1e12 if herk["ms"] else None,
            "herk_peak_tflops": 78.6, "trace": res["trace"]}

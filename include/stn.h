@@ -345,6 +345,22 @@ stn_status stn_reduce(stn_plan* plan, stn_batch* batch, stn_accum* acc, void* st
 stn_status stn_accum_read(stn_accum* acc, stn_result* out, void* stream);
 void stn_accum_destroy(stn_accum* acc);
 
+/* Bitstring samples from the ensemble's probability vector (Sec. III-G:
+ * sigma_approx, the average of the trajectories' probability vectors, is a
+ * distribution over the 2^n basis states).  For each j < m, out[j] = the basis
+ * index x (qubit q in bit q) drawn by inverse transform with the uniform u[j]:
+ * with the running sums F(x) = sigma(0) + ... + sigma(x) of the trajectories
+ * reduced into acc so far, the smallest x with F(x) > u[j] F(2^n - 1); when
+ * rounding leaves none, the smallest x with F(x) >= u[j] F(2^n - 1).  Indices
+ * of zero mass are never drawn unless all mass is zero (then x = 0).
+ *   u    device, m doubles in [0, 1), caller-owned (other values still give
+ *        indices in [0, 2^n))
+ *   out  device, m uint32, caller-owned
+ * Needs a plan with STN_OUT_DIAG or STN_OUT_RHO and at least one reduced
+ * batch (STN_E_STATE otherwise); m = 0 does nothing.  Enqueued on stream,
+ * after the stn_reduce calls enqueued there before it; does not sync. */
+stn_status stn_accum_sample(stn_accum* acc, const double* u, uint32_t m, uint32_t* out, void* stream);
+
 /* ---------------------------------------------------------------- job server
  * Many ensemble jobs (Sec. III-G, each one circuit + noise model + K) of
  * different sizes on one device at once.  Planner threads plan submitted

@@ -147,6 +147,7 @@ EXPORTS = {
     "stn_reduce": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "stn_accum_read": (C.c_int, [C.c_void_p, C.POINTER(Result), C.c_void_p]),
     "stn_accum_destroy": (None, [C.c_void_p]),
+    "stn_accum_sample": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
     "stn_server_opts_default": (None, [C.POINTER(ServerOpts)]),
     "stn_server_create": (C.c_int, [C.POINTER(ServerOpts), C.POINTER(C.c_void_p)]),
     "stn_server_submit": (C.c_int, [C.c_void_p, C.POINTER(Circuit), C.POINTER(NoiseModel), C.POINTER(Observable),
@@ -428,6 +429,21 @@ class Accum:
         if r.rho:
             out["rho"] = np.ctypeslib.as_array(r.rho, shape=(N * N * 2,)).copy().view(np.complex128).reshape(N, N)
         return out
+
+    def sample(self, u, out=None, stream=None):
+        """Bitstrings drawn from sigma_approx with the uniforms u (a float64
+        device tensor); returns an int32 device tensor of basis indices."""
+        import torch
+        if not (u.is_cuda and u.dtype == torch.float64 and u.is_contiguous()):
+            raise ValueError("u must be a contiguous float64 device tensor")
+        m = u.numel()
+        if out is None:
+            out = torch.empty(m, dtype=torch.int32, device=u.device)
+        if out.numel() < m or out.dtype != torch.int32 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int32 device tensor of at least u.numel() elements")
+        _check(self.plan.lib.stn_accum_sample(self.h, u.data_ptr(), m, out.data_ptr(),
+                                              stream if stream is not None else current_stream()))
+        return out[:m]
 
     def close(self):
         if getattr(self, "h", None):

@@ -721,4 +721,19 @@ void stn_accum_destroy(stn_accum* a) {
     delete a;
 }
 
+stn_status stn_accum_sample(stn_accum* a, const double* u, uint32_t m, uint32_t* out, void* stream) {
+    if (!a) return set_error(STN_E_INVALID, "NULL argument");
+    if (m && (!u || !out)) return set_error(STN_E_INVALID, "NULL uniforms or output");
+    stn_plan* p = a->plan;
+    if (!(p->opts.outputs & (STN_OUT_DIAG | STN_OUT_RHO)))
+        return set_error(STN_E_STATE, "accumulator keeps no diagonal (request STN_OUT_DIAG)");
+    if (!a->k_done) return set_error(STN_E_STATE, "no trajectories reduced");
+    if (p->n > 13) return set_error(STN_E_INVALID, "diagonal larger than the sampler's 64 KiB of LDS");
+    if (!m) return STN_OK;
+    return guarded([&] {
+        a->d_cdf.ensure(&p->alloc, ((size_t)1 << p->n) * 8);
+        launch_sample_bits(a, u, m, out, (hipStream_t)stream);
+    });
+}
+
 }  // extern "C"

@@ -17,6 +17,14 @@
 //             passes (mean, then squared deviations).
 // k_finish_*: mirror the upper triangle (rho_ji = conj(rho_ij), real
 //             diagonal) and scale by 1/K into output buffers.
+// k_cdf, k_sample_bits: bitstrings drawn from sigma by inverse transform.
+//             One workgroup forms the running sums F of the accumulated
+//             diagonal (each thread sums a contiguous run, the 256 run totals
+//             are offset in thread order); each sampling workgroup stages F in
+//             LDS (at most 64 KiB) and each lane binary-searches the smallest
+//             x with F(x) > u F(last), or, when rounding leaves none, the
+//             smallest x with F(x) >= u F(last).  Every index returned is in
+//             range whatever u holds.
 #include "stn_internal.h"
 
 namespace stn {
@@ -196,7 +204,67 @@ __global__ __launch_bounds__(256) void k_finish_diag(const double* __restrict__ 
     if (threadIdx.x == 0) *trace = tr;
 }
 
+__global__ __launch_bounds__(256) void k_cdf(const double* __restrict__ diag, uint32_t N, double* __restrict__ cdf) {
+    __shared__ double off[256];
+    const uint32_t per = (N + 255) / 256;
+    const uint32_t a = min(N, threadIdx.x * per), b = min(N, a + per);
+    double s = 0.0;
+    for (uint32_t i = a; i < b; ++i) s += diag[i];
+    off[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = 0.0;
+        for (int t = 0; t < 256; ++t) {
+            const double v = off[t];
+            off[t] = r;
+            r += v;
+        }
+    }
+    __syncthreads();
+    double r = off[threadIdx.x];
+    for (uint32_t i = a; i < b; ++i) {
+        r += diag[i];
+        cdf[i] = r;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sample_bits(const double* __restrict__ cdf, uint32_t N,
+                                                     const double* __restrict__ u, uint32_t m,
+                                                     uint32_t* __restrict__ out) {
+    extern __shared__ double F[];
+    for (uint32_t i = threadIdx.x; i < N; i += 256) F[i] = cdf[i];
+    __syncthreads();
+    const double total = F[N - 1];
+    for (uint32_t j = blockIdx.x * 256 + threadIdx.x; j < m; j += gridDim.x * 256) {
+        const double t = u[j] * total;
+        uint32_t lo = 0, hi = N;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (F[mid] > t) hi = mid; else lo = mid + 1;
+        }
+        if (lo == N) {
+            lo = 0;
+            hi = N - 1;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (F[mid] >= t) hi = mid; else lo = mid + 1;
+            }
+        }
+        out[j] = lo;
+    }
+}
+
 }  // namespace
+
+void launch_sample_bits(stn_accum* a, const double* u, uint32_t m, uint32_t* out, hipStream_t s) {
+    const uint32_t N = 1u << a->plan->n;
+    hipLaunchKernelGGL(k_cdf, dim3(1), dim3(256), 0, s, a->d_diag.as<double>(), N, a->d_cdf.as<double>());
+    STN_HIP(hipGetLastError());
+    const uint32_t blocks = std::min<uint32_t>((m + 255) / 256, 512);
+    hipLaunchKernelGGL(k_sample_bits, dim3(blocks), dim3(256), N * sizeof(double), s, a->d_cdf.as<double>(), N, u,
+                       m, out);
+    STN_HIP(hipGetLastError());
+}
 
 void launch_reduce(stn_plan* p, stn_batch* b, stn_accum* a, hipStream_t s) {
     const uint32_t N = 1u << p->n;

@@ -244,6 +244,7 @@ struct stn_accum {
     stn::DevBuf d_diag_out;          // double [2^n]: scaled by 1/K
     stn::DevBuf d_stats;             // double [4]: energy mean, SE, trace
     stn::DevBuf d_egather;           // double [k_done]: energies in trajectory order
+    stn::DevBuf d_cdf;               // double [2^n]: running sums of d_diag (bitstring sampling)
     std::vector<double> h_rho, h_diag, h_energies;
 };
 
@@ -304,6 +305,8 @@ void launch_energy_stats(stn_accum* a, uint64_t K, hipStream_t s);
 void launch_scatter_energy(const double* src, const uint32_t* map, uint32_t K, double* dst, hipStream_t s);
 // rho_out = mirror(rho)/K, diag_out = diag/K, stats[2] = trace
 void launch_finish_dense(stn_accum* a, hipStream_t s);
+// m bitstrings drawn from the accumulated diagonal with the uniforms u (device arrays)
+void launch_sample_bits(stn_accum* a, const double* u, uint32_t m, uint32_t* out, hipStream_t s);
 void launch_lightcone(stn_plan* p, stn_batch* b, hipStream_t s);
 // lightcone lowering (kernels_tn.hip): networks of every observable term
 void build_lightcone(stn_plan* p);

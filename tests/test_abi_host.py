@@ -155,6 +155,14 @@ def test_new_entry_points_validate_arguments():
     assert pl.info()["graphs"] == 1
     assert lib.stn_plan_set_graphs(pl.h, 0) == 0
     assert pl.info()["graphs"] == 0 and pl.info()["graph_captures"] == 0
+    # bitstring sampling: NULL accumulator, then an energy-only accumulator (no diagonal kept)
+    assert lib.stn_accum_sample(None, None, 0, None, None) == INVALID
+    from paper_2210_15874_amd import OUT_ENERGY
+    pe = plan(config_problem(0), outputs=OUT_ENERGY)
+    acc = pe.accum()
+    assert lib.stn_accum_sample(acc.h, None, 4, None, None) == INVALID
+    assert lib.stn_accum_sample(acc.h, None, 0, None, None) == 5    # STN_E_STATE
+    acc.close()
 
 
 def test_lightcone_slicing_plans():

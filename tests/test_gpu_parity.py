@@ -614,3 +614,69 @@ def test_lightcone_hbm_tier_against_statevector(n, seed, precision, tol):
         pl.close()
     m = len(pr.edges)
     np.testing.assert_allclose(res[stn.PLAN_LIGHTCONE] / m, res[stn.PLAN_SV_TILED] / m, atol=tol)
+
+
+# ----------------------------------------------------------------------------- bitstrings from sigma_approx
+
+@pytest.mark.parametrize("cfg,precision,dense", [(0, 128, "diag"), (1, 64, "rho")])
+def test_bitstring_sampling_matches_oracle(cfg, precision, dense):
+    """Bitstrings drawn from sigma_approx (Sec. III-G) by inverse transform,
+    against the oracle's draws from its own sigma_approx with the same
+    uniforms: equal index for index wherever u lies farther than the two
+    sides' cumulative-sum difference from a boundary of the oracle's interval,
+    and inside the widened interval otherwise.  Two reduced batches, 300001
+    draws (more than one grid-stride round, a ragged tail), the end points of
+    [0, 1), then m = 0 and m = 1."""
+    import torch
+    from oracle import simulate as sim
+    from oracle.sampling import sample_bitstrings
+    from workloads import config_problem
+    stn = stn_mod()
+    pr = config_problem(cfg)
+    outs = (stn.OUT_DIAG | stn.OUT_ENERGY) if dense == "diag" else (stn.OUT_RHO | stn.OUT_DIAG)
+    pl = stn.Plan(pr, outputs=outs, precision=precision)
+    acc = pl.accum()
+    half = pr.K // 2
+    for k0, K in ((0, half), (half, pr.K - half)):
+        b = pl.sample(pr.seed, k0, K)
+        pl.contract(b)
+        pl.reduce(b, acc)
+        b.close()
+    rng = np.random.default_rng(4100 + cfg)
+    m = 300001
+    u = rng.random(m)
+    u[:4] = [0.0, np.nextafter(1.0, 0.0), 0.5, 1e-300]
+    x = acc.sample(torch.from_numpy(u).cuda()).cpu().numpy().astype(np.int64)
+    torch.cuda.synchronize()
+    res = acc.read()
+    ens = sim.ensemble(pr, pr.seed, 0, pr.K)
+    sigma = ens["sigma_approx"]
+    tol = 1e-12 if precision == 128 else 1e-5
+    assert np.abs(res["diag"] - sigma).max() < tol
+    xo = sample_bitstrings(sigma, u)
+    N = 1 << pr.n_qubits
+    assert x.min() >= 0 and x.max() < N
+    Fo = np.cumsum(sigma) / sigma.sum()
+    Fg = np.cumsum(res["diag"]) / res["diag"].sum()
+    delta = 2 * np.abs(Fg - Fo).max() + 1e-15
+    lo = np.where(xo > 0, Fo[np.maximum(xo - 1, 0)], 0.0)
+    hi = Fo[xo]
+    near = (np.abs(u - lo) < delta) | (np.abs(u - hi) < delta)
+    assert (x[~near] == xo[~near]).all()
+    xn = x[near]
+    xl = np.where(xn > 0, Fo[np.maximum(xn - 1, 0)], 0.0)
+    assert ((xl - delta <= u[near]) & (u[near] < Fo[xn] + delta)).all()
+    assert near.mean() < 0.05
+    # sample frequencies follow sigma_approx (chi-square over bins of expected count >= 20)
+    p = sigma / sigma.sum()
+    counts = np.bincount(x, minlength=N)
+    big = p * m >= 20
+    chi2 = float(((counts[big] - m * p[big]) ** 2 / (m * p[big])).sum())
+    dof = int(big.sum())
+    assert chi2 < dof + 6 * math.sqrt(2 * dof)
+    # degenerate sizes
+    empty = acc.sample(torch.empty(0, dtype=torch.float64, device="cuda"))
+    assert empty.numel() == 0
+    one = acc.sample(torch.tensor([0.5], dtype=torch.float64, device="cuda")).cpu().numpy()
+    assert one[0] == x[2]
+    acc.close()
