@@ -228,6 +228,17 @@ __global__ __launch_bounds__(256) void k_cdf(const double* __restrict__ diag, ui
     }
 }
 
+// Smallest x with F[x] > t over N = 2^n sums (N when none): the count of sums
+// <= t, found by binary lifting (n dependent LDS reads, no divergence).
+__device__ __forceinline__ uint32_t count_le(const double* F, uint32_t N, double t) {
+    uint32_t pos = 0;
+    for (uint32_t bit = N >> 1; bit; bit >>= 1)
+        if (F[pos + bit - 1] <= t) pos += bit;
+    return F[pos] <= t ? N : pos;
+}
+
+constexpr uint32_t kDrawsPerLane = 4;
+
 __global__ __launch_bounds__(256) void k_sample_bits(const double* __restrict__ cdf, uint32_t N,
                                                      const double* __restrict__ u, uint32_t m,
                                                      uint32_t* __restrict__ out) {
@@ -235,22 +246,28 @@ __global__ __launch_bounds__(256) void k_sample_bits(const double* __restrict__ 
     for (uint32_t i = threadIdx.x; i < N; i += 256) F[i] = cdf[i];
     __syncthreads();
     const double total = F[N - 1];
-    for (uint32_t j = blockIdx.x * 256 + threadIdx.x; j < m; j += gridDim.x * 256) {
-        const double t = u[j] * total;
-        uint32_t lo = 0, hi = N;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (F[mid] > t) hi = mid; else lo = mid + 1;
+    const uint32_t span = 256 * kDrawsPerLane;
+    for (uint64_t j0 = (uint64_t)blockIdx.x * span + threadIdx.x; j0 < m; j0 += (uint64_t)gridDim.x * span) {
+        double t[kDrawsPerLane];
+#pragma unroll
+        for (uint32_t r = 0; r < kDrawsPerLane; ++r) {
+            const uint64_t j = j0 + r * 256;
+            t[r] = j < m ? u[j] * total : 0.0;
         }
-        if (lo == N) {
-            lo = 0;
-            hi = N - 1;
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (F[mid] >= t) hi = mid; else lo = mid + 1;
+#pragma unroll
+        for (uint32_t r = 0; r < kDrawsPerLane; ++r) {
+            const uint64_t j = j0 + r * 256;
+            uint32_t x = count_le(F, N, t[r]);
+            if (x == N) {  // u F(last) rounded up to F(last): the smallest x with F[x] >= t
+                uint32_t lo = 0, hi = N - 1;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (F[mid] >= t[r]) hi = mid; else lo = mid + 1;
+                }
+                x = lo;
             }
+            if (j < m) out[j] = x;
         }
-        out[j] = lo;
     }
 }
 
@@ -260,7 +277,7 @@ void launch_sample_bits(stn_accum* a, const double* u, uint32_t m, uint32_t* out
     const uint32_t N = 1u << a->plan->n;
     hipLaunchKernelGGL(k_cdf, dim3(1), dim3(256), 0, s, a->d_diag.as<double>(), N, a->d_cdf.as<double>());
     STN_HIP(hipGetLastError());
-    const uint32_t blocks = std::min<uint32_t>((m + 255) / 256, 512);
+    const uint32_t blocks = std::min<uint32_t>((m + 256 * kDrawsPerLane - 1) / (256 * kDrawsPerLane), 1024);
     hipLaunchKernelGGL(k_sample_bits, dim3(blocks), dim3(256), N * sizeof(double), s, a->d_cdf.as<double>(), N, u,
                        m, out);
     STN_HIP(hipGetLastError());
