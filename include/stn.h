@@ -135,6 +135,24 @@ typedef enum {
 typedef void* (*stn_alloc_fn)(size_t bytes, void* ctx);
 typedef void (*stn_free_fn)(void* ptr, void* ctx);
 
+/* The doubled network <0|U^dagger Z_u Z_v U|0> of one observable term, as a
+ * lightcone plan builds it (Sec. III-A: tensors over binary variables).  The
+ * arrays belong to the library and are valid during the callback only. */
+typedef struct {
+    uint32_t term;                  /* observable term index */
+    uint32_t u, v;                  /* its qubits */
+    uint32_t n_vars;                /* variables 0 .. n_vars-1 */
+    uint32_t n_tensors;
+    const uint32_t* tensor_offsets; /* n_tensors + 1 entries */
+    const uint32_t* tensor_vars;    /* variables of tensor t: [tensor_offsets[t], tensor_offsets[t+1]) */
+} stn_term_network;
+
+/* Caller-supplied contraction order (Sec. III-A/B: bucket elimination sums the
+ * variables out in a given order, whose quality sets the width).  Fills
+ * order[0 .. n_vars) with a permutation of the network's variables, first
+ * eliminated first, and returns 0; a nonzero return rejects the plan. */
+typedef int (*stn_order_fn)(const stn_term_network* net, uint32_t* order, void* ctx);
+
 typedef struct {
     uint32_t precision;     /* 64: complex64 contraction (FP32 arithmetic); 128: complex128 */
     uint32_t outputs;       /* STN_OUT_* bits */
@@ -151,6 +169,13 @@ typedef struct {
     uint32_t lc_slice_bits; /* lightcone plans: a network needing larger steps is sliced (Sec. III-C:
                                up to this many variables fixed to each value, the 2^bits results
                                summed); 0 = no slicing, at most 16 */
+    stn_order_fn lc_order_fn; /* lightcone plans: NULL = min-fill (order_restarts, order_seed); else
+                               called once per term, in term order, on the thread that calls
+                               stn_plan_create, whenever lightcone networks are built (an AUTO plan
+                               builds them to compare costs).  Not a permutation, or a nonzero
+                               return: STN_E_INVALID.  Steps above lc_max_rank: STN_E_UNSUPPORTED
+                               (an AUTO plan then takes another lowering).  Needs lc_slice_bits = 0 */
+    void* lc_order_ctx;     /* passed to lc_order_fn */
 } stn_plan_opts;
 
 typedef struct {

@@ -59,11 +59,40 @@ ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
+class TermNetwork(C.Structure):
+    _fields_ = [("term", C.c_uint32), ("u", C.c_uint32), ("v", C.c_uint32), ("n_vars", C.c_uint32),
+                ("n_tensors", C.c_uint32), ("tensor_offsets", C.POINTER(C.c_uint32)),
+                ("tensor_vars", C.POINTER(C.c_uint32))]
+
+
+ORDER_FN = C.CFUNCTYPE(C.c_int, C.POINTER(TermNetwork), C.POINTER(C.c_uint32), C.c_void_p)
+
+
+def _order_callback(fn):
+    """Wraps fn(net) -> sequence of variables (net: dict with term, u, v,
+    n_vars, tensors = list of variable lists) as an stn_order_fn."""
+    def cb(netp, order, _ctx):
+        try:
+            net = netp.contents
+            off = [net.tensor_offsets[i] for i in range(net.n_tensors + 1)]
+            tensors = [[net.tensor_vars[j] for j in range(off[t], off[t + 1])] for t in range(net.n_tensors)]
+            got = list(fn({"term": net.term, "u": net.u, "v": net.v, "n_vars": net.n_vars, "tensors": tensors}))
+            if len(got) != net.n_vars:
+                return 1
+            for i, x in enumerate(got):
+                order[i] = int(x)
+            return 0
+        except Exception:
+            return 1
+    return ORDER_FN(cb)
+
+
 class PlanOpts(C.Structure):
     _fields_ = [("precision", C.c_uint32), ("outputs", C.c_uint32), ("plan_kind", C.c_uint32),
                 ("max_batch", C.c_uint32), ("hbm_budget", C.c_uint64), ("order_restarts", C.c_uint32),
                 ("order_seed", C.c_uint64), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
-                ("alloc_ctx", C.c_void_p), ("lc_max_rank", C.c_uint32), ("lc_slice_bits", C.c_uint32)]
+                ("alloc_ctx", C.c_void_p), ("lc_max_rank", C.c_uint32), ("lc_slice_bits", C.c_uint32),
+                ("lc_order_fn", ORDER_FN), ("lc_order_ctx", C.c_void_p)]
 
 
 class PlanStats(C.Structure):
@@ -252,7 +281,7 @@ class Plan:
     """stn_plan_create for a workloads.Problem."""
 
     def __init__(self, problem, outputs=OUT_ENERGY, precision=64, plan_kind=PLAN_AUTO, max_batch=0,
-                 hbm_budget=0, torch_allocator=True, device=0, lc_max_rank=0, lc_slice_bits=0):
+                 hbm_budget=0, torch_allocator=True, device=0, lc_max_rank=0, lc_slice_bits=0, lc_order=None):
         self.lib = load()
         self.problem = problem
         self.n = problem.n_qubits
@@ -268,6 +297,10 @@ class Plan:
         opts.hbm_budget = hbm_budget
         opts.lc_max_rank = lc_max_rank
         opts.lc_slice_bits = lc_slice_bits
+        self._order_cb = None
+        if lc_order is not None:
+            self._order_cb = _order_callback(lc_order)
+            opts.lc_order_fn = self._order_cb
         self._alloc = None
         if torch_allocator:
             self._alloc = _TorchAllocator(device)

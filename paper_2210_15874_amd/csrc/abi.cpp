@@ -205,6 +205,8 @@ stn_status stn_plan_create(const stn_circuit* circuit, const stn_noise_model* no
         if (p->opts.precision != 64 && p->opts.precision != 128) fail(STN_E_INVALID, "precision must be 64 or 128");
         if ((p->opts.dev_alloc == nullptr) != (p->opts.dev_free == nullptr))
             fail(STN_E_INVALID, "dev_alloc and dev_free must be given together");
+        if (p->opts.lc_order_fn && p->opts.lc_slice_bits)
+            fail(STN_E_INVALID, "a caller-supplied contraction order excludes slicing (lc_slice_bits must be 0)");
         p->alloc.fn = p->opts.dev_alloc;
         p->alloc.ffn = p->opts.dev_free;
         p->alloc.ctx = p->opts.alloc_ctx;

@@ -275,8 +275,8 @@ void build_lightcone(stn_plan* p) {
     const int rank_cap = p->opts.lc_max_rank ? std::min<int>((int)p->opts.lc_max_rank, kMaxPos - 1) : kMaxPos - 1;
     const int slice_cap = (int)std::min<uint32_t>(p->opts.lc_slice_bits, kMaxSliceBits);
     for (size_t t = 0; t < p->obs_u.size(); ++t) {
-        d->nets.push_back(build_term(p, p->obs_u[t], p->obs_v[t], p->opts.order_restarts, p->opts.order_seed,
-                                     rank_cap, slice_cap));
+        d->nets.push_back(build_term(p, (uint32_t)t, p->obs_u[t], p->obs_v[t], p->opts.order_restarts,
+                                     p->opts.order_seed, rank_cap, slice_cap));
         const TnNetwork& net = d->nets.back();
         if (net.steps.empty() && !std::isfinite(net.cost)) {
             max_rank = std::max(max_rank, net.width);   // stopped early: too wide for this lowering

@@ -222,12 +222,59 @@ Lowered lower(const std::vector<Tensor>& base, int nv, const std::vector<int>& o
     return L;
 }
 
+// The caller's order for one term's network: validated as a permutation of
+// the variables, checked against max_rank, then lowered unsliced.
+TnNetwork lower_caller_order(const stn_plan* p, uint32_t term, const std::vector<Tensor>& ts, int nv, int max_rank,
+                             TnNetwork net) {
+    std::vector<uint32_t> offsets(1, 0), vars;
+    std::vector<std::vector<int>> tv;
+    for (auto& t : ts) {
+        for (int x : t.vars) vars.push_back((uint32_t)x);
+        offsets.push_back((uint32_t)vars.size());
+        tv.push_back(t.vars);
+    }
+    stn_term_network desc;
+    desc.term = term;
+    desc.u = net.u;
+    desc.v = net.v;
+    desc.n_vars = (uint32_t)nv;
+    desc.n_tensors = (uint32_t)ts.size();
+    desc.tensor_offsets = offsets.data();
+    desc.tensor_vars = vars.data();
+    std::vector<uint32_t> got((size_t)nv, 0);
+    if (p->opts.lc_order_fn(&desc, got.data(), p->opts.lc_order_ctx) != 0)
+        fail(STN_E_INVALID, "contraction order rejected by the caller for term " + std::to_string(term));
+    std::vector<char> seen((size_t)nv, 0);
+    std::vector<int> order;
+    for (uint32_t x : got) {
+        if (x >= (uint32_t)nv || seen[x])
+            fail(STN_E_INVALID, "contraction order of term " + std::to_string(term) + " is not a permutation of its " +
+                                    std::to_string(nv) + " variables");
+        seen[x] = 1;
+        order.push_back((int)x);
+    }
+    int widest = 0;
+    for (auto& st : step_sets(tv, order)) widest = std::max(widest, (int)st.size());
+    if (widest > max_rank + 1) {
+        net.width = widest;
+        net.cost = HUGE_VAL;
+        return net;
+    }
+    Lowered L = lower(ts, nv, order, {});
+    net.steps = std::move(L.steps);
+    net.width = L.width;
+    net.cost = L.cost;
+    net.arena = L.arena;
+    net.result = L.result;
+    return net;
+}
+
 }  // namespace
 
 // Network of one term: lightcone gates on the ket, the observable, the
 // conjugate gates on the bra, |0> at both ends of every chain.
-TnNetwork build_term(const stn_plan* p, uint32_t u, uint32_t v, uint32_t restarts, uint64_t seed, int max_rank,
-                     int slice_bits) {
+TnNetwork build_term(const stn_plan* p, uint32_t term, uint32_t u, uint32_t v, uint32_t restarts, uint64_t seed,
+                     int max_rank, int slice_bits) {
     const uint32_t n = p->n;
     // backward lightcone of {u, v}
     std::vector<char> in_cone(p->gates.size(), 0);
@@ -339,6 +386,7 @@ TnNetwork build_term(const stn_plan* p, uint32_t u, uint32_t v, uint32_t restart
     net.u = u;
     net.v = v;
     net.n_vars = nv;
+    if (p->opts.lc_order_fn) return lower_caller_order(p, term, ts, nv, max_rank, net);
     Lowered best;
     bool have = false;
     std::vector<int> sliced;   // slice index bit k fixes variable sliced[k]

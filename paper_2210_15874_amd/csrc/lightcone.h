@@ -44,8 +44,10 @@ struct TnNetwork {
 // Networks whose elimination order would need a step of rank above max_rank
 // are sliced (Sec. III-C: variables fixed to each of their values, the
 // results summed) by up to slice_bits variables; those still too wide come
-// back without steps, width = a lower bound, cost = infinity.
-TnNetwork build_term(const stn_plan* p, uint32_t u, uint32_t v, uint32_t restarts, uint64_t seed, int max_rank,
-                     int slice_bits);
+// back without steps, width = a lower bound, cost = infinity.  With a
+// caller-supplied order (opts.lc_order_fn) that order is lowered instead of
+// min-fill, unsliced; a network it leaves too wide comes back the same way.
+TnNetwork build_term(const stn_plan* p, uint32_t term, uint32_t u, uint32_t v, uint32_t restarts, uint64_t seed,
+                     int max_rank, int slice_bits);
 
 }  // namespace stn

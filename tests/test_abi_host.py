@@ -183,6 +183,70 @@ def test_lightcone_slicing_plans():
         plan(pr, plan_kind=PLAN_LIGHTCONE, lc_max_rank=12)
 
 
+def min_degree_order(net):
+    """A plain greedy minimum-degree elimination order, written here so that
+    the caller-order tests do not depend on the library's min-fill."""
+    nv = net["n_vars"]
+    adj = [set() for _ in range(nv)]
+    for t in net["tensors"]:
+        for a in t:
+            adj[a].update(b for b in t if b != a)
+    done, order = [False] * nv, []
+    for _ in range(nv):
+        v = min((x for x in range(nv) if not done[x]), key=lambda x: (len(adj[x]), x))
+        order.append(v)
+        done[v] = True
+        nb = list(adj[v])
+        for a in nb:
+            adj[a].discard(v)
+            adj[a].update(y for y in nb if y != a)
+        adj[v] = set()
+    return order
+
+
+def test_caller_contraction_order():
+    """A caller-supplied elimination order (Sec. III-A/B) replaces min-fill:
+    called once per term with that term's network, lowered as given (here one
+    that beats min-fill's width); orders that are not permutations, rejected
+    orders and orders with slicing are INVALID; an order too wide for the
+    rank cap is UNSUPPORTED, and an AUTO plan then takes the statevector."""
+    from workloads import make_problem, random_regular_graph, uniform_angles
+    from paper_2210_15874_amd import PLAN_LIGHTCONE, StnError
+    g, b = uniform_angles(1, 5)
+    pr = make_problem(40, random_regular_graph(40, 3, 4), g, b, 1e-3, 1e-2, 16, 6)
+    seen = []
+
+    def record(net):
+        seen.append(net)
+        return min_degree_order(net)
+    i = plan(pr, plan_kind=PLAN_LIGHTCONE, lc_order=record).info()
+    assert i["plan_name"] == "lightcone" and i["width"] <= 8
+    assert [(d["term"], d["u"], d["v"]) for d in seen] == [(t, u, v) for t, (u, v) in enumerate(pr.edges)]
+    for d in seen:
+        used = sorted({x for t in d["tensors"] for x in t})
+        assert used == list(range(d["n_vars"]))
+    # n=14, p=3: reversing the variable numbering gives width 15 where min-fill gives 20
+    g, b = uniform_angles(3, 904)
+    pr3 = make_problem(14, random_regular_graph(14, 3, 903), g, b, 5e-3, 2e-2, 6, 905)
+    base = plan(pr3, plan_kind=PLAN_LIGHTCONE).info()["width"]
+    rev = plan(pr3, plan_kind=PLAN_LIGHTCONE, lc_order=lambda net: range(net["n_vars"] - 1, -1, -1)).info()
+    assert rev["width"] < base
+    for bad in (lambda net: [0] * net["n_vars"],                 # not a permutation
+                lambda net: list(range(net["n_vars"] - 1)),       # too short (the callback rejects)
+                lambda net: 1 / 0):                               # raises (the callback rejects)
+        with pytest.raises(StnError, match="INVALID"):
+            plan(pr3, plan_kind=PLAN_LIGHTCONE, lc_order=bad)
+    with pytest.raises(StnError, match="INVALID"):
+        plan(pr3, plan_kind=PLAN_LIGHTCONE, lc_order=min_degree_order, lc_slice_bits=4)
+    # the numbering order needs steps above the rank cap at n=20, p=2
+    g, b = uniform_angles(2, 5)
+    pr2 = make_problem(20, random_regular_graph(20, 3, 11), g, b, 1e-3, 1e-2, 16, 6)
+    natural = lambda net: range(net["n_vars"])
+    with pytest.raises(StnError, match="UNSUPPORTED"):
+        plan(pr2, plan_kind=PLAN_LIGHTCONE, lc_order=natural)
+    assert plan(pr2, lc_order=natural).info()["plan_name"] == "sv_tiled"
+
+
 def test_server_needs_a_device_and_valid_options():
     from paper_2210_15874_amd import Server, StnError
     with pytest.raises(StnError, match="INVALID"):

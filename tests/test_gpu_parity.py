@@ -680,3 +680,39 @@ def test_bitstring_sampling_matches_oracle(cfg, precision, dense):
     one = acc.sample(torch.tensor([0.5], dtype=torch.float64, device="cuda")).cpu().numpy()
     assert one[0] == x[2]
     acc.close()
+
+
+# ----------------------------------------------------------------------------- caller-supplied contraction order
+
+@pytest.mark.parametrize("precision,tol", [(128, 1e-11), (64, 1e-5)])
+def test_caller_contraction_order_same_energies(precision, tol):
+    """Lightcone networks contracted in caller-supplied orders (Sec. III-A/B:
+    the order changes the cost, not the value): n=14 p=3 in the reversed
+    variable numbering (width 15, below min-fill's 20, intermediates in HBM)
+    against the full-statevector oracle, and n=20 p=2 in a minimum-degree
+    order against the min-fill plan, same draws."""
+    from oracle import simulate as sim
+    from test_abi_host import min_degree_order
+    from workloads import make_problem, random_regular_graph, uniform_angles
+    stn = stn_mod()
+    g, b = uniform_angles(3, 904)
+    pr = make_problem(14, random_regular_graph(14, 3, 903), g, b, 5e-3, 2e-2, 6, 905)
+    pl = stn.Plan(pr, plan_kind=stn.PLAN_LIGHTCONE, precision=precision,
+                  lc_order=lambda net: range(net["n_vars"] - 1, -1, -1))
+    assert pl.info()["width"] == 15
+    bt = pl.sample(pr.seed, 0, pr.K)
+    pl.contract(bt)
+    got = bt.energies()
+    ens = sim.ensemble(pr, pr.seed, 0, pr.K, want_states=False)
+    m = len(pr.edges)
+    np.testing.assert_allclose(got / m, ens["energies"] / m, atol=tol)
+    g, b = uniform_angles(2, 5)
+    pr2 = make_problem(20, random_regular_graph(20, 3, 11), g, b, 1e-3, 1e-2, 48, 6)
+    res = []
+    for order in (None, min_degree_order):
+        pl2 = stn.Plan(pr2, plan_kind=stn.PLAN_LIGHTCONE, precision=precision, lc_order=order)
+        bt = pl2.sample(pr2.seed, 0, pr2.K)
+        pl2.contract(bt)
+        res.append(bt.energies())
+    m2 = len(pr2.edges)
+    np.testing.assert_allclose(res[1] / m2, res[0] / m2, atol=tol)
