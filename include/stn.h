@@ -129,7 +129,9 @@ typedef enum {
     STN_PLAN_SV_LDS = 1,    /* whole trajectory state in LDS, any circuit, n <= 13 (c64) / 12 (c128) */
     STN_PLAN_SV_TILED = 2,  /* HBM statevector, LDS/register-tiled passes, QAOA-structured
                                circuits with Pauli noise, energy only */
-    STN_PLAN_LIGHTCONE = 3  /* per-term lightcone tensor networks, energy only */
+    STN_PLAN_LIGHTCONE = 3, /* per-term lightcone tensor networks, energy only */
+    STN_PLAN_SV_GATES = 4   /* HBM statevector, one pass per gate or noise site: any circuit and any
+                               channel (non-unitary ones included), 2 <= n <= 30, energy only */
 } stn_plan_kind;
 
 typedef void* (*stn_alloc_fn)(size_t bytes, void* ctx);
@@ -291,7 +293,7 @@ enum {
     STN_K_SAMPLE = 0,       /* Philox selection of every (trajectory, site) */
     STN_K_FRAME = 1,        /* Pauli-frame scan */
     STN_K_SV_LDS = 2,       /* whole-state-in-LDS contraction */
-    STN_K_SV_PASS = 3,      /* tiled statevector pass */
+    STN_K_SV_PASS = 3,      /* HBM statevector passes (tiled, or gate by gate) */
     STN_K_TILE_SUM = 4,     /* per-trajectory energy from tile partials */
     STN_K_HERK = 5,         /* FP64 rho_hat accumulation */
     STN_K_DIAG = 6,         /* FP64 sigma accumulation */

@@ -21,8 +21,8 @@ GATE_KIND = {"h": 0, "x": 1, "y": 2, "z": 3, "rx": 4, "ry": 5, "rz": 6, "zz": 7,
 CHANNEL_KIND = {"bitflip": 0, "depol1": 1, "depol2": 2, "ampdamp": 3, "kraus": 4}
 
 OUT_RHO, OUT_DIAG, OUT_ENERGY, OUT_STATES = 1, 2, 4, 8
-PLAN_AUTO, PLAN_SV_LDS, PLAN_SV_TILED, PLAN_LIGHTCONE = 0, 1, 2, 3
-PLAN_NAMES = {0: "auto", 1: "sv_lds", 2: "sv_tiled", 3: "lightcone"}
+PLAN_AUTO, PLAN_SV_LDS, PLAN_SV_TILED, PLAN_LIGHTCONE, PLAN_SV_GATES = 0, 1, 2, 3, 4
+PLAN_NAMES = {0: "auto", 1: "sv_lds", 2: "sv_tiled", 3: "lightcone", 4: "sv_gates"}
 STATUS = {0: "OK", 1: "INVALID", 2: "UNSUPPORTED", 3: "OOM", 4: "DEVICE", 5: "STATE"}
 
 

@@ -31,6 +31,7 @@ SOURCES = {
     "tables.cpp": "host",
     "kernels_sample.hip": "device",
     "kernels_sv_lds.hip": "device",
+    "kernels_sv_gates.hip": "device",
     "kernels_sv_tiled.hip": "device",
     "kernels_sv_tiled128.hip": "device",
     "kernels_reduce.hip": "device",

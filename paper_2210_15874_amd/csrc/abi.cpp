@@ -170,7 +170,7 @@ void batch_prepare(stn_plan* p, stn_batch* b, uint64_t k0, uint32_t K) {
     b->contracted = false;
     b->words = (uint32_t)((p->gates.size() + 31) / 32);
     b->d_idx.ensure(&p->alloc, (size_t)K * S);
-    if (p->kind != STN_PLAN_SV_LDS) {
+    if (p->kind != STN_PLAN_SV_LDS && p->kind != STN_PLAN_SV_GATES) {
         b->d_signs.ensure(&p->alloc, (size_t)K * std::max<uint32_t>(b->words, 1) * 4);
         b->d_frame.ensure(&p->alloc, (size_t)K * 16);
     }
@@ -298,7 +298,7 @@ stn_status stn_sample(stn_plan* p, uint64_t seed, uint64_t k0, uint32_t K, stn_b
         hipStream_t s = (hipStream_t)stream;
         ensure_uploaded(p, s);
         launch_sample(p, b, seed, s);
-        if (p->kind != STN_PLAN_SV_LDS) launch_frame(p, b, s);
+        if (p->kind != STN_PLAN_SV_LDS && p->kind != STN_PLAN_SV_GATES) launch_frame(p, b, s);
     });
     if (st != STN_OK) {
         delete b;
@@ -318,7 +318,7 @@ stn_status stn_resample(stn_batch* b, uint64_t seed, uint64_t k0, uint32_t K, vo
         hipStream_t s = (hipStream_t)stream;
         ensure_uploaded(p, s);
         launch_sample(p, b, seed, s);
-        if (p->kind != STN_PLAN_SV_LDS) launch_frame(p, b, s);
+        if (p->kind != STN_PLAN_SV_LDS && p->kind != STN_PLAN_SV_GATES) launch_frame(p, b, s);
     });
 }
 
@@ -340,7 +340,7 @@ stn_status stn_batch_from_indices(stn_plan* p, const uint8_t* idx, uint64_t k0, 
         b = new stn_batch();
         batch_prepare(p, b, k0, K);
         if (S) STN_HIP(hipMemcpyAsync(b->d_idx.p, idx, (size_t)K * S, hipMemcpyHostToDevice, s));
-        if (p->kind != STN_PLAN_SV_LDS) launch_frame(p, b, s);
+        if (p->kind != STN_PLAN_SV_LDS && p->kind != STN_PLAN_SV_GATES) launch_frame(p, b, s);
         STN_HIP(hipStreamSynchronize(s));
     });
     if (st != STN_OK) {
@@ -377,6 +377,7 @@ static void contract_launch(stn_plan* p, stn_batch* b, hipStream_t s) {
             else launch_sv_tiled(p, b, s);
             break;
         case STN_PLAN_LIGHTCONE: launch_lightcone(p, b, s); break;
+        case STN_PLAN_SV_GATES: launch_sv_gates(p, b, s); break;
         default: fail(STN_E_STATE, "plan has no lowering");
     }
 }
@@ -480,7 +481,7 @@ stn_status stn_contract_dedup(stn_plan* p, stn_batch* b, uint32_t* n_unique, voi
         hipStream_t s = (hipStream_t)stream;
         ensure_uploaded(p, s);
         const uint32_t K = b->K;
-        const bool by_index = p->kind == STN_PLAN_SV_LDS;   // else: gate signs and final frame X
+        const bool by_index = p->kind == STN_PLAN_SV_LDS || p->kind == STN_PLAN_SV_GATES;   // else: gate signs and final frame X
         const size_t S = p->sites.size(), W = b->words;
         // the trajectories' keys, read back once the sampling has finished
         std::vector<uint8_t> idx;

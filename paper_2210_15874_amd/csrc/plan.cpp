@@ -544,6 +544,7 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
             }
             if (tn_t >= 0 && (sv_t < 0 || tn_t < sv_t)) kind = STN_PLAN_LIGHTCONE;
             else if (sv_t >= 0) kind = STN_PLAN_SV_TILED;
+            else if (n <= kGatesMaxQubits) kind = STN_PLAN_SV_GATES;   // any circuit and channel
             else fail(STN_E_UNSUPPORTED, "no lowering for this circuit: " + why);
             if (kind != STN_PLAN_LIGHTCONE && p->lc && p->lc_free) {
                 p->lc_free(p->lc);
@@ -581,6 +582,19 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
     } else if (kind == STN_PLAN_LIGHTCONE) {
         if (dense_out) fail(STN_E_UNSUPPORTED, "the lightcone lowering produces energies only");
         if (!p->lc) build_lightcone(p);
+    } else if (kind == STN_PLAN_SV_GATES) {
+        if (dense_out) fail(STN_E_UNSUPPORTED, "the gate-by-gate lowering produces energies only");
+        if (n < 2 || n > kGatesMaxQubits) fail(STN_E_UNSUPPORTED, "the gate-by-gate lowering needs 2 <= n <= 30");
+        if (p->lc && p->lc_free) {
+            p->lc_free(p->lc);
+            p->lc = nullptr;
+        }
+        for (auto& g : p->gates) {   // gates as given (no Pauli-frame rewrite)
+            g.det_x = 0;
+            g.theta_eff = g.theta;
+        }
+        p->passes.clear();
+        build_lds_program(p);
     } else {
         fail(STN_E_INVALID, "unknown plan kind");
     }
@@ -601,6 +615,23 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
         const double per = (dense_out ? N * elem : 0) + 64.0 + p->sites.size();
         const double budget = p->opts.hbm_budget ? (double)p->opts.hbm_budget : 64.0 * (1ull << 30);
         p->max_batch = p->opts.max_batch ? p->opts.max_batch : (uint32_t)std::min(65535.0, std::max(1.0, budget / per));
+        p->peak_bytes = per * p->max_batch;
+    } else if (kind == STN_PLAN_SV_GATES) {
+        // every non-identity operator entry reads and writes the state once
+        p->width = n;
+        double ops = 0, fl = 0;
+        for (auto& o : p->lds_ops) {
+            if (o.kind == OP_IDENT) continue;
+            ops += 1;
+            const bool two = o.kind == OP_DENSE2 || o.kind == OP_DIAG2 || (o.kind == OP_SITE && p->sites[o.site].nq == 2);
+            fl += (two ? 32.0 : 8.0) * N;
+        }
+        p->n_passes = (uint32_t)ops;
+        p->bytes_per_traj = N * elem * (2.0 * ops + 2.0);
+        p->flops_per_traj = fl;
+        const double per = N * elem + 64.0 * 8.0 + 64.0 + p->sites.size();
+        const double budget = p->opts.hbm_budget ? (double)p->opts.hbm_budget : 64.0 * (1ull << 30);
+        p->max_batch = p->opts.max_batch ? p->opts.max_batch : (uint32_t)std::max(1.0, std::min(4096.0, std::floor(budget / per)));
         p->peak_bytes = per * p->max_batch;
     } else if (kind == STN_PLAN_LIGHTCONE) {
         // width / steps / flops / bytes set by build_lightcone

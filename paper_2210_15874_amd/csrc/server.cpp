@@ -255,6 +255,7 @@ uint64_t estimate_bytes(const stn_plan* p, uint32_t B, uint64_t K) {
     const double elem = p->opts.precision == 128 ? 16.0 : 8.0;
     if (p->kind == STN_PLAN_SV_TILED) b += (double)B * N * elem + (double)B * std::ldexp(1.0, (int)p->n - 14) * 8.0;
     if (p->kind == STN_PLAN_LIGHTCONE) b += (double)B * p->obs_u.size() * 8.0 + p->lc_arena_bytes;
+    if (p->kind == STN_PLAN_SV_GATES) b += (double)B * (N * elem + 64.0 * 8.0);
     b += kChunksInFlight * (double)B * (S + 4.0 * words + 16.0 + 8.0);     // batches
     b += std::ceil((double)K / kEnergyChunk) * kEnergyChunk * 8.0 + 2.0 * K * 8.0;  // accumulator
     b += 8.0 * (1 << 20);                                                  // tables and rounding
@@ -625,7 +626,7 @@ struct Device {
             stn_batch probe;
             batch_prepare(j.plan, &probe, 0, std::min<uint32_t>(K, kTuneSample));
             launch_sample(j.plan, &probe, j.seed, upload);
-            if (j.plan->kind != STN_PLAN_SV_LDS) launch_frame(j.plan, &probe, upload);
+            if (j.plan->kind != STN_PLAN_SV_LDS && j.plan->kind != STN_PLAN_SV_GATES) launch_frame(j.plan, &probe, upload);
             stn_tune_result tr{};
             const stn_status st0 = stn_plan_autotune(j.plan, &probe, 1, &tr, upload);
             if (st0 != STN_OK) throw Error{st0, stn_last_error()};
@@ -635,7 +636,7 @@ struct Device {
             sv->st.autotuned++;
         }
         launch_sample(j.plan, b, j.seed, s);
-        if (j.plan->kind != STN_PLAN_SV_LDS) launch_frame(j.plan, b, s);
+        if (j.plan->kind != STN_PLAN_SV_LDS && j.plan->kind != STN_PLAN_SV_GATES) launch_frame(j.plan, b, s);
         const stn_status st1 = stn_contract(j.plan, b, s);
         if (st1 != STN_OK) throw Error{st1, stn_last_error()};
         const stn_status st2 = stn_reduce(j.plan, b, j.acc, s);

@@ -214,6 +214,7 @@ struct stn_batch {
     stn::DevBuf d_frame;             // uint64 [K x 2]: final frame x mask, z mask
     stn::DevBuf d_energy;            // double [K]
     stn::DevBuf d_states;            // complex [K x 2^n] (float2 or double2)
+    stn::DevBuf d_gates_part;        // double [K x 64]: gate-by-gate lowering's energy slice sums
     stn::DevBuf d_queue;             // multi-batch launches led by this batch: their item counter
     stn::DevBuf d_map;               // stn_contract_dedup: representative of each trajectory
     stn_batch* unique = nullptr;     // stn_contract_dedup: the distinct trajectories
@@ -298,6 +299,9 @@ void launch_sample(stn_plan* p, stn_batch* b, uint64_t seed, hipStream_t s);
 void launch_frame(stn_plan* p, stn_batch* b, hipStream_t s);
 void launch_sv_lds(stn_plan* p, stn_batch* b, hipStream_t s);
 void launch_sv_tiled(stn_plan* p, stn_batch* b, hipStream_t s);
+// gate-by-gate HBM statevector lowering (any circuit and channel)
+constexpr uint32_t kGatesMaxQubits = 30;
+void launch_sv_gates(stn_plan* p, stn_batch* b, hipStream_t s);
 void launch_reduce(stn_plan* p, stn_batch* b, stn_accum* a, hipStream_t s);
 // fixed-order energy statistics over the gathered per-trajectory energies
 void launch_energy_stats(stn_accum* a, uint64_t K, hipStream_t s);

@@ -72,7 +72,7 @@ void upload_plan_tables(stn_plan* p, hipStream_t s) {
     up(p->d_obs, a, uv, s);
     up(p->d_obs_w, a, w, s);
 
-    if (p->kind == STN_PLAN_SV_LDS) {
+    if (p->kind == STN_PLAN_SV_LDS || p->kind == STN_PLAN_SV_GATES) {
         std::vector<LdsOp> ops = p->lds_ops, sops = p->site_ops;
         ops.push_back(LdsOp{});
         sops.push_back(LdsOp{});

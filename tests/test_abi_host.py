@@ -247,6 +247,29 @@ def test_caller_contraction_order():
     assert plan(pr2, lc_order=natural).info()["plan_name"] == "sv_tiled"
 
 
+def test_gate_by_gate_plans():
+    """<C> jobs with non-unitary channels above the whole-state-in-LDS size
+    have no Pauli frame (so no tiled or lightcone lowering): AUTO takes the
+    gate-by-gate HBM statevector; it is energy only and n <= 30."""
+    from workloads import make_problem, random_regular_graph, uniform_angles
+    from paper_2210_15874_amd import OUT_DIAG, OUT_ENERGY, PLAN_SV_GATES, StnError
+    g, b = uniform_angles(2, 31)
+    pr = make_problem(16, random_regular_graph(16, 3, 32), g, b, 1e-3, 1e-2, 8, 33, gamma_ad=0.01)
+    i = plan(pr).info()
+    assert i["plan_name"] == "sv_gates" and i["width"] == 16
+    n_ops = len(pr.gates) + len(pr.channels)
+    assert 0 < i["n_passes"] <= n_ops
+    assert i["bytes_per_traj"] == 8.0 * (1 << 16) * (2 * i["n_passes"] + 2)
+    pq = make_problem(16, random_regular_graph(16, 3, 32), g, b, 1e-3, 1e-2, 8, 33)
+    assert plan(pq, plan_kind=PLAN_SV_GATES).info()["plan_name"] == "sv_gates"
+    with pytest.raises(StnError, match="UNSUPPORTED"):
+        plan(pr, plan_kind=PLAN_SV_GATES, outputs=OUT_DIAG | OUT_ENERGY)
+    g1, b1 = uniform_angles(1, 34)
+    big = make_problem(32, random_regular_graph(32, 3, 35), g1, b1, 1e-3, 1e-2, 8, 36, gamma_ad=0.01)
+    with pytest.raises(StnError, match="UNSUPPORTED"):
+        plan(big, plan_kind=PLAN_SV_GATES)
+
+
 def test_server_needs_a_device_and_valid_options():
     from paper_2210_15874_amd import Server, StnError
     with pytest.raises(StnError, match="INVALID"):

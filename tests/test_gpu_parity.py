@@ -716,3 +716,79 @@ def test_caller_contraction_order_same_energies(precision, tol):
         res.append(bt.energies())
     m2 = len(pr2.edges)
     np.testing.assert_allclose(res[1] / m2, res[0] / m2, atol=tol)
+
+
+# ----------------------------------------------------------------------------- gate-by-gate HBM statevector
+
+@pytest.mark.parametrize("precision,tol", [(128, 1e-11), (64, 1e-5)])
+def test_gate_by_gate_amplitude_damping_against_oracle(precision, tol):
+    """<C> with amplitude damping above the whole-state-in-LDS size (n=14,
+    p=2, depolarizing + amplitude damping per layer: no Pauli frame, so
+    neither the tiled nor the lightcone lowering applies) against the
+    oracle's literal-Kraus statevectors, same draws; a second batch at
+    k0 = 5 with a ragged size."""
+    from oracle import simulate as sim
+    from workloads import make_problem, random_regular_graph, uniform_angles
+    stn = stn_mod()
+    g, b = uniform_angles(2, 31)
+    pr = make_problem(14, random_regular_graph(14, 3, 32), g, b, 2e-3, 2e-2, 12, 33, gamma_ad=0.05)
+    pl = stn.Plan(pr, precision=precision)
+    assert pl.info()["plan_name"] == "sv_gates"
+    m = len(pr.edges)
+    for k0, K in ((0, 12), (5, 7)):
+        bt = pl.sample(pr.seed, k0, K)
+        pl.contract(bt)
+        got = bt.energies()
+        ens = sim.ensemble(pr, pr.seed, k0, K, want_states=False)
+        np.testing.assert_allclose(got / m, ens["energies"] / m, atol=tol)
+        bt.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(128, 1e-11), (64, 2e-5)])
+def test_gate_by_gate_random_circuits_against_oracle(precision, tol):
+    """Random circuits of every gate kind (h, x, y, z, rx, ry, rz, u1, zz, cx,
+    u2) with every channel kind (bit flip, depolarizing, amplitude damping,
+    explicit Kraus sets on one and two qubits), n = 2..8, in the gate-by-gate
+    lowering against the oracle, same draws."""
+    from oracle import simulate as sim
+    from test_gpu_random import random_problem
+    stn = stn_mod()
+    done = 0
+    for seed in range(40):
+        pr = random_problem(seed)
+        if pr.n_qubits < 2 or not pr.edges:
+            continue
+        pl = stn.Plan(pr, plan_kind=stn.PLAN_SV_GATES, precision=precision)
+        bt = pl.sample(pr.seed, 0, pr.K)
+        pl.contract(bt)
+        got = bt.energies()
+        ens = sim.ensemble(pr, pr.seed, 0, pr.K, want_states=False)
+        scale = max(1.0, float(np.sum(pr.weights)))
+        np.testing.assert_allclose(got / scale, ens["energies"] / scale, atol=tol, err_msg=f"seed {seed}")
+        done += 1
+    assert done >= 20
+
+
+def test_gate_by_gate_matches_tiled_and_lds():
+    """The same trajectories in other lowerings: n=20 Pauli noise against the
+    tiled passes (complex64), n=10 against the whole-state-in-LDS kernel
+    (complex128)."""
+    stn = stn_mod()
+    pr = qaoa(20, 2, 44, 0.01, 0.05, 24)
+    res = {}
+    for kind in (stn.PLAN_SV_GATES, stn.PLAN_SV_TILED):
+        pl = stn.Plan(pr, plan_kind=kind)
+        bt = pl.sample(pr.seed, 0, pr.K)
+        pl.contract(bt)
+        res[kind] = bt.energies()
+    m = len(pr.edges)
+    np.testing.assert_allclose(res[stn.PLAN_SV_GATES] / m, res[stn.PLAN_SV_TILED] / m, atol=2e-5)
+    pr = qaoa(10, 3, 45, 0.01, 0.05, 32)
+    res = {}
+    for kind in (stn.PLAN_SV_GATES, stn.PLAN_SV_LDS):
+        pl = stn.Plan(pr, plan_kind=kind, precision=128)
+        bt = pl.sample(pr.seed, 0, pr.K)
+        pl.contract(bt)
+        res[kind] = bt.energies()
+    m = len(pr.edges)
+    np.testing.assert_allclose(res[stn.PLAN_SV_GATES] / m, res[stn.PLAN_SV_LDS] / m, atol=1e-12)
