@@ -104,6 +104,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean arrivals per second")
     ap.add_argument("--serve-check-every", type=int, default=4, help="complex128 check of every k-th served job")
     ap.add_argument("--rho-leg", type=int, default=1, help="n=12 rho_hat workload leg (0: skip)")
+    ap.add_argument("--gates-leg", type=int, default=1,
+                    help="n=20 amplitude-damping <C> job in the gate-by-gate lowering (0: skip)")
     ap.add_argument("--ksweep", action="store_true",
                     help="rho_hat leg: fidelity / trace distance vs the exact density matrix for K = 16..1024 "
                          "(adds minutes of CPU work)")
@@ -254,6 +256,8 @@ def main():
     torch.cuda.empty_cache()
     rho_leg = rho_hat_leg(stn, args.ksweep) if args.rho_leg else None
     torch.cuda.empty_cache()
+    gates = gates_leg(stn) if args.gates_leg else None
+    torch.cuda.empty_cache()
     serving = serving_leg(stn, args) if args.serve_jobs > 0 else None
 
     out = {
@@ -288,6 +292,7 @@ def main():
         "dedup": dedup,
         "plain_loop": plain,
         "rho_hat": rho_leg,
+        "sv_gates": gates,
         "serving": serving,
         "cpu_baseline": cpu,
     }
@@ -347,6 +352,33 @@ def plain_loop(stn, problem, n_traj, batched_value, variant=None):
     pl.close()
     v = n_traj / dt
     return {"value": v, "unit": "trajectories/s", "trajectories": n_traj, "batched_over_plain": batched_value / v}
+
+
+def gates_leg(stn):
+    """n=20 QAOA p=2, 3-regular, depolarizing + amplitude damping per layer,
+    K=256 <C>: no Pauli frame, so the gate-by-gate HBM statevector lowering
+    (one launch per gate or noise site).  Reports trajectories/s and the
+    HBM rate of its passes from the library's own per-class timing."""
+    import torch
+    from workloads import make_problem, random_regular_graph, uniform_angles
+    g, b = uniform_angles(2, 61)
+    pr = make_problem(20, random_regular_graph(20, 3, 62), g, b, 1e-3, 1e-2, 256, 63, gamma_ad=0.01)
+    pl = stn.Plan(pr, precision=64)
+    info = pl.info()
+    stn.simulate_batch_ensemble(pr, plan=pl)            # warm
+    torch.cuda.synchronize()
+    pl.profile(True)
+    t0 = time.perf_counter()
+    res = stn.simulate_batch_ensemble(pr, plan=pl)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = pl.profile_read()["sv_pass"]
+    pl.profile(False)
+    gbs = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9 if prof["ms"] else None
+    return {"workload": "qaoa-n20-p2-3reg-depol-ad-K256", "plan": info["plan_name"], "K": pr.K,
+            "passes_per_trajectory": info["n_passes"], "seconds": dt, "trajectories_per_s": pr.K / dt,
+            "pass_ms": prof["ms"], "hbm_GBps": gbs, "hbm_frac": gbs / 8000.0 if gbs else None,
+            "energy_mean": res["energy_mean"], "energy_se": res["energy_se"]}
 
 
 def rho_hat_leg(stn, ksweep):
