@@ -64,7 +64,12 @@ __global__ __launch_bounds__(256) void k_gates_init(V* __restrict__ psi, uint64_
 }
 
 // One operator-list entry over the batch.  nq = 1: groups are pairs over q0;
-// nq = 2: quadruples, local index bit 0 = q0, bit 1 = q1.
+// nq = 2: quadruples, local index bit 0 = q0, bit 1 = q1.  Each lane takes
+// kGroupsPerLane groups per round and issues all their loads before any
+// store (distinct groups never share an amplitude), so more bytes are in
+// flight per lane.
+constexpr uint32_t kGroupsPerLane = 4;
+
 template <class V>
 __global__ __launch_bounds__(256) void k_gates_op(V* __restrict__ psi, uint32_t n, uint32_t K, LdsOp op, uint32_t nq,
                                                   const V* __restrict__ vals, const LdsOp* __restrict__ site_ops,
@@ -74,58 +79,86 @@ __global__ __launch_bounds__(256) void k_gates_op(V* __restrict__ psi, uint32_t 
     const uint64_t groups = 1ull << (n - nq);
     const uint64_t total = groups * K;
     const uint64_t N = 1ull << n;
-    for (uint64_t it = (uint64_t)blockIdx.x * kGateThreads + threadIdx.x; it < total;
-         it += (uint64_t)gridDim.x * kGateThreads) {
-        const uint64_t k = it >> (n - nq), g = it & (groups - 1);
-        LdsOp o = op;
-        if (o.kind == OP_SITE) o = site_ops[site_off[op.site] + idx[k * S + op.site]];
-        if (o.kind == OP_IDENT) continue;
-        V* base = psi + k * N;
-        uint64_t ix[4];
-        const uint32_t m = 1u << nq;
-        if (nq == 1) {
-            ix[0] = insert0(g, qa);
-            ix[1] = ix[0] | (1ull << op.q0);
-        } else {
-            const uint64_t i = insert0(insert0(g, qa), qb);
-            ix[0] = i;
-            ix[1] = i | (1ull << op.q0);
-            ix[2] = i | (1ull << op.q1);
-            ix[3] = i | (1ull << op.q0) | (1ull << op.q1);
-        }
-        V a[4], r[4];
-        for (uint32_t l = 0; l < m; ++l) a[l] = base[ix[l]];
-        switch (o.kind) {
-            case OP_DENSE1:   // on q0 (a one-qubit site or gate)
-                r[0] = gadd(gmul(vals[o.mat], a[0]), gmul(vals[o.mat + 1], a[1]));
-                r[1] = gadd(gmul(vals[o.mat + 2], a[0]), gmul(vals[o.mat + 3], a[1]));
-                break;
-            case OP_DENSE2:
-                for (uint32_t l = 0; l < 4; ++l) {
-                    V acc = gmul(vals[o.mat + 4 * l], a[0]);
-                    for (uint32_t c = 1; c < 4; ++c) acc = gadd(acc, gmul(vals[o.mat + 4 * l + c], a[c]));
-                    r[l] = acc;
-                }
-                break;
-            case OP_DIAG1:
-                r[0] = gmul(vals[o.mat], a[0]);
-                r[1] = gmul(vals[o.mat + 1], a[1]);
-                break;
-            case OP_DIAG2:
-                for (uint32_t l = 0; l < 4; ++l) r[l] = gmul(vals[o.mat + l], a[l]);
-                break;
-            default: {        // OP_PAULI: amplitude at x moves to x ^ X with sign (-1)^|x & Z|
-                const uint64_t X = o.xmask, Z = o.zmask;
-                for (uint32_t l = 0; l < m; ++l) {
-                    uint32_t dst = 0;
-                    for (uint32_t t = 0; t < m; ++t)
-                        if ((ix[l] ^ X) == ix[t]) dst = t;
-                    r[dst] = gneg(a[l], __popcll(ix[l] & Z) & 1);
-                }
-                break;
+    const uint64_t b0 = 1ull << op.q0, b1 = nq == 2 ? 1ull << op.q1 : 0;
+    const uint64_t span = (uint64_t)kGateThreads * kGroupsPerLane;
+    for (uint64_t it0 = (uint64_t)blockIdx.x * span + threadIdx.x; it0 < total; it0 += (uint64_t)gridDim.x * span) {
+        LdsOp o[kGroupsPerLane];
+        uint64_t ix[kGroupsPerLane][4];
+        V a[kGroupsPerLane][4];
+        bool act[kGroupsPerLane];
+#pragma unroll
+        for (uint32_t r = 0; r < kGroupsPerLane; ++r) {
+            const uint64_t it = it0 + (uint64_t)r * kGateThreads;
+            act[r] = it < total;
+            if (!act[r]) continue;
+            const uint64_t k = it >> (n - nq), g = it & (groups - 1);
+            o[r] = op;
+            if (op.kind == OP_SITE) o[r] = site_ops[site_off[op.site] + idx[k * S + op.site]];
+            act[r] = o[r].kind != OP_IDENT;
+            if (!act[r]) continue;
+            const uint64_t i = nq == 1 ? insert0(g, qa) : insert0(insert0(g, qa), qb);
+            ix[r][0] = k * N + i;
+            ix[r][1] = k * N + (i | b0);
+            ix[r][2] = k * N + (i | b1);
+            ix[r][3] = k * N + (i | b0 | b1);
+            a[r][0] = psi[ix[r][0]];
+            a[r][1] = psi[ix[r][1]];
+            if (nq == 2) {
+                a[r][2] = psi[ix[r][2]];
+                a[r][3] = psi[ix[r][3]];
             }
         }
-        for (uint32_t l = 0; l < m; ++l) base[ix[l]] = r[l];
+#pragma unroll
+        for (uint32_t r = 0; r < kGroupsPerLane; ++r) {
+            if (!act[r]) continue;
+            const LdsOp& q = o[r];
+            V res[4];
+            switch (q.kind) {
+                case OP_DENSE1:   // on q0 (a one-qubit site or gate)
+                    res[0] = gadd(gmul(vals[q.mat], a[r][0]), gmul(vals[q.mat + 1], a[r][1]));
+                    res[1] = gadd(gmul(vals[q.mat + 2], a[r][0]), gmul(vals[q.mat + 3], a[r][1]));
+                    break;
+                case OP_DENSE2:
+#pragma unroll
+                    for (uint32_t l = 0; l < 4; ++l) {
+                        V acc = gmul(vals[q.mat + 4 * l], a[r][0]);
+#pragma unroll
+                        for (uint32_t c = 1; c < 4; ++c) acc = gadd(acc, gmul(vals[q.mat + 4 * l + c], a[r][c]));
+                        res[l] = acc;
+                    }
+                    break;
+                case OP_DIAG1:
+                    res[0] = gmul(vals[q.mat], a[r][0]);
+                    res[1] = gmul(vals[q.mat + 1], a[r][1]);
+                    break;
+                case OP_DIAG2:
+#pragma unroll
+                    for (uint32_t l = 0; l < 4; ++l) res[l] = gmul(vals[q.mat + l], a[r][l]);
+                    break;
+                default: {        // OP_PAULI: amplitude at x moves to x ^ X with sign (-1)^|x & Z|
+                    const uint64_t X = q.xmask, Z = q.zmask, base = ix[r][0] & ~(N - 1);
+#pragma unroll
+                    for (uint32_t t = 0; t < 4; ++t) {
+                        V v = a[r][0];
+                        uint64_t src = ix[r][0];
+#pragma unroll
+                        for (uint32_t l = 1; l < 4; ++l)
+                            if (l < (1u << nq) && ((ix[r][l] - base) ^ X) == ix[r][t] - base) {
+                                v = a[r][l];
+                                src = ix[r][l];
+                            }
+                        res[t] = gneg(v, __popcll((src - base) & Z) & 1);
+                    }
+                    break;
+                }
+            }
+            psi[ix[r][0]] = res[0];
+            psi[ix[r][1]] = res[1];
+            if (nq == 2) {
+                psi[ix[r][2]] = res[2];
+                psi[ix[r][3]] = res[3];
+            }
+        }
     }
 }
 
@@ -220,9 +253,23 @@ void launch_sv_gates(stn_plan* p, stn_batch* b, hipStream_t s) {
     prof_begin(p, STN_K_SV_PASS, s);
     if (dbl) run_gates<double2>(p, b, s, p->d_lds_vals64.as<double2>());
     else run_gates<float2>(p, b, s, p->d_lds_vals32.as<float2>());
-    double ops = 0;
-    for (const LdsOp& op : p->lds_ops) ops += op.kind != OP_IDENT;
-    prof_end(p, STN_K_SV_PASS, s, std::ldexp((double)b->K * elem, (int)n) * (2.0 * ops + 2.0), 0.0);
+    // bytes counted: entries that read and write every trajectory's state (gates,
+    // and noise sites none of whose operators is the identity).  Sites whose
+    // identity operator most trajectories draw are left out, so the figure is a
+    // lower bound on the bytes moved.
+    double full = 0;
+    for (const LdsOp& op : p->lds_ops) {
+        if (op.kind == OP_IDENT) continue;
+        if (op.kind != OP_SITE) {
+            full += 1;
+            continue;
+        }
+        bool any_ident = false;
+        for (uint32_t j = p->site_op_off[op.site]; j < p->site_op_off[op.site + 1]; ++j)
+            any_ident |= p->site_ops[j].kind == OP_IDENT;
+        full += any_ident ? 0 : 1;
+    }
+    prof_end(p, STN_K_SV_PASS, s, std::ldexp((double)b->K * elem, (int)n) * (2.0 * full + 2.0), 0.0);
 }
 
 }  // namespace stn

@@ -226,3 +226,25 @@ def test_plan_cache_reuses_plans():
     for s in range(3):
         ref = stn.simulate_batch_ensemble(pr, K=128, seed=100 + s)
         assert res[s]["energy_mean"] == ref["energy_mean"]
+
+
+def test_served_amplitude_damping_job_uses_gate_by_gate_lowering():
+    """A <C> job with amplitude damping above the whole-state-in-LDS size is
+    served through the gate-by-gate lowering, bit for bit as alone, beside a
+    job of another lowering."""
+    from workloads import make_problem, random_regular_graph, uniform_angles
+    stn = stn_mod()
+    g, b = uniform_angles(2, 71)
+    ad = make_problem(16, random_regular_graph(16, 3, 72), g, b, 1e-3, 1e-2, 48, 73, gamma_ad=0.02, name="ad16")
+    jobs = [ad, mixed_jobs()[0]]
+    ref = [alone(pr) for pr in jobs]
+    with stn.Server(hbm_budget=8 << 30, n_streams=4, max_active=8) as sv:
+        for i, pr in enumerate(jobs):
+            sv.submit(pr, tag=i)
+        sv.drain(300)
+        res = {r["tag"]: r for r in sv.poll(cap=64)}
+    assert res[0]["status"] == 0, res[0]["error"]
+    assert res[0]["plan_name"] == "sv_gates"
+    for i in range(len(jobs)):
+        assert res[i]["energy_mean"] == ref[i]["energy_mean"]
+        assert res[i]["energy_se"] == ref[i]["energy_se"]
