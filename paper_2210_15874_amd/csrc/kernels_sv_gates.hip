@@ -63,100 +63,108 @@ __global__ __launch_bounds__(256) void k_gates_init(V* __restrict__ psi, uint64_
     }
 }
 
-// One operator-list entry over the batch.  nq = 1: groups are pairs over q0;
-// nq = 2: quadruples, local index bit 0 = q0, bit 1 = q1.  Each lane takes
-// kGroupsPerLane groups per round and issues all their loads before any
-// store (distinct groups never share an amplitude), so more bytes are in
-// flight per lane.
+// One operator-list entry over the batch: grid (group chunks, trajectory).
+// nq = 1: groups are pairs over q0; nq = 2: quadruples, local index bit 0 =
+// q0, bit 1 = q1.  A workgroup serves one trajectory, so it resolves the
+// operator once (a trajectory that drew the identity returns at once) and
+// keeps its values in registers.  Each lane takes kGroupsPerLane groups per
+// round and issues all their loads before any store (distinct groups never
+// share an amplitude), so more bytes are in flight per lane.
 constexpr uint32_t kGroupsPerLane = 4;
+constexpr uint32_t kGateChunksMax = 256;
 
 template <class V>
-__global__ __launch_bounds__(256) void k_gates_op(V* __restrict__ psi, uint32_t n, uint32_t K, LdsOp op, uint32_t nq,
+__global__ __launch_bounds__(256) void k_gates_op(V* __restrict__ psi, uint32_t n, LdsOp op, uint32_t nq,
                                                   const V* __restrict__ vals, const LdsOp* __restrict__ site_ops,
                                                   const uint32_t* __restrict__ site_off,
                                                   const uint8_t* __restrict__ idx, uint32_t S) {
+    const uint64_t k = blockIdx.y;
+    LdsOp o = op;
+    if (op.kind == OP_SITE) o = site_ops[site_off[op.site] + idx[k * S + op.site]];
+    if (o.kind == OP_IDENT) return;   // the same for the whole workgroup; no barrier follows
     const uint32_t qa = nq == 2 ? min(op.q0, op.q1) : op.q0, qb = nq == 2 ? max(op.q0, op.q1) : 0;
     const uint64_t groups = 1ull << (n - nq);
-    const uint64_t total = groups * K;
-    const uint64_t N = 1ull << n;
+    V* base = psi + k * (1ull << n);
     const uint64_t b0 = 1ull << op.q0, b1 = nq == 2 ? 1ull << op.q1 : 0;
+    const uint32_t nv = o.kind == OP_DENSE2 ? 16 : (o.kind == OP_DENSE1 || o.kind == OP_DIAG2) ? 4
+                      : o.kind == OP_DIAG1 ? 2 : 0;
+    V m[16];
+#pragma unroll
+    for (uint32_t t = 0; t < 16; ++t) {
+        m[t].x = 0;
+        m[t].y = 0;
+        if (t < nv) m[t] = vals[o.mat + t];
+    }
     const uint64_t span = (uint64_t)kGateThreads * kGroupsPerLane;
-    for (uint64_t it0 = (uint64_t)blockIdx.x * span + threadIdx.x; it0 < total; it0 += (uint64_t)gridDim.x * span) {
-        LdsOp o[kGroupsPerLane];
+    for (uint64_t g0 = (uint64_t)blockIdx.x * span + threadIdx.x; g0 < groups; g0 += (uint64_t)gridDim.x * span) {
         uint64_t ix[kGroupsPerLane][4];
         V a[kGroupsPerLane][4];
         bool act[kGroupsPerLane];
 #pragma unroll
         for (uint32_t r = 0; r < kGroupsPerLane; ++r) {
-            const uint64_t it = it0 + (uint64_t)r * kGateThreads;
-            act[r] = it < total;
-            if (!act[r]) continue;
-            const uint64_t k = it >> (n - nq), g = it & (groups - 1);
-            o[r] = op;
-            if (op.kind == OP_SITE) o[r] = site_ops[site_off[op.site] + idx[k * S + op.site]];
-            act[r] = o[r].kind != OP_IDENT;
+            const uint64_t g = g0 + (uint64_t)r * kGateThreads;
+            act[r] = g < groups;
             if (!act[r]) continue;
             const uint64_t i = nq == 1 ? insert0(g, qa) : insert0(insert0(g, qa), qb);
-            ix[r][0] = k * N + i;
-            ix[r][1] = k * N + (i | b0);
-            ix[r][2] = k * N + (i | b1);
-            ix[r][3] = k * N + (i | b0 | b1);
-            a[r][0] = psi[ix[r][0]];
-            a[r][1] = psi[ix[r][1]];
+            ix[r][0] = i;
+            ix[r][1] = i | b0;
+            ix[r][2] = i | b1;
+            ix[r][3] = i | b0 | b1;
+            a[r][0] = base[ix[r][0]];
+            a[r][1] = base[ix[r][1]];
             if (nq == 2) {
-                a[r][2] = psi[ix[r][2]];
-                a[r][3] = psi[ix[r][3]];
+                a[r][2] = base[ix[r][2]];
+                a[r][3] = base[ix[r][3]];
             }
         }
 #pragma unroll
         for (uint32_t r = 0; r < kGroupsPerLane; ++r) {
             if (!act[r]) continue;
-            const LdsOp& q = o[r];
             V res[4];
-            switch (q.kind) {
+            switch (o.kind) {
                 case OP_DENSE1:   // on q0 (a one-qubit site or gate)
-                    res[0] = gadd(gmul(vals[q.mat], a[r][0]), gmul(vals[q.mat + 1], a[r][1]));
-                    res[1] = gadd(gmul(vals[q.mat + 2], a[r][0]), gmul(vals[q.mat + 3], a[r][1]));
+                    res[0] = gadd(gmul(m[0], a[r][0]), gmul(m[1], a[r][1]));
+                    res[1] = gadd(gmul(m[2], a[r][0]), gmul(m[3], a[r][1]));
                     break;
                 case OP_DENSE2:
 #pragma unroll
                     for (uint32_t l = 0; l < 4; ++l) {
-                        V acc = gmul(vals[q.mat + 4 * l], a[r][0]);
+                        V acc = gmul(m[4 * l], a[r][0]);
 #pragma unroll
-                        for (uint32_t c = 1; c < 4; ++c) acc = gadd(acc, gmul(vals[q.mat + 4 * l + c], a[r][c]));
+                        for (uint32_t c = 1; c < 4; ++c) acc = gadd(acc, gmul(m[4 * l + c], a[r][c]));
                         res[l] = acc;
                     }
                     break;
                 case OP_DIAG1:
-                    res[0] = gmul(vals[q.mat], a[r][0]);
-                    res[1] = gmul(vals[q.mat + 1], a[r][1]);
+                    res[0] = gmul(m[0], a[r][0]);
+                    res[1] = gmul(m[1], a[r][1]);
                     break;
                 case OP_DIAG2:
 #pragma unroll
-                    for (uint32_t l = 0; l < 4; ++l) res[l] = gmul(vals[q.mat + l], a[r][l]);
+                    for (uint32_t l = 0; l < 4; ++l) res[l] = gmul(m[l], a[r][l]);
                     break;
                 default: {        // OP_PAULI: amplitude at x moves to x ^ X with sign (-1)^|x & Z|
-                    const uint64_t X = q.xmask, Z = q.zmask, base = ix[r][0] & ~(N - 1);
+                    const uint64_t X = o.xmask, Z = o.zmask;
 #pragma unroll
                     for (uint32_t t = 0; t < 4; ++t) {
                         V v = a[r][0];
                         uint64_t src = ix[r][0];
 #pragma unroll
                         for (uint32_t l = 1; l < 4; ++l)
-                            if (l < (1u << nq) && ((ix[r][l] - base) ^ X) == ix[r][t] - base) {
+                            if (l < (1u << nq) && (ix[r][l] ^ X) == ix[r][t]) {
                                 v = a[r][l];
                                 src = ix[r][l];
                             }
-                        res[t] = gneg(v, __popcll((src - base) & Z) & 1);
+                        res[t] = gneg(v, __popcll(src & Z) & 1);
                     }
                     break;
                 }
             }
-            psi[ix[r][0]] = res[0];
-            psi[ix[r][1]] = res[1];
+            base[ix[r][0]] = res[0];
+            base[ix[r][1]] = res[1];
             if (nq == 2) {
-                psi[ix[r][2]] = res[2];
-                psi[ix[r][3]] = res[3];
+                base[ix[r][2]] = res[2];
+                base[ix[r][3]] = res[3];
             }
         }
     }
@@ -226,9 +234,10 @@ template <class V> void run_gates(stn_plan* p, stn_batch* b, hipStream_t s, cons
         } else {
             nq = (op.kind == OP_DENSE2 || op.kind == OP_DIAG2) ? 2 : 1;
         }
-        hipLaunchKernelGGL(k_gates_op<V>, dim3(grid((N >> nq) * K)), dim3(kGateThreads), 0, s, psi, n, K, op, nq,
-                           vals, p->d_site_ops.as<LdsOp>(), p->d_site_op_off.as<uint32_t>(), b->d_idx.as<uint8_t>(),
-                           S);
+        const uint64_t span = (uint64_t)kGateThreads * kGroupsPerLane;
+        const uint32_t chunks = (uint32_t)std::min<uint64_t>(((N >> nq) + span - 1) / span, kGateChunksMax);
+        hipLaunchKernelGGL(k_gates_op<V>, dim3(chunks, K), dim3(kGateThreads), 0, s, psi, n, op, nq, vals,
+                           p->d_site_ops.as<LdsOp>(), p->d_site_op_off.as<uint32_t>(), b->d_idx.as<uint8_t>(), S);
         STN_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_gates_energy<V>, dim3(kEnergySlices, K), dim3(kGateThreads), 0, s, psi, n,
