@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void k_gates_init(V* __restrict__ psi, uint64_
 // round and issues all their loads before any store (distinct groups never
 // share an amplitude), so more bytes are in flight per lane.
 constexpr uint32_t kGroupsPerLane = 4;
-constexpr uint32_t kGateChunksMax = 256;
+constexpr uint32_t kGateChunksMax = 2048;   // enough workgroups for one trajectory at n = 30
 
 template <class V>
 __global__ __launch_bounds__(256) void k_gates_op(V* __restrict__ psi, uint32_t n, LdsOp op, uint32_t nq,

@@ -792,3 +792,20 @@ def test_gate_by_gate_matches_tiled_and_lds():
         res[kind] = bt.energies()
     m = len(pr.edges)
     np.testing.assert_allclose(res[stn.PLAN_SV_GATES] / m, res[stn.PLAN_SV_LDS] / m, atol=1e-12)
+
+
+def test_gate_by_gate_large_state_matches_tiled():
+    """n=24 (2^23 pairs per trajectory: the chunk cap is reached and every
+    workgroup loops), K=8: the gate-by-gate lowering against the tiled
+    passes on the same trajectories."""
+    stn = stn_mod()
+    pr = qaoa(24, 1, 46, 0.01, 0.05, 8)
+    res = {}
+    for kind in (stn.PLAN_SV_GATES, stn.PLAN_SV_TILED):
+        pl = stn.Plan(pr, plan_kind=kind)
+        bt = pl.sample(pr.seed, 0, pr.K)
+        pl.contract(bt)
+        res[kind] = bt.energies()
+        bt.close()
+    m = len(pr.edges)
+    np.testing.assert_allclose(res[stn.PLAN_SV_GATES] / m, res[stn.PLAN_SV_TILED] / m, atol=2e-5)
