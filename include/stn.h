@@ -119,7 +119,7 @@ typedef struct {
 
 enum {
     STN_OUT_RHO = 1,        /* rho_hat (n <= 13) */
-    STN_OUT_DIAG = 2,       /* sigma_approx = diag(rho_hat) (n <= 13) */
+    STN_OUT_DIAG = 2,       /* sigma_approx = diag(rho_hat) (n <= 13; up to 30 in the gate-by-gate lowering) */
     STN_OUT_ENERGY = 4,     /* <C> and its standard error (needs an observable) */
     STN_OUT_STATES = 8      /* keep per-trajectory statevectors in the batch (n <= 13) */
 };
@@ -131,7 +131,7 @@ typedef enum {
                                circuits with Pauli noise, energy only */
     STN_PLAN_LIGHTCONE = 3, /* per-term lightcone tensor networks, energy only */
     STN_PLAN_SV_GATES = 4   /* HBM statevector, one pass per gate or noise site: any circuit and any
-                               channel (non-unitary ones included), 2 <= n <= 30, energy only */
+                               channel (non-unitary ones included), 2 <= n <= 30, energy and sigma */
 } stn_plan_kind;
 
 typedef void* (*stn_alloc_fn)(size_t bytes, void* ctx);
@@ -384,7 +384,8 @@ void stn_accum_destroy(stn_accum* acc);
  *        indices in [0, 2^n))
  *   out  device, m uint32, caller-owned
  * Needs a plan with STN_OUT_DIAG or STN_OUT_RHO and at least one reduced
- * batch (STN_E_STATE otherwise); m = 0 does nothing.  Enqueued on stream,
+ * batch (STN_E_STATE otherwise); m = 0 does nothing.  Up to 2^13 states the
+ * running sums are searched in LDS, above that in device memory.  Enqueued on stream,
  * after the stn_reduce calls enqueued there before it; does not sync. */
 stn_status stn_accum_sample(stn_accum* acc, const double* u, uint32_t m, uint32_t* out, void* stream);
 

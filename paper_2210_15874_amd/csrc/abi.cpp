@@ -731,7 +731,6 @@ stn_status stn_accum_sample(stn_accum* a, const double* u, uint32_t m, uint32_t*
     if (!(p->opts.outputs & (STN_OUT_DIAG | STN_OUT_RHO)))
         return set_error(STN_E_STATE, "accumulator keeps no diagonal (request STN_OUT_DIAG)");
     if (!a->k_done) return set_error(STN_E_STATE, "no trajectories reduced");
-    if (p->n > 13) return set_error(STN_E_INVALID, "diagonal larger than the sampler's 64 KiB of LDS");
     if (!m) return STN_OK;
     return guarded([&] {
         a->d_cdf.ensure(&p->alloc, ((size_t)1 << p->n) * 8);

@@ -21,7 +21,8 @@
 //             One workgroup forms the running sums F of the accumulated
 //             diagonal (each thread sums a contiguous run, the 256 run totals
 //             are offset in thread order); each sampling workgroup stages F in
-//             LDS (at most 64 KiB) and each lane binary-searches the smallest
+//             LDS (up to 2^13 values; larger F is searched where it lies in
+//             device memory) and each lane binary-searches the smallest
 //             x with F(x) > u F(last), or, when rounding leaves none, the
 //             smallest x with F(x) >= u F(last).  Every index returned is in
 //             range whatever u holds.
@@ -239,12 +240,19 @@ __device__ __forceinline__ uint32_t count_le(const double* F, uint32_t N, double
 
 constexpr uint32_t kDrawsPerLane = 4;
 
+constexpr uint32_t kSampleLdsMax = 8192;
+
+template <bool kLds>
 __global__ __launch_bounds__(256) void k_sample_bits(const double* __restrict__ cdf, uint32_t N,
                                                      const double* __restrict__ u, uint32_t m,
                                                      uint32_t* __restrict__ out) {
-    extern __shared__ double F[];
-    for (uint32_t i = threadIdx.x; i < N; i += 256) F[i] = cdf[i];
-    __syncthreads();
+    extern __shared__ double lds_F[];
+    const double* F = cdf;
+    if (kLds) {
+        for (uint32_t i = threadIdx.x; i < N; i += 256) lds_F[i] = cdf[i];
+        __syncthreads();
+        F = lds_F;
+    }
     const double total = F[N - 1];
     const uint32_t span = 256 * kDrawsPerLane;
     for (uint64_t j0 = (uint64_t)blockIdx.x * span + threadIdx.x; j0 < m; j0 += (uint64_t)gridDim.x * span) {
@@ -278,8 +286,12 @@ void launch_sample_bits(stn_accum* a, const double* u, uint32_t m, uint32_t* out
     hipLaunchKernelGGL(k_cdf, dim3(1), dim3(256), 0, s, a->d_diag.as<double>(), N, a->d_cdf.as<double>());
     STN_HIP(hipGetLastError());
     const uint32_t blocks = std::min<uint32_t>((m + 256 * kDrawsPerLane - 1) / (256 * kDrawsPerLane), 1024);
-    hipLaunchKernelGGL(k_sample_bits, dim3(blocks), dim3(256), N * sizeof(double), s, a->d_cdf.as<double>(), N, u,
-                       m, out);
+    if (N <= kSampleLdsMax)
+        hipLaunchKernelGGL(k_sample_bits<true>, dim3(blocks), dim3(256), N * sizeof(double), s, a->d_cdf.as<double>(),
+                           N, u, m, out);
+    else
+        hipLaunchKernelGGL(k_sample_bits<false>, dim3(blocks), dim3(256), 0, s, a->d_cdf.as<double>(), N, u, m,
+                           out);
     STN_HIP(hipGetLastError());
 }
 

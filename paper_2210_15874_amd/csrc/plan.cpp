@@ -520,7 +520,11 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
         if (n <= lds_max) {
             kind = STN_PLAN_SV_LDS;
         } else if (dense_out) {
-            fail(STN_E_UNSUPPORTED, "density-matrix / state outputs need n <= " + std::to_string(lds_max));
+            // sigma alone is kept by the gate-by-gate lowering; rho_hat and states need LDS sizes
+            if ((outs & (STN_OUT_RHO | STN_OUT_STATES)) || n > kGatesMaxQubits)
+                fail(STN_E_UNSUPPORTED, "rho_hat / state outputs need n <= " + std::to_string(lds_max) +
+                                            " (sigma alone: n <= 30)");
+            kind = STN_PLAN_SV_GATES;
         } else {
             // statevector passes vs lightcone networks: estimated seconds per trajectory
             // (HBM-bound passes at ~4 TB/s; lightcone networks: their own estimate)
@@ -583,7 +587,8 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
         if (dense_out) fail(STN_E_UNSUPPORTED, "the lightcone lowering produces energies only");
         if (!p->lc) build_lightcone(p);
     } else if (kind == STN_PLAN_SV_GATES) {
-        if (dense_out) fail(STN_E_UNSUPPORTED, "the gate-by-gate lowering produces energies only");
+        if (outs & (STN_OUT_RHO | STN_OUT_STATES))
+            fail(STN_E_UNSUPPORTED, "the gate-by-gate lowering keeps energies and sigma only");
         if (n < 2 || n > kGatesMaxQubits) fail(STN_E_UNSUPPORTED, "the gate-by-gate lowering needs 2 <= n <= 30");
         if (p->lc && p->lc_free) {
             p->lc_free(p->lc);

@@ -250,9 +250,10 @@ def test_caller_contraction_order():
 def test_gate_by_gate_plans():
     """<C> jobs with non-unitary channels above the whole-state-in-LDS size
     have no Pauli frame (so no tiled or lightcone lowering): AUTO takes the
-    gate-by-gate HBM statevector; it is energy only and n <= 30."""
+    gate-by-gate HBM statevector, also for sigma above that size; it keeps
+    energies and sigma only, for n <= 30."""
     from workloads import make_problem, random_regular_graph, uniform_angles
-    from paper_2210_15874_amd import OUT_DIAG, OUT_ENERGY, PLAN_SV_GATES, StnError
+    from paper_2210_15874_amd import OUT_DIAG, OUT_ENERGY, OUT_RHO, OUT_STATES, PLAN_SV_GATES, StnError
     g, b = uniform_angles(2, 31)
     pr = make_problem(16, random_regular_graph(16, 3, 32), g, b, 1e-3, 1e-2, 8, 33, gamma_ad=0.01)
     i = plan(pr).info()
@@ -262,8 +263,14 @@ def test_gate_by_gate_plans():
     assert i["bytes_per_traj"] == 8.0 * (1 << 16) * (2 * i["n_passes"] + 2)
     pq = make_problem(16, random_regular_graph(16, 3, 32), g, b, 1e-3, 1e-2, 8, 33)
     assert plan(pq, plan_kind=PLAN_SV_GATES).info()["plan_name"] == "sv_gates"
-    with pytest.raises(StnError, match="UNSUPPORTED"):
-        plan(pr, plan_kind=PLAN_SV_GATES, outputs=OUT_DIAG | OUT_ENERGY)
+    # sigma (DIAG) is kept up to n = 30 by this lowering; rho_hat and states are not
+    assert plan(pr, outputs=OUT_DIAG | OUT_ENERGY).info()["plan_name"] == "sv_gates"
+    assert plan(pq, outputs=OUT_DIAG).info()["plan_name"] == "sv_gates"
+    for outs in (OUT_RHO, OUT_STATES | OUT_ENERGY):
+        with pytest.raises(StnError, match="UNSUPPORTED"):
+            plan(pr, plan_kind=PLAN_SV_GATES, outputs=outs)
+        with pytest.raises(StnError, match="UNSUPPORTED"):
+            plan(pr, outputs=outs)
     g1, b1 = uniform_angles(1, 34)
     big = make_problem(32, random_regular_graph(32, 3, 35), g1, b1, 1e-3, 1e-2, 8, 36, gamma_ad=0.01)
     with pytest.raises(StnError, match="UNSUPPORTED"):

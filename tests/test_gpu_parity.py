@@ -809,3 +809,58 @@ def test_gate_by_gate_large_state_matches_tiled():
         bt.close()
     m = len(pr.edges)
     np.testing.assert_allclose(res[stn.PLAN_SV_GATES] / m, res[stn.PLAN_SV_TILED] / m, atol=2e-5)
+
+
+def check_bitstrings(x, u, sigma, diag):
+    """Draws x (from the library, with uniforms u) against the oracle's draws
+    from its own sigma: equal wherever u lies farther than the two sides'
+    cumulative-sum difference from a boundary of the oracle's interval, and
+    inside the widened interval otherwise."""
+    from oracle.sampling import sample_bitstrings
+    xo = sample_bitstrings(sigma, u)
+    assert x.min() >= 0 and x.max() < len(sigma)
+    Fo = np.cumsum(sigma) / sigma.sum()
+    Fg = np.cumsum(diag) / diag.sum()
+    delta = 2 * np.abs(Fg - Fo).max() + 1e-15
+    lo = np.where(xo > 0, Fo[np.maximum(xo - 1, 0)], 0.0)
+    near = (np.abs(u - lo) < delta) | (np.abs(u - Fo[xo]) < delta)
+    assert (x[~near] == xo[~near]).all()
+    xn = x[near]
+    xl = np.where(xn > 0, Fo[np.maximum(xn - 1, 0)], 0.0)
+    assert ((xl - delta <= u[near]) & (u[near] < Fo[xn] + delta)).all()
+    assert near.mean() < 0.05
+
+
+@pytest.mark.parametrize("precision,tol", [(128, 1e-11), (64, 1e-5)])
+def test_gate_by_gate_sigma_and_bitstrings_against_oracle(precision, tol):
+    """sigma_approx above the whole-state-in-LDS size (n=14, amplitude
+    damping: the gate-by-gate lowering keeps it) against the oracle, over two
+    reduced batches; bitstrings drawn from it (running sums searched in
+    device memory: 2^14 states) against the oracle's sampler."""
+    import torch
+    from oracle import simulate as sim
+    from workloads import make_problem, random_regular_graph, uniform_angles
+    stn = stn_mod()
+    g, b = uniform_angles(2, 31)
+    pr = make_problem(14, random_regular_graph(14, 3, 32), g, b, 2e-3, 2e-2, 12, 33, gamma_ad=0.05)
+    pl = stn.Plan(pr, outputs=stn.OUT_DIAG | stn.OUT_ENERGY, precision=precision)
+    assert pl.info()["plan_name"] == "sv_gates"
+    acc = pl.accum()
+    for k0, K in ((0, 7), (7, 5)):
+        bt = pl.sample(pr.seed, k0, K)
+        pl.contract(bt)
+        pl.reduce(bt, acc)
+        bt.close()
+    ens = sim.ensemble(pr, pr.seed, 0, pr.K)
+    sigma = ens["sigma_approx"]
+    rng = np.random.default_rng(4200)
+    u = rng.random(200001)
+    u[:3] = [0.0, np.nextafter(1.0, 0.0), 0.5]
+    x = acc.sample(torch.from_numpy(u).cuda()).cpu().numpy().astype(np.int64)
+    torch.cuda.synchronize()
+    res = acc.read()
+    assert np.abs(res["diag"] - sigma).max() < tol * sigma.max()
+    m = len(pr.edges)
+    assert abs(res["energy_mean"] - ens["energies"].mean()) / m < tol
+    check_bitstrings(x, u, sigma, res["diag"])
+    acc.close()
