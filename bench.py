@@ -106,9 +106,6 @@ def main():
     ap.add_argument("--rho-leg", type=int, default=1, help="n=12 rho_hat workload leg (0: skip)")
     ap.add_argument("--gates-leg", type=int, default=1,
                     help="n=20 amplitude-damping <C> job in the gate-by-gate lowering (0: skip)")
-    ap.add_argument("--ksweep", action="store_true",
-                    help="rho_hat leg: fidelity / trace distance vs the exact density matrix for K = 16..1024 "
-                         "(adds minutes of CPU work)")
     ap.add_argument("--uneven", action="store_true",
                     help="only the uneven-batch leg: 64 jobs (n 10..30, p 1..6, K 256..8192) submitted at once to "
                          "the job server, for --uneven-window seconds")
@@ -254,7 +251,7 @@ def main():
     torch.cuda.empty_cache()
     plain = plain_loop(stn, problem, args.plain_traj, value, tune["chosen"]) if args.plain_traj > 0 else None
     torch.cuda.empty_cache()
-    rho_leg = rho_hat_leg(stn, args.ksweep) if args.rho_leg else None
+    rho_leg = rho_hat_leg(stn) if args.rho_leg else None
     torch.cuda.empty_cache()
     gates = gates_leg(stn) if args.gates_leg else None
     torch.cuda.empty_cache()
@@ -381,13 +378,10 @@ def gates_leg(stn):
             "energy_mean": res["energy_mean"], "energy_se": res["energy_se"]}
 
 
-def rho_hat_leg(stn, ksweep):
+def rho_hat_leg(stn):
     """n=12 QAOA p=2, 3-regular, depolarizing + amplitude damping, K=1024 in
     one launch: complex64 contraction, FP64 rho_hat (4096 x 4096).  Times the
-    job and its FP64 matrix-core rank-K update; with ksweep, the fidelity and
-    trace distance of nested prefixes K = 16 .. 1024 against the exact
-    density matrix (oracle, CPU)."""
-    import numpy as np
+    job, its FP64 matrix-core rank-K update and bitstring draws from sigma."""
     import torch
     from workloads import config_problem
     pr = config_problem(1)
@@ -430,35 +424,6 @@ def rho_hat_leg(stn, ksweep):
            "kernels_ms": {k: v["ms"] for k, v in prof.items() if v["launches"]},
            "herk_fp64_tflops": herk["flops"] / (herk["ms"] * 1e-3) / 1e12 if herk["ms"] else None,
            "herk_peak_tflops": 78.6, "trace": res["trace"]}
-    if ksweep:
-        from oracle import metrics, simulate as sim
-        t1 = time.perf_counter()
-        print("rho_hat leg: exact density matrix (oracle, CPU) ...", file=sys.stderr, flush=True)
-        rho = sim.density_matrix(pr)
-        N = rho.shape[0]
-        rho = rho.reshape(N, N)
-        out["dm_oracle_seconds"] = time.perf_counter() - t1
-        edges = [0, 16, 32, 64, 128, 256, 512, 1024]
-        acc_sum = np.zeros((N, N), dtype=np.complex128)
-        rows = []
-        for a, b in zip(edges[:-1], edges[1:]):
-            acc = pl.accum()
-            bt = pl.sample(pr.seed, a, b - a)
-            pl.contract(bt)
-            pl.reduce(bt, acc)
-            r = acc.read()
-            acc_sum += r["rho"] * r["k_done"]
-            acc.close()
-            bt.close()
-            est = acc_sum / b
-            est_n = est / np.trace(est).real
-            rows.append({"K": b, "trace": float(np.trace(est).real),
-                         "fidelity": metrics.uhlmann_fidelity(rho, est_n),
-                         "trace_distance": metrics.trace_distance(rho, est_n),
-                         "frobenius": metrics.frobenius(rho, est_n),
-                         "eq2_error": metrics.paper_error(np.diag(est_n).real, np.diag(rho).real)})
-            print(f"rho_hat leg: K={b} {rows[-1]}", file=sys.stderr, flush=True)
-        out["ksweep"] = rows
     pl.close()
     return out
 

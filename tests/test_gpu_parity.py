@@ -864,3 +864,39 @@ def test_gate_by_gate_sigma_and_bitstrings_against_oracle(precision, tol):
     assert abs(res["energy_mean"] - ens["energies"].mean()) / m < tol
     check_bitstrings(x, u, sigma, res["diag"])
     acc.close()
+
+
+def test_rho_hat_converges_to_exact_density_matrix_n12():
+    """n=12, p=2 with amplitude damping (the rho_hat workload): nested
+    prefixes K = 16 .. 1024 of the GPU ensemble against the oracle's exact
+    density matrix (Eq. (1)), estimate normalised by its trace.  Frobenius
+    distance falls about as K^(-1/2), the Eq. (2) error about as K^(-1)
+    (Sec. IV), and the trace distance falls."""
+    from oracle import metrics, simulate as sim
+    from workloads import config_problem
+    stn = stn_mod()
+    pr = config_problem(1)
+    rho = sim.density_matrix(pr)
+    N = rho.shape[0]
+    pl = stn.Plan(pr, outputs=stn.OUT_RHO, precision=64)
+    edges = [0, 16, 32, 64, 128, 256, 512, 1024]
+    acc_sum = np.zeros((N, N), dtype=np.complex128)
+    rows = []
+    for a, b in zip(edges[:-1], edges[1:]):
+        acc = pl.accum()
+        bt = pl.sample(pr.seed, a, b - a)
+        pl.contract(bt)
+        pl.reduce(bt, acc)
+        r = acc.read()
+        acc_sum += r["rho"] * r["k_done"]
+        acc.close()
+        bt.close()
+        est = acc_sum / b
+        est = est / np.trace(est).real
+        td = metrics.trace_distance(rho, est) if b in (16, 1024) else float("nan")
+        rows.append((b, td, metrics.frobenius(rho, est), metrics.paper_error(np.diag(est).real, np.diag(rho).real)))
+        print("K=%d TD=%.3f Frob=%.3f Eq2=%.2e" % rows[-1], flush=True)
+    first, last = rows[0], rows[-1]
+    assert last[2] < first[2] / 4          # 64x the trajectories: about 8x smaller
+    assert last[3] < first[3] / 16        # about 64x smaller
+    assert last[1] < first[1]
