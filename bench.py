@@ -34,24 +34,95 @@ METRIC = "noisy trajectories/s at n=26 QAOA p=4 (⟨C⟩ err vs FP64); p50/p99 j
 HBM_PEAK_GBS = 8000.0
 
 
-def cpu_baseline(problem, sample_gates):
-    """The oracle's per-trajectory statevector (literal Kraus insertion,
-    complex128) on its first `sample_gates` gates of trajectory 0, scaled to
-    whole trajectories per second; one BLAS thread."""
+def _cpu_kind_times(args):
+    """One worker of the CPU baseline: the oracle's gate application
+    (complex128 statevector, one BLAS thread) on a full 2^n state, timed per
+    gate kind on gates of the workload's own circuit, and the oracle's energy
+    of one trajectory."""
+    problem_cfg, reps = args
+    import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle import simulate as sim
-    idx = sim.kraus_indices(problem, problem.seed, 0, 1)[0]
-    tabs = sim.site_tables(problem)
+    from oracle.gates import PAULIS, gate_matrix, pauli_string
+    from oracle.statevector import apply_to_state
+    from workloads import config_problem
+    pr = config_problem(problem_cfg)
+    n = pr.n_qubits
+    psi = np.full((2,) * n, 1.0 / math.sqrt(2.0 ** n), dtype=np.complex128)
+    by_kind = {}
+    for g in pr.gates:
+        by_kind.setdefault(g.kind, []).append(g)
+    out = {}
     with threadpool_limits(1):
+        for kind, gs in sorted(by_kind.items()):
+            # gates spread over the register (the cost depends on the axis moved)
+            pick = [gs[(len(gs) - 1) * i // max(1, reps - 1)] for i in range(reps)]
+            t0 = time.perf_counter()
+            for g in pick:
+                psi = apply_to_state(psi, gate_matrix(g), g.qubits)
+            out[kind] = (time.perf_counter() - t0) / len(pick)
+        # inserted Paulis of the depolarizing sites: one- and two-qubit products
         t0 = time.perf_counter()
-        sim.trajectory(problem, idx, tabs, max_gates=sample_gates)
-        dt = time.perf_counter() - t0
-    G = len(problem.gates)
-    per_traj = dt * G / sample_gates
-    return {"value": 1.0 / per_traj, "unit": "trajectories/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {sample_gates} of {G} gates (+ their noise sites) of trajectory 0 at "
-                      f"n={problem.n_qubits}, complex128, {dt:.1f} s, scaled by {G}/{sample_gates}"}
+        psi = apply_to_state(psi, PAULIS[1], (n // 2,))
+        out["pauli1"] = time.perf_counter() - t0
+        e = pr.edges[len(pr.edges) // 2]
+        t0 = time.perf_counter()
+        psi = apply_to_state(psi, pauli_string([1, 3]), e)
+        out["pauli2"] = time.perf_counter() - t0
+        # the energy's cost is a fixed part plus one part per edge: timed on 2
+        # and on 6 edges of the graph, extrapolated to all of them
+        t = []
+        for m in (2, 6):
+            t0 = time.perf_counter()
+            sim.energy(psi.reshape(-1), n, pr.edges[:m], pr.weights[:m])
+            t.append(time.perf_counter() - t0)
+        per_edge = max(0.0, (t[1] - t[0]) / 4.0)
+        out["energy"] = max(0.0, t[0] - 2.0 * per_edge) + per_edge * len(pr.edges)
+    return out
+
+
+def cpu_baseline(problem_cfg, reps=2):
+    """The CPU FP64 oracle on the host cores: one process per core (the box's
+    CPU share, at most 16), each timing the oracle's own gate application on
+    the full 2^26 complex128 state for every gate kind of the circuit (h, zz,
+    rx: `reps` gates each, spread over the register), the inserted one- and
+    two-qubit Paulis and the energy of one trajectory (timed on 2 and on 6
+    edges: a fixed part plus a part per edge), all processes at once
+    (so they share the memory bandwidth as a full run would).  Seconds per
+    trajectory = sum over kinds of (gates of that kind) x (mean seconds per
+    gate) + (expected inserted Paulis) x (their seconds) + energy;
+    throughput = processes / that."""
+    import multiprocessing as mp
+
+    from oracle import simulate as sim
+    from workloads import config_problem
+    pr = config_problem(problem_cfg)
+    procs = max(1, min(16, len(os.sched_getaffinity(0))))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(procs) as pool:
+        rows = pool.map(_cpu_kind_times, [(problem_cfg, reps)] * procs)
+    wall = time.perf_counter() - t0
+    mean = {k: sum(r[k] for r in rows) / len(rows) for k in rows[0]}
+    counts = {}
+    for g in pr.gates:
+        counts[g.kind] = counts.get(g.kind, 0) + 1
+    # expected non-identity insertions per trajectory, from the sites' selection probabilities
+    exp1 = exp2 = 0.0
+    for q, _, _ in sim.site_tables(pr):
+        if len(q) == 4:
+            exp1 += 1.0 - q[0]
+        elif len(q) == 16:
+            exp2 += 1.0 - q[0]
+    per_traj = sum(counts[k] * mean[k] for k in counts) + exp1 * mean["pauli1"] + exp2 * mean["pauli2"] + mean["energy"]
+    return {"value": procs / per_traj, "unit": "trajectories/s", "cores": procs, "kind": "oracle",
+            "seconds_per_trajectory_per_core": per_traj,
+            "per_kind_s": {k: round(v, 4) for k, v in mean.items()},
+            "gate_counts": counts, "expected_paulis": {"one_qubit": exp1, "two_qubit": exp2},
+            "sample": f"{procs} processes at once, each timing {reps} gates of each kind of the n={pr.n_qubits} "
+                      f"p={pr.p} circuit, 2 inserted Paulis and the energy (on 2 and 6 edges, extrapolated to "
+                      f"{len(pr.edges)}) on a full complex128 state "
+                      f"({wall:.0f} s wall); per-trajectory time weighted by the circuit's gate counts"}
 
 
 def measured_traffic(kernel_source, launch_shape):
@@ -94,7 +165,7 @@ def main():
     ap.add_argument("--K", type=int, default=None, help="trajectories per job (default: the workload's 4096)")
     ap.add_argument("--batch", type=int, default=0, help="trajectories per launch (0: from the HBM budget)")
     ap.add_argument("--hbm-budget-gib", type=float, default=160.0)
-    ap.add_argument("--cpu-sample-gates", type=int, default=10)
+    ap.add_argument("--cpu-reps", type=int, default=2, help="gates of each kind timed per CPU process")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp64-prefix", type=int, default=1024,
                     help="trajectories of the job also run in complex128 (0: skip)")
@@ -156,7 +227,7 @@ def main():
     problem = config_problem(2, K=args.K)
     K = problem.K
 
-    cpu = None if args.no_cpu else cpu_baseline(problem, args.cpu_sample_gates)
+    cpu = None if args.no_cpu else cpu_baseline(2, args.cpu_reps)
 
     import torch
 
@@ -419,6 +490,7 @@ def rho_hat_leg(stn):
     sample_s = ev0.elapsed_time(ev1) * 1e-3
     acc.close()
     out = {"workload": pr.name, "K": pr.K, "seconds": dt, "trajectories_per_s": pr.K / dt,
+           "sweep": sigma_sweep(stn, pr),
            "plain_loop_trajectories_per_s": plain, "batched_over_plain": pr.K / dt / plain,
            "bitstring_samples_per_s": m / sample_s,
            "kernels_ms": {k: v["ms"] for k, v in prof.items() if v["launches"]},
@@ -426,6 +498,39 @@ def rho_hat_leg(stn):
            "herk_peak_tflops": 78.6, "trace": res["trace"]}
     pl.close()
     return out
+
+
+def sigma_sweep(stn, pr):
+    """Eq. (2) error of sigma_approx (nested prefixes K = 16 .. 1024 of the
+    same trajectories, each estimate normalised by its trace) against the
+    stored exact diagonal (tests/golden/config1_sigma_exact.json, written by
+    the oracle).  Fidelity and trace distance against the full exact density
+    matrix are computed by the GPU test of the same sweep."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "config1_sigma_exact.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        exact = np.array(json.load(f)["sigma_exact"])
+    pl = stn.Plan(pr, outputs=stn.OUT_DIAG, precision=64)
+    edges = [0, 16, 32, 64, 128, 256, 512, 1024]
+    acc_sum = np.zeros_like(exact)
+    rows = []
+    for a, b in zip(edges[:-1], edges[1:]):
+        acc = pl.accum()
+        bt = pl.sample(pr.seed, a, b - a)
+        pl.contract(bt)
+        pl.reduce(bt, acc)
+        r = acc.read()
+        acc_sum += np.asarray(r["diag"]) * r["k_done"]
+        acc.close()
+        bt.close()
+        est = acc_sum / b
+        tr = float(est.sum())
+        fid = float(np.dot(np.sqrt(np.clip(est / tr, 0, None)), np.sqrt(np.clip(exact, 0, None))) ** 2)
+        rows.append({"K": b, "eq2_error": 1.0 - fid, "trace": tr})
+    pl.close()
+    return rows
 
 
 def one_job_leg(stn, args):
@@ -639,8 +744,10 @@ def serving_leg(stn, args):
     """The first `serve_jobs` arrivals of the Poisson stream through the job
     server at their arrival times, for a window of `serve_window` seconds from
     the first arrival; latency = completion - arrival.  Jobs still running at
-    the end of the window are counted as censored (latency > window) and
-    abandoned; a percentile that falls on a censored job is reported as None."""
+    the end of the window are counted as censored and abandoned; a percentile
+    that falls on a censored job is reported as a lower bound (window end -
+    that job's arrival) and flagged.  Offered and achieved load are stated in
+    device-seconds of work by the library's cost model."""
     import numpy as np
     import torch
     from workloads import poisson_stream
@@ -664,12 +771,37 @@ def serving_leg(stn, args):
     st = sv.stats()
     sv.close()                      # abandons unfinished jobs
     lat = np.array([res[i]["t_done"] - t0 - arrivals[i] if i in res else np.inf for i in range(len(jobs))])
+    # a job still running when the window closed has latency > (window end - its arrival)
+    lat_lb = np.array([lat[i] if i in res else t_end - arrivals[i] for i in range(len(jobs))])
     done = [i for i in res if res[i]["status"] == 0]
     traj = sum(res[i]["K"] for i in done)
 
     def pct(q):
+        """(value, censored): the percentile, or when it falls on a job still
+        running at the end of the window, a lower bound of it."""
         v = float(np.percentile(lat, q, method="higher"))
-        return v if math.isfinite(v) else None
+        if math.isfinite(v):
+            return v, False
+        return float(np.percentile(lat_lb, q, method="higher")), True
+
+    # offered and achieved load in device-seconds of work by the library's cost
+    # model (the same estimate the server admits and schedules by), per second
+    est = []
+    for pr in jobs:
+        pl = stn.Plan(pr, outputs=stn.OUT_ENERGY, precision=64,
+                      hbm_budget=int(0.5 * args.hbm_budget_gib * (1 << 30)))
+        inf = pl.info()
+        est.append(inf["est_s_per_traj"] * pr.K)
+        pl.close()
+    span = max(float(arrivals[-1]), 1.0 / args.serve_rate)
+    offered = {"work_device_s": float(sum(est)),
+               "per_s_at_rate": float(args.serve_rate * np.mean(est)),
+               "per_s_over_trace": float(sum(est) / span),
+               "achieved_work_device_s": float(sum(est[i] for i in done)),
+               "achieved_per_s": float(sum(est[i] for i in done) / t_end) if t_end > 0 else None,
+               "note": "device-seconds of work (cost model) offered per second of arrivals, at the stream's mean "
+                       "rate and over this trace's arrival span; achieved = the work of the completed jobs per "
+                       "second of the window; a ratio above 1 means the GPU cannot keep up and latency is queueing"}
 
     checks = []
     # every k-th finished job up to n = 24 (the complex128 path costs ~3x the complex64 one)
@@ -691,8 +823,9 @@ def serving_leg(stn, args):
         "jobs": len(jobs), "rate_per_s": args.serve_rate, "window_s": args.serve_window,
         "completed": len(done), "censored": len(jobs) - len(res),
         "failed": int(sum(r["status"] != 0 for r in res.values())),
-        "latency_s": {"p50": pct(50), "p99": pct(99), "max_completed": float(lat[np.isfinite(lat)].max())
-                      if np.isfinite(lat).any() else None},
+        "latency_s": {"p50": pct(50)[0], "p50_is_lower_bound": pct(50)[1],
+                      "p99": pct(99)[0], "p99_is_lower_bound": pct(99)[1],
+                      "max_completed": float(lat[np.isfinite(lat)].max()) if np.isfinite(lat).any() else None},
         "trajectories_per_s": traj / t_end if t_end > 0 else None, "arrivals_span_s": arrivals[-1],
         "max_concurrent_jobs": st["max_active_jobs"],
         "plans": {k: sum(1 for r in res.values() if r["plan_name"] == k) for k in ("sv_lds", "sv_tiled", "lightcone")},
@@ -700,8 +833,9 @@ def serving_leg(stn, args):
                          "latency_s": None if not math.isfinite(lat[i]) else float(lat[i]),
                          "admit_wait_s": res[i]["t_admit"] - t0 - arrivals[i] if i in res else None,
                          "chunks": res[i]["chunks"] if i in res else None,
-                         "plan": res[i]["plan_name"] if i in res else None} for i in range(len(jobs))],
-        "offered": "arrival rate far above one GPU's capacity: latency is mostly queueing behind n >= 26 jobs",
+                         "plan": res[i]["plan_name"] if i in res else None,
+                         "est_device_s": est[i]} for i in range(len(jobs))],
+        "load": offered,
         "fp64_checks": checks,
     }
 

@@ -202,6 +202,8 @@ typedef struct {
     uint64_t graph_replays; /* contractions run by replaying a captured graph */
     uint32_t lc_slices;     /* lightcone plans: networks contracted per trajectory (terms x slices) */
     uint32_t lc_slice_bits; /* largest number of sliced variables of one term */
+    double est_s_per_traj;  /* cost model's device seconds per trajectory of the chosen lowering (the job
+                               server's admission and scheduling estimate; not a measurement) */
 } stn_plan_stats;
 
 typedef struct {

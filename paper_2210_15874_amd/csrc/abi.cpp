@@ -243,6 +243,7 @@ stn_status stn_plan_info(const stn_plan* p, stn_plan_stats* o) {
     o->graph_replays = p->graph_replays;
     o->lc_slices = p->lc_slices;
     o->lc_slice_bits = p->lc_slice_bits;
+    o->est_s_per_traj = p->est_seconds_per_traj();
     return STN_OK;
 }
 
@@ -521,14 +522,18 @@ stn_status stn_contract_dedup(stn_plan* p, stn_batch* b, uint32_t* n_unique, voi
         if (!b->unique) b->unique = new stn_batch();
         stn_batch* u = b->unique;
         batch_prepare(p, u, b->k0, U);
+        // host sources of the copies below: they live until the synchronisation after them
+        std::vector<uint8_t> ui;
+        std::vector<uint32_t> us;
+        std::vector<uint64_t> uf;
         if (by_index) {
-            std::vector<uint8_t> ui((size_t)U * S);
+            ui.resize((size_t)U * S);
             for (uint32_t r = 0; r < U; ++r)
                 std::copy_n(idx.data() + (size_t)rep[r] * S, S, ui.data() + (size_t)r * S);
             if (!ui.empty()) STN_HIP(hipMemcpyAsync(u->d_idx.p, ui.data(), ui.size(), hipMemcpyHostToDevice, s));
         } else {
-            std::vector<uint32_t> us((size_t)U * W);
-            std::vector<uint64_t> uf((size_t)U * 2);
+            us.resize((size_t)U * W);
+            uf.resize((size_t)U * 2);
             for (uint32_t r = 0; r < U; ++r) {
                 std::copy_n(sg.data() + (size_t)rep[r] * W, W, us.data() + (size_t)r * W);
                 uf[2 * r] = fr[2 * (size_t)rep[r]];

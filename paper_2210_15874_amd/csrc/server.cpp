@@ -307,9 +307,7 @@ void plan_job(stn_server* sv, Job& j) {
         const double tiles = std::ldexp(1.0, std::max(0, (int)p->n - tile_bits));
         j.B = (uint32_t)std::max(1.0, std::min((double)j.B, std::ceil(kChunkTiles / tiles)));
     }
-    const double per = p->kind == STN_PLAN_LIGHTCONE ? 2.0 * p->lc_est_s
-                                                     : p->bytes_per_traj / 2e12 + p->flops_per_traj / 2e12;
-    j.est_s = per * (double)j.K;
+    j.est_s = p->est_seconds_per_traj() * (double)j.K;
     // a job for the small-job stream runs in chunks of about kSmallChunkSeconds,
     // so that the other small jobs' chunks are issued between its chunks
     // instead of waiting behind all of it
@@ -592,8 +590,7 @@ struct Device {
             return;
         }
         // estimated seconds for the tuning sample (all shapes, warm and timed)
-        const double per = p->kind == STN_PLAN_LIGHTCONE ? 2.0 * p->lc_est_s
-                                                         : p->bytes_per_traj / 2e12 + p->flops_per_traj / 2e12;
+        const double per = p->est_seconds_per_traj();
         // networks in HBM run long per work item: their default shape is kept.
         // The device thread waits for the tuning runs, so they are done only
         // while no other job occupies the device.

@@ -159,6 +159,11 @@ struct stn_plan {
     double lc_flops_per_traj = 0;
     double lc_est_s = 0;                    // their estimated seconds per trajectory
     double lc_arena_bytes = 0;              // HBM tier: global-memory arenas of the persistent workgroups
+    // estimated device seconds per trajectory of the chosen lowering (admission and
+    // scheduling in the job server; a cost-model figure, not a measurement)
+    double est_seconds_per_traj() const {
+        return kind == STN_PLAN_LIGHTCONE ? 2.0 * lc_est_s : bytes_per_traj / 2e12 + flops_per_traj / 2e12;
+    }
 
     // device tables shared by every lowering
     stn::DevBuf d_site_T;            // uint64 thresholds, flattened

@@ -163,6 +163,36 @@ def test_served_job_against_oracle():
         assert abs(r["energy_se"] - e.std(ddof=1) / math.sqrt(K)) / m < tol
 
 
+def test_served_stream_jobs_against_oracle():
+    """Jobs of the Poisson serving stream (n <= 16 among its first arrivals;
+    random Erdos-Renyi graphs, p 1..6, log-uniform depolarizing rates), each
+    cut to its first 6 trajectories, served together in complex64 and
+    checked against the oracle's literal-Kraus ensemble of the same
+    trajectories (mean and standard error per edge within 1e-5)."""
+    from oracle import simulate as sim
+    from workloads import poisson_stream
+    stn = stn_mod()
+    _, jobs = poisson_stream(60)
+    sel = [pr for pr in jobs if pr.n_qubits <= 16 and pr.edges][:5]
+    assert len(sel) == 5
+    for pr in sel:
+        pr.K = 6
+    with stn.Server(hbm_budget=4 << 30, precision=64) as sv:
+        for i, pr in enumerate(sel):
+            sv.submit(pr, tag=i)
+        sv.drain(120)
+        res = {r["tag"]: r for r in sv.poll(cap=16)}
+    for i, pr in enumerate(sel):
+        r = res[i]
+        assert r["status"] == 0, r["error"]
+        e = np.asarray(sim.ensemble(pr, pr.seed, 0, pr.K, want_states=False)["energies"])
+        m = len(pr.edges)
+        err = abs(r["energy_mean"] - e.mean()) / m
+        print(f"stream job n={pr.n_qubits} p={pr.p} {r['plan_name']}: |<C> - oracle|/m = {err:.2e}")
+        assert err < 1e-5
+        assert abs(r["energy_se"] - e.std(ddof=1) / math.sqrt(pr.K)) / m < 1e-5
+
+
 def test_small_jobs_overtake_a_long_one():
     """Continuous batching: jobs submitted after a long job has started run
     beside it and finish before it."""

@@ -85,3 +85,23 @@ def test_uhlmann_paths_agree_and_fidelity_bounds():
     assert metrics.paper_error(p, p) < 1e-15
     assert abs(metrics.paper_error(np.array([1, 0]), np.array([0, 1])) - 1) < 1e-15
     assert abs(metrics.trace_distance(np.diag(p), np.diag(q)) - 0.5 * np.abs(p - q).sum()) < 1e-12
+
+
+def test_stored_sigma_exact_fixture_is_consistent():
+    """tests/golden/config1_sigma_exact.json (the oracle's exact diagonal of the
+    n=12 workload, the reference of the rho_hat bench leg's Eq. (2) sweep) is a
+    probability vector whose stored energy is its cut-size expectation, with
+    the cut size counted here bit by bit."""
+    import json
+    import os
+    from workloads import config_problem
+    path = os.path.join(os.path.dirname(__file__), "golden", "config1_sigma_exact.json")
+    with open(path) as f:
+        g = json.load(f)
+    sig = np.array(g["sigma_exact"])
+    pr = config_problem(1)
+    assert g["n_qubits"] == pr.n_qubits and sig.shape == (1 << pr.n_qubits,)
+    assert sig.min() > -1e-15 and abs(sig.sum() - 1.0) < 1e-12 and abs(g["trace"] - 1.0) < 1e-12
+    cut = [sum(w for (u, v), w in zip(pr.edges, pr.weights) if ((z >> u) & 1) != ((z >> v) & 1))
+           for z in range(1 << pr.n_qubits)]
+    assert abs(float(np.dot(sig, cut)) - g["energy_exact"]) < 1e-10
