@@ -933,8 +933,10 @@ def test_rho_hat_converges_to_exact_density_matrix_n12():
                          eq2_error=metrics.paper_error(np.diag(est).real, np.diag(rho).real), trace=tr))
         print("K=%(K)d F=%(uhlmann_F).4f TD=%(trace_distance).4f Frob=%(frobenius).4f Eq2=%(eq2_error).2e "
               "Tr=%(trace).6f" % rows[-1], flush=True)
-    # the state-based fidelity equals the matrix definition on the final estimate
-    assert abs(rows[-1]["uhlmann_F"] - metrics.uhlmann_fidelity(rho, est)) < 1e-6
+    # the state-based fidelity equals the matrix definition on the final estimate; the matrix
+    # form takes square roots of the rounding-level eigenvalues in the null space of the
+    # rank-1024 estimate (about 3000 of them), which adds up to about 1e-5
+    assert abs(rows[-1]["uhlmann_F"] - metrics.uhlmann_fidelity(rho, est)) < 1e-4
     if os.environ.get("STN_RECORD_DIR"):
         os.makedirs(os.environ["STN_RECORD_DIR"], exist_ok=True)
         with open(os.path.join(os.environ["STN_RECORD_DIR"], "rho_hat_sweep_n12.json"), "w") as f:
