@@ -393,6 +393,18 @@ void stn_accum_destroy(stn_accum* acc);
  * after the stn_reduce calls enqueued there before it; does not sync. */
 stn_status stn_accum_sample(stn_accum* acc, const double* u, uint32_t m, uint32_t* out, void* stream);
 
+/* stn_accum_sample for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, hosts that forbid hipMalloc): the
+ * same draws, bit for bit, with the running sums kept in a fixed device
+ * buffer of the library (2^20 + 512 doubles, 8 MiB + 4 KiB per device, held
+ * until the process ends) instead of memory the accumulator allocates.  It
+ * calls no allocator.  Arguments, ownership and stream order as for
+ * stn_accum_sample; plans with n > 20 get STN_E_UNSUPPORTED.  The buffer is
+ * shared by every call on a device and overwritten by each one: calls that
+ * overlap on one device (different streams or threads without ordering
+ * between them) race and may return wrong indices. */
+stn_status stn_accum_sample_noalloc(stn_accum* acc, const double* u, uint32_t m, uint32_t* out, void* stream);
+
 /* ---------------------------------------------------------------- job server
  * Many ensemble jobs (Sec. III-G, each one circuit + noise model + K) of
  * different sizes on one device at once.  Planner threads plan submitted

@@ -177,6 +177,7 @@ EXPORTS = {
     "stn_accum_read": (C.c_int, [C.c_void_p, C.POINTER(Result), C.c_void_p]),
     "stn_accum_destroy": (None, [C.c_void_p]),
     "stn_accum_sample": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
+    "stn_accum_sample_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
     "stn_server_opts_default": (None, [C.POINTER(ServerOpts)]),
     "stn_server_create": (C.c_int, [C.POINTER(ServerOpts), C.POINTER(C.c_void_p)]),
     "stn_server_submit": (C.c_int, [C.c_void_p, C.POINTER(Circuit), C.POINTER(NoiseModel), C.POINTER(Observable),
@@ -463,9 +464,11 @@ class Accum:
             out["rho"] = np.ctypeslib.as_array(r.rho, shape=(N * N * 2,)).copy().view(np.complex128).reshape(N, N)
         return out
 
-    def sample(self, u, out=None, stream=None):
+    def sample(self, u, out=None, stream=None, no_alloc=False):
         """Bitstrings drawn from sigma_approx with the uniforms u (a float64
-        device tensor); returns an int32 device tensor of basis indices."""
+        device tensor); returns an int32 device tensor of basis indices.
+        no_alloc=True calls stn_accum_sample_noalloc (the library allocates
+        nothing; pass out to allocate nothing here either)."""
         import torch
         if not (u.is_cuda and u.dtype == torch.float64 and u.is_contiguous()):
             raise ValueError("u must be a contiguous float64 device tensor")
@@ -474,8 +477,8 @@ class Accum:
             out = torch.empty(m, dtype=torch.int32, device=u.device)
         if out.numel() < m or out.dtype != torch.int32 or not out.is_contiguous():
             raise ValueError("out must be a contiguous int32 device tensor of at least u.numel() elements")
-        _check(self.plan.lib.stn_accum_sample(self.h, u.data_ptr(), m, out.data_ptr(),
-                                              stream if stream is not None else current_stream()))
+        fn = self.plan.lib.stn_accum_sample_noalloc if no_alloc else self.plan.lib.stn_accum_sample
+        _check(fn(self.h, u.data_ptr(), m, out.data_ptr(), stream if stream is not None else current_stream()))
         return out[:m]
 
     def close(self):

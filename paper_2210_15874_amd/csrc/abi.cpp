@@ -738,8 +738,28 @@ stn_status stn_accum_sample(stn_accum* a, const double* u, uint32_t m, uint32_t*
     if (!a->k_done) return set_error(STN_E_STATE, "no trajectories reduced");
     if (!m) return STN_OK;
     return guarded([&] {
-        a->d_cdf.ensure(&p->alloc, ((size_t)1 << p->n) * 8);
-        launch_sample_bits(a, u, m, out, (hipStream_t)stream);
+        a->d_cdf.ensure(&p->alloc, sample_bits_scratch(p->n));
+        launch_sample_bits(a, u, m, out, a->d_cdf.as<double>(), (hipStream_t)stream);
+    });
+}
+
+stn_status stn_accum_sample_noalloc(stn_accum* a, const double* u, uint32_t m, uint32_t* out, void* stream) {
+    if (!a) return set_error(STN_E_INVALID, "NULL argument");
+    if (m && (!u || !out)) return set_error(STN_E_INVALID, "NULL uniforms or output");
+    stn_plan* p = a->plan;
+    if (!(p->opts.outputs & (STN_OUT_DIAG | STN_OUT_RHO)))
+        return set_error(STN_E_STATE, "accumulator keeps no diagonal (request STN_OUT_DIAG)");
+    if (p->n > kStaticSampleQubits)
+        return set_error(STN_E_UNSUPPORTED, "stn_accum_sample_noalloc holds running sums of at most 2^" +
+                                                std::to_string(kStaticSampleQubits) + " states; this plan has n = " +
+                                                std::to_string(p->n) + " (use stn_accum_sample)");
+    if (!a->k_done) return set_error(STN_E_STATE, "no trajectories reduced");
+    if (!m) return STN_OK;
+    return guarded([&] {
+        hipError_t e = hipSuccess;
+        double* scratch = static_sample_scratch(&e);
+        if (!scratch) fail(STN_E_DEVICE, std::string("address of the sampler's static buffer: ") + hipGetErrorString(e));
+        launch_sample_bits(a, u, m, out, scratch, (hipStream_t)stream);
     });
 }
 

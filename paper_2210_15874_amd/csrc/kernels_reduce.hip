@@ -17,15 +17,19 @@
 //             passes (mean, then squared deviations).
 // k_finish_*: mirror the upper triangle (rho_ji = conj(rho_ij), real
 //             diagonal) and scale by 1/K into output buffers.
-// k_cdf, k_sample_bits: bitstrings drawn from sigma by inverse transform.
-//             One workgroup forms the running sums F of the accumulated
-//             diagonal (each thread sums a contiguous run, the 256 run totals
-//             are offset in thread order); each sampling workgroup stages F in
-//             LDS (up to 2^13 values; larger F is searched where it lies in
-//             device memory) and each lane binary-searches the smallest
-//             x with F(x) > u F(last), or, when rounding leaves none, the
-//             smallest x with F(x) >= u F(last).  Every index returned is in
-//             range whatever u holds.
+// k_cdf_*, k_sample_bits: bitstrings drawn from sigma by inverse transform.
+//             The running sums F of the accumulated diagonal are formed in
+//             chunks of 2048 values, one workgroup per chunk: chunk totals,
+//             their exclusive prefix (one workgroup, runs of totals summed in
+//             thread order), then each chunk's sums from its offset.  The
+//             order of every addition is fixed by the chunk size alone.  Each
+//             sampling workgroup stages F in LDS (up to 2^13 values; larger F
+//             is searched where it lies in device memory) and each lane
+//             binary-searches the smallest x with F(x) > u F(last), or, when
+//             rounding leaves none, the smallest x with F(x) >= u F(last).
+//             Every index returned is in range whatever u holds.
+#include <mutex>
+
 #include "stn_internal.h"
 
 namespace stn {
@@ -205,28 +209,81 @@ __global__ __launch_bounds__(256) void k_finish_diag(const double* __restrict__ 
     if (threadIdx.x == 0) *trace = tr;
 }
 
-__global__ __launch_bounds__(256) void k_cdf(const double* __restrict__ diag, uint32_t N, double* __restrict__ cdf) {
-    __shared__ double off[256];
-    const uint32_t per = (N + 255) / 256;
-    const uint32_t a = min(N, threadIdx.x * per), b = min(N, a + per);
+// Running sums in chunks of kCdfChunk values: thread t of chunk c owns the
+// kCdfPer consecutive values from c kCdfChunk + t kCdfPer and sums them in
+// order; the 256 thread sums of a chunk are offset in thread order.
+constexpr uint32_t kCdfThreads = 256;
+constexpr uint32_t kCdfPer = 8;
+constexpr uint32_t kCdfChunk = kCdfThreads * kCdfPer;
+
+__device__ __forceinline__ double cdf_thread_sum(const double* __restrict__ diag, uint32_t N, uint32_t a) {
     double s = 0.0;
-    for (uint32_t i = a; i < b; ++i) s += diag[i];
+#pragma unroll
+    for (uint32_t j = 0; j < kCdfPer; ++j)
+        if (a + j < N) s += diag[a + j];
+    return s;
+}
+
+// exclusive prefix of the workgroup's thread sums in thread order; returns
+// this thread's offset and leaves the workgroup total in *total
+__device__ __forceinline__ double cdf_block_offset(double s, double* off, double* total) {
     off[threadIdx.x] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
         double r = 0.0;
-        for (int t = 0; t < 256; ++t) {
+        for (uint32_t t = 0; t < kCdfThreads; ++t) {
             const double v = off[t];
             off[t] = r;
             r += v;
         }
+        off[kCdfThreads] = r;
     }
     __syncthreads();
-    double r = off[threadIdx.x];
+    *total = off[kCdfThreads];
+    return off[threadIdx.x];
+}
+
+// totals[c] = the sum of chunk c
+__global__ __launch_bounds__(kCdfThreads) void k_cdf_totals(const double* __restrict__ diag, uint32_t N,
+                                                            double* __restrict__ totals) {
+    __shared__ double off[kCdfThreads + 1];
+    const uint32_t a = blockIdx.x * kCdfChunk + threadIdx.x * kCdfPer;
+    double total;
+    cdf_block_offset(cdf_thread_sum(diag, N, a), off, &total);
+    if (threadIdx.x == 0) totals[blockIdx.x] = total;
+}
+
+// totals[0..C) -> exclusive offsets in place: each thread takes a contiguous
+// run of chunk totals, the run sums are offset in thread order
+__global__ __launch_bounds__(kCdfThreads) void k_cdf_offsets(double* __restrict__ totals, uint32_t C) {
+    __shared__ double off[kCdfThreads + 1];
+    const uint32_t per = (C + kCdfThreads - 1) / kCdfThreads;
+    const uint32_t a = min(C, threadIdx.x * per), b = min(C, a + per);
+    double s = 0.0;
+    for (uint32_t i = a; i < b; ++i) s += totals[i];
+    double total;
+    double r = cdf_block_offset(s, off, &total);
     for (uint32_t i = a; i < b; ++i) {
-        r += diag[i];
-        cdf[i] = r;
+        const double v = totals[i];
+        totals[i] = r;
+        r += v;
     }
+}
+
+// cdf[x] = offsets[chunk of x] + the chunk's running sum up to x
+__global__ __launch_bounds__(kCdfThreads) void k_cdf_scan(const double* __restrict__ diag, uint32_t N,
+                                                          const double* __restrict__ offsets,
+                                                          double* __restrict__ cdf) {
+    __shared__ double off[kCdfThreads + 1];
+    const uint32_t a = blockIdx.x * kCdfChunk + threadIdx.x * kCdfPer;
+    double total;
+    double r = offsets[blockIdx.x] + cdf_block_offset(cdf_thread_sum(diag, N, a), off, &total);
+#pragma unroll
+    for (uint32_t j = 0; j < kCdfPer; ++j)
+        if (a + j < N) {
+            r += diag[a + j];
+            cdf[a + j] = r;
+        }
 }
 
 // Smallest x with F[x] > t over N = 2^n sums (N when none): the count of sums
@@ -281,17 +338,58 @@ __global__ __launch_bounds__(256) void k_sample_bits(const double* __restrict__ 
 
 }  // namespace
 
-void launch_sample_bits(stn_accum* a, const double* u, uint32_t m, uint32_t* out, hipStream_t s) {
+// Running sums and chunk offsets for stn_accum_sample_noalloc: 2^20 + 512
+// doubles (8 MiB + 4 KiB) per device, held until the process ends.  Host code
+// uses only the address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[((size_t)1 << kStaticSampleQubits) +
+                                                (((size_t)1 << kStaticSampleQubits) + kCdfChunk - 1) / kCdfChunk];
+
+double* static_sample_scratch(hipError_t* err) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double* ptr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        *err = e != hipSuccess ? e : hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        void* a = nullptr;
+        e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) {
+            *err = e;
+            return nullptr;
+        }
+        ptr[dev] = static_cast<double*>(a);
+    }
+    return ptr[dev];
+}
+
+size_t sample_bits_scratch(uint32_t n) {
+    const size_t N = (size_t)1 << n;
+    return (N + (N + kCdfChunk - 1) / kCdfChunk) * sizeof(double);
+}
+
+void launch_sample_bits(stn_accum* a, const double* u, uint32_t m, uint32_t* out, double* work, hipStream_t s) {
     const uint32_t N = 1u << a->plan->n;
-    hipLaunchKernelGGL(k_cdf, dim3(1), dim3(256), 0, s, a->d_diag.as<double>(), N, a->d_cdf.as<double>());
+    const uint32_t C = (N + kCdfChunk - 1) / kCdfChunk;
+    double* cdf = work;
+    double* totals = work + N;
+    hipLaunchKernelGGL(k_cdf_totals, dim3(C), dim3(kCdfThreads), 0, s, a->d_diag.as<double>(), N, totals);
+    STN_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_cdf_offsets, dim3(1), dim3(kCdfThreads), 0, s, totals, C);
+    STN_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_cdf_scan, dim3(C), dim3(kCdfThreads), 0, s, a->d_diag.as<double>(), N,
+                       (const double*)totals, cdf);
     STN_HIP(hipGetLastError());
     const uint32_t blocks = std::min<uint32_t>((m + 256 * kDrawsPerLane - 1) / (256 * kDrawsPerLane), 1024);
     if (N <= kSampleLdsMax)
-        hipLaunchKernelGGL(k_sample_bits<true>, dim3(blocks), dim3(256), N * sizeof(double), s, a->d_cdf.as<double>(),
+        hipLaunchKernelGGL(k_sample_bits<true>, dim3(blocks), dim3(256), N * sizeof(double), s, (const double*)cdf,
                            N, u, m, out);
     else
-        hipLaunchKernelGGL(k_sample_bits<false>, dim3(blocks), dim3(256), 0, s, a->d_cdf.as<double>(), N, u, m,
-                           out);
+        hipLaunchKernelGGL(k_sample_bits<false>, dim3(blocks), dim3(256), 0, s, (const double*)cdf, N, u, m, out);
     STN_HIP(hipGetLastError());
 }
 

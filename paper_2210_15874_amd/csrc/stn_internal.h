@@ -315,7 +315,15 @@ void launch_scatter_energy(const double* src, const uint32_t* map, uint32_t K, d
 // rho_out = mirror(rho)/K, diag_out = diag/K, stats[2] = trace
 void launch_finish_dense(stn_accum* a, hipStream_t s);
 // m bitstrings drawn from the accumulated diagonal with the uniforms u (device arrays)
-void launch_sample_bits(stn_accum* a, const double* u, uint32_t m, uint32_t* out, hipStream_t s);
+// bitstring sampling: running sums of acc's diagonal into work (device, at
+// least sample_bits_scratch(n) bytes), then one draw per uniform
+size_t sample_bits_scratch(uint32_t n);
+void launch_sample_bits(stn_accum* a, const double* u, uint32_t m, uint32_t* out, double* work, hipStream_t s);
+// the sampler's fixed device buffer on the current device (running sums of up
+// to 2^kStaticSampleQubits states); NULL with the HIP error in *err when its
+// address is unavailable
+constexpr uint32_t kStaticSampleQubits = 20;
+double* static_sample_scratch(hipError_t* err);
 void launch_lightcone(stn_plan* p, stn_batch* b, hipStream_t s);
 // lightcone lowering (kernels_tn.hip): networks of every observable term
 void build_lightcone(stn_plan* p);
