@@ -204,6 +204,9 @@ typedef struct {
     uint32_t lc_slice_bits; /* largest number of sliced variables of one term */
     double est_s_per_traj;  /* cost model's device seconds per trajectory of the chosen lowering (the job
                                server's admission and scheduling estimate; not a measurement) */
+    uint32_t lc_group;      /* lightcone plans: trajectories one workgroup contracts in lockstep */
+    uint32_t lc_width_lower_bound; /* 1 when lc_width is only a lower bound: the elimination-order search
+                               stopped at the first step above the rank cap, before finishing the order */
 } stn_plan_stats;
 
 typedef struct {

@@ -102,7 +102,8 @@ class PlanStats(C.Structure):
                 ("flops_per_traj", C.c_double), ("peak_bytes", C.c_double), ("lc_width", C.c_uint32),
                 ("lc_flops_per_traj", C.c_double), ("variant", C.c_uint32), ("tuned", C.c_uint32),
                 ("graphs", C.c_uint32), ("graph_captures", C.c_uint64), ("graph_replays", C.c_uint64),
-                ("lc_slices", C.c_uint32), ("lc_slice_bits", C.c_uint32), ("est_s_per_traj", C.c_double)]
+                ("lc_slices", C.c_uint32), ("lc_slice_bits", C.c_uint32), ("est_s_per_traj", C.c_double),
+                ("lc_group", C.c_uint32), ("lc_width_lower_bound", C.c_uint32)]
 
 
 class TuneResult(C.Structure):

@@ -244,6 +244,8 @@ stn_status stn_plan_info(const stn_plan* p, stn_plan_stats* o) {
     o->lc_slices = p->lc_slices;
     o->lc_slice_bits = p->lc_slice_bits;
     o->est_s_per_traj = p->est_seconds_per_traj();
+    o->lc_group = p->lc_group;
+    o->lc_width_lower_bound = p->lc_width_lb;
     return STN_OK;
 }
 

@@ -15,9 +15,10 @@
 // only the gate values (signs) differ, so the trajectory index is the batch
 // dimension of the contraction kernel (kernels_tn.hip).
 //
-// Intermediates are placed in a per-workgroup arena by a first-fit
-// allocator; networks whose arena fits the LDS budget are contracted
-// entirely in LDS, one workgroup per (trajectory, term).
+// Intermediates are placed by a first-fit allocator in two per-workgroup
+// arenas: small ones in LDS while it has room, the others in global memory.
+// A network whose intermediates all fit in LDS never touches global memory
+// between its inputs and its result.
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -36,6 +37,7 @@ struct Tensor {
     int conj = 0;                    // bra side
     std::vector<int> vars;           // variable ids; local index bit k = vars[k]
     int arena = -1;                  // offset (TN_INTER)
+    int lds = 0;                     // offset is in the LDS arena
 };
 
 bool diagonal_kind(uint32_t k) { return k == STN_G_RZ || k == STN_G_Z || k == STN_G_ZZ; }
@@ -95,8 +97,38 @@ struct Lowered {
     std::vector<TnStepRec> steps;
     int width = 0;
     double cost = 0;         // sum over steps of 2^(vars in the step) * inputs
-    int arena = 0;           // complex slots
-    int result = -1;         // final scalar tensor id
+    int arena = 0;           // complex slots in global memory
+    int lds_arena = 0;       // complex slots in LDS
+    int result = -1;         // arena slot of the final scalar
+    int result_lds = 0;
+    double gbytes = 0;       // global-memory intermediates read and written
+    std::vector<int> order;  // the elimination order lowered
+};
+
+// Intermediates of at most lds_tensor_max slots go to an LDS arena of
+// lds_slots slots while it has room, all others to global memory.
+struct TnArenaLimits {
+    int lds_slots = 0;
+    int lds_tensor_max = 0;
+};
+
+// First-fit placement of tensors in one arena of `cap` slots (cap < 0: unbounded).
+struct FirstFit {
+    std::map<int, int> used;  // offset -> size
+    int cap = -1;
+    int high = 0;             // slots used at most
+    int alloc(int size) {     // -1 when it does not fit
+        int off = 0;
+        for (auto& kv : used) {
+            if (kv.first - off >= size) break;
+            off = std::max(off, kv.first + kv.second);
+        }
+        if (cap >= 0 && off + size > cap) return -1;
+        used[off] = size;
+        high = std::max(high, off + size);
+        return off;
+    }
+    void release(int off) { used.erase(off); }
 };
 
 // Variables of every step of bucket elimination along `order` (the
@@ -125,7 +157,7 @@ std::vector<std::vector<int>> step_sets(const std::vector<std::vector<int>>& tv,
 }
 
 Lowered lower(const std::vector<Tensor>& base, int nv, const std::vector<int>& order,
-              const std::vector<int>& sliced) {
+              const std::vector<int>& sliced, TnArenaLimits lim) {
     Lowered L;
     auto slice_bit = [&](int x) {
         const auto it = std::find(sliced.begin(), sliced.end(), x);
@@ -133,19 +165,22 @@ Lowered lower(const std::vector<Tensor>& base, int nv, const std::vector<int>& o
     };
     std::vector<Tensor> pool = base;
     std::vector<char> alive(pool.size(), 1);
-    // arena: first fit over [offset, size) free blocks
-    std::map<int, int> used;  // offset -> size
-    auto alloc = [&](int size) {
-        int off = 0;
-        for (auto& kv : used) {
-            if (kv.first - off >= size) break;
-            off = std::max(off, kv.first + kv.second);
+    // two arenas: small tensors in LDS while it has room, the rest in global memory
+    FirstFit gmem, lds;
+    lds.cap = lim.lds_slots;
+    auto alloc = [&](Tensor& t, int size) {
+        t.lds = 0;
+        if (size <= lim.lds_tensor_max) {
+            const int off = lds.alloc(size);
+            if (off >= 0) {
+                t.lds = 1;
+                t.arena = off;
+                return;
+            }
         }
-        used[off] = size;
-        L.arena = std::max(L.arena, off + size);
-        return off;
+        t.arena = gmem.alloc(size);
     };
-    auto release = [&](int off) { used.erase(off); };
+    auto release = [&](const Tensor& t) { (t.lds ? lds : gmem).release(t.arena); };
     for (int v : order) {
         if (slice_bit(v) >= 0) continue;
         std::vector<int> bucket;
@@ -173,6 +208,7 @@ Lowered lower(const std::vector<Tensor>& base, int nv, const std::vector<int>& o
             in.gate = pool[i].gate;
             in.conj = pool[i].conj;
             in.arena = pool[i].arena;
+            in.lds = pool[i].lds;
             // position of each of the input's variables in the step's index space
             // (output variables at bits 0..|out|-1, the summed variable at |out|;
             // a sliced variable: its bit of the slice index)
@@ -188,10 +224,15 @@ Lowered lower(const std::vector<Tensor>& base, int nv, const std::vector<int>& o
         Tensor t;
         t.kind = TN_INTER;
         t.vars = out;
-        t.arena = alloc(1 << out.size());
+        alloc(t, 1 << out.size());
         for (int i : bucket)
-            if (pool[i].kind == TN_INTER) release(pool[i].arena);
+            if (pool[i].kind == TN_INTER) {
+                if (!pool[i].lds) L.gbytes += std::ldexp(1.0, (int)pool[i].vars.size());
+                release(pool[i]);
+            }
+        if (!t.lds) L.gbytes += std::ldexp(1.0, (int)out.size());
         st.out_arena = t.arena;
+        st.out_lds = t.lds;
         pool.push_back(t);
         alive.push_back(1);
         L.steps.push_back(st);
@@ -211,21 +252,58 @@ Lowered lower(const std::vector<Tensor>& base, int nv, const std::vector<int>& o
             in.gate = pool[i].gate;
             in.conj = pool[i].conj;
             in.arena = pool[i].arena;
+            in.lds = pool[i].lds;
             fin.inputs.push_back(in);
         }
-    fin.out_arena = alloc(1);
-    for (auto& in : fin.inputs)
-        if (in.kind == TN_INTER) release(in.arena);
+    Tensor res;
+    res.kind = TN_INTER;
+    alloc(res, 1);
+    for (size_t i = 0; i < pool.size(); ++i)
+        if (alive[i] && pool[i].kind == TN_INTER) release(pool[i]);
+    fin.out_arena = res.arena;
+    fin.out_lds = res.lds;
     L.steps.push_back(fin);
-    L.result = fin.out_arena;
+    L.result = res.arena;
+    L.result_lds = res.lds;
+    L.arena = gmem.high;
+    L.lds_arena = lds.high;
+    L.order = order;
     (void)nv;
     return L;
 }
 
+// Lowers `order` for an LDS arena of lds_slots slots with every tensor cap
+// from the whole arena down to 2^6 slots, and keeps the lowering that moves
+// the fewest bytes through global memory (a large tensor kept in LDS can push
+// several smaller ones out).
+Lowered lower_best_placement(const std::vector<Tensor>& base, int nv, const std::vector<int>& order,
+                             const std::vector<int>& sliced, int lds_slots) {
+    TnArenaLimits lim;
+    lim.lds_slots = lds_slots;
+    lim.lds_tensor_max = lds_slots;
+    Lowered best = lower(base, nv, order, sliced, lim);
+    for (int cap = lds_slots / 2; cap >= 64; cap /= 2) {
+        lim.lds_tensor_max = cap;
+        Lowered L = lower(base, nv, order, sliced, lim);
+        if (L.gbytes < best.gbytes) best = std::move(L);
+    }
+    return best;
+}
+
+void take(TnNetwork& net, Lowered&& L) {
+    net.steps = std::move(L.steps);
+    net.width = L.width;
+    net.cost = L.cost;
+    net.arena = L.arena;
+    net.lds_arena = L.lds_arena;
+    net.result = L.result;
+    net.result_lds = L.result_lds;
+}
+
 // The caller's order for one term's network: validated as a permutation of
 // the variables, checked against max_rank, then lowered unsliced.
-TnNetwork lower_caller_order(const stn_plan* p, uint32_t term, const std::vector<Tensor>& ts, int nv, int max_rank,
-                             TnNetwork net) {
+std::vector<TnNetwork> lower_caller_order(const stn_plan* p, uint32_t term, const std::vector<Tensor>& ts, int nv,
+                                          int max_rank, TnNetwork net, const std::vector<int>& lds_slots) {
     std::vector<uint32_t> offsets(1, 0), vars;
     std::vector<std::vector<int>> tv;
     for (auto& t : ts) {
@@ -258,23 +336,23 @@ TnNetwork lower_caller_order(const stn_plan* p, uint32_t term, const std::vector
     if (widest > max_rank + 1) {
         net.width = widest;
         net.cost = HUGE_VAL;
-        return net;
+        return std::vector<TnNetwork>(lds_slots.size(), net);
     }
-    Lowered L = lower(ts, nv, order, {});
-    net.steps = std::move(L.steps);
-    net.width = L.width;
-    net.cost = L.cost;
-    net.arena = L.arena;
-    net.result = L.result;
-    return net;
+    std::vector<TnNetwork> out;
+    for (int slots : lds_slots) {
+        TnNetwork n2 = net;
+        take(n2, lower_best_placement(ts, nv, order, {}, slots));
+        out.push_back(std::move(n2));
+    }
+    return out;
 }
 
 }  // namespace
 
 // Network of one term: lightcone gates on the ket, the observable, the
 // conjugate gates on the bra, |0> at both ends of every chain.
-TnNetwork build_term(const stn_plan* p, uint32_t term, uint32_t u, uint32_t v, uint32_t restarts, uint64_t seed,
-                     int max_rank, int slice_bits) {
+std::vector<TnNetwork> build_term(const stn_plan* p, uint32_t term, uint32_t u, uint32_t v, uint32_t restarts,
+                                  uint64_t seed, int max_rank, int slice_bits, const std::vector<int>& lds_slots) {
     const uint32_t n = p->n;
     // backward lightcone of {u, v}
     std::vector<char> in_cone(p->gates.size(), 0);
@@ -386,7 +464,10 @@ TnNetwork build_term(const stn_plan* p, uint32_t term, uint32_t u, uint32_t v, u
     net.u = u;
     net.v = v;
     net.n_vars = nv;
-    if (p->opts.lc_order_fn) return lower_caller_order(p, term, ts, nv, max_rank, net);
+    if (p->opts.lc_order_fn) return lower_caller_order(p, term, ts, nv, max_rank, net, lds_slots);
+    TnArenaLimits lim;   // the order search places like the first budget, without the cap search
+    lim.lds_slots = lds_slots.empty() ? 0 : lds_slots[0];
+    lim.lds_tensor_max = lim.lds_slots;
     Lowered best;
     bool have = false;
     std::vector<int> sliced;   // slice index bit k fixes variable sliced[k]
@@ -409,7 +490,7 @@ TnNetwork build_term(const stn_plan* p, uint32_t term, uint32_t u, uint32_t v, u
                 deg_lb = deg_lb ? std::min(deg_lb, deg) : deg;
                 continue;
             }
-            Lowered L = lower(ts, nv, order, sliced);
+            Lowered L = lower(ts, nv, order, sliced, lim);
             if (!have || L.width < best.width || (L.width == best.width && L.cost < best.cost)) {
                 best = std::move(L);
                 have = true;
@@ -433,15 +514,17 @@ TnNetwork build_term(const stn_plan* p, uint32_t term, uint32_t u, uint32_t v, u
     if (!have) {   // no order within max_rank: width is at least deg_lb + 1
         net.width = deg_lb + 1;
         net.cost = HUGE_VAL;
-        return net;
+        return std::vector<TnNetwork>(lds_slots.size(), net);
     }
-    net.steps = std::move(best.steps);
-    net.width = best.width;
     net.slice_bits = (int)sliced.size();
-    net.cost = std::ldexp(best.cost, net.slice_bits);
-    net.arena = best.arena;
-    net.result = best.result;
-    return net;
+    std::vector<TnNetwork> out;
+    for (int slots : lds_slots) {
+        TnNetwork n2 = net;
+        take(n2, lower_best_placement(ts, nv, best.order, sliced, slots));
+        n2.cost = std::ldexp(n2.cost, n2.slice_bits);
+        out.push_back(std::move(n2));
+    }
+    return out;
 }
 
 }  // namespace stn

@@ -18,6 +18,7 @@ struct TnInputRec {
     int gate = -1;
     int conj = 0;
     int arena = -1;
+    int lds = 0;                   // TN_INTER: the tensor lives in the workgroup's LDS arena
     // local index bit k of the input = bit pos[k] of the step's index, or,
     // where pos[k] < 0, bit -1 - pos[k] of the slice index
     std::vector<int> pos;
@@ -28,6 +29,7 @@ struct TnStepRec {
     std::vector<int> out_vars;
     std::vector<TnInputRec> inputs;
     int out_arena = -1;
+    int out_lds = 0;               // the output goes to the LDS arena
 };
 
 struct TnNetwork {
@@ -36,8 +38,10 @@ struct TnNetwork {
     int width = 0;                 // largest step index space (output rank + 1), per slice
     int slice_bits = 0;            // variables fixed by the slice index (2^slice_bits slices, summed)
     double cost = 0;               // sum over steps of 2^width(step) * inputs, times the slices
-    int arena = 0;                 // complex slots of intermediates
+    int arena = 0;                 // complex slots of intermediates in global memory
+    int lds_arena = 0;             // complex slots of intermediates in LDS
     int result = -1;               // arena slot of the final scalar
+    int result_lds = 0;            // ... in the LDS arena
     std::vector<TnStepRec> steps;
 };
 
@@ -47,7 +51,10 @@ struct TnNetwork {
 // back without steps, width = a lower bound, cost = infinity.  With a
 // caller-supplied order (opts.lc_order_fn) that order is lowered instead of
 // min-fill, unsliced; a network it leaves too wide comes back the same way.
-TnNetwork build_term(const stn_plan* p, uint32_t term, uint32_t u, uint32_t v, uint32_t restarts, uint64_t seed,
-                     int max_rank, int slice_bits);
+// The order found is lowered once per LDS budget in lds_slots (one network
+// each, same order): intermediates are placed in an LDS arena of that many
+// slots while it has room (first fit), all others in global memory.
+std::vector<TnNetwork> build_term(const stn_plan* p, uint32_t term, uint32_t u, uint32_t v, uint32_t restarts,
+                                  uint64_t seed, int max_rank, int slice_bits, const std::vector<int>& lds_slots);
 
 }  // namespace stn

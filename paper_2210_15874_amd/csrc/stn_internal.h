@@ -203,6 +203,8 @@ struct stn_plan {
     uint32_t variant = 0;                   // launch shape of the contraction kernels (autotuner)
     uint32_t grid_cap = 0;                  // persistent kernels use at most this many workgroups (0: all CUs)
     uint32_t lc_slices = 0, lc_slice_bits = 0;   // lightcone: networks per trajectory, most sliced variables
+    uint32_t lc_group = 0;                       // lightcone: trajectories per workgroup work item
+    uint32_t lc_width_lb = 0;                    // lightcone: lc_width is a lower bound (search stopped at the cap)
     bool graphs = false;                    // stn_contract replays HIP graphs (stn_plan_set_graphs)
     uint64_t graph_captures = 0, graph_replays = 0;
     bool tuned = false;
