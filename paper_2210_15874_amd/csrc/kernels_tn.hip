@@ -56,7 +56,7 @@ struct TnSmall {
 };
 
 struct TnStep {
-    int32_t out_bits, sum, out_off, out_lds;
+    int32_t out_bits, nsum, out_off, out_lds;   // nsum: summed variables, step bits out_bits ..
     int32_t main0, n_main, small0, n_small;
     int32_t tab_bits, generic, pad[2];   // generic: a per-element input is not an intermediate
     uint32_t tbit[kStepBits];   // table-index value of each step bit
@@ -114,19 +114,22 @@ __device__ __forceinline__ V tn_value(int kind, int gate, int conj, int off, int
 }
 
 // The output elements of a step whose NM per-element inputs are all
-// intermediates (src: flat pointers, LDS or global).  Output bits below klog
-// are the thread's; the loop visits the higher bits in blocks of 2^LOGU
-// iterations: the block index in Gray code order (one step bit, so one local
-// bit of each input, flips from block to block) and the 2^LOGU low loop bits
-// in every combination inside a block, whose loads are all issued before any
-// product is formed.
-template <class V, int NM, int LOGU>
+// intermediates (src: flat pointers, LDS or global), summing 2^LOGX values
+// of its summed variables (xi / xt: each input's and the table's local-index
+// offset of every such value).  Output bits below klog are the thread's; the
+// loop visits the higher bits in blocks of 2^LOGU iterations: the block
+// index in Gray code order (one step bit, so one local bit of each input,
+// flips from block to block) and the 2^LOGU low loop bits in every
+// combination inside a block, whose loads are all issued before any product
+// is formed.
+template <class V, int NM, int LOGU, int LOGX>
 __device__ __forceinline__ void step_elements(const TnStep& st, const TnMain* __restrict__ mn, const V* tab,
                                               int has_tab, V* out, const V* const (&src)[kMaxMain],
-                                              const uint32_t (&li)[kMaxMain], const uint32_t (&xi)[kMaxMain],
-                                              uint32_t lt, uint32_t xt, int sum, uint32_t iters, int klog,
+                                              const uint32_t (&li)[kMaxMain], const uint32_t (&xi)[kMaxMain][2],
+                                              uint32_t lt, const uint32_t (&xt)[2], uint32_t iters, int klog,
                                               uint32_t olo) {
     constexpr uint32_t U = 1u << LOGU;
+    constexpr int X = 1 << LOGX;
     uint32_t fl[LOGU + 1][NM + 1];
 #pragma unroll
     for (int k = 0; k < LOGU; ++k) {
@@ -147,8 +150,27 @@ __device__ __forceinline__ void step_elements(const TnStep& st, const TnMain* __
             for (int i = 0; i < NM; ++i) lj[i] ^= mn[i].bit[b];
             lj[NM] ^= st.tbit[b];
         }
-        V val[U][2][NM > 0 ? NM : 1];
-        V tv[U][2];
+        if constexpr (U * X * (NM + 1) > (sizeof(V) > 8 ? 8 : 16)) {
+            // too many values to hold at once: one summed value after another
+            static_assert(U == 1, "unrolled blocks stay within the register budget");
+            V acc;
+            acc.x = 0;
+            acc.y = 0;
+#pragma unroll
+            for (int x = 0; x < X; ++x) {
+                const uint32_t ox = ((x & 1) ? xt[0] : 0u) ^ ((x & 2) ? xt[1] : 0u);
+                V v = has_tab ? tab[lt ^ lj[NM] ^ ox] : cone<V>();
+#pragma unroll
+                for (int i = 0; i < NM; ++i)
+                    v = cmul(v, src[i][li[i] ^ lj[i] ^ ((x & 1) ? xi[i][0] : 0u) ^ ((x & 2) ? xi[i][1] : 0u)]);
+                acc.x += v.x;
+                acc.y += v.y;
+            }
+            out[oj | olo] = acc;
+            continue;
+        }
+        V val[U][X][NM > 0 ? NM : 1];
+        V tv[U][X];
 #pragma unroll
         for (uint32_t u = 0; u < U; ++u) {
             uint32_t d[NM + 1];
@@ -160,11 +182,12 @@ __device__ __forceinline__ void step_elements(const TnStep& st, const TnMain* __
                     if ((u >> k) & 1u) d[i] ^= fl[k][i];
             }
 #pragma unroll
-            for (int x = 0; x < 2; ++x) {
-                if (x > sum) break;
-                tv[u][x] = has_tab ? tab[lt ^ d[NM] ^ (x ? xt : 0u)] : cone<V>();
+            for (int x = 0; x < X; ++x) {
+                const uint32_t ox = ((x & 1) ? xt[0] : 0u) ^ ((x & 2) ? xt[1] : 0u);
+                tv[u][x] = has_tab ? tab[lt ^ d[NM] ^ ox] : cone<V>();
 #pragma unroll
-                for (int i = 0; i < NM; ++i) val[u][x][i] = src[i][li[i] ^ d[i] ^ (x ? xi[i] : 0u)];
+                for (int i = 0; i < NM; ++i)
+                    val[u][x][i] = src[i][li[i] ^ d[i] ^ ((x & 1) ? xi[i][0] : 0u) ^ ((x & 2) ? xi[i][1] : 0u)];
             }
         }
 #pragma unroll
@@ -173,8 +196,7 @@ __device__ __forceinline__ void step_elements(const TnStep& st, const TnMain* __
             acc.x = 0;
             acc.y = 0;
 #pragma unroll
-            for (int x = 0; x < 2; ++x) {
-                if (x > sum) break;
+            for (int x = 0; x < X; ++x) {
                 V v = tv[u][x];
 #pragma unroll
                 for (int i = 0; i < NM; ++i) v = cmul(v, val[u][x][i]);
@@ -186,26 +208,44 @@ __device__ __forceinline__ void step_elements(const TnStep& st, const TnMain* __
     }
 }
 
-// block size of the element loop: more loads in flight for steps with few
-// inputs, bounded by the loop's length (a power of two)
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+
+// block size of the element loop: more loads in flight when a step reads few
+// values per output, bounded by the loop's length (a power of two)
+template <class V, int NM, int LOGX>
+__device__ __forceinline__ void step_elements_u(const TnStep& st, const TnMain* __restrict__ mn, const V* tab,
+                                                int has_tab, V* out, const V* const (&src)[kMaxMain],
+                                                const uint32_t (&li)[kMaxMain], const uint32_t (&xi)[kMaxMain][2],
+                                                uint32_t lt, const uint32_t (&xt)[2], uint32_t iters, int klog,
+                                                uint32_t olo) {
+    constexpr int kValues = (sizeof(V) > 8 ? 8 : 16) / ((1 << LOGX) * (NM + 1));
+    constexpr int kMaxU = ilog2c(kValues) < 2 ? ilog2c(kValues) : 2;
+    const int lg = __builtin_ctz(iters);
+    const int u = lg < kMaxU ? lg : kMaxU;
+    if (u >= 2 && kMaxU >= 2)
+        step_elements<V, NM, (kMaxU >= 2 ? 2 : 0), LOGX>(st, mn, tab, has_tab, out, src, li, xi, lt, xt, iters, klog, olo);
+    else if (u == 1 && kMaxU >= 1)
+        step_elements<V, NM, (kMaxU >= 1 ? 1 : 0), LOGX>(st, mn, tab, has_tab, out, src, li, xi, lt, xt, iters, klog, olo);
+    else
+        step_elements<V, NM, 0, LOGX>(st, mn, tab, has_tab, out, src, li, xi, lt, xt, iters, klog, olo);
+}
+
 template <class V, int NM>
 __device__ __forceinline__ void step_elements_any(const TnStep& st, const TnMain* __restrict__ mn, const V* tab,
                                                   int has_tab, V* out, const V* const (&src)[kMaxMain],
-                                                  const uint32_t (&li)[kMaxMain], const uint32_t (&xi)[kMaxMain],
-                                                  uint32_t lt, uint32_t xt, int sum, uint32_t iters, int klog,
-                                                  uint32_t olo) {
-    constexpr int kWide = sizeof(V) > 8 ? 1 : 0;   // complex128 values take twice the registers
-    constexpr int kMaxU = (NM <= 3 ? 2 : 1) - kWide;
-    const int lg = __builtin_ctz(iters);
-    const int u = lg < kMaxU ? lg : kMaxU;
-    if (u >= 3 && kMaxU >= 3)
-        step_elements<V, NM, (kMaxU >= 3 ? 3 : 0)>(st, mn, tab, has_tab, out, src, li, xi, lt, xt, sum, iters, klog, olo);
-    else if (u == 2 && kMaxU >= 2)
-        step_elements<V, NM, (kMaxU >= 2 ? 2 : 0)>(st, mn, tab, has_tab, out, src, li, xi, lt, xt, sum, iters, klog, olo);
-    else if (u == 1 && kMaxU >= 1)
-        step_elements<V, NM, (kMaxU >= 1 ? 1 : 0)>(st, mn, tab, has_tab, out, src, li, xi, lt, xt, sum, iters, klog, olo);
-    else
-        step_elements<V, NM, 0>(st, mn, tab, has_tab, out, src, li, xi, lt, xt, sum, iters, klog, olo);
+                                                  const uint32_t (&li)[kMaxMain], const uint32_t (&xi)[kMaxMain][2],
+                                                  uint32_t lt, const uint32_t (&xt)[2], int nsum, uint32_t iters,
+                                                  int klog, uint32_t olo, bool wide) {
+    // (complex128 plans are lowered without merged steps: nsum <= 1)
+    constexpr int kX = sizeof(V) > 8 ? 1 : 2;
+    if (wide) {
+        if (nsum >= 2) step_elements_u<V, NM, kX>(st, mn, tab, has_tab, out, src, li, xi, lt, xt, iters, klog, olo);
+        else step_elements_u<V, NM, 1>(st, mn, tab, has_tab, out, src, li, xi, lt, xt, iters, klog, olo);
+    } else {
+        if (nsum >= 2) step_elements<V, NM, 0, kX>(st, mn, tab, has_tab, out, src, li, xi, lt, xt, 1u, klog, olo);
+        else if (nsum == 1) step_elements<V, NM, 0, 1>(st, mn, tab, has_tab, out, src, li, xi, lt, xt, 1u, klog, olo);
+        else step_elements<V, NM, 0, 0>(st, mn, tab, has_tab, out, src, li, xi, lt, xt, 1u, klog, olo);
+    }
 }
 
 // The element loop of one step for one trajectory of the group: pointers to
@@ -217,8 +257,8 @@ template <class V, bool WIDE>
 __device__ __forceinline__ void step_item(const TnStep& st, const TnMain* __restrict__ mn, int n_main, int n_small,
                                           const V* tab, V* lds, V* ga, const V* __restrict__ gtab,
                                           const uint32_t* sg, const uint32_t (&li)[kMaxMain],
-                                          const uint32_t (&xi)[kMaxMain], uint32_t lt, uint32_t xt, int sum,
-                                          uint32_t iters, int klog, uint32_t olo) {
+                                          const uint32_t (&xi)[kMaxMain][2], uint32_t lt, const uint32_t (&xt)[2],
+                                          int nsum, uint32_t iters, int klog, uint32_t olo) {
     V* out = st.out_lds ? lds + st.out_off : ga + st.out_off;
     if (!st.generic) {
         const V* src[kMaxMain];
@@ -227,26 +267,14 @@ __device__ __forceinline__ void step_item(const TnStep& st, const TnMain* __rest
             src[i] = lds;
             if (i < n_main) src[i] = mn[i].lds ? (const V*)lds + mn[i].off : (const V*)ga + mn[i].off;
         }
-        if (WIDE) {
-            switch (n_main) {
-                case 0: step_elements_any<V, 0>(st, mn, tab, n_small, out, src, li, xi, lt, xt, sum, iters, klog, olo); break;
-                case 1: step_elements_any<V, 1>(st, mn, tab, n_small, out, src, li, xi, lt, xt, sum, iters, klog, olo); break;
-                case 2: step_elements_any<V, 2>(st, mn, tab, n_small, out, src, li, xi, lt, xt, sum, iters, klog, olo); break;
-                case 3: step_elements_any<V, 3>(st, mn, tab, n_small, out, src, li, xi, lt, xt, sum, iters, klog, olo); break;
-                case 4: step_elements_any<V, 4>(st, mn, tab, n_small, out, src, li, xi, lt, xt, sum, iters, klog, olo); break;
-                case 5: step_elements_any<V, 5>(st, mn, tab, n_small, out, src, li, xi, lt, xt, sum, iters, klog, olo); break;
-                default: step_elements_any<V, 6>(st, mn, tab, n_small, out, src, li, xi, lt, xt, sum, iters, klog, olo); break;
-            }
-        } else {
-            switch (n_main) {
-                case 0: step_elements<V, 0, 0>(st, mn, tab, n_small, out, src, li, xi, lt, xt, sum, 1u, klog, olo); break;
-                case 1: step_elements<V, 1, 0>(st, mn, tab, n_small, out, src, li, xi, lt, xt, sum, 1u, klog, olo); break;
-                case 2: step_elements<V, 2, 0>(st, mn, tab, n_small, out, src, li, xi, lt, xt, sum, 1u, klog, olo); break;
-                case 3: step_elements<V, 3, 0>(st, mn, tab, n_small, out, src, li, xi, lt, xt, sum, 1u, klog, olo); break;
-                case 4: step_elements<V, 4, 0>(st, mn, tab, n_small, out, src, li, xi, lt, xt, sum, 1u, klog, olo); break;
-                case 5: step_elements<V, 5, 0>(st, mn, tab, n_small, out, src, li, xi, lt, xt, sum, 1u, klog, olo); break;
-                default: step_elements<V, 6, 0>(st, mn, tab, n_small, out, src, li, xi, lt, xt, sum, 1u, klog, olo); break;
-            }
+        switch (n_main) {
+            case 0: step_elements_any<V, 0>(st, mn, tab, n_small, out, src, li, xi, lt, xt, nsum, iters, klog, olo, WIDE); break;
+            case 1: step_elements_any<V, 1>(st, mn, tab, n_small, out, src, li, xi, lt, xt, nsum, iters, klog, olo, WIDE); break;
+            case 2: step_elements_any<V, 2>(st, mn, tab, n_small, out, src, li, xi, lt, xt, nsum, iters, klog, olo, WIDE); break;
+            case 3: step_elements_any<V, 3>(st, mn, tab, n_small, out, src, li, xi, lt, xt, nsum, iters, klog, olo, WIDE); break;
+            case 4: step_elements_any<V, 4>(st, mn, tab, n_small, out, src, li, xi, lt, xt, nsum, iters, klog, olo, WIDE); break;
+            case 5: step_elements_any<V, 5>(st, mn, tab, n_small, out, src, li, xi, lt, xt, nsum, iters, klog, olo, WIDE); break;
+            default: step_elements_any<V, 6>(st, mn, tab, n_small, out, src, li, xi, lt, xt, nsum, iters, klog, olo, WIDE); break;
         }
         return;
     }
@@ -265,11 +293,12 @@ __device__ __forceinline__ void step_item(const TnStep& st, const TnMain* __rest
         V acc;
         acc.x = 0;
         acc.y = 0;
-        for (int x = 0; x <= sum; ++x) {
-            V v = n_small ? tab[lt ^ ljt ^ (x ? xt : 0u)] : cone<V>();
+        for (int x = 0; x < (1 << nsum); ++x) {
+            V v = n_small ? tab[lt ^ ljt ^ ((x & 1) ? xt[0] : 0u) ^ ((x & 2) ? xt[1] : 0u)] : cone<V>();
             for (int i = 0; i < n_main; ++i)
                 v = cmul(v, tn_value<V>(mn[i].kind, mn[i].gate, mn[i].conj, mn[i].off, mn[i].lds,
-                                        li[i] ^ lj[i] ^ (x ? xi[i] : 0u), lds, ga, gtab, sg));
+                                        li[i] ^ lj[i] ^ ((x & 1) ? xi[i][0] : 0u) ^ ((x & 2) ? xi[i][1] : 0u), lds,
+                                        ga, gtab, sg));
             acc.x += v.x;
             acc.y += v.y;
         }
@@ -297,7 +326,7 @@ __device__ __forceinline__ void run_group(typename Cx<R>::T* lds, typename Cx<R>
     const uint32_t tid = threadIdx.x;
     for (int s = 0; s < tm.n_steps; ++s) {
         const TnStep& st = steps[tm.step0 + s];
-        const int out_bits = st.out_bits, sum = st.sum, n_main = st.n_main, n_small = st.n_small;
+        const int out_bits = st.out_bits, nsum = st.nsum, n_main = st.n_main, n_small = st.n_small;
         const TnMain* __restrict__ mn = mains + st.main0;
         // 1. the small factors' product table of every trajectory
         if (n_small) {
@@ -325,12 +354,12 @@ __device__ __forceinline__ void run_group(typename Cx<R>::T* lds, typename Cx<R>
         // 2. per-thread parts of every index (low step bits and slice bits)
         const int tbits = out_bits < klog ? out_bits : klog;
         const uint32_t olo = tid & ((1u << tbits) - 1u);
-        uint32_t li[kMaxMain], xi[kMaxMain];
-        uint32_t lt = 0, xt = 0;
+        uint32_t li[kMaxMain], xi[kMaxMain][2];
+        uint32_t lt = 0, xt[2] = {0, 0};
 #pragma unroll
         for (int i = 0; i < kMaxMain; ++i) {
             li[i] = 0;
-            xi[i] = 0;
+            xi[i][0] = xi[i][1] = 0;
         }
         // (descriptor values are uniform: loaded once, then masked per thread)
         for (int b = 0; b < tbits; ++b) {
@@ -347,25 +376,28 @@ __device__ __forceinline__ void run_group(typename Cx<R>::T* lds, typename Cx<R>
                     for (int b = 0; b < tm.slice_bits; ++b)
                         if ((slice >> b) & 1u) li[i] |= mn[i].sbit[b];
         }
-        if (sum) {
-            xt = st.tbit[out_bits];
+        // local-index bits of the summed variables (value bit k = step bit out_bits + k)
 #pragma unroll
-            for (int i = 0; i < kMaxMain; ++i)
-                if (i < n_main) xi[i] = mn[i].bit[out_bits];
-        }
+        for (int k = 0; k < 2; ++k)
+            if (k < nsum) {
+                xt[k] = st.tbit[out_bits + k];
+#pragma unroll
+                for (int i = 0; i < kMaxMain; ++i)
+                    if (i < n_main) xi[i][k] = mn[i].bit[out_bits + k];
+            }
         // 3. the output elements of every trajectory
         if (out_bits >= klog) {
             const uint32_t iters = 1u << (out_bits - klog);
             for (uint32_t t = 0; t < ng; ++t)
                 step_item<V, true>(st, mn, n_main, n_small, tabs + t * tab_item, lds + t * lds_item,
                                    ga ? ga + (size_t)t * g_item : ga, gtab, signs + (size_t)t * words, li, xi, lt, xt,
-                                   sum, iters, klog, olo);
+                                   nsum, iters, klog, olo);
         } else {
             const uint32_t per = nthreads >> out_bits;
             for (uint32_t t = tid >> out_bits; t < ng; t += per)
                 step_item<V, false>(st, mn, n_main, n_small, tabs + t * tab_item, lds + t * lds_item,
                                     ga ? ga + (size_t)t * g_item : ga, gtab, signs + (size_t)t * words, li, xi, lt,
-                                    xt, sum, 1u, klog, olo);
+                                    xt, nsum, 1u, klog, olo);
         }
         __syncthreads();
     }
@@ -476,7 +508,7 @@ void describe(TnDevice* d, const TnNetwork& net, int tab_cap) {
     for (const TnStepRec& sr : net.steps) {
         TnStep st{};
         st.out_bits = (int32_t)sr.out_vars.size();
-        st.sum = sr.elim >= 0 ? 1 : 0;
+        st.nsum = sr.nsum;
         st.out_off = sr.out_arena;
         st.out_lds = sr.out_lds;
         std::vector<int> order(sr.inputs.size());
@@ -601,12 +633,14 @@ void gate_tensor(const GateRec& g, int s, cd* out) {
 
 }  // namespace
 
-// Cost model of the trajectory group size: a step costs a workgroup about
-// kStepSeconds whatever its size (descriptor loads, table, barriers), shared
-// by the group's trajectories; global-memory intermediates move at
-// kArenaBytesPerS over the device.
+// Cost model of the trajectory group size (calibrated on n = 22..29, p = 2
+// Erdos-Renyi jobs): a step costs a workgroup about kStepSeconds whatever its
+// size (descriptor loads, table, barriers), shared by the group's
+// trajectories; global-memory intermediates move at kArenaBytesPerS over the
+// device.
 constexpr double kStepSeconds = 3e-6;
 constexpr double kArenaBytesPerS = 3e12;
+constexpr double kFlopsPerS = 8e13;      // element arithmetic, mostly hidden under the memory traffic
 constexpr int kTabBytes = 16 * 1024;     // small-factor tables of all trajectories of a group
 constexpr uint32_t kGroupSizes[] = {1, 2, 4, 8, 16};
 
@@ -679,14 +713,19 @@ void build_lightcone(stn_plan* p) {
             }
         }
         // workgroups the device holds at once: one per CU with global-memory
-        // intermediates (1024 threads), four of 256 threads otherwise
-        const double wgs = arena ? 256.0 : 1024.0;
+        // intermediates (1024 threads), four of 256 threads otherwise; fewer
+        // when the arenas of one per CU exceed the budget, and the device is
+        // then only partly busy
+        double wgs = arena ? 256.0 : 1024.0;
         if (arena) {
             const double stride = (double)((arena + 63) / 64 * 64);
-            if (std::floor(budget / 2 / (stride * elem * tb)) < 32) continue;   // arenas exceed the budget
+            const double fit = std::floor(budget / 2 / (stride * elem * tb));
+            if (fit < 32) continue;   // arenas exceed the budget
+            wgs = std::min(wgs, fit);
         }
-        const double est = (double)runs * kStepSeconds / (tb * wgs) + gbytes / kArenaBytesPerS +
-                           8.0 * cost / 8e12;
+        const double busy = wgs / (arena ? 256.0 : 1024.0);
+        const double est = (double)runs * kStepSeconds / (tb * wgs) +
+                           (gbytes / kArenaBytesPerS + 8.0 * cost / kFlopsPerS) / busy;
         if (best < 0 || est < best_est) {
             best = k;
             best_est = est;

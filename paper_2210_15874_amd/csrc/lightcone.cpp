@@ -156,16 +156,128 @@ std::vector<std::vector<int>> step_sets(const std::vector<std::vector<int>>& tv,
     return sets;
 }
 
-Lowered lower(const std::vector<Tensor>& base, int nv, const std::vector<int>& order,
-              const std::vector<int>& sliced, TnArenaLimits lim) {
+// A step of bucket elimination before placement: input tensor ids, summed
+// variables, output variables in storage order, output tensor id.
+struct SymStep {
+    std::vector<int> in;
+    std::vector<int> sums;
+    std::vector<int> out;
+    int out_id = -1;
+    bool dead = false;
+};
+
+
+// Bucket elimination along `order` (sliced variables skipped) in three
+// phases: eliminate() does 1 and 2, place() does 3.
+//  1. Each variable's bucket (the live tensors that hold it) becomes one step
+//     whose output holds the bucket's other variables, in first-seen order
+//     with the largest input first.
+//  2. Merged-index steps: a step whose output's only reader sums one more
+//     variable and adds nothing but small factors (all of whose variables
+//     are in that output or summed there) is folded into its reader, which
+//     then sums both variables over the same index space; the intermediate
+//     is never written.  At most max_sums variables per step.
+//  3. Intermediates are placed in step order (an output before its inputs
+//     are released, so they never alias), small ones in LDS while it has
+//     room, the others in global memory.
+struct Symbolic {
+    std::vector<Tensor> pool;      // base tensors, then one per step output
+    std::vector<SymStep> steps;    // the last one multiplies the remaining scalars
+    int result = -1;               // tensor id of the final scalar
+};
+
+// phases 1 and 2 (they do not depend on the placement)
+Symbolic eliminate(const std::vector<Tensor>& base, const std::vector<int>& order, const std::vector<int>& sliced,
+                   int max_sums) {
+    auto is_sliced = [&](int x) { return std::find(sliced.begin(), sliced.end(), x) != sliced.end(); };
+    // 1. symbolic elimination
+    std::vector<Tensor> pool = base;
+    std::vector<char> alive(pool.size(), 1);
+    std::vector<SymStep> steps;
+    for (int v : order) {
+        if (is_sliced(v)) continue;
+        std::vector<int> bucket;
+        for (size_t i = 0; i < pool.size(); ++i)
+            if (alive[i] && std::find(pool[i].vars.begin(), pool[i].vars.end(), v) != pool[i].vars.end())
+                bucket.push_back((int)i);
+        if (bucket.empty()) continue;
+        std::stable_sort(bucket.begin(), bucket.end(),
+                         [&](int a, int b) { return pool[a].vars.size() > pool[b].vars.size(); });
+        SymStep st;
+        st.in = bucket;
+        st.sums = {v};
+        for (int i : bucket)
+            for (int x : pool[i].vars)
+                if (x != v && !is_sliced(x) && std::find(st.out.begin(), st.out.end(), x) == st.out.end())
+                    st.out.push_back(x);
+        for (int i : bucket) alive[i] = 0;
+        Tensor t;
+        t.kind = TN_INTER;
+        t.vars = st.out;
+        st.out_id = (int)pool.size();
+        pool.push_back(t);
+        alive.push_back(1);
+        steps.push_back(st);
+    }
+    SymStep fin;   // remaining scalars (no variables but sliced ones) multiply into the result
+    for (size_t i = 0; i < pool.size(); ++i)
+        if (alive[i]) {
+            for (int x : pool[i].vars)
+                if (!is_sliced(x)) fail(STN_E_INVALID, "tensor left with open indices");
+            fin.in.push_back((int)i);
+        }
+    Tensor res;
+    res.kind = TN_INTER;
+    fin.out_id = (int)pool.size();
+    pool.push_back(res);
+    steps.push_back(fin);
+    const int result = fin.out_id;
+    // 2. merged-index steps
+    std::vector<int> reader(pool.size(), -1);
+    for (size_t k = 0; k < steps.size(); ++k)
+        for (int i : steps[k].in) reader[i] = (int)k;
+    for (size_t k = 0; k + 1 < steps.size(); ++k) {
+        SymStep& s = steps[k];
+        const int c = reader[s.out_id];
+        if (c < 0 || steps[c].sums.empty() || (int)(s.sums.size() + steps[c].sums.size()) > max_sums) continue;
+        SymStep& r = steps[c];
+        bool small_only = true;
+        for (int i : r.in) {
+            if (i == s.out_id) continue;
+            for (int x : pool[i].vars)
+                if (!is_sliced(x) && std::find(s.out.begin(), s.out.end(), x) == s.out.end() &&
+                    std::find(r.sums.begin(), r.sums.end(), x) == r.sums.end())
+                    small_only = false;
+            if (pool[i].vars.size() > 2) small_only = false;
+        }
+        if (!small_only) continue;
+        std::vector<int> in = s.in;
+        for (int i : r.in)
+            if (i != s.out_id) in.push_back(i);
+        std::vector<int> sums = s.sums;
+        sums.insert(sums.end(), r.sums.begin(), r.sums.end());
+        r.in = in;
+        r.sums = sums;
+        for (int i : r.in) reader[i] = c;
+        s.dead = true;
+    }
+    Symbolic out;
+    out.pool = std::move(pool);
+    out.steps = std::move(steps);
+    out.result = result;
+    return out;
+}
+
+// phase 3 on a copy of the symbolic steps' tensors
+Lowered place(const Symbolic& sym, const std::vector<int>& order, const std::vector<int>& sliced,
+              TnArenaLimits lim) {
     Lowered L;
     auto slice_bit = [&](int x) {
         const auto it = std::find(sliced.begin(), sliced.end(), x);
         return it == sliced.end() ? -1 : (int)(it - sliced.begin());
     };
-    std::vector<Tensor> pool = base;
-    std::vector<char> alive(pool.size(), 1);
-    // two arenas: small tensors in LDS while it has room, the rest in global memory
+    std::vector<Tensor> pool = sym.pool;
+    // 3. placement and lowering to step records
     FirstFit gmem, lds;
     lds.cap = lim.lds_slots;
     auto alloc = [&](Tensor& t, int size) {
@@ -181,28 +293,16 @@ Lowered lower(const std::vector<Tensor>& base, int nv, const std::vector<int>& o
         t.arena = gmem.alloc(size);
     };
     auto release = [&](const Tensor& t) { (t.lds ? lds : gmem).release(t.arena); };
-    for (int v : order) {
-        if (slice_bit(v) >= 0) continue;
-        std::vector<int> bucket;
-        for (size_t i = 0; i < pool.size(); ++i)
-            if (alive[i] && std::find(pool[i].vars.begin(), pool[i].vars.end(), v) != pool[i].vars.end())
-                bucket.push_back((int)i);
-        if (bucket.empty()) continue;
-        // output variables: union minus v, in first-seen order (largest input first)
-        std::sort(bucket.begin(), bucket.end(),
-                  [&](int a, int b) { return pool[a].vars.size() > pool[b].vars.size(); });
-        std::vector<int> out;
-        for (int i : bucket)
-            for (int x : pool[i].vars)
-                if (x != v && slice_bit(x) < 0 && std::find(out.begin(), out.end(), x) == out.end())
-                    out.push_back(x);
-        TnStepRec st;
-        st.elim = v;
-        st.out_vars = out;
-        const int full = (int)out.size() + 1;
+    for (auto& st : sym.steps) {
+        if (st.dead) continue;
+        TnStepRec rec;
+        rec.elim = st.sums.empty() ? -1 : st.sums[0];
+        rec.nsum = (int)st.sums.size();
+        rec.out_vars = st.out;
+        const int full = (int)st.out.size() + rec.nsum;
         L.width = std::max(L.width, full);
-        L.cost += std::ldexp(1.0, full) * bucket.size();
-        for (int i : bucket) {
+        L.cost += std::ldexp(1.0, full) * st.in.size();
+        for (int i : st.in) {
             TnInputRec in;
             in.kind = pool[i].kind;
             in.gate = pool[i].gate;
@@ -210,85 +310,67 @@ Lowered lower(const std::vector<Tensor>& base, int nv, const std::vector<int>& o
             in.arena = pool[i].arena;
             in.lds = pool[i].lds;
             // position of each of the input's variables in the step's index space
-            // (output variables at bits 0..|out|-1, the summed variable at |out|;
+            // (output variables at bits 0..|out|-1, the summed ones from |out|;
             // a sliced variable: its bit of the slice index)
             for (int x : pool[i].vars) {
-                const auto it = std::find(out.begin(), out.end(), x);
                 const int sb = slice_bit(x);
-                in.pos.push_back(sb >= 0 ? -1 - sb : x == v ? (int)out.size() : (int)(it - out.begin()));
+                if (sb >= 0) {
+                    in.pos.push_back(-1 - sb);
+                    continue;
+                }
+                const auto it = std::find(st.out.begin(), st.out.end(), x);
+                if (it != st.out.end()) {
+                    in.pos.push_back((int)(it - st.out.begin()));
+                } else {
+                    const auto is = std::find(st.sums.begin(), st.sums.end(), x);
+                    if (is == st.sums.end()) fail(STN_E_INVALID, "lightcone lowering: input variable not in its step");
+                    in.pos.push_back((int)st.out.size() + (int)(is - st.sums.begin()));
+                }
             }
-            st.inputs.push_back(in);
-            alive[i] = 0;
+            rec.inputs.push_back(in);
         }
-        // the output is written while the inputs are read: allocate it first
-        Tensor t;
-        t.kind = TN_INTER;
-        t.vars = out;
-        alloc(t, 1 << out.size());
-        for (int i : bucket)
+        // the output is placed while the inputs are still held: no aliasing
+        Tensor& t = pool[st.out_id];
+        alloc(t, 1 << st.out.size());
+        for (int i : st.in)
             if (pool[i].kind == TN_INTER) {
                 if (!pool[i].lds) L.gbytes += std::ldexp(1.0, (int)pool[i].vars.size());
                 release(pool[i]);
             }
-        if (!t.lds) L.gbytes += std::ldexp(1.0, (int)out.size());
-        st.out_arena = t.arena;
-        st.out_lds = t.lds;
-        pool.push_back(t);
-        alive.push_back(1);
-        L.steps.push_back(st);
+        if (!t.lds) L.gbytes += std::ldexp(1.0, (int)st.out.size());
+        rec.out_arena = t.arena;
+        rec.out_lds = t.lds;
+        L.steps.push_back(rec);
     }
-    // remaining scalars (no variables but sliced ones) multiply into the result
-    TnStepRec fin;
-    fin.elim = -1;
-    for (size_t i = 0; i < pool.size(); ++i)
-        if (alive[i]) {
-            TnInputRec in;
-            for (int x : pool[i].vars) {
-                const int sb = slice_bit(x);
-                if (sb < 0) fail(STN_E_INVALID, "tensor left with open indices");
-                in.pos.push_back(-1 - sb);
-            }
-            in.kind = pool[i].kind;
-            in.gate = pool[i].gate;
-            in.conj = pool[i].conj;
-            in.arena = pool[i].arena;
-            in.lds = pool[i].lds;
-            fin.inputs.push_back(in);
-        }
-    Tensor res;
-    res.kind = TN_INTER;
-    alloc(res, 1);
-    for (size_t i = 0; i < pool.size(); ++i)
-        if (alive[i] && pool[i].kind == TN_INTER) release(pool[i]);
-    fin.out_arena = res.arena;
-    fin.out_lds = res.lds;
-    L.steps.push_back(fin);
-    L.result = res.arena;
-    L.result_lds = res.lds;
+    L.result = pool[sym.result].arena;
+    L.result_lds = pool[sym.result].lds;
     L.arena = gmem.high;
     L.lds_arena = lds.high;
     L.order = order;
-    (void)nv;
     return L;
 }
 
-// Lowers `order` for an LDS arena of lds_slots slots with every tensor cap
-// from the whole arena down to 2^6 slots, and keeps the lowering that moves
-// the fewest bytes through global memory (a large tensor kept in LDS can push
-// several smaller ones out).
-Lowered lower_best_placement(const std::vector<Tensor>& base, int nv, const std::vector<int>& order,
-                             const std::vector<int>& sliced, int lds_slots) {
+
+// Lowers `order` for an LDS arena of lds_slots slots with tensor caps of the
+// whole arena, a quarter and a sixteenth of it, and keeps the lowering that
+// moves the fewest bytes through global memory (a large tensor kept in LDS
+// can push several smaller ones out).
+Lowered lower_best_placement(const Symbolic& sym, const std::vector<int>& order, const std::vector<int>& sliced,
+                             int lds_slots) {
     TnArenaLimits lim;
     lim.lds_slots = lds_slots;
     lim.lds_tensor_max = lds_slots;
-    Lowered best = lower(base, nv, order, sliced, lim);
-    for (int cap = lds_slots / 2; cap >= 64; cap /= 2) {
+    Lowered best = place(sym, order, sliced, lim);
+    for (int cap = lds_slots / 4; cap >= 64 && cap >= lds_slots / 16; cap /= 4) {
         lim.lds_tensor_max = cap;
-        Lowered L = lower(base, nv, order, sliced, lim);
+        Lowered L = place(sym, order, sliced, lim);
         if (L.gbytes < best.gbytes) best = std::move(L);
     }
     return best;
 }
+
+// merged-index steps (two summed variables) in complex64 plans only
+int max_sums(const stn_plan* p) { return p->opts.precision == 128 ? 1 : 2; }
 
 void take(TnNetwork& net, Lowered&& L) {
     net.steps = std::move(L.steps);
@@ -339,9 +421,10 @@ std::vector<TnNetwork> lower_caller_order(const stn_plan* p, uint32_t term, cons
         return std::vector<TnNetwork>(lds_slots.size(), net);
     }
     std::vector<TnNetwork> out;
+    const Symbolic sym = eliminate(ts, order, {}, max_sums(p));
     for (int slots : lds_slots) {
         TnNetwork n2 = net;
-        take(n2, lower_best_placement(ts, nv, order, {}, slots));
+        take(n2, lower_best_placement(sym, order, {}, slots));
         out.push_back(std::move(n2));
     }
     return out;
@@ -465,10 +548,11 @@ std::vector<TnNetwork> build_term(const stn_plan* p, uint32_t term, uint32_t u, 
     net.v = v;
     net.n_vars = nv;
     if (p->opts.lc_order_fn) return lower_caller_order(p, term, ts, nv, max_rank, net, lds_slots);
-    TnArenaLimits lim;   // the order search places like the first budget, without the cap search
-    lim.lds_slots = lds_slots.empty() ? 0 : lds_slots[0];
-    lim.lds_tensor_max = lim.lds_slots;
-    Lowered best;
+    struct Scored {
+        std::vector<int> order;
+        int width = 0;
+        double cost = 0;
+    } best;
     bool have = false;
     std::vector<int> sliced;   // slice index bit k fixes variable sliced[k]
     int deg_lb = 0;
@@ -490,9 +574,17 @@ std::vector<TnNetwork> build_term(const stn_plan* p, uint32_t term, uint32_t u, 
                 deg_lb = deg_lb ? std::min(deg_lb, deg) : deg;
                 continue;
             }
-            Lowered L = lower(ts, nv, order, sliced, lim);
-            if (!have || L.width < best.width || (L.width == best.width && L.cost < best.cost)) {
-                best = std::move(L);
+            // width and work of the plain elimination (no merging or placement)
+            const Symbolic sym = eliminate(ts, order, sliced, 1);
+            Scored sc;
+            for (auto& st : sym.steps) {
+                const int full = (int)(st.out.size() + st.sums.size());
+                sc.width = std::max(sc.width, full);
+                sc.cost += std::ldexp(1.0, full) * st.in.size();
+            }
+            if (!have || sc.width < best.width || (sc.width == best.width && sc.cost < best.cost)) {
+                sc.order = order;
+                best = std::move(sc);
                 have = true;
             }
         }
@@ -518,9 +610,10 @@ std::vector<TnNetwork> build_term(const stn_plan* p, uint32_t term, uint32_t u, 
     }
     net.slice_bits = (int)sliced.size();
     std::vector<TnNetwork> out;
+    const Symbolic sym = eliminate(ts, best.order, sliced, max_sums(p));
     for (int slots : lds_slots) {
         TnNetwork n2 = net;
-        take(n2, lower_best_placement(ts, nv, best.order, sliced, slots));
+        take(n2, lower_best_placement(sym, best.order, sliced, slots));
         n2.cost = std::ldexp(n2.cost, n2.slice_bits);
         out.push_back(std::move(n2));
     }

@@ -25,7 +25,9 @@ struct TnInputRec {
 };
 
 struct TnStepRec {
-    int elim = -1;                 // summed variable (-1: the final product of scalars)
+    int elim = -1;                 // first summed variable (-1: the final product of scalars)
+    int nsum = 0;                  // summed variables (step index bits out_vars.size() ..); more than one
+                                   // when consecutive eliminations are merged into one step
     std::vector<int> out_vars;
     std::vector<TnInputRec> inputs;
     int out_arena = -1;

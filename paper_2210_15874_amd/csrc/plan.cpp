@@ -527,7 +527,7 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
             kind = STN_PLAN_SV_GATES;
         } else {
             // statevector passes vs lightcone networks: estimated seconds per trajectory
-            // (HBM-bound passes at ~4 TB/s; lightcone networks: their own estimate)
+            // (HBM-bound passes; lightcone networks: their own estimate)
             double sv_t = -1, tn_t = -1;
             const bool c128 = p->opts.precision == 128;
             if (n >= (c128 ? 13u : 14u) && build_tiled(p, why)) {
@@ -536,7 +536,9 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
                 double bytes = 0;
                 for (auto& ps : p->passes)
                     bytes += std::ldexp(c128 ? 16.0 : 8.0, (int)n) * ((ps.init ? 0 : 1) + (ps.last ? 0 : 1));
-                sv_t = bytes / 4e12;
+                // measured: about 5 TB/s while the strided tiles keep runs of
+                // 128 bytes or more (n <= 24), about 3 TB/s at n = 26
+                sv_t = bytes / (n <= 24 ? 5e12 : 3e12);
             }
             try {
                 build_lightcone(p);

@@ -162,7 +162,7 @@ struct stn_plan {
     // estimated device seconds per trajectory of the chosen lowering (admission and
     // scheduling in the job server; a cost-model figure, not a measurement)
     double est_seconds_per_traj() const {
-        return kind == STN_PLAN_LIGHTCONE ? 2.0 * lc_est_s : bytes_per_traj / 2e12 + flops_per_traj / 2e12;
+        return kind == STN_PLAN_LIGHTCONE ? lc_est_s : bytes_per_traj / 3e12 + flops_per_traj / 5e13;
     }
 
     // device tables shared by every lowering
