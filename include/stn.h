@@ -185,11 +185,11 @@ typedef struct {
     uint32_t n_qubits, n_gates, n_sites;
     uint32_t max_batch;
     uint32_t width;         /* contraction width: n for statevector plans, max rank for lightcone */
-    uint32_t n_passes;      /* statevector HBM passes per trajectory (tiled plan; gate-by-gate plan: its
-                               non-identity operator-list entries, one launch each) */
+    uint32_t n_passes;      /* statevector HBM passes per trajectory (tiled plan; gate-by-gate plan: its fused
+                               groups of operator-list entries, one launch each) */
     uint32_t n_steps;       /* contraction steps (lightcone plan) */
     double bytes_per_traj;  /* algorithmic HBM bytes per trajectory (cost model; gate-by-gate plan: an upper
-                               bound, every entry counted as moving the whole state) */
+                               bound, every fused group counted as moving the whole state) */
     double flops_per_traj;  /* algorithmic flops per trajectory (cost model) */
     double peak_bytes;      /* device working memory at max_batch */
     uint32_t lc_width;      /* lightcone networks' width when the planner built them (0: not built); a lower bound when

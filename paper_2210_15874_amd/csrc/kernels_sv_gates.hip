@@ -3,21 +3,26 @@
 // simulated to its statevector; Eq. (1): after a gate, each of its channels
 // contributes one Kraus operator, picked per trajectory).  The batch's states
 // psi[k][x] (complex64 or complex128, 2^n per trajectory, trajectory-major)
-// stay in HBM; every entry of the plan's operator list (the gate list with a
-// noise-site entry after each gate's channels) is one launch over the whole
-// batch.  A launch's item is one group of amplitudes that the operator mixes:
-// a pair over q0 (one-qubit operators) or a quadruple over (q0, q1) (two-qubit
-// ones).  At a noise site each trajectory resolves its own operator (identity,
-// a Pauli as a signed permutation with its global phase dropped, or the dense
-// K_j / sqrt(q_j)), always on the site's qubits, so a launch's items are the
-// same for every trajectory.  Each launch reads and writes the batch once; no
-// operators are fused.
+// stay in HBM.  The plan's operator list (the gates in order, with a
+// noise-site entry after each gate for each of its channels) is cut into
+// groups of consecutive entries whose qubits, together with the four lowest
+// storage bits, fit one tile of 13 storage bits (12 in complex128).  Each
+// group is one launch: a workgroup serves one trajectory, resolves the
+// group's operators for it once (at a noise site the trajectory's own
+// operator: identity, a Pauli as a signed permutation with its global phase
+// dropped, or the dense K_j / sqrt(q_j)), then for each of its tiles loads the
+// 2^13 amplitudes into LDS, applies the group's operators in order and stores
+// them back.  A group all of whose operators are the identity for a
+// trajectory leaves that trajectory untouched.  The first group generates
+// |0..0> instead of loading.
 //
 // Energy: <psi|C|psi>, C = sum_t w_t [z_u != z_v], per trajectory: each
 // workgroup sums |psi(x)|^2 C(x) over one contiguous slice in binary64 in a
 // fixed order and tree, then one lane per trajectory adds the slices in
 // order, so the value does not depend on the launch.
-#include "stn_internal.h"
+#include <algorithm>
+
+#include "sv_ops.h"
 
 namespace stn {
 
@@ -26,27 +31,6 @@ namespace {
 template <class R> struct Cg;
 template <> struct Cg<float> { using T = float2; };
 template <> struct Cg<double> { using T = double2; };
-
-template <class V> __device__ __forceinline__ V gmul(V a, V b) {
-    V r;
-    r.x = a.x * b.x - a.y * b.y;
-    r.y = a.x * b.y + a.y * b.x;
-    return r;
-}
-template <class V> __device__ __forceinline__ V gadd(V a, V b) {
-    a.x += b.x;
-    a.y += b.y;
-    return a;
-}
-template <class V> __device__ __forceinline__ V gneg(V a, bool neg) {
-    if (neg) { a.x = -a.x; a.y = -a.y; }
-    return a;
-}
-
-__device__ __forceinline__ uint64_t insert0(uint64_t p, uint32_t q) {
-    const uint64_t lo = p & ((1ull << q) - 1ull);
-    return ((p ^ lo) << 1) | lo;
-}
 
 constexpr uint32_t kGateThreads = 256;
 constexpr uint32_t kEnergySlices = 64;   // workgroups per trajectory in the energy sum
@@ -63,110 +47,93 @@ __global__ __launch_bounds__(256) void k_gates_init(V* __restrict__ psi, uint64_
     }
 }
 
-// One operator-list entry over the batch: grid (group chunks, trajectory).
-// nq = 1: groups are pairs over q0; nq = 2: quadruples, local index bit 0 =
-// q0, bit 1 = q1.  A workgroup serves one trajectory, so it resolves the
-// operator once (a trajectory that drew the identity returns at once) and
-// keeps its values in registers.  Each lane takes kGroupsPerLane groups per
-// round and issues all their loads before any store (distinct groups never
-// share an amplitude), so more bytes are in flight per lane.
-constexpr uint32_t kGroupsPerLane = 4;
-constexpr uint32_t kGateChunksMax = 2048;   // enough workgroups for one trajectory at n = 30
+constexpr uint32_t kTileThreads = 256;
 
+__device__ __forceinline__ uint64_t remap_mask(uint64_t m, const uint8_t* local) {
+    uint64_t r = 0;
+    for (; m; m &= m - 1) r |= 1ull << local[__builtin_ctzll(m)];
+    return r;
+}
+
+// One group over the batch: grid (tile chunks, trajectory).  LDS: the tile
+// (2^g.nbits amplitudes) and the group's operators resolved for this
+// trajectory.
 template <class V>
-__global__ __launch_bounds__(256) void k_gates_op(V* __restrict__ psi, uint32_t n, LdsOp op, uint32_t nq,
-                                                  const V* __restrict__ vals, const LdsOp* __restrict__ site_ops,
-                                                  const uint32_t* __restrict__ site_off,
-                                                  const uint8_t* __restrict__ idx, uint32_t S) {
+__global__ __launch_bounds__(256) void k_gates_tile(V* __restrict__ psi, uint32_t n, const GateGroup g, int init,
+                                                    const LdsOp* __restrict__ gops, const V* __restrict__ vals,
+                                                    const LdsOp* __restrict__ site_ops,
+                                                    const uint32_t* __restrict__ site_off,
+                                                    const uint8_t* __restrict__ idx, uint32_t S) {
+    extern __shared__ __align__(16) char smem[];
+    const uint32_t T = 1u << g.nbits;
+    V* tile = reinterpret_cast<V*>(smem);
+    LdsOp* ops = reinterpret_cast<LdsOp*>(tile + T);
+    __shared__ int s_any;
+    const uint32_t tid = threadIdx.x;
     const uint64_t k = blockIdx.y;
-    LdsOp o = op;
-    if (op.kind == OP_SITE) o = site_ops[site_off[op.site] + idx[k * S + op.site]];
-    if (o.kind == OP_IDENT) return;   // the same for the whole workgroup; no barrier follows
-    const uint32_t qa = nq == 2 ? min(op.q0, op.q1) : op.q0, qb = nq == 2 ? max(op.q0, op.q1) : 0;
-    const uint64_t groups = 1ull << (n - nq);
-    V* base = psi + k * (1ull << n);
-    const uint64_t b0 = 1ull << op.q0, b1 = nq == 2 ? 1ull << op.q1 : 0;
-    const uint32_t nv = o.kind == OP_DENSE2 ? 16 : (o.kind == OP_DENSE1 || o.kind == OP_DIAG2) ? 4
-                      : o.kind == OP_DIAG1 ? 2 : 0;
-    V m[16];
-#pragma unroll
-    for (uint32_t t = 0; t < 16; ++t) {
-        m[t].x = 0;
-        m[t].y = 0;
-        if (t < nv) m[t] = vals[o.mat + t];
+    if (tid == 0) s_any = 0;
+    __syncthreads();
+    // this trajectory's operators on tile-local qubits
+    for (uint32_t i = tid; i < g.n_ops; i += kTileThreads) {
+        LdsOp o = gops[g.op0 + i];
+        if (o.kind == OP_SITE) {
+            o = site_ops[site_off[o.site] + idx[k * S + o.site]];
+            o.q0 = g.local[o.q0 & 31u];
+            o.q1 = g.local[o.q1 & 31u];
+            o.xmask = remap_mask(o.xmask, g.local);
+            o.zmask = remap_mask(o.zmask, g.local);
+        }
+        if (o.kind != OP_IDENT) s_any = 1;
+        ops[i] = o;
     }
-    const uint64_t span = (uint64_t)kGateThreads * kGroupsPerLane;
-    for (uint64_t g0 = (uint64_t)blockIdx.x * span + threadIdx.x; g0 < groups; g0 += (uint64_t)gridDim.x * span) {
-        uint64_t ix[kGroupsPerLane][4];
-        V a[kGroupsPerLane][4];
-        bool act[kGroupsPerLane];
-#pragma unroll
-        for (uint32_t r = 0; r < kGroupsPerLane; ++r) {
-            const uint64_t g = g0 + (uint64_t)r * kGateThreads;
-            act[r] = g < groups;
-            if (!act[r]) continue;
-            const uint64_t i = nq == 1 ? insert0(g, qa) : insert0(insert0(g, qa), qb);
-            ix[r][0] = i;
-            ix[r][1] = i | b0;
-            ix[r][2] = i | b1;
-            ix[r][3] = i | b0 | b1;
-            a[r][0] = base[ix[r][0]];
-            a[r][1] = base[ix[r][1]];
-            if (nq == 2) {
-                a[r][2] = base[ix[r][2]];
-                a[r][3] = base[ix[r][3]];
-            }
+    __syncthreads();
+    if (!s_any && !init) return;   // the same for the whole workgroup
+    // storage index = tile base | spread(local index), spread(j) = sum_l bit l of j << tb[l]
+    uint64_t fixed = (1ull << n) - 1ull;
+    for (uint32_t l = 0; l < g.nbits; ++l) fixed &= ~(1ull << g.tb[l]);
+    uint64_t zt = 0;
+    for (uint32_t l = 0; l < g.nbits && l < 8; ++l)
+        if ((tid >> l) & 1u) zt |= 1ull << g.tb[l];
+    const uint32_t nt = 1u << (n - g.nbits);
+    V* st = psi + (k << n);
+    for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
+        uint64_t base = 0;
+        {
+            uint32_t v = t;
+            for (uint64_t m = fixed; m; m &= m - 1, v >>= 1)
+                if (v & 1u) base |= m & (~m + 1);
         }
-#pragma unroll
-        for (uint32_t r = 0; r < kGroupsPerLane; ++r) {
-            if (!act[r]) continue;
-            V res[4];
-            switch (o.kind) {
-                case OP_DENSE1:   // on q0 (a one-qubit site or gate)
-                    res[0] = gadd(gmul(m[0], a[r][0]), gmul(m[1], a[r][1]));
-                    res[1] = gadd(gmul(m[2], a[r][0]), gmul(m[3], a[r][1]));
-                    break;
-                case OP_DENSE2:
-#pragma unroll
-                    for (uint32_t l = 0; l < 4; ++l) {
-                        V acc = gmul(m[4 * l], a[r][0]);
-#pragma unroll
-                        for (uint32_t c = 1; c < 4; ++c) acc = gadd(acc, gmul(m[4 * l + c], a[r][c]));
-                        res[l] = acc;
-                    }
-                    break;
-                case OP_DIAG1:
-                    res[0] = gmul(m[0], a[r][0]);
-                    res[1] = gmul(m[1], a[r][1]);
-                    break;
-                case OP_DIAG2:
-#pragma unroll
-                    for (uint32_t l = 0; l < 4; ++l) res[l] = gmul(m[l], a[r][l]);
-                    break;
-                default: {        // OP_PAULI: amplitude at x moves to x ^ X with sign (-1)^|x & Z|
-                    const uint64_t X = o.xmask, Z = o.zmask;
-#pragma unroll
-                    for (uint32_t t = 0; t < 4; ++t) {
-                        V v = a[r][0];
-                        uint64_t src = ix[r][0];
-#pragma unroll
-                        for (uint32_t l = 1; l < 4; ++l)
-                            if (l < (1u << nq) && (ix[r][l] ^ X) == ix[r][t]) {
-                                v = a[r][l];
-                                src = ix[r][l];
-                            }
-                        res[t] = gneg(v, __popcll(src & Z) & 1);
-                    }
-                    break;
-                }
+        for (uint32_t r = 0; (r << 8) < T; ++r) {
+            const uint32_t j = tid + (r << 8);
+            if (j >= T) break;
+            uint64_t z = base | zt;
+            for (uint32_t l = 8; l < g.nbits; ++l)
+                if ((r >> (l - 8)) & 1u) z |= 1ull << g.tb[l];
+            V v;
+            if (init) {
+                v.x = z == 0 ? 1 : 0;
+                v.y = 0;
+            } else {
+                v = st[z];
             }
-            base[ix[r][0]] = res[0];
-            base[ix[r][1]] = res[1];
-            if (nq == 2) {
-                base[ix[r][2]] = res[2];
-                base[ix[r][3]] = res[3];
-            }
+            tile[j] = v;
         }
+        __syncthreads();
+        for (uint32_t i = 0; i < g.n_ops; ++i) {
+            const LdsOp o = ops[i];
+            if (o.kind == OP_IDENT) continue;   // uniform: no barrier needed
+            apply_lds_op<V>(tile, T, o, vals, tid, kTileThreads);
+            __syncthreads();
+        }
+        for (uint32_t r = 0; (r << 8) < T; ++r) {
+            const uint32_t j = tid + (r << 8);
+            if (j >= T) break;
+            uint64_t z = base | zt;
+            for (uint32_t l = 8; l < g.nbits; ++l)
+                if ((r >> (l - 8)) & 1u) z |= 1ull << g.tb[l];
+            st[z] = tile[j];
+        }
+        __syncthreads();   // the tile is reloaded next round
     }
 }
 
@@ -215,30 +182,29 @@ template <class V> void run_gates(stn_plan* p, stn_batch* b, hipStream_t s, cons
     const uint32_t n = p->n, K = b->K;
     const uint64_t N = 1ull << n;
     V* psi = b->d_states.as<V>();
-    const uint32_t cap = 256 * 16;
-    auto grid = [&](uint64_t items) {
-        return (uint32_t)std::min<uint64_t>((items + kGateThreads - 1) / kGateThreads, cap);
-    };
-    hipLaunchKernelGGL(k_gates_init<V>, dim3(grid(N * K)), dim3(kGateThreads), 0, s, psi, N * K, n);
-    STN_HIP(hipGetLastError());
     const uint32_t S = (uint32_t)p->sites.size();
-    for (LdsOp op : p->lds_ops) {
-        uint32_t nq;
-        if (op.kind == OP_SITE) {   // the entry names the site; its groups are over the site's qubits
-            const SiteRec& site = p->sites[op.site];
-            nq = site.nq;
-            op.q0 = site.q0;
-            op.q1 = site.q1;
-        } else if (op.kind == OP_IDENT) {
-            continue;
-        } else {
-            nq = (op.kind == OP_DENSE2 || op.kind == OP_DIAG2) ? 2 : 1;
-        }
-        const uint64_t span = (uint64_t)kGateThreads * kGroupsPerLane;
-        const uint32_t chunks = (uint32_t)std::min<uint64_t>(((N >> nq) + span - 1) / span, kGateChunksMax);
-        hipLaunchKernelGGL(k_gates_op<V>, dim3(chunks, K), dim3(kGateThreads), 0, s, psi, n, op, nq, vals,
-                           p->d_site_ops.as<LdsOp>(), p->d_site_op_off.as<uint32_t>(), b->d_idx.as<uint8_t>(), S);
+    if (p->gate_groups.empty()) {   // no operators: the state stays |0..0>
+        const uint32_t grid = (uint32_t)std::min<uint64_t>((N * K + kGateThreads - 1) / kGateThreads, 4096);
+        hipLaunchKernelGGL(k_gates_init<V>, dim3(grid), dim3(kGateThreads), 0, s, psi, N * K, n);
         STN_HIP(hipGetLastError());
+    }
+    bool first = true;
+    for (const GateGroup& g : p->gate_groups) {
+        const size_t lds = (sizeof(V) << g.nbits) + sizeof(LdsOp) * kGroupMaxOps;
+        static bool raised[2] = {false, false};
+        if (lds > 64 * 1024 && !raised[sizeof(V) > 8]) {
+            STN_HIP(hipFuncSetAttribute((const void*)k_gates_tile<V>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)((sizeof(V) << 13) + sizeof(LdsOp) * kGroupMaxOps)));
+            raised[sizeof(V) > 8] = true;
+        }
+        // about 2048 workgroups in all; each loops over its share of a trajectory's tiles
+        const uint32_t nt = 1u << (n - g.nbits);
+        const uint32_t chunks = std::max<uint32_t>(1, std::min<uint32_t>(nt, (2048 + K - 1) / K));
+        hipLaunchKernelGGL(k_gates_tile<V>, dim3(chunks, K), dim3(kTileThreads), lds, s, psi, n, g, first ? 1 : 0,
+                           p->d_gate_group_ops.as<LdsOp>(), vals, p->d_site_ops.as<LdsOp>(),
+                           p->d_site_op_off.as<uint32_t>(), b->d_idx.as<uint8_t>(), S);
+        STN_HIP(hipGetLastError());
+        first = false;
     }
     hipLaunchKernelGGL(k_gates_energy<V>, dim3(kEnergySlices, K), dim3(kGateThreads), 0, s, psi, n,
                        p->d_obs.as<uint32_t>(), p->d_obs_w.as<double>(), (uint32_t)p->obs_u.size(),
@@ -251,6 +217,77 @@ template <class V> void run_gates(stn_plan* p, stn_batch* b, hipStream_t s, cons
 
 }  // namespace
 
+// Cuts the operator list into groups whose qubits, with the four lowest
+// storage bits (runs of at least 128 bytes), fit one tile; the tile is filled
+// up with the lowest remaining storage bits.  Operators keep their order.
+void build_gate_groups(stn_plan* p) {
+    const uint32_t n = p->n;
+    const uint32_t tile_bits = std::min<uint32_t>(n, p->opts.precision == 128 ? 12u : 13u);
+    const uint64_t low = n > tile_bits ? 0xFull : (1ull << n) - 1ull;
+    p->gate_groups.clear();
+    p->gate_group_ops.clear();
+    std::vector<LdsOp> cur;
+    uint64_t qs = low;
+    auto qubits = [&](const LdsOp& o) -> uint64_t {
+        switch (o.kind) {
+            case OP_DENSE1: case OP_DIAG1: return 1ull << o.q0;
+            case OP_DENSE2: case OP_DIAG2: return (1ull << o.q0) | (1ull << o.q1);
+            case OP_PAULI: return o.xmask | o.zmask;
+            case OP_SITE: {
+                const SiteRec& st = p->sites[o.site];
+                return (1ull << st.q0) | (st.nq == 2 ? 1ull << st.q1 : 0ull);
+            }
+            default: return 0;
+        }
+    };
+    auto close = [&]() {
+        if (cur.empty()) return;
+        GateGroup g{};
+        uint64_t tile = qs;
+        for (uint32_t q = 0; q < n && (uint32_t)__builtin_popcountll(tile) < tile_bits; ++q) tile |= 1ull << q;
+        g.nbits = (uint32_t)__builtin_popcountll(tile);
+        for (int q = 0; q < 32; ++q) g.local[q] = 0xFF;
+        uint32_t l = 0;
+        for (uint32_t q = 0; q < n; ++q)
+            if ((tile >> q) & 1ull) {
+                g.tb[l] = (uint8_t)q;
+                g.local[q] = (uint8_t)l;
+                ++l;
+            }
+        g.op0 = (uint32_t)p->gate_group_ops.size();
+        g.n_ops = (uint32_t)cur.size();
+        for (LdsOp o : cur) {
+            if (o.kind != OP_SITE) {   // gates on tile-local qubits now; sites are remapped per trajectory
+                o.q0 = g.local[o.q0 & 31u] == 0xFF ? 0 : g.local[o.q0 & 31u];
+                o.q1 = g.local[o.q1 & 31u] == 0xFF ? 0 : g.local[o.q1 & 31u];
+                uint64_t x = 0, z = 0;
+                for (uint64_t m = o.xmask; m; m &= m - 1) x |= 1ull << g.local[__builtin_ctzll(m)];
+                for (uint64_t m = o.zmask; m; m &= m - 1) z |= 1ull << g.local[__builtin_ctzll(m)];
+                o.xmask = x;
+                o.zmask = z;
+            }
+            p->gate_group_ops.push_back(o);
+        }
+        p->gate_groups.push_back(g);
+        cur.clear();
+        qs = low;
+    };
+    for (const LdsOp& o : p->lds_ops) {
+        if (o.kind == OP_IDENT) continue;
+        const uint64_t q = qubits(o);
+        if ((uint32_t)__builtin_popcountll(qs | q) > tile_bits || cur.size() >= kGroupMaxOps) close();
+        qs |= q;
+        cur.push_back(o);
+    }
+    close();
+}
+
+void upload_gate_groups(stn_plan* p, hipStream_t s) {
+    std::vector<LdsOp> ops = p->gate_group_ops;
+    ops.push_back(LdsOp{});
+    upload(p->d_gate_group_ops, &p->alloc, ops.data(), ops.size() * sizeof(LdsOp), s);
+}
+
 void launch_sv_gates(stn_plan* p, stn_batch* b, hipStream_t s) {
     const uint32_t n = p->n;
     if (n < 2 || n > kGatesMaxQubits) fail(STN_E_UNSUPPORTED, "gate-by-gate lowering needs 2 <= n <= 30");
@@ -262,23 +299,10 @@ void launch_sv_gates(stn_plan* p, stn_batch* b, hipStream_t s) {
     prof_begin(p, STN_K_SV_PASS, s);
     if (dbl) run_gates<double2>(p, b, s, p->d_lds_vals64.as<double2>());
     else run_gates<float2>(p, b, s, p->d_lds_vals32.as<float2>());
-    // bytes counted: entries that read and write every trajectory's state (gates,
-    // and noise sites none of whose operators is the identity).  Sites whose
-    // identity operator most trajectories draw are left out, so the figure is a
-    // lower bound on the bytes moved.
-    double full = 0;
-    for (const LdsOp& op : p->lds_ops) {
-        if (op.kind == OP_IDENT) continue;
-        if (op.kind != OP_SITE) {
-            full += 1;
-            continue;
-        }
-        bool any_ident = false;
-        for (uint32_t j = p->site_op_off[op.site]; j < p->site_op_off[op.site + 1]; ++j)
-            any_ident |= p->site_ops[j].kind == OP_IDENT;
-        full += any_ident ? 0 : 1;
-    }
-    prof_end(p, STN_K_SV_PASS, s, std::ldexp((double)b->K * elem, (int)n) * (2.0 * full + 2.0), 0.0);
+    // bytes: every group reads and writes each trajectory's state (the first
+    // one only writes), and the energy reads it once more
+    prof_end(p, STN_K_SV_PASS, s, std::ldexp((double)b->K * elem, (int)n) * 2.0 * (double)p->gate_groups.size(),
+             0.0);
 }
 
 }  // namespace stn

@@ -12,7 +12,7 @@
 // C = sum_t w_t [z_u != z_v]: each amplitude's term in binary64 into LDS, and
 // a pairwise tree over the 2^n terms, so the result does not depend on the
 // workgroup size (a launch shape the autotuner picks).
-#include "stn_internal.h"
+#include "sv_ops.h"
 
 namespace stn {
 
@@ -21,28 +21,6 @@ namespace {
 template <class R> struct Cx;
 template <> struct Cx<float> { using T = float2; };
 template <> struct Cx<double> { using T = double2; };
-
-template <class V> __device__ __forceinline__ V cmul(V a, V b) {
-    V r;
-    r.x = a.x * b.x - a.y * b.y;
-    r.y = a.x * b.y + a.y * b.x;
-    return r;
-}
-template <class V> __device__ __forceinline__ V cadd(V a, V b) {
-    a.x += b.x;
-    a.y += b.y;
-    return a;
-}
-template <class V> __device__ __forceinline__ V cneg_if(V a, bool neg) {
-    if (neg) { a.x = -a.x; a.y = -a.y; }
-    return a;
-}
-
-// index with a zero bit inserted at position q
-__device__ __forceinline__ uint32_t ins0(uint32_t p, uint32_t q) {
-    const uint32_t lo = p & ((1u << q) - 1u);
-    return ((p ^ lo) << 1) | lo;
-}
 
 // One trajectory of one plan in the workgroup's LDS (psi: 2^n amplitudes,
 // plus 2^n binary64 terms for complex128): the gate list with the picked
@@ -69,69 +47,7 @@ __device__ __forceinline__ void lds_trajectory(typename Cx<R>::T* psi, uint32_t 
     for (uint32_t oi = 0; oi < n_ops; ++oi) {
         LdsOp o = ops[oi];
         if (o.kind == OP_SITE) o = site_ops[site_off[o.site] + row[o.site]];
-        switch (o.kind) {
-            case OP_DENSE1: {
-                const V m0 = vals[o.mat], m1 = vals[o.mat + 1], m2 = vals[o.mat + 2], m3 = vals[o.mat + 3];
-                const uint32_t bit = 1u << o.q0;
-                for (uint32_t p = tid; p < N / 2; p += kThreads) {
-                    const uint32_t i0 = ins0(p, o.q0), i1 = i0 | bit;
-                    const V a = psi[i0], c = psi[i1];
-                    psi[i0] = cadd(cmul(m0, a), cmul(m1, c));
-                    psi[i1] = cadd(cmul(m2, a), cmul(m3, c));
-                }
-                break;
-            }
-            case OP_DENSE2: {
-                const uint32_t qa = o.q0 < o.q1 ? o.q0 : o.q1, qb = o.q0 < o.q1 ? o.q1 : o.q0;
-                const uint32_t b0 = 1u << o.q0, b1 = 1u << o.q1;
-                for (uint32_t p = tid; p < N / 4; p += kThreads) {
-                    const uint32_t i = ins0(ins0(p, qa), qb);
-                    const uint32_t ix[4] = {i, i | b0, i | b1, i | b0 | b1};
-                    V v[4];
-#pragma unroll
-                    for (int l = 0; l < 4; ++l) v[l] = psi[ix[l]];
-#pragma unroll
-                    for (int l = 0; l < 4; ++l) {
-                        V acc = cmul(vals[o.mat + 4 * l], v[0]);
-#pragma unroll
-                        for (int m = 1; m < 4; ++m) acc = cadd(acc, cmul(vals[o.mat + 4 * l + m], v[m]));
-                        psi[ix[l]] = acc;
-                    }
-                }
-                break;
-            }
-            case OP_DIAG1: {
-                const V d0 = vals[o.mat], d1 = vals[o.mat + 1];
-                for (uint32_t i = tid; i < N; i += kThreads) psi[i] = cmul((i >> o.q0) & 1 ? d1 : d0, psi[i]);
-                break;
-            }
-            case OP_DIAG2: {
-                const V d0 = vals[o.mat], d1 = vals[o.mat + 1], d2 = vals[o.mat + 2], d3 = vals[o.mat + 3];
-                for (uint32_t i = tid; i < N; i += kThreads) {
-                    // selects, not an indexed local array (which would live in scratch)
-                    const bool a = (i >> o.q0) & 1, b = (i >> o.q1) & 1;
-                    const V lo = a ? d1 : d0, hi = a ? d3 : d2;
-                    psi[i] = cmul(b ? hi : lo, psi[i]);
-                }
-                break;
-            }
-            case OP_PAULI: {
-                const uint32_t x = (uint32_t)o.xmask, z = (uint32_t)o.zmask;
-                if (x == 0) {
-                    for (uint32_t i = tid; i < N; i += kThreads) psi[i] = cneg_if(psi[i], __popc(i & z) & 1);
-                } else {
-                    const uint32_t lb = __ffs(x) - 1;
-                    for (uint32_t p = tid; p < N / 2; p += kThreads) {
-                        const uint32_t i = ins0(p, lb), j = i ^ x;
-                        const V a = psi[i], c = psi[j];
-                        psi[j] = cneg_if(a, __popc(i & z) & 1);
-                        psi[i] = cneg_if(c, __popc(j & z) & 1);
-                    }
-                }
-                break;
-            }
-            default: break;  // identity
-        }
+        apply_lds_op<V>(psi, N, o, vals, tid, kThreads);
         __syncthreads();
     }
     // energy <psi|C|psi> in binary64: per-amplitude terms, then a fixed tree

@@ -602,6 +602,7 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
         }
         p->passes.clear();
         build_lds_program(p);
+        build_gate_groups(p);
     } else {
         fail(STN_E_INVALID, "unknown plan kind");
     }
@@ -624,17 +625,17 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
         p->max_batch = p->opts.max_batch ? p->opts.max_batch : (uint32_t)std::min(65535.0, std::max(1.0, budget / per));
         p->peak_bytes = per * p->max_batch;
     } else if (kind == STN_PLAN_SV_GATES) {
-        // every non-identity operator entry reads and writes the state once
+        // every fused group reads and writes the state once (the first only
+        // writes), and the energy reads it
         p->width = n;
-        double ops = 0, fl = 0;
+        double fl = 0;
         for (auto& o : p->lds_ops) {
             if (o.kind == OP_IDENT) continue;
-            ops += 1;
             const bool two = o.kind == OP_DENSE2 || o.kind == OP_DIAG2 || (o.kind == OP_SITE && p->sites[o.site].nq == 2);
             fl += (two ? 32.0 : 8.0) * N;
         }
-        p->n_passes = (uint32_t)ops;
-        p->bytes_per_traj = N * elem * (2.0 * ops + 2.0);
+        p->n_passes = (uint32_t)p->gate_groups.size();
+        p->bytes_per_traj = N * elem * 2.0 * (double)p->gate_groups.size();
         p->flops_per_traj = fl;
         const double per = N * elem + 64.0 * 8.0 + 64.0 + p->sites.size();
         const double budget = p->opts.hbm_budget ? (double)p->opts.hbm_budget : 64.0 * (1ull << 30);

@@ -84,6 +84,16 @@ struct LdsOp {
     uint32_t pad;
 };
 
+// Gate-by-gate lowering: consecutive operator-list entries whose qubits fit
+// one tile of storage bits run as one pass over the tiles.
+constexpr uint32_t kGroupMaxOps = 128;
+struct GateGroup {
+    uint32_t op0, n_ops;     // entries gate_group_ops[op0 .. op0 + n_ops)
+    uint32_t nbits;          // tile bits
+    uint8_t tb[16];          // storage bit of each tile-local bit, ascending
+    uint8_t local[32];       // tile-local bit of each qubit, 0xFF outside the tile
+};
+
 struct SiteRec {
     uint32_t gate = 0, nq = 1, q0 = 0, q1 = 0, J = 0;
     std::vector<double> q;           // selection probabilities
@@ -177,6 +187,9 @@ struct stn_plan {
 
     // SV_LDS lowering
     std::vector<stn::LdsOp> lds_ops;
+    std::vector<stn::GateGroup> gate_groups;   // gate-by-gate lowering: fused passes over tiles
+    std::vector<stn::LdsOp> gate_group_ops;    // their operators, on tile-local qubits
+    stn::DevBuf d_gate_group_ops;
     std::vector<stn::cd> lds_vals;          // dense / diag values of gates
     std::vector<uint32_t> site_op_off;      // per site: first entry in site_ops
     std::vector<stn::LdsOp> site_ops;       // per (site, j) operator descriptors
@@ -309,6 +322,10 @@ void launch_sv_tiled(stn_plan* p, stn_batch* b, hipStream_t s);
 // gate-by-gate HBM statevector lowering (any circuit and channel)
 constexpr uint32_t kGatesMaxQubits = 30;
 void launch_sv_gates(stn_plan* p, stn_batch* b, hipStream_t s);
+// gate-by-gate lowering: fuses the operator list into tile passes (plan time)
+// and uploads them
+void build_gate_groups(stn_plan* p);
+void upload_gate_groups(stn_plan* p, hipStream_t s);
 void launch_reduce(stn_plan* p, stn_batch* b, stn_accum* a, hipStream_t s);
 // fixed-order energy statistics over the gathered per-trajectory energies
 void launch_energy_stats(stn_accum* a, uint64_t K, hipStream_t s);

@@ -80,6 +80,7 @@ void upload_plan_tables(stn_plan* p, hipStream_t s) {
         up(p->d_site_ops, a, sops, s);
         up(p->d_site_op_off, a, p->site_op_off, s);
         up_complex(p->d_lds_vals32, p->d_lds_vals64, a, p->lds_vals, s);
+        if (p->kind == STN_PLAN_SV_GATES) upload_gate_groups(p, s);
     } else if (p->kind == STN_PLAN_SV_TILED) {
         if (p->opts.precision == 128) upload_tiled128(p, s);
         else upload_tiled(p, s);
