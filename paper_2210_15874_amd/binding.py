@@ -15,7 +15,8 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libstn.so")
+# STN_LIBRARY names another build of the same library (e.g. the host-sanitizer build)
+LIB_PATH = os.environ.get("STN_LIBRARY") or os.path.join(_HERE, "libstn.so")
 
 GATE_KIND = {"h": 0, "x": 1, "y": 2, "z": 3, "rx": 4, "ry": 5, "rz": 6, "zz": 7, "cx": 8, "u1": 9, "u2": 10}
 CHANNEL_KIND = {"bitflip": 0, "depol1": 1, "depol2": 2, "ampdamp": 3, "kraus": 4}

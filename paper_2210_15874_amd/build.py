@@ -61,6 +61,56 @@ def _compile(src, kind):
     return out, r.stderr
 
 
+# Host-side AddressSanitizer + UndefinedBehaviorSanitizer build of the
+# library (host sources instrumented, device code as usual), for CPU tests of
+# the planner; loaded into a process that preloads the sanitizer runtime.
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+ASAN_BUILD = os.path.join(ROOT, "_build_asan")
+ASAN_LIB = os.path.join(ASAN_BUILD, "libstn_asan.so")
+
+
+def sanitizer_runtime():
+    """Path of the AddressSanitizer runtime the instrumented library needs."""
+    r = subprocess.run([hipcc(), "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if r.returncode == 0 and os.path.isabs(path) and os.path.exists(path):
+        return path
+    import glob
+    hits = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not hits:
+        raise RuntimeError("AddressSanitizer runtime not found")
+    return hits[-1]
+
+
+def build_sanitized_library():
+    """Builds _build_asan/libstn_asan.so: host sources with ASan + UBSan."""
+    os.makedirs(ASAN_BUILD, exist_ok=True)
+
+    def one(kv):
+        src, kind = kv
+        out = os.path.join(ASAN_BUILD, src + ".o")
+        path = os.path.join(CSRC, src)
+        if kind == "host":
+            cmd = [hipcc(), "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-g"] + COMMON + HOST_ONLY + SANITIZE + \
+                  ["-c", path, "-o", out]
+        else:
+            cmd = [hipcc(), "-x", "hip"] + COMMON + DEVICE + ["-c", path, "-o", out]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+        return out
+
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        objs = list(ex.map(one, SOURCES.items()))
+    cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-pthread", "-Xarch_host", "-fsanitize=address",
+           "-Xarch_host", "-fsanitize=undefined", "-shared-libsan", "-o", ASAN_LIB] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    return ASAN_LIB
+
+
 def build_library(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:

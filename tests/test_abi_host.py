@@ -296,3 +296,41 @@ def test_server_needs_a_device_and_valid_options():
     if not has_gpu:
         with pytest.raises(StnError, match="DEVICE"):
             Server()
+
+
+def test_planning_mixed_workloads():
+    """Host planning of every lowering on a spread of inputs (the sanitizer
+    run executes this too): random circuits of every gate and channel kind in
+    the LDS and gate-by-gate lowerings, Erdos-Renyi QAOA jobs through AUTO
+    (lightcone networks with trajectory groups and merged steps, or the tiled
+    statevector), complex128 lightcone plans, sliced networks, and the
+    paper's 4-regular experiment circuits."""
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from random_circuits import random_problem
+    from workloads import erdos_renyi_graph, make_problem, paper_experiment_problem, uniform_angles
+    from paper_2210_15874_amd import OUT_DIAG, OUT_ENERGY, OUT_RHO, PLAN_LIGHTCONE, PLAN_SV_GATES, PLAN_SV_LDS
+    for seed in range(12):
+        pr = random_problem(seed)
+        outs = OUT_RHO | OUT_DIAG | (OUT_ENERGY if pr.edges else 0)
+        assert plan(pr, outputs=outs, plan_kind=PLAN_SV_LDS).info()["plan_name"] == "sv_lds"
+        big = random_problem(100 + seed, n_range=(14, 20))
+        i = plan(big, outputs=OUT_DIAG, plan_kind=PLAN_SV_GATES).info()
+        assert i["plan_name"] == "sv_gates" and 0 < i["n_passes"]
+    for n, p, kind in [(22, 2, "lightcone"), (29, 2, "lightcone"), (20, 1, "lightcone"), (24, 3, "sv_tiled"),
+                       (16, 3, "sv_tiled")]:
+        g, b = uniform_angles(p, 5000 + n)
+        pr = make_problem(n, erdos_renyi_graph(n, 3.0 / (n - 1), 4000 + n), g, b, 1e-3, 1e-2, 64, 6000 + n)
+        i = plan(pr).info()
+        assert i["plan_name"] == kind, (n, p, i["plan_name"])
+        if kind == "lightcone":
+            assert i["lc_group"] in (1, 2, 4, 8, 16) and i["lc_width_lower_bound"] == 0
+        i128 = plan(pr, precision=128, plan_kind=PLAN_LIGHTCONE).info() if p <= 2 else None
+        if i128:
+            assert i128["width"] == i["width"] or kind != "lightcone"
+    g, b = uniform_angles(3, 5014)
+    pr = make_problem(14, erdos_renyi_graph(14, 3.0 / 13, 4014), g, b, 1e-3, 1e-2, 16, 6014)
+    i = plan(pr, plan_kind=PLAN_LIGHTCONE, lc_max_rank=12, lc_slice_bits=10).info()
+    assert i["lc_slice_bits"] > 0 and i["width"] <= 13
+    for n in (5, 8, 12):
+        assert plan(paper_experiment_problem(n, 0), outputs=OUT_DIAG).info()["plan_name"] == "sv_lds"

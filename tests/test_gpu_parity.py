@@ -768,7 +768,7 @@ def test_gate_by_gate_random_circuits_against_oracle(precision, tol):
     non-unitary channel scales the trajectory, and its energy and rounding
     error with it (Pauli-noise trajectories have norm 1)."""
     from oracle import simulate as sim
-    from test_gpu_random import random_problem
+    from random_circuits import random_problem
     stn = stn_mod()
     done, worst = 0, 0.0
     for seed in range(40):
