@@ -144,6 +144,11 @@ def measured_traffic(kernel_source, launch_shape):
     return t["traffic_bytes_per_launch"] / 1e9
 
 
+def note(msg):
+    """Progress line on stderr (one per leg), so a long run shows where it is."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def fp64_check(energies_by_k, problem):
     """Largest |<C>_k - <C>_k(oracle, FP64)| / m over the stored oracle samples."""
     path = os.path.join(ROOT, "tests", "golden", "config2_sampled.json")
@@ -227,7 +232,10 @@ def main():
     problem = config_problem(2, K=args.K)
     K = problem.K
 
+    if not args.no_cpu:
+        note("CPU oracle baseline")
     cpu = None if args.no_cpu else cpu_baseline(2, args.cpu_reps)
+    note("plan and autotune")
 
     import torch
 
@@ -263,6 +271,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    note(f"{args.warmup} warm-up and {args.steps} timed steps")
     for _ in range(args.warmup):
         job()
     torch.cuda.synchronize()
@@ -290,6 +299,7 @@ def main():
     # apart from the headline value, which contracts every trajectory)
     dedup = None
     if args.dedup:
+        note("de-duplicated job")
         import numpy as np
         unique = 0
 
@@ -318,14 +328,19 @@ def main():
 
     plan.close()                    # release the headline workspace before the other legs
     torch.cuda.empty_cache()
+    note("complex128 leg")
     fp64 = fp64_leg(stn, problem, res["energies"], args.fp64_prefix) if args.fp64_prefix > 0 else None
     torch.cuda.empty_cache()
+    note("plain per-trajectory loop")
     plain = plain_loop(stn, problem, args.plain_traj, value, tune["chosen"]) if args.plain_traj > 0 else None
     torch.cuda.empty_cache()
+    note("rho_hat leg")
     rho_leg = rho_hat_leg(stn) if args.rho_leg else None
     torch.cuda.empty_cache()
+    note("gate-by-gate leg")
     gates = gates_leg(stn) if args.gates_leg else None
     torch.cuda.empty_cache()
+    note("serving leg")
     serving = serving_leg(stn, args) if args.serve_jobs > 0 else None
 
     out = {

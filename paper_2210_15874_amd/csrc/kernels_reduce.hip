@@ -16,7 +16,8 @@
 //             in a fixed order (strided per thread, then a fixed tree), two
 //             passes (mean, then squared deviations).
 // k_finish_*: mirror the upper triangle (rho_ji = conj(rho_ij), real
-//             diagonal) and scale by 1/K into output buffers.
+//             diagonal) and scale by 1/K into output buffers; the trace of
+//             sigma from chunk sums of 2048 values added in chunk order.
 // k_cdf_*, k_sample_bits: bitstrings drawn from sigma by inverse transform.
 //             The running sums F of the accumulated diagonal are formed in
 //             chunks of 2048 values, one workgroup per chunk: chunk totals,
@@ -196,15 +197,33 @@ __global__ __launch_bounds__(256) void k_finish_rho(const double2* __restrict__ 
     out[t] = make_double2(v.x * inv, v.y * inv);
 }
 
+// sigma = diag / K in chunks of 2048 values, one workgroup each (each thread
+// 8 consecutive values, summed in order, then the workgroup's fixed tree):
+// parts[c] = the chunk's sum
 __global__ __launch_bounds__(256) void k_finish_diag(const double* __restrict__ diag, uint32_t N, double inv,
-                                                     double* __restrict__ out, double* __restrict__ trace) {
+                                                     double* __restrict__ out, double* __restrict__ parts) {
     __shared__ double red[256];
+    const uint32_t a = blockIdx.x * 2048u + threadIdx.x * 8u;
     double s = 0.0;
-    for (uint32_t i = threadIdx.x; i < N; i += 256) {
-        const double v = diag[i] * inv;
-        out[i] = v;
-        s += v;
-    }
+#pragma unroll
+    for (uint32_t j = 0; j < 8; ++j)
+        if (a + j < N) {
+            const double v = diag[a + j] * inv;
+            out[a + j] = v;
+            s += v;
+        }
+    const double tr = block_sum(s, red);
+    if (threadIdx.x == 0) parts[blockIdx.x] = tr;
+}
+
+// trace = the chunk sums in order: contiguous runs per thread, then the fixed tree
+__global__ __launch_bounds__(256) void k_finish_trace(const double* __restrict__ parts, uint32_t C,
+                                                      double* __restrict__ trace) {
+    __shared__ double red[256];
+    const uint32_t per = (C + 255) / 256;
+    const uint32_t a = min(C, threadIdx.x * per), b = min(C, a + per);
+    double s = 0.0;
+    for (uint32_t i = a; i < b; ++i) s += parts[i];
     const double tr = block_sum(s, red);
     if (threadIdx.x == 0) *trace = tr;
 }
@@ -464,8 +483,13 @@ void launch_finish_dense(stn_accum* a, hipStream_t s) {
                            a->d_rho.as<double2>(), N, inv, a->d_rho_out.as<double2>());
         STN_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_finish_diag, dim3(1), dim3(256), 0, s, a->d_diag.as<double>(), N, inv,
-                       a->d_diag_out.as<double>(), a->d_stats.as<double>() + 2);
+    const uint32_t C = (N + 2047) / 2048;
+    a->d_parts.ensure(&a->plan->alloc, (size_t)C * 8);
+    hipLaunchKernelGGL(k_finish_diag, dim3(C), dim3(256), 0, s, a->d_diag.as<double>(), N, inv,
+                       a->d_diag_out.as<double>(), a->d_parts.as<double>());
+    STN_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_finish_trace, dim3(1), dim3(256), 0, s, (const double*)a->d_parts.as<double>(), C,
+                       a->d_stats.as<double>() + 2);
     STN_HIP(hipGetLastError());
 }
 

@@ -491,6 +491,7 @@ struct TnDevice {
     uint32_t grid = 0;          // persistent workgroups (global-memory tier)
     uint32_t F = 0;             // slices of all terms (work items per trajectory)
     uint32_t resident[2][kTnVariants] = {};   // workgroups the device holds at once, per precision and shape
+    uint32_t per_cu[2][kTnVariants] = {};     // ... and per CU
     DevBuf terms, steps, mains, smalls, gtab32, gtab64, zz, garena, slices, toff;
 };
 
@@ -842,6 +843,7 @@ void launch_lightcone(stn_plan* p, stn_batch* b, hipStream_t s) {
         STN_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         STN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ker.f, (int)ker.threads, lds));
         res = (uint32_t)std::max(1, per_cu) * (uint32_t)std::max(1, cus);
+        d->per_cu[dbl][v] = (uint32_t)std::max(1, per_cu);
     }
     const uint32_t max_grid = d->hbm ? std::min(d->grid, res) : res;
     if (d->hbm) d->garena.ensure(&p->alloc, (size_t)max_grid * d->TB * d->stride * elem);
@@ -853,7 +855,7 @@ void launch_lightcone(stn_plan* p, stn_batch* b, hipStream_t s) {
         const uint64_t items = (uint64_t)F * ((nb + d->TB - 1) / d->TB);
         uint32_t grid = (uint32_t)std::min<uint64_t>(max_grid, items);
         // a job server may keep some CUs free for other jobs' kernels
-        if (d->hbm && p->grid_cap) grid = std::min(grid, p->grid_cap);
+        if (p->grid_cap) grid = std::min(grid, std::max(1u, p->grid_cap * d->per_cu[dbl][v]));
         prof_begin(p, STN_K_TN_STEP, s);
         if (dbl)
             launch_tn<double>(p, d, ker, grid, lds, sg, b->words, nb, s);

@@ -23,7 +23,6 @@
 #include <cmath>
 #include <map>
 #include <random>
-#include <set>
 
 #include "lightcone.h"
 
@@ -48,30 +47,47 @@ bool diagonal_kind(uint32_t k) { return k == STN_G_RZ || k == STN_G_Z || k == ST
 // *deg_seen receives the largest degree met.
 std::vector<int> minfill_order(int nv, const std::vector<std::vector<int>>& tensors, std::mt19937_64* rng,
                                int max_deg, int* deg_seen) {
-    std::vector<std::set<int>> adj(nv);
+    // adjacency as bit rows; fill and degree kept per variable and recomputed
+    // only where an elimination changed a neighbourhood
+    const size_t W = ((size_t)nv + 63) / 64;
+    std::vector<uint64_t> A((size_t)nv * W, 0);
+    auto row = [&](int v) { return A.data() + (size_t)v * W; };
     for (auto& t : tensors)
         for (int a : t)
             for (int b : t)
-                if (a != b) adj[a].insert(b);
+                if (a != b) row(a)[b >> 6] |= 1ull << (b & 63);
+    std::vector<long> fill(nv, 0);
+    std::vector<int> deg(nv, 0);
+    // fill(v) = pairs of v's neighbours that are not adjacent: each neighbour a
+    // counts the neighbours outside its own row, itself included, hence - deg
+    auto recompute = [&](int v) {
+        const uint64_t* r = row(v);
+        int d = 0;
+        for (size_t w = 0; w < W; ++w) d += __builtin_popcountll(r[w]);
+        long f = 0;
+        for (size_t w = 0; w < W; ++w)
+            for (uint64_t m = r[w]; m; m &= m - 1) {
+                const uint64_t* ra = row((int)(w * 64 + __builtin_ctzll(m)));
+                for (size_t x = 0; x < W; ++x) f += __builtin_popcountll(r[x] & ~ra[x]);
+            }
+        deg[v] = d;
+        fill[v] = (f - d) / 2;
+    };
+    for (int v = 0; v < nv; ++v) recompute(v);
     std::vector<char> done(nv, 0);
     std::vector<int> order;
+    std::vector<uint64_t> nb(W), dirty(W);
     for (int it = 0; it < nv; ++it) {
         long best_fill = -1;
         int best_deg = 0;
         std::vector<int> cands;
         for (int v = 0; v < nv; ++v) {
             if (done[v]) continue;
-            long fill = 0;
-            const std::vector<int> nb(adj[v].begin(), adj[v].end());
-            for (size_t i = 0; i < nb.size(); ++i)
-                for (size_t j = i + 1; j < nb.size(); ++j)
-                    if (!adj[nb[i]].count(nb[j])) ++fill;
-            const int deg = (int)nb.size();
-            if (best_fill < 0 || fill < best_fill || (fill == best_fill && deg < best_deg)) {
-                best_fill = fill;
-                best_deg = deg;
+            if (best_fill < 0 || fill[v] < best_fill || (fill[v] == best_fill && deg[v] < best_deg)) {
+                best_fill = fill[v];
+                best_deg = deg[v];
                 cands.assign(1, v);
-            } else if (fill == best_fill && deg == best_deg) {
+            } else if (fill[v] == best_fill && deg[v] == best_deg) {
                 cands.push_back(v);
             }
         }
@@ -81,13 +97,25 @@ std::vector<int> minfill_order(int nv, const std::vector<std::vector<int>>& tens
         if (best_deg > max_deg) return {};
         done[v] = 1;
         order.push_back(v);
-        const std::vector<int> nb(adj[v].begin(), adj[v].end());
-        for (int a : nb) {
-            adj[a].erase(v);
-            for (int b : nb)
-                if (a != b) adj[a].insert(b);
-        }
-        adj[v].clear();
+        // the neighbours of v become a clique; v leaves the graph
+        std::copy(row(v), row(v) + W, nb.begin());
+        std::fill(dirty.begin(), dirty.end(), 0ull);
+        for (size_t w = 0; w < W; ++w)
+            for (uint64_t m = nb[w]; m; m &= m - 1) {
+                const int a = (int)(w * 64 + __builtin_ctzll(m));
+                uint64_t* ra = row(a);
+                for (size_t x = 0; x < W; ++x) ra[x] |= nb[x];
+                ra[a >> 6] &= ~(1ull << (a & 63));
+                ra[v >> 6] &= ~(1ull << (v & 63));
+                for (size_t x = 0; x < W; ++x) dirty[x] |= ra[x];
+            }
+        std::fill(row(v), row(v) + W, 0ull);
+        for (size_t w = 0; w < W; ++w) dirty[w] |= nb[w];
+        for (size_t w = 0; w < W; ++w)
+            for (uint64_t m = dirty[w]; m; m &= m - 1) {
+                const int u = (int)(w * 64 + __builtin_ctzll(m));
+                if (!done[u]) recompute(u);
+            }
     }
     return order;
 }
@@ -268,7 +296,7 @@ Symbolic eliminate(const std::vector<Tensor>& base, const std::vector<int>& orde
     return out;
 }
 
-// phase 3 on a copy of the symbolic steps' tensors
+// phase 3: placement of the intermediates (the symbolic pool is only read)
 Lowered place(const Symbolic& sym, const std::vector<int>& order, const std::vector<int>& sliced,
               TnArenaLimits lim) {
     Lowered L;
@@ -276,23 +304,23 @@ Lowered place(const Symbolic& sym, const std::vector<int>& order, const std::vec
         const auto it = std::find(sliced.begin(), sliced.end(), x);
         return it == sliced.end() ? -1 : (int)(it - sliced.begin());
     };
-    std::vector<Tensor> pool = sym.pool;
-    // 3. placement and lowering to step records
+    const std::vector<Tensor>& pool = sym.pool;
+    std::vector<int> arena(pool.size(), -1);
+    std::vector<char> in_lds(pool.size(), 0);
     FirstFit gmem, lds;
     lds.cap = lim.lds_slots;
-    auto alloc = [&](Tensor& t, int size) {
-        t.lds = 0;
+    auto alloc = [&](int id, int size) {
         if (size <= lim.lds_tensor_max) {
             const int off = lds.alloc(size);
             if (off >= 0) {
-                t.lds = 1;
-                t.arena = off;
+                in_lds[id] = 1;
+                arena[id] = off;
                 return;
             }
         }
-        t.arena = gmem.alloc(size);
+        arena[id] = gmem.alloc(size);
     };
-    auto release = [&](const Tensor& t) { (t.lds ? lds : gmem).release(t.arena); };
+    auto release = [&](int id) { (in_lds[id] ? lds : gmem).release(arena[id]); };
     for (auto& st : sym.steps) {
         if (st.dead) continue;
         TnStepRec rec;
@@ -307,8 +335,8 @@ Lowered place(const Symbolic& sym, const std::vector<int>& order, const std::vec
             in.kind = pool[i].kind;
             in.gate = pool[i].gate;
             in.conj = pool[i].conj;
-            in.arena = pool[i].arena;
-            in.lds = pool[i].lds;
+            in.arena = arena[i];
+            in.lds = in_lds[i];
             // position of each of the input's variables in the step's index space
             // (output variables at bits 0..|out|-1, the summed ones from |out|;
             // a sliced variable: its bit of the slice index)
@@ -327,29 +355,27 @@ Lowered place(const Symbolic& sym, const std::vector<int>& order, const std::vec
                     in.pos.push_back((int)st.out.size() + (int)(is - st.sums.begin()));
                 }
             }
-            rec.inputs.push_back(in);
+            rec.inputs.push_back(std::move(in));
         }
         // the output is placed while the inputs are still held: no aliasing
-        Tensor& t = pool[st.out_id];
-        alloc(t, 1 << st.out.size());
+        alloc(st.out_id, 1 << st.out.size());
         for (int i : st.in)
             if (pool[i].kind == TN_INTER) {
-                if (!pool[i].lds) L.gbytes += std::ldexp(1.0, (int)pool[i].vars.size());
-                release(pool[i]);
+                if (!in_lds[i]) L.gbytes += std::ldexp(1.0, (int)pool[i].vars.size());
+                release(i);
             }
-        if (!t.lds) L.gbytes += std::ldexp(1.0, (int)st.out.size());
-        rec.out_arena = t.arena;
-        rec.out_lds = t.lds;
-        L.steps.push_back(rec);
+        if (!in_lds[st.out_id]) L.gbytes += std::ldexp(1.0, (int)st.out.size());
+        rec.out_arena = arena[st.out_id];
+        rec.out_lds = in_lds[st.out_id];
+        L.steps.push_back(std::move(rec));
     }
-    L.result = pool[sym.result].arena;
-    L.result_lds = pool[sym.result].lds;
+    L.result = arena[sym.result];
+    L.result_lds = in_lds[sym.result];
     L.arena = gmem.high;
     L.lds_arena = lds.high;
     L.order = order;
     return L;
 }
-
 
 // Lowers `order` for an LDS arena of lds_slots slots with tensor caps of the
 // whole arena, a quarter and a sixteenth of it, and keeps the lowering that

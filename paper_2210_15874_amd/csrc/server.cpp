@@ -228,6 +228,7 @@ struct stn_server {
     std::mutex m;                          // guards the queues, cache, results and stats below
     std::condition_variable cv_plan, cv_ready, cv_done;
     std::deque<std::shared_ptr<stn::Job>> to_plan, ready;
+    uint32_t planning = 0;                 // jobs a planner thread is working on
     std::deque<stn_job_result> results;
     std::list<std::pair<std::string, stn_plan*>> cache;   // idle plans, most recent first
     uint64_t next_id = 1;
@@ -332,6 +333,7 @@ void planner_loop(stn_server* sv) {
             if (sv->to_plan.empty() || (sv->stop && !sv->opts.drain_on_destroy)) return;
             j = sv->to_plan.front();
             sv->to_plan.pop_front();
+            sv->planning++;
         }
         try {
             plan_job(sv, *j);
@@ -351,6 +353,7 @@ void planner_loop(stn_server* sv) {
                                         });
             j->t_ready = sv->now();
             sv->ready.insert(pos, j);
+            sv->planning--;
             sv->planned++;
         }
         sv->cv_ready.notify_one();
@@ -491,10 +494,11 @@ struct Device {
     // that size may fill only 15/16 of the budget, so small jobs always find
     // room.  A long job (estimated over kSmallJobSeconds of device time, so
     // bound for the large-job streams) is held back while the small-job
-    // stream has work, for at most kLongJobHold seconds after its planning
-    // finished: short jobs then get the whole device first rather than the
-    // CUs a long job's persistent kernels leave free; the first job not held
-    // takes the oldest job's place in the rule above.
+    // stream has work or other jobs are still being planned (they may be
+    // short), for at most kLongJobHold seconds after its planning finished:
+    // short jobs then get the whole device first rather than the CUs a long
+    // job's persistent kernels leave free; the first job not held takes the
+    // oldest job's place in the rule above.
     bool admit() {
         std::shared_ptr<Job> j;
         {
@@ -505,7 +509,8 @@ struct Device {
             const uint64_t left = budget - std::min(budget, bytes_admitted);
             const uint64_t left_big = (budget - budget / 16) - std::min(budget - budget / 16, bytes_admitted);
             const double now = sv->now();
-            const bool small_busy = hipStreamQuery(streams[0]) == hipErrorNotReady;
+            const bool small_busy = hipStreamQuery(streams[0]) == hipErrorNotReady || !sv->to_plan.empty() ||
+                                    sv->planning > 0;
             size_t pick = SIZE_MAX;
             bool head = true;
             for (size_t i = 0; i < sv->ready.size(); ++i) {

@@ -266,6 +266,7 @@ struct stn_accum {
     stn::DevBuf d_stats;             // double [4]: energy mean, SE, trace
     stn::DevBuf d_egather;           // double [k_done]: energies in trajectory order
     stn::DevBuf d_cdf;               // double [2^n]: running sums of d_diag (bitstring sampling)
+    stn::DevBuf d_parts;             // double [2^n / 2048]: chunk sums of sigma (its trace)
     std::vector<double> h_rho, h_diag, h_energies;
 };
 

@@ -21,7 +21,7 @@ def gpu():
     torch.cuda.set_device(0)
 
 
-from random_circuits import random_problem  # noqa: E402
+from random_circuits import random_kraus, random_problem, random_unitary  # noqa: E402
 
 
 @pytest.mark.parametrize("precision,tol", [(128, 1e-12), (64, 1e-5)])
