@@ -178,6 +178,12 @@ typedef struct {
                                return: STN_E_INVALID.  Steps above lc_max_rank: STN_E_UNSUPPORTED
                                (an AUTO plan then takes another lowering).  Needs lc_slice_bits = 0 */
     void* lc_order_ctx;     /* passed to lc_order_fn */
+    uint32_t sv_full_state; /* tiled complex64 plans: 1 = keep all 2^n amplitudes per trajectory.  0 (default):
+                               keep the 2^(n-1) with qubit n-1 = 0.  Every trajectory circuit of the tiled
+                               lowering (H on every qubit, then zz and rx gates whose signs the Pauli frame
+                               sets) commutes with X on all qubits and starts from a state it fixes, so
+                               psi(~z) = psi(z) exactly, and the ZZ observable takes equal values at z and ~z;
+                               needs n >= 15 */
 } stn_plan_opts;
 
 typedef struct {
@@ -207,6 +213,8 @@ typedef struct {
     uint32_t lc_group;      /* lightcone plans: trajectories one workgroup contracts in lockstep */
     uint32_t lc_width_lower_bound; /* 1 when lc_width is only a lower bound: the elimination-order search
                                stopped at the first step above the rank cap, before finishing the order */
+    uint32_t half_state;    /* tiled plan keeps half the amplitudes (see stn_plan_opts.sv_full_state); bytes_per_traj
+                               and peak_bytes count those */
 } stn_plan_stats;
 
 typedef struct {

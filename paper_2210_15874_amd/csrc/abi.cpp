@@ -246,6 +246,7 @@ stn_status stn_plan_info(const stn_plan* p, stn_plan_stats* o) {
     o->est_s_per_traj = p->est_seconds_per_traj();
     o->lc_group = p->lc_group;
     o->lc_width_lower_bound = p->lc_width_lb;
+    o->half_state = p->sv_half ? 1u : 0u;
     return STN_OK;
 }
 

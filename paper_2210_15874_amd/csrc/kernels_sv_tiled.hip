@@ -30,6 +30,15 @@
 // storing: FP32 within a thread, binary64 across threads, tiles and
 // trajectories.
 //
+// Half-state plans keep only the amplitudes with qubit n-1 = 0: every
+// trajectory's state satisfies psi(~z) = psi(z) (the circuits commute with X
+// on all qubits), so psi(z', 1) is read at the complement of z' in the
+// stored half.  A tile holding qubit n-1 (as tile bit 13) thus holds its own
+// amplitudes and, for qubit n-1 = 1, those of the complemented tile, stored
+// in reverse order; only one of each complementary pair of tiles is visited
+// (the top fixed bit is 0).  Phases, rotations and the energy see the full
+// index z; the energy over the half is doubled.
+//
 // Tiles that hold only two low storage bits read 32-byte runs; the four
 // workgroups that share each 128-byte line get tile indices x, x+8, x+16,
 // x+24, which the dispatcher places on the same XCD at the same time, so each
@@ -68,8 +77,10 @@ struct DiagTab {
 };
 
 struct Pass2 {
-    uint32_t tb[kQ];            // storage bit of tile-index bit i
-    uint64_t fixed_mask;        // storage bits outside the tile
+    uint32_t tb[kQ];            // qubit (storage bit) of tile-index bit i
+    uint64_t fixed_mask;        // storage bits outside the tile (half-state: the top one of a mirror tile excluded)
+    uint64_t mirror;            // half-state tile holding qubit n-1: 1 << (n-1); else 0
+    uint64_t half_mask;         // half-state: 2^(n-1) - 1
     uint32_t share;             // fixed storage bits below the 128-byte line (0..2)
     float amp0;
     int32_t mix_gate[2][3][5];  // [segment][layout][register bit]: rx gate, -1 = none (t = 0)
@@ -254,28 +265,52 @@ __device__ __forceinline__ uint32_t tile_of(uint32_t x, uint32_t share) {
     return (g << share) | j;
 }
 
-// float4 = the amplitude pair of tile bit 0 (storage bit 0)
+// float4 = the amplitude pair of tile bit 0 (storage bit 0): z (bit 0 clear)
+// and z | 1, or, where z holds the mirror qubit, the pair stored at
+// ~z - 1 and ~z (so in the other order).  z = z0 | off_j with off_j the
+// register bits' part (uniform); the mirror qubit is tile bit 13, a register
+// bit of layout L0 (decided per register pair, uniform) and a thread bit of
+// L2 (decided per thread).  half_mask is all ones in full-state plans.
+template <const int* R>
+struct TileAddr {
+    uint64_t zm, rb;     // z0 without the mirror bit; half_mask - 1 - zm (reversed base)
+    bool mthr;           // z0 itself holds the mirror bit
+    __device__ __forceinline__ TileAddr(uint64_t z0, const Pass2& P)
+        : zm(z0 & P.half_mask), rb(P.half_mask - 1u - (z0 & P.half_mask)), mthr((z0 & P.mirror) != 0) {}
+    // element index of pair jp; *mir: stored reversed
+    __device__ __forceinline__ uint64_t at(int jp, const Pass2& P, bool* mir) const {
+        uint64_t off = 0;
+#pragma unroll
+        for (int r = 1; r < 5; ++r) off |= (uint64_t)((jp >> (r - 1)) & 1) << P.tb[R[r]];
+        const bool m = mthr || (off & P.mirror) != 0;
+        off &= P.half_mask;
+        *mir = m;
+        return m ? rb - off : zm + off;
+    }
+};
+
 template <const int* R>
 __device__ __forceinline__ void load_tile(float2 (&v)[kRegs], const float2* st, uint64_t z0, const Pass2& P) {
+    const TileAddr<R> A(z0, P);
 #pragma unroll
     for (int jp = 0; jp < kRegs / 2; ++jp) {
-        uint64_t z = z0;
-#pragma unroll
-        for (int r = 1; r < 5; ++r) z |= (uint64_t)((jp >> (r - 1)) & 1) << P.tb[R[r]];
-        const float4 w = *reinterpret_cast<const float4*>(st + z);
-        v[2 * jp] = make_float2(w.x, w.y);
-        v[2 * jp + 1] = make_float2(w.z, w.w);
+        bool mir;
+        const uint64_t a = A.at(jp, P, &mir);
+        const float4 w = *reinterpret_cast<const float4*>(st + a);
+        v[2 * jp] = mir ? make_float2(w.z, w.w) : make_float2(w.x, w.y);
+        v[2 * jp + 1] = mir ? make_float2(w.x, w.y) : make_float2(w.z, w.w);
     }
 }
 
 template <const int* R>
 __device__ __forceinline__ void store_tile(const float2 (&v)[kRegs], float2* st, uint64_t z0, const Pass2& P) {
+    const TileAddr<R> A(z0, P);
 #pragma unroll
     for (int jp = 0; jp < kRegs / 2; ++jp) {
-        uint64_t z = z0;
-#pragma unroll
-        for (int r = 1; r < 5; ++r) z |= (uint64_t)((jp >> (r - 1)) & 1) << P.tb[R[r]];
-        *reinterpret_cast<float4*>(st + z) = make_float4(v[2 * jp].x, v[2 * jp].y, v[2 * jp + 1].x, v[2 * jp + 1].y);
+        bool mir;
+        const uint64_t a = A.at(jp, P, &mir);
+        const float2 lo = mir ? v[2 * jp + 1] : v[2 * jp], hi = mir ? v[2 * jp] : v[2 * jp + 1];
+        *reinterpret_cast<float4*>(st + a) = make_float4(lo.x, lo.y, hi.x, hi.y);
     }
 }
 
@@ -561,7 +596,21 @@ TiledTables build_tables(stn_plan* p) {
         for (uint32_t q = 0; q < n; ++q)
             if ((ps.tile_mask >> q) & 1) P.tb[t++] = q;
         if (t != kQ || P.tb[0] != 0) fail(STN_E_INVALID, "tile must hold 14 storage bits including bit 0");
-        P.fixed_mask = (N - 1) & ~(uint64_t)ps.tile_mask;
+        if (p->sv_half) {
+            // stored: qubits 0 .. n-2; a tile holding qubit n-1 (tile bit 13)
+            // also covers the complemented tile, so its top fixed bit is 0
+            const uint64_t Nh = N / 2;
+            P.half_mask = Nh - 1;
+            P.fixed_mask = (Nh - 1) & ~(uint64_t)ps.tile_mask;
+            if ((ps.tile_mask >> (n - 1)) & 1) {
+                if (P.tb[kQ - 1] != n - 1 || !P.fixed_mask) fail(STN_E_INVALID, "half-state tile layout");
+                P.mirror = 1ull << (n - 1);
+                P.fixed_mask &= ~(1ull << (63 - __builtin_clzll(P.fixed_mask)));
+            }
+        } else {
+            P.half_mask = ~0ull;
+            P.fixed_mask = (N - 1) & ~(uint64_t)ps.tile_mask;
+        }
         P.share = (uint32_t)__builtin_popcountll(P.fixed_mask & 0xFull);
         P.amp0 = (float)std::pow(2.0, -0.5 * n);
         int fl = (ps.init ? 1 : 0) | (ps.diag_a >= 0 ? 2 : 0) | (ps.mix2 >= 0 ? 4 : 0) | (ps.last ? 8 : 0);
@@ -634,7 +683,9 @@ TiledTables build_tables(stn_plan* p) {
                 T.eedges.insert(T.eedges.end(), cat[c].begin(), cat[c].end());
                 T.ew.insert(T.ew.end(), cw[c].begin(), cw[c].end());
             }
-            P.e_scale = acc_scale * acc_scale;
+            // half-state: the visited amplitudes are half of the whole, and
+            // their complements carry equal weight and equal cut values
+            P.e_scale = acc_scale * acc_scale * (p->sv_half ? 2.0 : 1.0);
         }
         T.passes.push_back(P);
         T.flags.push_back(fl);
@@ -670,9 +721,10 @@ void upload_tiled(stn_plan* p, hipStream_t s) {
 }
 
 void launch_sv_tiled(stn_plan* p, stn_batch* b, hipStream_t s) {
-    const uint32_t n = p->n;
-    const uint64_t N = 1ull << n;
-    const uint32_t tiles_log2 = n - kQ;
+    // N: amplitudes stored per trajectory (2^(n-1) for half-state plans)
+    const uint32_t n = p->n, ns = p->sv_half ? n - 1 : n;
+    const uint64_t N = 1ull << ns;
+    const uint32_t tiles_log2 = ns - kQ;
     const uint32_t tiles = 1u << tiles_log2;
     const uint32_t B = std::min(p->max_batch, b->K);
     if (b->words > 64) fail(STN_E_UNSUPPORTED, "tiled lowering supports at most 2048 gates");
@@ -702,7 +754,7 @@ void launch_sv_tiled(stn_plan* p, stn_batch* b, hipStream_t s) {
             if (blocks % (8u << P.share) || grid % 32) P.share = 0;  // grouping needs whole XCD rounds
             const double elems = (double)nb * (double)N;
             prof_begin(p, STN_K_SV_PASS, s);
-            hipLaunchKernelGGL(pass_kernel(fl, two), dim3(grid), dim3(kThreads), 0, s, p->d_work.as<float2>(), P, n,
+            hipLaunchKernelGGL(pass_kernel(fl, two), dim3(grid), dim3(kThreads), 0, s, p->d_work.as<float2>(), P, ns,
                                tiles_log2, blocks, b->d_signs.as<uint32_t>() + (size_t)c0 * b->words, b->words,
                                b->d_frame.as<uint64_t>() + 2 * (size_t)c0, d->dedges.as<int4>(),
                                d->phase.as<float2>(), d->eedges.as<int2>(), d->ew.as<double>(),

@@ -400,6 +400,14 @@ bool build_tiled(stn_plan* p, std::string& why) {
 
 }  // namespace
 
+// Whether a complex64 tiled plan keeps half the amplitudes.  Every circuit
+// of the tiled lowering (H on every qubit, zz and rx gates with the signs
+// the Pauli frame sets) commutes with X on all qubits and |+>^n is fixed by
+// it, so every trajectory has psi(~z) = psi(z); the ZZ observable takes the
+// same value at z and ~z.  The kernels then store the amplitudes with qubit
+// n-1 = 0 and read psi(z', 1) at ~z'.
+static bool tiled_half(const stn_plan* p) { return p->opts.precision == 64 && p->n >= 15 && !p->opts.sv_full_state; }
+
 // Pass schedule of the tiled lowering.  A layer's rotations are split over
 // tiles: the first holds the low `tile_bits` storage bits, the next ones
 // `coal` low bits (coalescing) plus the next high qubits.  Rotations on
@@ -534,8 +542,9 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
                 if (c128) schedule_tiled(p, tiled128_tile_bits(), 3);
                 else schedule_tiled(p, 14, 2);
                 double bytes = 0;
+                const int stored = (int)n - (tiled_half(p) ? 1 : 0);
                 for (auto& ps : p->passes)
-                    bytes += std::ldexp(c128 ? 16.0 : 8.0, (int)n) * ((ps.init ? 0 : 1) + (ps.last ? 0 : 1));
+                    bytes += std::ldexp(c128 ? 16.0 : 8.0, stored) * ((ps.init ? 0 : 1) + (ps.last ? 0 : 1));
                 // measured: about 5 TB/s while the strided tiles keep runs of
                 // 128 bytes or more (n <= 24), about 3 TB/s at n = 26
                 sv_t = bytes / (n <= 24 ? 5e12 : 3e12);
@@ -585,6 +594,7 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
         } else {
             schedule_tiled(p, 14, 2);
         }
+        p->sv_half = tiled_half(p);
     } else if (kind == STN_PLAN_LIGHTCONE) {
         if (dense_out) fail(STN_E_UNSUPPORTED, "the lightcone lowering produces energies only");
         if (!p->lc) build_lightcone(p);
@@ -649,14 +659,15 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
         p->width = n;
         p->n_passes = (uint32_t)p->passes.size();
         double bytes = 0, fl = 0;
+        const double Ns = p->sv_half ? N / 2 : N;   // amplitudes stored (and updated) per trajectory
         for (auto& ps : p->passes) {
-            bytes += (ps.init ? 0 : N * elem) + (ps.last ? 0 : N * elem);
-            fl += N * 6.0 * (__builtin_popcount(ps.mix1_mask) + __builtin_popcount(ps.mix2_mask)) +
-                  N * 6.0 * ((ps.diag_a >= 0) + (ps.diag_b >= 0)) + (ps.last ? N * 4.0 : 0);
+            bytes += (ps.init ? 0 : Ns * elem) + (ps.last ? 0 : Ns * elem);
+            fl += Ns * 6.0 * (__builtin_popcount(ps.mix1_mask) + __builtin_popcount(ps.mix2_mask)) +
+                  Ns * 6.0 * ((ps.diag_a >= 0) + (ps.diag_b >= 0)) + (ps.last ? Ns * 4.0 : 0);
         }
         p->bytes_per_traj = bytes;
         p->flops_per_traj = fl;
-        const double per = N * elem + 64.0 * 1024;
+        const double per = Ns * elem + 64.0 * 1024;
         const double budget = p->opts.hbm_budget ? (double)p->opts.hbm_budget : 64.0 * (1ull << 30);
         p->max_batch = p->opts.max_batch ? p->opts.max_batch : (uint32_t)std::max(1.0, std::min(4096.0, std::floor(budget / per)));
         p->peak_bytes = per * p->max_batch;

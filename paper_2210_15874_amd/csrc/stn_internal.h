@@ -218,6 +218,7 @@ struct stn_plan {
     uint32_t lc_slices = 0, lc_slice_bits = 0;   // lightcone: networks per trajectory, most sliced variables
     uint32_t lc_group = 0;                       // lightcone: trajectories per workgroup work item
     uint32_t lc_width_lb = 0;                    // lightcone: lc_width is a lower bound (search stopped at the cap)
+    bool sv_half = false;                        // tiled complex64: psi(~z) = psi(z), only qubit n-1 = 0 stored
     bool graphs = false;                    // stn_contract replays HIP graphs (stn_plan_set_graphs)
     uint64_t graph_captures = 0, graph_replays = 0;
     bool tuned = false;

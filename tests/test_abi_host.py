@@ -85,10 +85,18 @@ def test_plan_kinds_and_cost_model():
     assert i0["plan_name"] == "sv_lds" and i0["n_sites"] == 21
     i2 = plan(config_problem(2)).info()
     assert i2["plan_name"] == "sv_tiled" and i2["n_gates"] == 286 and i2["n_sites"] == 286
-    # every pass reads and writes the 2^26 complex64 state, except the first
-    # (generated) and last (reduced to the energy)
-    N = 2 ** 26 * 8
+    # every pass reads and writes the stored complex64 amplitudes, except the
+    # first (generated) and last (reduced to the energy); by the bit-flip
+    # symmetry of these circuits half the 2^26 amplitudes are stored
+    N = 2 ** 25 * 8
+    assert i2["half_state"] == 1
     assert i2["bytes_per_traj"] == (2 * i2["n_passes"] - 2) * N
+    assert i2["peak_bytes"] == i2["max_batch"] * (N + 64 * 1024)
+    full = plan(config_problem(2), full_state=True).info()
+    assert full["half_state"] == 0 and full["n_passes"] == i2["n_passes"]
+    assert full["bytes_per_traj"] == 2 * i2["bytes_per_traj"]
+    # complex128 plans and the 14-qubit minimum keep every amplitude
+    assert plan(config_problem(2), precision=128).info()["half_state"] == 0
 
 
 def test_validation_errors():

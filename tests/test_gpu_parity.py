@@ -172,14 +172,14 @@ def test_exhaustive_enumeration_matches_dm(pi, precision, tol):
 
 def qaoa(n, p, seed, lam1, lam2, K):
     from workloads import make_problem, random_regular_graph, uniform_angles
-    edges = random_regular_graph(n, 3, seed)
+    edges = random_regular_graph(n, 3 if n % 2 == 0 else 4, seed)   # no 3-regular graph on odd n
     g, b = uniform_angles(p, seed + 1)
     return make_problem(n, edges, g, b, lam1, lam2, K, seed + 2)
 
 
 @pytest.mark.parametrize("precision,tol", [(64, 1e-5), (128, 1e-12)])
 @pytest.mark.parametrize("n,p,K,lam", [(14, 2, 48, (1e-3, 1e-2)), (14, 1, 32, (0.05, 0.2)), (16, 3, 12, (0.02, 0.1)),
-                                       (12, 2, 20, (0.02, 0.1))])
+                                       (15, 2, 16, (0.02, 0.1)), (12, 2, 20, (0.02, 0.1))])
 def test_tiled_energies_same_draws(n, p, K, lam, precision, tol):
     """Pauli-frame rewrite + tiled passes against literal Kraus insertion."""
     from oracle import simulate as sim
@@ -267,6 +267,33 @@ def test_lightcone_energies_same_draws(n, p, K, lam, precision):
     m = max(1, len(pr.edges))
     tol = 1e-5 if precision == 64 else 1e-11
     np.testing.assert_allclose(got / m, ens["energies"] / m, atol=tol)
+
+
+@pytest.mark.parametrize("n,p", [(15, 2), (17, 3), (27, 2)])
+def test_tiled_half_state_against_full_state(n, p):
+    """Half-state plans (only qubit n-1 = 0 stored; the tile holding qubit
+    n-1 also covers the complemented tile, stored in reverse) against
+    full-state plans on the same draws, in every launch shape.  n = 15 has a
+    single tile per pass; n = 27 has three tiles per layer."""
+    stn = stn_mod()
+    pr = qaoa(n, p, 700 + n, 2e-2, 1e-1, 10)
+    res = {}
+    for full in (True, False):
+        pl = stn.Plan(pr, plan_kind=stn.PLAN_SV_TILED, full_state=full, max_batch=4)
+        info = pl.info()
+        assert info["half_state"] == (0 if full else 1)
+        for variant in (0, 1, 2):
+            pl.set_variant(variant)
+            b = pl.sample(pr.seed, 0, pr.K)
+            pl.contract(b)
+            res[(full, variant)] = b.energies()
+            b.close()
+        pl.close()
+        torch.cuda.empty_cache()
+    m = len(pr.edges)
+    ref = res[(True, 2)]
+    for key, e in res.items():
+        np.testing.assert_allclose(e / m, ref / m, atol=1e-5, err_msg=str(key))
 
 
 def test_tiled_complex64_against_complex128_n22():
