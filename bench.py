@@ -125,11 +125,11 @@ def cpu_baseline(problem_cfg, reps=2):
                       f"({wall:.0f} s wall); per-trajectory time weighted by the circuit's gate counts"}
 
 
-def measured_traffic(kernel_source, launch_shape):
+def measured_traffic(kernel_source, launch_shape, per_launch):
     """HBM bytes per launch of the tiled pass from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary, or None if the kernel source has changed
     since the counters were taken or they were taken with another launch
-    shape."""
+    shape or another number of trajectories per launch."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "sv_pass_qaoa_n26_p4_traffic.json")
     if not os.path.exists(path):
@@ -139,7 +139,7 @@ def measured_traffic(kernel_source, launch_shape):
     with open(os.path.join(ROOT, kernel_source), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != t["source_sha256"]:
             return None
-    if t.get("launch_shape") != launch_shape:
+    if t.get("launch_shape") != launch_shape or t.get("trajectories_per_launch") != per_launch:
         return None
     return t["traffic_bytes_per_launch"] / 1e9
 
@@ -364,8 +364,8 @@ def main():
                    "plan_ms": plan_ms},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None,
-                     "traffic": measured_traffic("paper_2210_15874_amd/csrc/kernels_sv_tiled.hip", tune["chosen"])
-                     if kname == "sv_pass" and B == 319 else None, "traffic_unit": "GB per launch",
+                     "traffic": measured_traffic("paper_2210_15874_amd/csrc/kernels_sv_tiled.hip", tune["chosen"], B)
+                     if kname == "sv_pass" else None, "traffic_unit": "GB per launch",
                      "launches": kern["launches"], "avg_launch_ms": kern["ms"] / max(1, kern["launches"]),
                      "bytes_per_launch": kern["bytes"] / max(1, kern["launches"])},
         "kernels": {k: {"launches": v["launches"], "ms": v["ms"]} for k, v in prof.items() if v["launches"]},

@@ -266,51 +266,76 @@ __device__ __forceinline__ uint32_t tile_of(uint32_t x, uint32_t share) {
 }
 
 // float4 = the amplitude pair of tile bit 0 (storage bit 0): z (bit 0 clear)
-// and z | 1, or, where z holds the mirror qubit, the pair stored at
-// ~z - 1 and ~z (so in the other order).  z = z0 | off_j with off_j the
-// register bits' part (uniform); the mirror qubit is tile bit 13, a register
-// bit of layout L0 (decided per register pair, uniform) and a thread bit of
-// L2 (decided per thread).  half_mask is all ones in full-state plans.
+// and z | 1.  MIR (a half-state tile holding qubit n-1): where z holds qubit
+// n-1 the pair is stored at ~z - 1 and ~z (so in the other order).  Qubit
+// n-1 is tile bit 13: register bit 4 of layout L0 (the upper 8 register
+// pairs) and thread bit 8 of layout L2 (threads 256..511, whole waves).
 template <const int* R>
-struct TileAddr {
-    uint64_t zm, rb;     // z0 without the mirror bit; half_mask - 1 - zm (reversed base)
-    bool mthr;           // z0 itself holds the mirror bit
-    __device__ __forceinline__ TileAddr(uint64_t z0, const Pass2& P)
-        : zm(z0 & P.half_mask), rb(P.half_mask - 1u - (z0 & P.half_mask)), mthr((z0 & P.mirror) != 0) {}
-    // element index of pair jp; *mir: stored reversed
-    __device__ __forceinline__ uint64_t at(int jp, const Pass2& P, bool* mir) const {
-        uint64_t off = 0;
+__device__ __forceinline__ uint64_t reg_off(int jp, const Pass2& P, int nbits) {
+    uint64_t off = 0;
 #pragma unroll
-        for (int r = 1; r < 5; ++r) off |= (uint64_t)((jp >> (r - 1)) & 1) << P.tb[R[r]];
-        const bool m = mthr || (off & P.mirror) != 0;
-        off &= P.half_mask;
-        *mir = m;
-        return m ? rb - off : zm + off;
-    }
-};
+    for (int r = 1; r < 5; ++r)
+        if (r <= nbits) off |= (uint64_t)((jp >> (r - 1)) & 1) << P.tb[R[r]];
+    return off;
+}
 
-template <const int* R>
+template <const int* R, bool MIR>
 __device__ __forceinline__ void load_tile(float2 (&v)[kRegs], const float2* st, uint64_t z0, const Pass2& P) {
-    const TileAddr<R> A(z0, P);
+    if constexpr (!MIR) {
 #pragma unroll
-    for (int jp = 0; jp < kRegs / 2; ++jp) {
-        bool mir;
-        const uint64_t a = A.at(jp, P, &mir);
-        const float4 w = *reinterpret_cast<const float4*>(st + a);
-        v[2 * jp] = mir ? make_float2(w.z, w.w) : make_float2(w.x, w.y);
-        v[2 * jp + 1] = mir ? make_float2(w.x, w.y) : make_float2(w.z, w.w);
+        for (int jp = 0; jp < kRegs / 2; ++jp) {
+            const float4 w = *reinterpret_cast<const float4*>(st + (z0 | reg_off<R>(jp, P, 4)));
+            v[2 * jp] = make_float2(w.x, w.y);
+            v[2 * jp + 1] = make_float2(w.z, w.w);
+        }
+    } else {
+        static_assert(R == L0R, "half-state tiles are loaded in layout L0");
+        const uint64_t rb = P.half_mask - 1u - z0;   // z0 holds no bit of qubit n-1 in L0
+#pragma unroll
+        for (int jp = 0; jp < kRegs / 2; ++jp) {
+            const uint64_t off = reg_off<R>(jp, P, 3);
+            if (jp < 8) {
+                const float4 w = *reinterpret_cast<const float4*>(st + (z0 | off));
+                v[2 * jp] = make_float2(w.x, w.y);
+                v[2 * jp + 1] = make_float2(w.z, w.w);
+            } else {
+                const float4 w = *reinterpret_cast<const float4*>(st + (rb - off));
+                v[2 * jp] = make_float2(w.z, w.w);
+                v[2 * jp + 1] = make_float2(w.x, w.y);
+            }
+        }
     }
 }
 
-template <const int* R>
+template <const int* R, bool MIR>
 __device__ __forceinline__ void store_tile(const float2 (&v)[kRegs], float2* st, uint64_t z0, const Pass2& P) {
-    const TileAddr<R> A(z0, P);
+    auto plain = [&](uint64_t zb, int nbits, int j0, int j1) {
 #pragma unroll
-    for (int jp = 0; jp < kRegs / 2; ++jp) {
-        bool mir;
-        const uint64_t a = A.at(jp, P, &mir);
-        const float2 lo = mir ? v[2 * jp + 1] : v[2 * jp], hi = mir ? v[2 * jp] : v[2 * jp + 1];
-        *reinterpret_cast<float4*>(st + a) = make_float4(lo.x, lo.y, hi.x, hi.y);
+        for (int jp = 0; jp < kRegs / 2; ++jp) {
+            if (jp < j0 || jp >= j1) continue;
+            *reinterpret_cast<float4*>(st + (zb | reg_off<R>(jp, P, nbits))) =
+                make_float4(v[2 * jp].x, v[2 * jp].y, v[2 * jp + 1].x, v[2 * jp + 1].y);
+        }
+    };
+    auto mirrored = [&](uint64_t rb, int nbits, int j0, int j1) {
+#pragma unroll
+        for (int jp = 0; jp < kRegs / 2; ++jp) {
+            if (jp < j0 || jp >= j1) continue;
+            *reinterpret_cast<float4*>(st + (rb - reg_off<R>(jp, P, nbits))) =
+                make_float4(v[2 * jp + 1].x, v[2 * jp + 1].y, v[2 * jp].x, v[2 * jp].y);
+        }
+    };
+    if constexpr (!MIR) {
+        plain(z0, 4, 0, kRegs / 2);
+    } else if constexpr (R == L0R) {
+        plain(z0, 3, 0, 8);
+        mirrored(P.half_mask - 1u - z0, 3, 8, kRegs / 2);
+    } else {
+        // layout L2: the wave's threads all hold qubit n-1 = 1, or all 0
+        if (__builtin_amdgcn_readfirstlane((uint32_t)((z0 & P.mirror) != 0)))
+            mirrored(P.half_mask - 1u - (z0 & P.half_mask), 4, 0, kRegs / 2);
+        else
+            plain(z0, 4, 0, kRegs / 2);
     }
 }
 
@@ -375,7 +400,7 @@ __device__ __forceinline__ float energy_part(const float2 (&v)[kRegs], const Pas
 // TWO: two resident workgroups per CU (half the LDS, at most 128 registers,
 // no prefetch): one workgroup's loads and stores overlap the other's
 // arithmetic and exchanges.
-template <int FL, bool TWO>
+template <int FL, bool TWO, bool MIR>
 __global__ __launch_bounds__(kThreads, TWO ? 4 : 1) void k_sv_pass(float2* __restrict__ psi, const Pass2 P, uint32_t n,
                                                       uint32_t tiles_log2, uint32_t total,
                                                       const uint32_t* __restrict__ signs, uint32_t words,
@@ -415,7 +440,7 @@ __global__ __launch_bounds__(kThreads, TWO ? 4 : 1) void k_sv_pass(float2* __res
 #pragma unroll
         for (int j = 0; j < kRegs; ++j) v[j] = make_float2(P.amp0, 0.f);
     } else {
-        load_tile<L0R>(v, psi + ((size_t)b << n), base | zt0, P);
+        load_tile<L0R, MIR>(v, psi + ((size_t)b << n), base | zt0, P);
     }
     uint32_t sb = 0xffffffffu;  // trajectory whose signs are in LDS
     while (true) {
@@ -429,7 +454,7 @@ __global__ __launch_bounds__(kThreads, TWO ? 4 : 1) void k_sv_pass(float2* __res
             fn = tile_of(xn, P.share);
             bn = fn >> tiles_log2;
             basen = pdep64(fn & tmask, P.fixed_mask);
-            if (!kInit && kPrefetch) load_tile<L0R>(nx, psi + ((size_t)bn << n), basen | zt0, P);
+            if (!kInit && kPrefetch) load_tile<L0R, MIR>(nx, psi + ((size_t)bn << n), basen | zt0, P);
         }
         if (b != sb) {  // uniform: a new trajectory's signs and zz weights
             __syncthreads();
@@ -475,8 +500,8 @@ __global__ __launch_bounds__(kThreads, TWO ? 4 : 1) void k_sv_pass(float2* __res
         }
 
         if (!kLast) {
-            if (kSeg2) store_tile<L0R>(v, st, base | zt0, P);
-            else store_tile<L2R>(v, st, base | zt2, P);
+            if (kSeg2) store_tile<L0R, MIR>(v, st, base | zt0, P);
+            else store_tile<L2R, MIR>(v, st, base | zt2, P);
         } else {
             const uint64_t fx = frame[2 * (size_t)b];
             const float accf = kSeg2 ? energy_part<L0R>(v, P, base | zt0, fx, eedges, ew)
@@ -504,7 +529,7 @@ __global__ __launch_bounds__(kThreads, TWO ? 4 : 1) void k_sv_pass(float2* __res
 #pragma unroll
             for (int j = 0; j < kRegs; ++j) v[j] = nx[j];
         } else {
-            load_tile<L0R>(v, psi + ((size_t)b << n), base | zt0, P);
+            load_tile<L0R, MIR>(v, psi + ((size_t)b << n), base | zt0, P);
         }
     }
 }
@@ -528,17 +553,20 @@ __global__ __launch_bounds__(256) void k_tile_sum(const double* __restrict__ par
 typedef void (*PassKernel)(float2*, const Pass2, uint32_t, uint32_t, uint32_t, const uint32_t*, uint32_t,
                            const uint64_t*, const int4*, const float2*, const int2*, const double*, double*);
 
-template <bool TWO>
+template <bool TWO, bool MIR>
 PassKernel pass_kernel_of(int fl) {
     static const PassKernel tab[16] = {
-        k_sv_pass<0, TWO>,  k_sv_pass<1, TWO>,  k_sv_pass<2, TWO>,  k_sv_pass<3, TWO>,
-        k_sv_pass<4, TWO>,  k_sv_pass<5, TWO>,  k_sv_pass<6, TWO>,  k_sv_pass<7, TWO>,
-        k_sv_pass<8, TWO>,  k_sv_pass<9, TWO>,  k_sv_pass<10, TWO>, k_sv_pass<11, TWO>,
-        k_sv_pass<12, TWO>, k_sv_pass<13, TWO>, k_sv_pass<14, TWO>, k_sv_pass<15, TWO>};
+        k_sv_pass<0, TWO, MIR>,  k_sv_pass<1, TWO, MIR>,  k_sv_pass<2, TWO, MIR>,  k_sv_pass<3, TWO, MIR>,
+        k_sv_pass<4, TWO, MIR>,  k_sv_pass<5, TWO, MIR>,  k_sv_pass<6, TWO, MIR>,  k_sv_pass<7, TWO, MIR>,
+        k_sv_pass<8, TWO, MIR>,  k_sv_pass<9, TWO, MIR>,  k_sv_pass<10, TWO, MIR>, k_sv_pass<11, TWO, MIR>,
+        k_sv_pass<12, TWO, MIR>, k_sv_pass<13, TWO, MIR>, k_sv_pass<14, TWO, MIR>, k_sv_pass<15, TWO, MIR>};
     return tab[fl & 15];
 }
 
-PassKernel pass_kernel(int fl, bool two) { return two ? pass_kernel_of<true>(fl) : pass_kernel_of<false>(fl); }
+PassKernel pass_kernel(int fl, bool two, bool mir) {
+    if (mir) return two ? pass_kernel_of<true, true>(fl) : pass_kernel_of<false, true>(fl);
+    return two ? pass_kernel_of<true, false>(fl) : pass_kernel_of<false, false>(fl);
+}
 
 struct TiledTables {
     std::vector<Pass2> passes;
@@ -754,7 +782,7 @@ void launch_sv_tiled(stn_plan* p, stn_batch* b, hipStream_t s) {
             if (blocks % (8u << P.share) || grid % 32) P.share = 0;  // grouping needs whole XCD rounds
             const double elems = (double)nb * (double)N;
             prof_begin(p, STN_K_SV_PASS, s);
-            hipLaunchKernelGGL(pass_kernel(fl, two), dim3(grid), dim3(kThreads), 0, s, p->d_work.as<float2>(), P, ns,
+            hipLaunchKernelGGL(pass_kernel(fl, two, P.mirror != 0), dim3(grid), dim3(kThreads), 0, s, p->d_work.as<float2>(), P, ns,
                                tiles_log2, blocks, b->d_signs.as<uint32_t>() + (size_t)c0 * b->words, b->words,
                                b->d_frame.as<uint64_t>() + 2 * (size_t)c0, d->dedges.as<int4>(),
                                d->phase.as<float2>(), d->eedges.as<int2>(), d->ew.as<double>(),
