@@ -831,6 +831,8 @@ def serving_leg(stn, args):
             m = max(1, len(jobs[i].edges))
             checks.append({"job": i, "n": jobs[i].n_qubits, "p": jobs[i].p, "K": jobs[i].K,
                            "plan": res[i]["plan_name"],
+                           "reference": "complex128 path, same draws, through the server (served jobs against "
+                                        "the oracle: tests/test_gpu_server.py)",
                            "abs_err_per_edge": abs(res[i]["energy_mean"] - ref[i]["energy_mean"]) / m,
                            "se_per_edge": res[i]["energy_se"] / m})
     torch.cuda.synchronize()

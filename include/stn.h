@@ -178,12 +178,12 @@ typedef struct {
                                return: STN_E_INVALID.  Steps above lc_max_rank: STN_E_UNSUPPORTED
                                (an AUTO plan then takes another lowering).  Needs lc_slice_bits = 0 */
     void* lc_order_ctx;     /* passed to lc_order_fn */
-    uint32_t sv_full_state; /* tiled complex64 plans: 1 = keep all 2^n amplitudes per trajectory.  0 (default):
+    uint32_t sv_full_state; /* tiled plans: 1 = keep all 2^n amplitudes per trajectory.  0 (default):
                                keep the 2^(n-1) with qubit n-1 = 0.  Every trajectory circuit of the tiled
                                lowering (H on every qubit, then zz and rx gates whose signs the Pauli frame
                                sets) commutes with X on all qubits and starts from a state it fixes, so
                                psi(~z) = psi(z) exactly, and the ZZ observable takes equal values at z and ~z;
-                               needs n >= 15 */
+                               needs n >= 15 (complex64) / 13 (complex128) */
 } stn_plan_opts;
 
 typedef struct {

@@ -13,6 +13,12 @@
 // exp(-i base m(z)) with the integer m(z) = sum_e mult_e sigma_e [z_u != z_v]
 // looked up in a binary64 table.  The last pass accumulates
 // sum_z |psi_z|^2 C(z xor F_x) in binary64, in a fixed order.
+//
+// Half-state plans (psi(~z) = psi(z) for every trajectory of these
+// circuits) store only qubit n-1 = 0; a tile holding qubit n-1 (tile bit
+// 11) reads and writes its qubit n-1 = 1 amplitudes at the complemented
+// index, and only one tile of each complementary pair is visited.  The
+// energy over the stored half is doubled.
 #include <cmath>
 
 #include "stn_internal.h"
@@ -22,13 +28,17 @@ namespace stn {
 namespace {
 
 constexpr int kQ128 = 12;
-constexpr int kT128 = 256;
-constexpr int kPerThread = (1 << kQ128) / kT128;   // 16
+constexpr int kT128 = 512;
+constexpr int kTBits = 9;                          // thread bits of the tile index
+constexpr int kPerThread = (1 << kQ128) / kT128;   // 8
 constexpr int kMaxEdges128 = 1024;
 
 struct Pass128 {
-    uint32_t tb[kQ128];         // storage bit of tile bit i
-    uint64_t fixed_mask;        // storage bits outside the tile
+    uint32_t tb[kQ128];         // qubit (storage bit) of tile bit i
+    uint64_t fixed_mask;        // storage bits outside the tile (half-state: the top one of a mirror tile excluded)
+    uint64_t mirror;            // half-state tile holding qubit n-1: 1 << (n-1); else 0
+    uint64_t half_mask;         // half-state: 2^(n-1) - 1; else all ones
+    double escale;              // 2 for half-state plans (the complemented half), else 1
     int32_t diag[2];            // layer whose diagonal starts segment s (-1 none)
     int32_t nrot[2];            // rotations of segment s
     int32_t rot_bit[2][kQ128];  // tile bit rotated
@@ -74,23 +84,29 @@ __global__ __launch_bounds__(kT128) void k_sv128_pass(double2* __restrict__ psi,
     double2* st = psi + ((size_t)b << n);
     const uint32_t* sg = signs + (size_t)b * words;
 
-    // storage index of tile index t = tid + 256 i: thread part | i part
+    // qubit index of tile index t = tid + 512 i: thread part | i part; its
+    // storage index: the same, or the complement within the stored half
+    // where it holds qubit n-1
     uint64_t zlo = base;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) zlo |= (uint64_t)((tid >> k) & 1u) << P.tb[k];
+    for (int k = 0; k < kTBits; ++k) zlo |= (uint64_t)((tid >> k) & 1u) << P.tb[k];
     uint64_t zhi[kPerThread];
 #pragma unroll
     for (int i = 0; i < kPerThread; ++i) {
         uint64_t z = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) z |= (uint64_t)((i >> k) & 1) << P.tb[8 + k];
+        for (int k = 0; k < kQ128 - kTBits; ++k) z |= (uint64_t)((i >> k) & 1) << P.tb[kTBits + k];
         zhi[i] = z;
     }
+    auto at = [&](int i) -> uint64_t {
+        const uint64_t z = zlo | zhi[i];
+        return (z & P.mirror) ? (~z & P.half_mask) : z;
+    };
 
 #pragma unroll
     for (int i = 0; i < kPerThread; ++i) {
         const uint32_t t = tid + kT128 * i;
-        tile[t] = P.init ? make_double2(P.amp0, 0.0) : st[zlo | zhi[i]];
+        tile[t] = P.init ? make_double2(P.amp0, 0.0) : st[at(i)];
     }
     __syncthreads();
 
@@ -152,10 +168,10 @@ __global__ __launch_bounds__(kT128) void k_sv128_pass(double2* __restrict__ psi,
             if (tid < w) red[tid] += red[tid + w];
             __syncthreads();
         }
-        if (tid == 0) partials[blk] = red[0];
+        if (tid == 0) partials[blk] = red[0] * P.escale;
     } else {
 #pragma unroll
-        for (int i = 0; i < kPerThread; ++i) st[zlo | zhi[i]] = tile[tid + kT128 * i];
+        for (int i = 0; i < kPerThread; ++i) st[at(i)] = tile[tid + kT128 * i];
     }
 }
 
@@ -220,7 +236,21 @@ void upload_tiled128(stn_plan* p, hipStream_t s) {
         for (uint32_t q = 0; q < n; ++q)
             if ((ps.tile_mask >> q) & 1) P.tb[t++] = q;
         if (t != kQ128) fail(STN_E_INVALID, "complex128 tile must hold 12 storage bits");
-        P.fixed_mask = N & ~(uint64_t)ps.tile_mask;
+        P.escale = 1.0;
+        P.half_mask = ~0ull;
+        if (p->sv_half) {
+            const uint64_t Nh = (1ull << (n - 1)) - 1;
+            P.half_mask = Nh;
+            P.escale = 2.0;
+            P.fixed_mask = Nh & ~(uint64_t)ps.tile_mask;
+            if ((ps.tile_mask >> (n - 1)) & 1) {
+                if (P.tb[kQ128 - 1] != n - 1 || !P.fixed_mask) fail(STN_E_INVALID, "half-state tile layout");
+                P.mirror = 1ull << (n - 1);
+                P.fixed_mask &= ~(1ull << (63 - __builtin_clzll(P.fixed_mask)));
+            }
+        } else {
+            P.fixed_mask = N & ~(uint64_t)ps.tile_mask;
+        }
         P.init = ps.init;
         P.last = ps.last;
         P.amp0 = std::pow(2.0, -0.5 * n);
@@ -259,9 +289,10 @@ void upload_tiled128(stn_plan* p, hipStream_t s) {
 }
 
 void launch_sv_tiled128(stn_plan* p, stn_batch* b, hipStream_t s) {
-    const uint32_t n = p->n;
-    const uint64_t N = 1ull << n;
-    const uint32_t tiles_log2 = n - kQ128;
+    // N: amplitudes stored per trajectory (2^(n-1) for half-state plans)
+    const uint32_t n = p->n, ns = p->sv_half ? n - 1 : n;
+    const uint64_t N = 1ull << ns;
+    const uint32_t tiles_log2 = ns - kQ128;
     const uint32_t tiles = 1u << tiles_log2;
     const uint32_t B = std::min(p->max_batch, b->K);
     if ((uint64_t)B * tiles > 0x7fffffffull) fail(STN_E_UNSUPPORTED, "batch slice too large");
@@ -275,7 +306,7 @@ void launch_sv_tiled128(stn_plan* p, stn_batch* b, hipStream_t s) {
         for (const Pass128& P : d->passes) {
             const double elems = (double)nb * (double)N;
             prof_begin(p, STN_K_SV_PASS, s);
-            hipLaunchKernelGGL(k_sv128_pass, dim3(blocks), dim3(kT128), 0, s, p->d_work.as<double2>(), P, n,
+            hipLaunchKernelGGL(k_sv128_pass, dim3(blocks), dim3(kT128), 0, s, p->d_work.as<double2>(), P, ns,
                                tiles_log2, b->d_signs.as<uint32_t>() + (size_t)c0 * b->words, b->words,
                                b->d_frame.as<uint64_t>() + 2 * (size_t)c0, d->ledges.as<int4>(),
                                d->lofs.as<uint32_t>(), d->phase.as<double2>(), d->phmid.as<uint32_t>(),

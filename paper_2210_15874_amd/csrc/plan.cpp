@@ -400,13 +400,17 @@ bool build_tiled(stn_plan* p, std::string& why) {
 
 }  // namespace
 
-// Whether a complex64 tiled plan keeps half the amplitudes.  Every circuit
+// Whether a tiled plan keeps half the amplitudes.  Every circuit
 // of the tiled lowering (H on every qubit, zz and rx gates with the signs
 // the Pauli frame sets) commutes with X on all qubits and |+>^n is fixed by
 // it, so every trajectory has psi(~z) = psi(z); the ZZ observable takes the
 // same value at z and ~z.  The kernels then store the amplitudes with qubit
-// n-1 = 0 and read psi(z', 1) at ~z'.
-static bool tiled_half(const stn_plan* p) { return p->opts.precision == 64 && p->n >= 15 && !p->opts.sv_full_state; }
+// n-1 = 0 and read psi(z', 1) at ~z'.  A tile must fit in the stored
+// qubits with one fixed bit left: n >= 15 for the 14-qubit complex64
+// tiles, n >= 13 for the 12-qubit complex128 ones.
+static bool tiled_half(const stn_plan* p) {
+    return p->n >= (p->opts.precision == 64 ? 15u : 13u) && !p->opts.sv_full_state;
+}
 
 // Pass schedule of the tiled lowering.  A layer's rotations are split over
 // tiles: the first holds the low `tile_bits` storage bits, the next ones

@@ -95,8 +95,7 @@ def test_plan_kinds_and_cost_model():
     full = plan(config_problem(2), full_state=True).info()
     assert full["half_state"] == 0 and full["n_passes"] == i2["n_passes"]
     assert full["bytes_per_traj"] == 2 * i2["bytes_per_traj"]
-    # complex128 plans and the 14-qubit minimum keep every amplitude
-    assert plan(config_problem(2), precision=128).info()["half_state"] == 0
+    assert plan(config_problem(2), precision=128).info()["half_state"] == 1
 
 
 def test_validation_errors():
@@ -124,9 +123,12 @@ def test_complex128_tiled_plan():
     i = plan(pr, precision=128).info()
     assert i["plan_name"] == "sv_tiled"
     # 12-qubit tiles: 3 tiles per layer, alternating order merges layer
-    # boundaries, so p = 4 layers cost 4 * (3 - 1) + 1 passes of 2^26 * 16 B
-    assert i["n_passes"] == 9
-    assert i["bytes_per_traj"] == (2 * 9 - 2) * 2 ** 26 * 16
+    # boundaries, so p = 4 layers cost 4 * (3 - 1) + 1 passes of the stored
+    # half, 2^25 * 16 B
+    assert i["n_passes"] == 9 and i["half_state"] == 1
+    assert i["bytes_per_traj"] == (2 * 9 - 2) * 2 ** 25 * 16
+    full = plan(pr, precision=128, full_state=True).info()
+    assert full["half_state"] == 0 and full["bytes_per_traj"] == 2 * i["bytes_per_traj"]
 
 
 def test_lightcone_plans_and_auto_choice():
