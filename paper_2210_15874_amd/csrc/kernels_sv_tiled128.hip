@@ -56,14 +56,32 @@ __device__ __forceinline__ uint64_t pdep64_128(uint64_t v, uint64_t mask) {
     return r;
 }
 
-__device__ __forceinline__ uint32_t ins0_128(uint32_t p, uint32_t q) {
-    const uint32_t lo = p & ((1u << q) - 1u);
-    return ((p ^ lo) << 1) | lo;
+// rx on register bit RB of a thread's 8 elements: [[c, -i s], [-i s, c]]
+template <int RB>
+__device__ __forceinline__ void rot8(double2 (&v)[8], double c, double sn) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        if (j & (1 << RB)) continue;
+        const double2 a = v[j], w = v[j | (1 << RB)];
+        v[j] = make_double2(c * a.x + sn * w.y, c * a.y - sn * w.x);
+        v[j | (1 << RB)] = make_double2(sn * a.y + c * w.x, -sn * a.x + c * w.y);
+    }
 }
+
+// LDS slot of tile index t: bits 0..3 XOR (t4, t5, t6, t6), so that in
+// every layout (3 register bits 3k..3k+2, the others from the thread index)
+// each 16 consecutive lanes read 16 distinct 16-byte bank groups
+__device__ __forceinline__ uint32_t slot128(uint32_t t) { return t ^ ((t >> 4) & 7u) ^ (((t >> 6) & 1u) << 3); }
 
 __device__ __forceinline__ bool flipped(const uint32_t* sg, int g) { return (sg[g >> 5] >> (g & 31)) & 1u; }
 
-__global__ __launch_bounds__(kT128) void k_sv128_pass(double2* __restrict__ psi, const Pass128 P, uint32_t n,
+// element bit (0..2: tile bits 9..11, the bits of i in t = tid + 512 i)
+// holding qubit q, or -1
+__device__ __forceinline__ int elem_bit(const Pass128& P, int q) {
+    return (uint32_t)q == P.tb[kTBits] ? 0 : (uint32_t)q == P.tb[kTBits + 1] ? 1 : (uint32_t)q == P.tb[kTBits + 2] ? 2 : -1;
+}
+
+__global__ __launch_bounds__(kT128) __attribute__((amdgpu_waves_per_eu(4))) void k_sv128_pass(double2* __restrict__ psi, const Pass128 P, uint32_t n,
                                                       uint32_t tiles_log2, const uint32_t* __restrict__ signs,
                                                       uint32_t words, const uint64_t* __restrict__ frame,
                                                       const int4* __restrict__ ledges,
@@ -90,23 +108,19 @@ __global__ __launch_bounds__(kT128) void k_sv128_pass(double2* __restrict__ psi,
     uint64_t zlo = base;
 #pragma unroll
     for (int k = 0; k < kTBits; ++k) zlo |= (uint64_t)((tid >> k) & 1u) << P.tb[k];
-    uint64_t zhi[kPerThread];
-#pragma unroll
-    for (int i = 0; i < kPerThread; ++i) {
-        uint64_t z = 0;
+    // (the element part of the index is uniform: recomputed where used
+    // rather than held in registers)
+    auto at = [&](int i) -> uint64_t {
+        uint64_t z = zlo;
 #pragma unroll
         for (int k = 0; k < kQ128 - kTBits; ++k) z |= (uint64_t)((i >> k) & 1) << P.tb[kTBits + k];
-        zhi[i] = z;
-    }
-    auto at = [&](int i) -> uint64_t {
-        const uint64_t z = zlo | zhi[i];
         return (z & P.mirror) ? (~z & P.half_mask) : z;
     };
 
 #pragma unroll
     for (int i = 0; i < kPerThread; ++i) {
         const uint32_t t = tid + kT128 * i;
-        tile[t] = P.init ? make_double2(P.amp0, 0.0) : st[at(i)];
+        tile[slot128(t)] = P.init ? make_double2(P.amp0, 0.0) : st[at(i)];
     }
     __syncthreads();
 
@@ -120,46 +134,108 @@ __global__ __launch_bounds__(kT128) void k_sv128_pass(double2* __restrict__ psi,
             }
             __syncthreads();
             const double2* ph = phase + phmid[L];
+            // m(z) over the thread's elements: the zz gates whose qubits are
+            // both outside the element bits (tile bits 9..11) give a constant,
+            // those with one inside a term linear in that bit, those with both
+            // inside a term of the bit pair
+            int32_t m0 = 0, h[3] = {0, 0, 0}, w2[3] = {0, 0, 0};
+            for (uint32_t e = 0; e < ne; ++e) {
+                const int4 E = ledges[e0 + e];
+                const int32_t w = smult[e];
+                const int iu = elem_bit(P, E.x), iv = elem_bit(P, E.y);
+                if (iu < 0 && iv < 0) {
+                    m0 += (((zlo >> E.x) ^ (zlo >> E.y)) & 1u) ? w : 0;
+                } else if (iu < 0 || iv < 0) {
+                    const int r = iu < 0 ? iv : iu;
+                    const uint32_t other = (uint32_t)(zlo >> (iu < 0 ? E.x : E.y)) & 1u;
+                    m0 += other ? w : 0;
+                    const int32_t d = other ? -w : w;
+                    h[0] += r == 0 ? d : 0;     // (selects, not indexing: the arrays stay in registers)
+                    h[1] += r == 1 ? d : 0;
+                    h[2] += r == 2 ? d : 0;
+                } else {
+                    const int pr = iu + iv - 1;  // pairs (0,1), (0,2), (1,2)
+                    w2[0] += pr == 0 ? w : 0;
+                    w2[1] += pr == 1 ? w : 0;
+                    w2[2] += pr == 2 ? w : 0;
+                }
+            }
+#pragma unroll
             for (int i = 0; i < kPerThread; ++i) {
                 const uint32_t t = tid + kT128 * i;
-                const uint64_t z = zlo | zhi[i];
-                int32_t m = 0;
-                for (uint32_t e = 0; e < ne; ++e) {
-                    const int4 E = ledges[e0 + e];
-                    m += (((z >> E.x) ^ (z >> E.y)) & 1u) ? smult[e] : 0;
-                }
-                const double2 c = ph[m], a = tile[t];
-                tile[t] = make_double2(c.x * a.x - c.y * a.y, c.x * a.y + c.y * a.x);
+                const int b0 = i & 1, b1 = (i >> 1) & 1, b2 = (i >> 2) & 1;
+                const int32_t m = m0 + (b0 ? h[0] : 0) + (b1 ? h[1] : 0) + (b2 ? h[2] : 0) +
+                                  ((b0 ^ b1) ? w2[0] : 0) + ((b0 ^ b2) ? w2[1] : 0) + ((b1 ^ b2) ? w2[2] : 0);
+                const double2 c = ph[m], a = tile[slot128(t)];
+                tile[slot128(t)] = make_double2(c.x * a.x - c.y * a.y, c.x * a.y + c.y * a.x);
             }
             __syncthreads();
         }
-        for (int r = 0; r < P.nrot[s]; ++r) {
-            const uint32_t bit = (uint32_t)P.rot_bit[s][r];
-            const int g = P.rot_gate[s][r];
-            const double c = gcs[g].x, sn = flipped(sg, g) ? -gcs[g].y : gcs[g].y;
-            for (uint32_t k = tid; k < (1u << (kQ128 - 1)); k += kT128) {
-                const uint32_t t0 = ins0_128(k, bit), t1 = t0 | (1u << bit);
-                const double2 a = tile[t0], v = tile[t1];
-                // [[c, -i s], [-i s, c]] (a, v)
-                tile[t0] = make_double2(c * a.x + sn * v.y, c * a.y - sn * v.x);
-                tile[t1] = make_double2(sn * a.y + c * v.x, -sn * a.x + c * v.y);
+        // rotations in registers: layout k gives each thread the 8 elements
+        // of tile bits 3k .. 3k+2 (its other 9 bits from the thread index)
+        for (int k = 0; k < kQ128 / 3; ++k) {
+            bool any = false;
+            for (int r = 0; r < P.nrot[s]; ++r) any |= P.rot_bit[s][r] / 3 == k;
+            if (!any) continue;
+            const uint32_t lo = tid & ((1u << (3 * k)) - 1u);
+            const uint32_t tbase = lo | ((tid >> (3 * k)) << (3 * k + 3));
+            double2 v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = tile[slot128(tbase | ((uint32_t)j << (3 * k)))];
+            for (int r = 0; r < P.nrot[s]; ++r) {
+                if (P.rot_bit[s][r] / 3 != k) continue;
+                const int rb = P.rot_bit[s][r] - 3 * k;
+                const int g = P.rot_gate[s][r];
+                const double c = gcs[g].x, sn = flipped(sg, g) ? -gcs[g].y : gcs[g].y;
+                // rb is uniform (a scalar branch); each case indexes the registers statically
+                if (rb == 0) rot8<0>(v, c, sn);
+                else if (rb == 1) rot8<1>(v, c, sn);
+                else rot8<2>(v, c, sn);
             }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) tile[slot128(tbase | ((uint32_t)j << (3 * k)))] = v[j];
             __syncthreads();
         }
     }
 
     if (P.last) {
+        // C(z xor F_x) split as the diagonal above, on the flipped bits
         const uint64_t fx = frame[2 * (size_t)b];
+        const uint64_t zf = zlo ^ fx;
+        double c0 = 0.0, hc[3] = {0.0, 0.0, 0.0}, w2c[3] = {0.0, 0.0, 0.0};
+        for (uint32_t e = 0; e < n_terms; ++e) {
+            const int2 E = oedges[e];
+            const double w = ow[e];
+            const int iu = elem_bit(P, E.x), iv = elem_bit(P, E.y);
+            if (iu < 0 && iv < 0) {
+                if (((zf >> E.x) ^ (zf >> E.y)) & 1u) c0 += w;
+            } else if (iu < 0 || iv < 0) {
+                const int r = iu < 0 ? iv : iu;
+                const uint32_t other = (uint32_t)(zf >> (iu < 0 ? E.x : E.y)) & 1u;
+                if (other) c0 += w;
+                const double d = other ? -w : w;
+                hc[0] += r == 0 ? d : 0.0;
+                hc[1] += r == 1 ? d : 0.0;
+                hc[2] += r == 2 ? d : 0.0;
+            } else {
+                const int pr = iu + iv - 1;
+                w2c[0] += pr == 0 ? w : 0.0;
+                w2c[1] += pr == 1 ? w : 0.0;
+                w2c[2] += pr == 2 ? w : 0.0;
+            }
+        }
+        uint32_t fi = 0;   // frame bits on the element bits
+#pragma unroll
+        for (int r = 0; r < kQ128 - kTBits; ++r) fi |= (uint32_t)((fx >> P.tb[kTBits + r]) & 1u) << r;
         double acc = 0.0;
+#pragma unroll
         for (int i = 0; i < kPerThread; ++i) {
             const uint32_t t = tid + kT128 * i;
-            const uint64_t z = (zlo | zhi[i]) ^ fx;
-            double cz = 0.0;
-            for (uint32_t e = 0; e < n_terms; ++e) {
-                const int2 E = oedges[e];
-                if (((z >> E.x) ^ (z >> E.y)) & 1u) cz += ow[e];
-            }
-            const double2 a = tile[t];
+            const uint32_t ie = (uint32_t)i ^ fi;
+            const int b0 = ie & 1, b1 = (ie >> 1) & 1, b2 = (ie >> 2) & 1;
+            const double cz = c0 + (b0 ? hc[0] : 0.0) + (b1 ? hc[1] : 0.0) + (b2 ? hc[2] : 0.0) +
+                              ((b0 ^ b1) ? w2c[0] : 0.0) + ((b0 ^ b2) ? w2c[1] : 0.0) + ((b1 ^ b2) ? w2c[2] : 0.0);
+            const double2 a = tile[slot128(t)];
             acc += (a.x * a.x + a.y * a.y) * cz;
         }
         red[tid] = acc;
@@ -171,7 +247,7 @@ __global__ __launch_bounds__(kT128) void k_sv128_pass(double2* __restrict__ psi,
         if (tid == 0) partials[blk] = red[0] * P.escale;
     } else {
 #pragma unroll
-        for (int i = 0; i < kPerThread; ++i) st[at(i)] = tile[tid + kT128 * i];
+        for (int i = 0; i < kPerThread; ++i) st[at(i)] = tile[slot128(tid + kT128 * i)];
     }
 }
 
