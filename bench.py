@@ -186,6 +186,9 @@ def main():
                     help="only the uneven-batch leg: 64 jobs (n 10..30, p 1..6, K 256..8192) submitted at once to "
                          "the job server, for --uneven-window seconds")
     ap.add_argument("--uneven-window", type=float, default=900.0)
+    ap.add_argument("--uneven-leg-window", type=float, default=60.0,
+                    help="seconds of the uneven-batch leg in the default run (0: skip); jobs still running at "
+                         "its end are reported as censored")
     ap.add_argument("--job", type=str, default=None,
                     help="only one job n,p,K[,precision[,lc_max_rank,lc_slice_bits]] (QAOA on an Erdos-Renyi graph, "
                          "p_edge 3/(n-1), depolarizing 1e-3/1e-2) through the plan API with the planner's choice of "
@@ -342,6 +345,11 @@ def main():
     torch.cuda.empty_cache()
     note("serving leg")
     serving = serving_leg(stn, args) if args.serve_jobs > 0 else None
+    torch.cuda.empty_cache()
+    uneven = None
+    if args.uneven_leg_window > 0:
+        note("uneven batch leg")
+        uneven = uneven_leg(stn, args, args.uneven_leg_window)
 
     out = {
         "metric": METRIC,
@@ -377,6 +385,7 @@ def main():
         "rho_hat": rho_leg,
         "sv_gates": gates,
         "serving": serving,
+        "uneven_batch": uneven,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
@@ -705,10 +714,11 @@ def graph_leg(stn, chunks=400):
     return out
 
 
-def uneven_leg(stn, args):
+def uneven_leg(stn, args, window=None):
     """64 QAOA jobs, n ~ U{10..30}, p ~ U{1..6}, Erdos-Renyi p_edge = 3/(n-1),
     K ~ U{256..8192}, submitted at once to the job server; runs until all are
     done or the window ends (jobs still running then are censored)."""
+    window = args.uneven_window if window is None else window
     import numpy as np
     import torch
     from workloads import uneven_batch
@@ -721,7 +731,7 @@ def uneven_leg(stn, args):
     for i, pr in enumerate(jobs):
         sv.submit(pr, tag=i)
     last_chunks, last_print = 0, 0.0
-    while sv.clock() - t0 < args.uneven_window and len(res) < len(jobs):
+    while sv.clock() - t0 < window and len(res) < len(jobs):
         for r in sv.poll(wait=1.0, cap=4096):
             res[r["tag"]] = r
             print(f"uneven: job {r['tag']} n={jobs[r['tag']].n_qubits} p={jobs[r['tag']].p} K={r['K']} "
@@ -732,7 +742,7 @@ def uneven_leg(stn, args):
             print(f"uneven: {st['clock'] - t0:.0f} s, {st['completed']} jobs done, {st['chunks']} chunks issued",
                   file=sys.stderr, flush=True)
             last_chunks, last_print = st["chunks"], st["clock"]
-    t_end = min(sv.clock() - t0, args.uneven_window)
+    t_end = min(sv.clock() - t0, window)
     st = sv.stats()
     sv.close()
     done = [i for i in res if res[i]["status"] == 0]
@@ -745,7 +755,15 @@ def uneven_leg(stn, args):
         d["trajectories"] += res[i]["K"]
     censored = [{"n": jobs[i].n_qubits, "p": jobs[i].p, "K": jobs[i].K} for i in range(len(jobs)) if i not in res]
     torch.cuda.synchronize()
-    return {"jobs": len(jobs), "window_s": args.uneven_window, "completed": len(done),
+    # the batch's work in device-seconds by the library's cost model (the
+    # server's admission and scheduling estimate), done and in all
+    est = []
+    for pr in jobs:
+        pl = stn.Plan(pr, outputs=stn.OUT_ENERGY, precision=64, hbm_budget=int(0.5 * args.hbm_budget_gib * (1 << 30)))
+        est.append(pl.info()["est_s_per_traj"] * pr.K)
+        pl.close()
+    return {"jobs": len(jobs), "window_s": window, "completed": len(done),
+            "work_device_s": {"all": float(sum(est)), "completed": float(sum(est[i] for i in done))},
             "failed": int(sum(r["status"] != 0 for r in res.values())), "censored": censored,
             "makespan_s": t_end, "trajectories": traj, "trajectories_per_s": traj / t_end if t_end > 0 else None,
             "completion_s": {"p50": float(np.percentile(lat, 50, method="higher"))

@@ -24,8 +24,11 @@
 // sum_t w_t (1 - f_t <Z_u Z_v>_t) / 2 in binary64 with the final Pauli
 // frame's sign f_t, in term order.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <exception>
 #include <mutex>
+#include <thread>
 
 #include "lightcone.h"
 
@@ -649,6 +652,8 @@ constexpr uint32_t kGroupSizes[] = {1, 2, 4, 8, 16};
 // Each term's order is lowered once per group size (the LDS arena of a
 // trajectory shrinks as the group grows, so more intermediates may go to
 // global memory); the group size with the smallest estimated time is kept.
+thread_local uint32_t tl_plan_threads = 0;
+
 void build_lightcone(stn_plan* p) {
     if (!p->frame_ok) fail(STN_E_UNSUPPORTED, "lightcone lowering needs Pauli noise and Pauli-rotation gates after the noise");
     if (p->obs_u.empty()) fail(STN_E_UNSUPPORTED, "lightcone lowering needs an observable");
@@ -666,9 +671,41 @@ void build_lightcone(stn_plan* p) {
     bool aborted = false;
     const int rank_cap = p->opts.lc_max_rank ? std::min<int>((int)p->opts.lc_max_rank, kStepBits - 1) : kStepBits - 1;
     const int slice_cap = (int)std::min<uint32_t>(p->opts.lc_slice_bits, kMaxSliceBits);
-    for (size_t t = 0; t < p->obs_u.size(); ++t) {
-        std::vector<TnNetwork> nets = build_term(p, (uint32_t)t, p->obs_u[t], p->obs_v[t], p->opts.order_restarts,
-                                                 p->opts.order_seed, rank_cap, slice_cap, budgets);
+    // Terms are independent and each is built deterministically (its own
+    // seeded restarts), so they are built on a few host threads and then
+    // taken in term order; a caller-supplied order function is called on
+    // this thread, in term order.  Once a term is too wide no new term is
+    // started (every earlier term has been).
+    const size_t T = p->obs_u.size();
+    std::vector<std::vector<TnNetwork>> built(T);
+    std::vector<std::exception_ptr> errs(T);
+    std::atomic<size_t> next{0};
+    std::atomic<bool> stop{false};
+    auto worker = [&] {
+        for (size_t t; !stop.load() && (t = next.fetch_add(1)) < T;) {
+            try {
+                built[t] = build_term(p, (uint32_t)t, p->obs_u[t], p->obs_v[t], p->opts.order_restarts,
+                                      p->opts.order_seed, rank_cap, slice_cap, budgets);
+                if (built[t][0].steps.empty() && !std::isfinite(built[t][0].cost)) stop = true;
+            } catch (...) {
+                errs[t] = std::current_exception();
+                stop = true;
+            }
+        }
+    };
+    const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+    const size_t cap = tl_plan_threads ? tl_plan_threads : 8;
+    const size_t nthreads = p->opts.lc_order_fn ? 1 : std::min<size_t>({T, hw, cap});
+    if (nthreads <= 1) {
+        worker();
+    } else {
+        std::vector<std::thread> pool;
+        for (size_t i = 0; i < nthreads; ++i) pool.emplace_back(worker);
+        for (auto& th : pool) th.join();
+    }
+    for (size_t t = 0; t < T; ++t) {
+        if (errs[t]) std::rethrow_exception(errs[t]);
+        std::vector<TnNetwork>& nets = built[t];
         const TnNetwork& net = nets[0];
         if (net.steps.empty() && !std::isfinite(net.cost)) {
             max_rank = std::max(max_rank, net.width);   // stopped early: too wide for this lowering

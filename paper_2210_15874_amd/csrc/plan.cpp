@@ -553,13 +553,19 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
                 // 128 bytes or more (n <= 24), about 3 TB/s at n = 26
                 sv_t = bytes / (n <= 24 ? 5e12 : 3e12);
             }
-            try {
-                build_lightcone(p);
-                tn_t = p->lc_est_s;
-            } catch (const Error& e) {
-                if (e.status != STN_E_UNSUPPORTED) throw;
-                if (why.empty()) why = e.msg;
-                else why += "; " + e.msg;
+            // below half a microsecond per trajectory (a few ms of device
+            // time for thousands of trajectories) the networks cannot save
+            // what building them costs (milliseconds per observable term)
+            constexpr double kNetworksWorthSeconds = 0.5e-6;
+            if (sv_t < 0 || sv_t >= kNetworksWorthSeconds) {
+                try {
+                    build_lightcone(p);
+                    tn_t = p->lc_est_s;
+                } catch (const Error& e) {
+                    if (e.status != STN_E_UNSUPPORTED) throw;
+                    if (why.empty()) why = e.msg;
+                    else why += "; " + e.msg;
+                }
             }
             if (tn_t >= 0 && (sv_t < 0 || tn_t < sv_t)) kind = STN_PLAN_LIGHTCONE;
             else if (sv_t >= 0) kind = STN_PLAN_SV_TILED;

@@ -325,6 +325,7 @@ void plan_job(stn_server* sv, Job& j) {
 }
 
 void planner_loop(stn_server* sv) {
+    tl_plan_threads = 1;   // jobs are planned in parallel by the planner threads themselves
     for (;;) {
         std::shared_ptr<Job> j;
         {

@@ -316,6 +316,12 @@ uint32_t tiled_variants(const stn_plan* p);
 // planner (plan.cpp)
 void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, const stn_observable* ob);
 
+// Host threads a plan built on this thread may use for its lightcone
+// networks (0: up to 8).  The job server's planner threads set 1: they
+// already plan several jobs at once, and the device thread must not wait for
+// a CPU.
+extern thread_local uint32_t tl_plan_threads;
+
 // launchers (kernels_*.hip)
 void launch_sample(stn_plan* p, stn_batch* b, uint64_t seed, hipStream_t s);
 void launch_frame(stn_plan* p, stn_batch* b, hipStream_t s);
