@@ -47,7 +47,8 @@ __global__ __launch_bounds__(256) void k_gates_init(V* __restrict__ psi, uint64_
     }
 }
 
-constexpr uint32_t kTileThreads = 256;
+constexpr uint32_t kTileLog = 9;                  // 512 threads: 4 waves per SIMD at two workgroups per CU
+constexpr uint32_t kTileThreads = 1u << kTileLog;
 
 __device__ __forceinline__ uint64_t remap_mask(uint64_t m, const uint8_t* local) {
     uint64_t r = 0;
@@ -59,7 +60,7 @@ __device__ __forceinline__ uint64_t remap_mask(uint64_t m, const uint8_t* local)
 // (2^g.nbits amplitudes) and the group's operators resolved for this
 // trajectory.
 template <class V>
-__global__ __launch_bounds__(256) void k_gates_tile(V* __restrict__ psi, uint32_t n, const GateGroup g, int init,
+__global__ __launch_bounds__(kTileThreads) void k_gates_tile(V* __restrict__ psi, uint32_t n, const GateGroup g, int init,
                                                     const LdsOp* __restrict__ gops, const V* __restrict__ vals,
                                                     const LdsOp* __restrict__ site_ops,
                                                     const uint32_t* __restrict__ site_off,
@@ -92,7 +93,7 @@ __global__ __launch_bounds__(256) void k_gates_tile(V* __restrict__ psi, uint32_
     uint64_t fixed = (1ull << n) - 1ull;
     for (uint32_t l = 0; l < g.nbits; ++l) fixed &= ~(1ull << g.tb[l]);
     uint64_t zt = 0;
-    for (uint32_t l = 0; l < g.nbits && l < 8; ++l)
+    for (uint32_t l = 0; l < g.nbits && l < kTileLog; ++l)
         if ((tid >> l) & 1u) zt |= 1ull << g.tb[l];
     const uint32_t nt = 1u << (n - g.nbits);
     V* st = psi + (k << n);
@@ -103,12 +104,12 @@ __global__ __launch_bounds__(256) void k_gates_tile(V* __restrict__ psi, uint32_
             for (uint64_t m = fixed; m; m &= m - 1, v >>= 1)
                 if (v & 1u) base |= m & (~m + 1);
         }
-        for (uint32_t r = 0; (r << 8) < T; ++r) {
-            const uint32_t j = tid + (r << 8);
+        for (uint32_t r = 0; (r << kTileLog) < T; ++r) {
+            const uint32_t j = tid + (r << kTileLog);
             if (j >= T) break;
             uint64_t z = base | zt;
-            for (uint32_t l = 8; l < g.nbits; ++l)
-                if ((r >> (l - 8)) & 1u) z |= 1ull << g.tb[l];
+            for (uint32_t l = kTileLog; l < g.nbits; ++l)
+                if ((r >> (l - kTileLog)) & 1u) z |= 1ull << g.tb[l];
             V v;
             if (init) {
                 v.x = z == 0 ? 1 : 0;
@@ -122,15 +123,15 @@ __global__ __launch_bounds__(256) void k_gates_tile(V* __restrict__ psi, uint32_
         for (uint32_t i = 0; i < g.n_ops; ++i) {
             const LdsOp o = ops[i];
             if (o.kind == OP_IDENT) continue;   // uniform: no barrier needed
-            apply_lds_op<V>(tile, T, o, vals, tid, kTileThreads);
+            apply_lds_op<V, 8>(tile, T, o, vals, tid, kTileThreads);
             __syncthreads();
         }
-        for (uint32_t r = 0; (r << 8) < T; ++r) {
-            const uint32_t j = tid + (r << 8);
+        for (uint32_t r = 0; (r << kTileLog) < T; ++r) {
+            const uint32_t j = tid + (r << kTileLog);
             if (j >= T) break;
             uint64_t z = base | zt;
-            for (uint32_t l = 8; l < g.nbits; ++l)
-                if ((r >> (l - 8)) & 1u) z |= 1ull << g.tb[l];
+            for (uint32_t l = kTileLog; l < g.nbits; ++l)
+                if ((r >> (l - kTileLog)) & 1u) z |= 1ull << g.tb[l];
             st[z] = tile[j];
         }
         __syncthreads();   // the tile is reloaded next round

@@ -32,18 +32,33 @@ __device__ __forceinline__ uint32_t op_ins0(uint32_t p, uint32_t q) {
     return ((p ^ lo) << 1) | lo;
 }
 
-template <class V>
+// The loops over amplitude pairs (or amplitudes) take kOpUnroll of a
+// thread's items per round, all loads before any arithmetic, so that the LDS
+// latency of one item overlaps the others' (worth it where few waves share a
+// SIMD: the tiles of the gate-by-gate lowering); items of one operator are
+// disjoint, so the order of the loads and stores within a round is free.
+template <class V, uint32_t kOpUnroll = 1>
 __device__ __forceinline__ void apply_lds_op(V* psi, uint32_t N, const LdsOp& o, const V* __restrict__ vals,
                                              uint32_t tid, uint32_t nthreads) {
     switch (o.kind) {
         case OP_DENSE1: {
             const V m0 = vals[o.mat], m1 = vals[o.mat + 1], m2 = vals[o.mat + 2], m3 = vals[o.mat + 3];
             const uint32_t bit = 1u << o.q0;
-            for (uint32_t p = tid; p < N / 2; p += nthreads) {
-                const uint32_t i0 = op_ins0(p, o.q0), i1 = i0 | bit;
-                const V a = psi[i0], c = psi[i1];
-                psi[i0] = op_cadd(op_cmul(m0, a), op_cmul(m1, c));
-                psi[i1] = op_cadd(op_cmul(m2, a), op_cmul(m3, c));
+            for (uint32_t p0 = tid; p0 < N / 2; p0 += kOpUnroll * nthreads) {
+                uint32_t i0[kOpUnroll];
+                V a[kOpUnroll], c[kOpUnroll];
+#pragma unroll
+                for (uint32_t u = 0; u < kOpUnroll; ++u) {
+                    const uint32_t p = p0 + u * nthreads;
+                    i0[u] = op_ins0(p < N / 2 ? p : 0u, o.q0);
+                    if (p < N / 2) { a[u] = psi[i0[u]]; c[u] = psi[i0[u] | bit]; }
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < kOpUnroll; ++u) {
+                    if (p0 + u * nthreads >= N / 2) continue;
+                    psi[i0[u]] = op_cadd(op_cmul(m0, a[u]), op_cmul(m1, c[u]));
+                    psi[i0[u] | bit] = op_cadd(op_cmul(m2, a[u]), op_cmul(m3, c[u]));
+                }
             }
             break;
         }
@@ -68,30 +83,70 @@ __device__ __forceinline__ void apply_lds_op(V* psi, uint32_t N, const LdsOp& o,
         }
         case OP_DIAG1: {
             const V d0 = vals[o.mat], d1 = vals[o.mat + 1];
-            for (uint32_t i = tid; i < N; i += nthreads) psi[i] = op_cmul((i >> o.q0) & 1 ? d1 : d0, psi[i]);
+            for (uint32_t i0 = tid; i0 < N; i0 += kOpUnroll * nthreads) {
+                V a[kOpUnroll];
+#pragma unroll
+                for (uint32_t u = 0; u < kOpUnroll; ++u)
+                    if (i0 + u * nthreads < N) a[u] = psi[i0 + u * nthreads];
+#pragma unroll
+                for (uint32_t u = 0; u < kOpUnroll; ++u) {
+                    const uint32_t i = i0 + u * nthreads;
+                    if (i < N) psi[i] = op_cmul((i >> o.q0) & 1 ? d1 : d0, a[u]);
+                }
+            }
             break;
         }
         case OP_DIAG2: {
             const V d0 = vals[o.mat], d1 = vals[o.mat + 1], d2 = vals[o.mat + 2], d3 = vals[o.mat + 3];
-            for (uint32_t i = tid; i < N; i += nthreads) {
-                // selects, not an indexed local array (which would live in scratch)
-                const bool a = (i >> o.q0) & 1, b = (i >> o.q1) & 1;
-                const V lo = a ? d1 : d0, hi = a ? d3 : d2;
-                psi[i] = op_cmul(b ? hi : lo, psi[i]);
+            for (uint32_t i0 = tid; i0 < N; i0 += kOpUnroll * nthreads) {
+                V a[kOpUnroll];
+#pragma unroll
+                for (uint32_t u = 0; u < kOpUnroll; ++u)
+                    if (i0 + u * nthreads < N) a[u] = psi[i0 + u * nthreads];
+#pragma unroll
+                for (uint32_t u = 0; u < kOpUnroll; ++u) {
+                    const uint32_t i = i0 + u * nthreads;
+                    if (i >= N) continue;
+                    // selects, not an indexed local array (which would live in scratch)
+                    const bool qa = (i >> o.q0) & 1, qb = (i >> o.q1) & 1;
+                    const V lo = qa ? d1 : d0, hi = qa ? d3 : d2;
+                    psi[i] = op_cmul(qb ? hi : lo, a[u]);
+                }
             }
             break;
         }
         case OP_PAULI: {
             const uint32_t x = (uint32_t)o.xmask, z = (uint32_t)o.zmask;
             if (x == 0) {
-                for (uint32_t i = tid; i < N; i += nthreads) psi[i] = op_neg_if(psi[i], __popc(i & z) & 1);
+                for (uint32_t i0 = tid; i0 < N; i0 += kOpUnroll * nthreads) {
+                    V a[kOpUnroll];
+#pragma unroll
+                    for (uint32_t u = 0; u < kOpUnroll; ++u)
+                        if (i0 + u * nthreads < N) a[u] = psi[i0 + u * nthreads];
+#pragma unroll
+                    for (uint32_t u = 0; u < kOpUnroll; ++u) {
+                        const uint32_t i = i0 + u * nthreads;
+                        if (i < N) psi[i] = op_neg_if(a[u], __popc(i & z) & 1);
+                    }
+                }
             } else {
                 const uint32_t lb = __ffs(x) - 1;
-                for (uint32_t p = tid; p < N / 2; p += nthreads) {
-                    const uint32_t i = op_ins0(p, lb), j = i ^ x;
-                    const V a = psi[i], c = psi[j];
-                    psi[j] = op_neg_if(a, __popc(i & z) & 1);
-                    psi[i] = op_neg_if(c, __popc(j & z) & 1);
+                for (uint32_t p0 = tid; p0 < N / 2; p0 += kOpUnroll * nthreads) {
+                    uint32_t ii[kOpUnroll];
+                    V a[kOpUnroll], c[kOpUnroll];
+#pragma unroll
+                    for (uint32_t u = 0; u < kOpUnroll; ++u) {
+                        const uint32_t p = p0 + u * nthreads;
+                        ii[u] = op_ins0(p < N / 2 ? p : 0u, lb);
+                        if (p < N / 2) { a[u] = psi[ii[u]]; c[u] = psi[ii[u] ^ x]; }
+                    }
+#pragma unroll
+                    for (uint32_t u = 0; u < kOpUnroll; ++u) {
+                        if (p0 + u * nthreads >= N / 2) continue;
+                        const uint32_t i = ii[u], j = i ^ x;
+                        psi[j] = op_neg_if(a[u], __popc(i & z) & 1);
+                        psi[i] = op_neg_if(c[u], __popc(j & z) & 1);
+                    }
                 }
             }
             break;
