@@ -50,6 +50,18 @@ __global__ __launch_bounds__(256) void k_gates_init(V* __restrict__ psi, uint64_
 constexpr uint32_t kTileLog = 9;                  // 512 threads: 4 waves per SIMD at two workgroups per CU
 constexpr uint32_t kTileThreads = 1u << kTileLog;
 
+// a thread's tile elements: tile index tid + r * kTileThreads, r < tile_per<V>
+// (tiles of at most 13 bits in complex64, 12 in complex128)
+template <class V> constexpr uint32_t tile_per() { return (sizeof(V) > 8 ? (1u << 12) : (1u << 13)) / kTileThreads; }
+
+// storage bits of the tile bits above the thread bits, for round r (uniform)
+__device__ __forceinline__ uint64_t tile_hi(const GateGroup& g, uint32_t r) {
+    uint64_t z = 0;
+    for (uint32_t l = kTileLog; l < g.nbits; ++l)
+        if ((r >> (l - kTileLog)) & 1u) z |= 1ull << g.tb[l];
+    return z;
+}
+
 __device__ __forceinline__ uint64_t remap_mask(uint64_t m, const uint8_t* local) {
     uint64_t r = 0;
     for (; m; m &= m - 1) r |= 1ull << local[__builtin_ctzll(m)];
@@ -104,35 +116,46 @@ __global__ __launch_bounds__(kTileThreads) void k_gates_tile(V* __restrict__ psi
             for (uint64_t m = fixed; m; m &= m - 1, v >>= 1)
                 if (v & 1u) base |= m & (~m + 1);
         }
-        for (uint32_t r = 0; (r << kTileLog) < T; ++r) {
-            const uint32_t j = tid + (r << kTileLog);
-            if (j >= T) break;
-            uint64_t z = base | zt;
-            for (uint32_t l = kTileLog; l < g.nbits; ++l)
-                if ((r >> (l - kTileLog)) & 1u) z |= 1ull << g.tb[l];
-            V v;
+        // all of a thread's loads are issued before any is written to LDS
+        // (rounds r: uniform, tile index tid + r * threads)
+        constexpr uint32_t kTilePer = tile_per<V>();
+        V vv[kTilePer];
+#pragma unroll
+        for (uint32_t r = 0; r < kTilePer; ++r) {
+            if ((r << kTileLog) >= T) break;
+            if (tid + (r << kTileLog) >= T) continue;   // tiles smaller than the workgroup
+            const uint64_t z = base | zt | tile_hi(g, r);
             if (init) {
-                v.x = z == 0 ? 1 : 0;
-                v.y = 0;
+                vv[r].x = z == 0 ? 1 : 0;
+                vv[r].y = 0;
             } else {
-                v = st[z];
+                vv[r] = st[z];
             }
-            tile[j] = v;
+        }
+#pragma unroll
+        for (uint32_t r = 0; r < kTilePer; ++r) {
+            if ((r << kTileLog) >= T) break;
+            if (tid + (r << kTileLog) >= T) continue;   // tiles smaller than the workgroup
+            tile[tid + (r << kTileLog)] = vv[r];
         }
         __syncthreads();
         for (uint32_t i = 0; i < g.n_ops; ++i) {
             const LdsOp o = ops[i];
             if (o.kind == OP_IDENT) continue;   // uniform: no barrier needed
-            apply_lds_op<V, 8>(tile, T, o, vals, tid, kTileThreads);
+            apply_lds_op<V, (sizeof(V) > 8 ? 2u : 8u)>(tile, T, o, vals, tid, kTileThreads);
             __syncthreads();
         }
-        for (uint32_t r = 0; (r << kTileLog) < T; ++r) {
-            const uint32_t j = tid + (r << kTileLog);
-            if (j >= T) break;
-            uint64_t z = base | zt;
-            for (uint32_t l = kTileLog; l < g.nbits; ++l)
-                if ((r >> (l - kTileLog)) & 1u) z |= 1ull << g.tb[l];
-            st[z] = tile[j];
+#pragma unroll
+        for (uint32_t r = 0; r < kTilePer; ++r) {
+            if ((r << kTileLog) >= T) break;
+            if (tid + (r << kTileLog) >= T) continue;   // tiles smaller than the workgroup
+            vv[r] = tile[tid + (r << kTileLog)];
+        }
+#pragma unroll
+        for (uint32_t r = 0; r < kTilePer; ++r) {
+            if ((r << kTileLog) >= T) break;
+            if (tid + (r << kTileLog) >= T) continue;   // tiles smaller than the workgroup
+            st[base | zt | tile_hi(g, r)] = vv[r];
         }
         __syncthreads();   // the tile is reloaded next round
     }
