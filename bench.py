@@ -368,6 +368,7 @@ def main():
                    "graph": "random 3-regular (seed 1002)", "K": K, "lambda1": 1e-3, "lambda2": 1e-2,
                    "contraction": "complex64 (FP32), FP64 reductions", "plan": info["plan_name"],
                    "trajectories_per_launch": B, "passes_per_trajectory": info["n_passes"],
+                   "stored_amplitudes_per_trajectory": 2 ** (problem.n_qubits - info["half_state"]),
                    "launch_shape": {"chosen": tune["chosen"], "ms_per_variant": tune["ms"]},
                    "plan_ms": plan_ms},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
