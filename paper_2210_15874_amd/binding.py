@@ -240,7 +240,10 @@ class _TorchAllocator:
             return None
 
     def _free(self, ptr, ctx):
-        self.torch.cuda.caching_allocator_delete(ptr)
+        cuda = getattr(self.torch, "cuda", None)
+        if cuda is None:   # interpreter shutdown: torch is torn down already; the process releases the memory
+            return
+        cuda.caching_allocator_delete(ptr)
 
 
 def _problem_structs(problem, with_observable):

@@ -305,7 +305,8 @@ void plan_job(stn_server* sv, Job& j) {
     // (~32k tiles per launch): the rest of the memory serves other jobs
     if (p->kind == STN_PLAN_SV_TILED) {
         const int tile_bits = p->opts.precision == 128 ? (int)tiled128_tile_bits() : 14;
-        const double tiles = std::ldexp(1.0, std::max(0, (int)p->n - tile_bits));
+        const int stored = (int)p->n - (p->sv_half ? 1 : 0);   // half-state plans keep 2^(n-1) amplitudes
+        const double tiles = std::ldexp(1.0, std::max(0, stored - tile_bits));
         j.B = (uint32_t)std::max(1.0, std::min((double)j.B, std::ceil(kChunkTiles / tiles)));
     }
     j.est_s = p->est_seconds_per_traj() * (double)j.K;
