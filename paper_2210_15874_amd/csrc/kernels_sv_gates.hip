@@ -62,6 +62,13 @@ __device__ __forceinline__ uint64_t tile_hi(const GateGroup& g, uint32_t r) {
     return z;
 }
 
+__device__ __forceinline__ uint64_t tile_hi2(const GateGroup& g, uint32_t r) {
+    uint64_t z = 0;
+    for (uint32_t l = kTileLog + 1; l < g.nbits; ++l)
+        if ((r >> (l - kTileLog - 1)) & 1u) z |= 1ull << g.tb[l];
+    return z;
+}
+
 __device__ __forceinline__ uint64_t remap_mask(uint64_t m, const uint8_t* local) {
     uint64_t r = 0;
     for (; m; m &= m - 1) r |= 1ull << local[__builtin_ctzll(m)];
@@ -107,6 +114,9 @@ __global__ __launch_bounds__(kTileThreads) void k_gates_tile(V* __restrict__ psi
     uint64_t zt = 0;
     for (uint32_t l = 0; l < g.nbits && l < kTileLog; ++l)
         if ((tid >> l) & 1u) zt |= 1ull << g.tb[l];
+    uint64_t zt2 = 0;   // pair layout: tile bits 1 .. kTileLog from the thread index
+    for (uint32_t l = 1; l < g.nbits && l <= kTileLog; ++l)
+        if ((tid >> (l - 1)) & 1u) zt2 |= 1ull << g.tb[l];
     const uint32_t nt = 1u << (n - g.nbits);
     V* st = psi + (k << n);
     for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
@@ -117,26 +127,53 @@ __global__ __launch_bounds__(kTileThreads) void k_gates_tile(V* __restrict__ psi
                 if (v & 1u) base |= m & (~m + 1);
         }
         // all of a thread's loads are issued before any is written to LDS
-        // (rounds r: uniform, tile index tid + r * threads)
         constexpr uint32_t kTilePer = tile_per<V>();
+        // complex64: amplitude pairs along tile bit 0 = storage bit 0 (every
+        // group tile holds it), one 16-byte access per pair
+        constexpr bool kPairs = sizeof(V) == 8;
         V vv[kTilePer];
+        if constexpr (kPairs) {
+            // pair p = tid + r * threads: tile indices 2p, 2p + 1 (tiles smaller
+            // than two per thread leave the upper threads idle)
 #pragma unroll
-        for (uint32_t r = 0; r < kTilePer; ++r) {
-            if ((r << kTileLog) >= T) break;
-            if (tid + (r << kTileLog) >= T) continue;   // tiles smaller than the workgroup
-            const uint64_t z = base | zt | tile_hi(g, r);
-            if (init) {
-                vv[r].x = z == 0 ? 1 : 0;
-                vv[r].y = 0;
-            } else {
-                vv[r] = st[z];
+            for (uint32_t r = 0; r < kTilePer / 2; ++r) {
+                if ((r << (kTileLog + 1)) >= T) break;
+                if (2 * (tid + (r << kTileLog)) >= T) continue;
+                const uint64_t z = base | zt2 | tile_hi2(g, r);
+                if (init) {
+                    vv[2 * r].x = z == 0 ? 1 : 0; vv[2 * r].y = 0;
+                    vv[2 * r + 1].x = 0; vv[2 * r + 1].y = 0;
+                } else {
+                    const float4 w = *reinterpret_cast<const float4*>(st + z);
+                    vv[2 * r].x = w.x; vv[2 * r].y = w.y; vv[2 * r + 1].x = w.z; vv[2 * r + 1].y = w.w;
+                }
             }
-        }
 #pragma unroll
-        for (uint32_t r = 0; r < kTilePer; ++r) {
-            if ((r << kTileLog) >= T) break;
-            if (tid + (r << kTileLog) >= T) continue;   // tiles smaller than the workgroup
-            tile[tid + (r << kTileLog)] = vv[r];
+            for (uint32_t r = 0; r < kTilePer / 2; ++r) {
+                if ((r << (kTileLog + 1)) >= T) break;
+                if (2 * (tid + (r << kTileLog)) >= T) continue;
+                const uint32_t j = 2 * (tid + (r << kTileLog));
+                *reinterpret_cast<float4*>(tile + j) = make_float4(vv[2 * r].x, vv[2 * r].y, vv[2 * r + 1].x, vv[2 * r + 1].y);
+            }
+        } else {
+#pragma unroll
+            for (uint32_t r = 0; r < kTilePer; ++r) {
+                if ((r << kTileLog) >= T) break;
+                if (tid + (r << kTileLog) >= T) continue;   // tiles smaller than the workgroup
+                const uint64_t z = base | zt | tile_hi(g, r);
+                if (init) {
+                    vv[r].x = z == 0 ? 1 : 0;
+                    vv[r].y = 0;
+                } else {
+                    vv[r] = st[z];
+                }
+            }
+#pragma unroll
+            for (uint32_t r = 0; r < kTilePer; ++r) {
+                if ((r << kTileLog) >= T) break;
+                if (tid + (r << kTileLog) >= T) continue;
+                tile[tid + (r << kTileLog)] = vv[r];
+            }
         }
         __syncthreads();
         for (uint32_t i = 0; i < g.n_ops; ++i) {
@@ -145,17 +182,34 @@ __global__ __launch_bounds__(kTileThreads) void k_gates_tile(V* __restrict__ psi
             apply_lds_op<V, (sizeof(V) > 8 ? 2u : 8u)>(tile, T, o, vals, tid, kTileThreads);
             __syncthreads();
         }
+        if constexpr (kPairs) {
 #pragma unroll
-        for (uint32_t r = 0; r < kTilePer; ++r) {
-            if ((r << kTileLog) >= T) break;
-            if (tid + (r << kTileLog) >= T) continue;   // tiles smaller than the workgroup
-            vv[r] = tile[tid + (r << kTileLog)];
-        }
+            for (uint32_t r = 0; r < kTilePer / 2; ++r) {
+                if ((r << (kTileLog + 1)) >= T) break;
+                if (2 * (tid + (r << kTileLog)) >= T) continue;
+                const float4 w = *reinterpret_cast<const float4*>(tile + 2 * (tid + (r << kTileLog)));
+                vv[2 * r].x = w.x; vv[2 * r].y = w.y; vv[2 * r + 1].x = w.z; vv[2 * r + 1].y = w.w;
+            }
 #pragma unroll
-        for (uint32_t r = 0; r < kTilePer; ++r) {
-            if ((r << kTileLog) >= T) break;
-            if (tid + (r << kTileLog) >= T) continue;   // tiles smaller than the workgroup
-            st[base | zt | tile_hi(g, r)] = vv[r];
+            for (uint32_t r = 0; r < kTilePer / 2; ++r) {
+                if ((r << (kTileLog + 1)) >= T) break;
+                if (2 * (tid + (r << kTileLog)) >= T) continue;
+                *reinterpret_cast<float4*>(st + (base | zt2 | tile_hi2(g, r))) =
+                    make_float4(vv[2 * r].x, vv[2 * r].y, vv[2 * r + 1].x, vv[2 * r + 1].y);
+            }
+        } else {
+#pragma unroll
+            for (uint32_t r = 0; r < kTilePer; ++r) {
+                if ((r << kTileLog) >= T) break;
+                if (tid + (r << kTileLog) >= T) continue;
+                vv[r] = tile[tid + (r << kTileLog)];
+            }
+#pragma unroll
+            for (uint32_t r = 0; r < kTilePer; ++r) {
+                if ((r << kTileLog) >= T) break;
+                if (tid + (r << kTileLog) >= T) continue;
+                st[base | zt | tile_hi(g, r)] = vv[r];
+            }
         }
         __syncthreads();   // the tile is reloaded next round
     }
@@ -278,6 +332,8 @@ void build_gate_groups(stn_plan* p) {
                 g.local[q] = (uint8_t)l;
                 ++l;
             }
+        // the kernels move complex64 amplitudes in pairs along tile bit 0
+        if (g.tb[0] != 0) fail(STN_E_INVALID, "gate group tile without storage bit 0");
         g.op0 = (uint32_t)p->gate_group_ops.size();
         g.n_ops = (uint32_t)cur.size();
         for (LdsOp o : cur) {
