@@ -225,23 +225,61 @@ __device__ double gates_block_sum(double v, double* red) {
     return red[0];
 }
 
-// grid (kEnergySlices, K): slice partials of sum_x |psi(x)|^2 C(x)
+// C(x) = sum_t w_t [x_u != x_v], every term
+__device__ __forceinline__ double cut_value(uint64_t x, const uint32_t* __restrict__ uv, const double* __restrict__ w,
+                                            uint32_t n_terms) {
+    double c = 0.0;
+    for (uint32_t t = 0; t < n_terms; ++t)
+        if (((x >> uv[2 * t]) ^ (x >> uv[2 * t + 1])) & 1) c += w[t];
+    return c;
+}
+
+// grid (kEnergySlices, K): slice partials of sum_x |psi(x)|^2 C(x).  A slice
+// of whole 256-amplitude rows (n >= 14) is visited by each thread in Gray
+// code order of the row index: one bit q of x flips per step, and C changes
+// only by the terms on qubit q (adj: per qubit, offsets [n + 1] then term
+// indices), so the work per amplitude is the degree of one qubit rather than
+// every term; C is recomputed from scratch every 64 steps (binary64 sums of
+// +-w_t, so no drift accumulates).
 template <class V>
 __global__ __launch_bounds__(256) void k_gates_energy(const V* __restrict__ psi, uint32_t n,
                                                       const uint32_t* __restrict__ uv, const double* __restrict__ w,
-                                                      uint32_t n_terms, double* __restrict__ part) {
+                                                      uint32_t n_terms, const uint32_t* __restrict__ adj,
+                                                      double* __restrict__ part) {
     __shared__ double red[kGateThreads];
     const uint64_t N = 1ull << n;
     const uint64_t per = (N + kEnergySlices - 1) / kEnergySlices;
     const uint64_t a = min<uint64_t>(N, blockIdx.x * per), b = min<uint64_t>(N, a + per);
     const V* base = psi + (uint64_t)blockIdx.y * N;
     double s = 0.0;
-    for (uint64_t x = a + threadIdx.x; x < b; x += kGateThreads) {
+    if (per % kGateThreads == 0 && a + per <= N) {
+        const uint32_t rows = (uint32_t)(per / kGateThreads);   // a power of two; a is a multiple of per
+        uint64_t x = a + threadIdx.x;
         double c = 0.0;
-        for (uint32_t t = 0; t < n_terms; ++t)
-            if (((x >> uv[2 * t]) ^ (x >> uv[2 * t + 1])) & 1) c += w[t];
-        const V v = base[x];
-        s += ((double)v.x * v.x + (double)v.y * v.y) * c;
+        for (uint32_t k = 0; k < rows; ++k) {
+            if (k) {
+                const uint32_t q = 8 + __builtin_ctz(k);
+                if ((k & 63u) == 0) {
+                    x ^= 1ull << q;
+                    c = cut_value(x, uv, w, n_terms);
+                } else {
+                    for (uint32_t e = adj[q]; e < adj[q + 1]; ++e) {
+                        const uint32_t t = adj[n + 1 + e];
+                        c += (((x >> uv[2 * t]) ^ (x >> uv[2 * t + 1])) & 1) ? -w[t] : w[t];
+                    }
+                    x ^= 1ull << q;
+                }
+            } else {
+                c = cut_value(x, uv, w, n_terms);
+            }
+            const V v = base[x];
+            s += ((double)v.x * v.x + (double)v.y * v.y) * c;
+        }
+    } else {
+        for (uint64_t x = a + threadIdx.x; x < b; x += kGateThreads) {
+            const V v = base[x];
+            s += ((double)v.x * v.x + (double)v.y * v.y) * cut_value(x, uv, w, n_terms);
+        }
     }
     const double tot = gates_block_sum(s, red);
     if (threadIdx.x == 0) part[(uint64_t)blockIdx.y * kEnergySlices + blockIdx.x] = tot;
@@ -286,7 +324,7 @@ template <class V> void run_gates(stn_plan* p, stn_batch* b, hipStream_t s, cons
     }
     hipLaunchKernelGGL(k_gates_energy<V>, dim3(kEnergySlices, K), dim3(kGateThreads), 0, s, psi, n,
                        p->d_obs.as<uint32_t>(), p->d_obs_w.as<double>(), (uint32_t)p->obs_u.size(),
-                       b->d_gates_part.as<double>());
+                       p->d_obs_adj.as<uint32_t>(), b->d_gates_part.as<double>());
     STN_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_gates_energy_sum, dim3((K + kGateThreads - 1) / kGateThreads), dim3(kGateThreads), 0, s,
                        b->d_gates_part.as<double>(), K, b->d_energy.as<double>());

@@ -184,6 +184,7 @@ struct stn_plan {
     stn::DevBuf d_gate_dx;           // uint64 deterministic X mask applied after each gate (tiled lowering)
     stn::DevBuf d_obs;               // observable: u, v (uint32 pairs)
     stn::DevBuf d_obs_w;             // weights (double)
+    stn::DevBuf d_obs_adj;           // observable terms per qubit: offsets [n + 1], then term indices
 
     // SV_LDS lowering
     std::vector<stn::LdsOp> lds_ops;

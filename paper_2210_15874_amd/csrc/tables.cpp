@@ -71,6 +71,23 @@ void upload_plan_tables(stn_plan* p, hipStream_t s) {
     w.push_back(0);
     up(p->d_obs, a, uv, s);
     up(p->d_obs_w, a, w, s);
+    {
+        // terms per qubit (each term under both of its qubits)
+        std::vector<uint32_t> adj(p->n + 1, 0), terms;
+        for (size_t t = 0; t < p->obs_u.size(); ++t) {
+            adj[p->obs_u[t] + 1]++;
+            adj[p->obs_v[t] + 1]++;
+        }
+        for (uint32_t q = 0; q < p->n; ++q) adj[q + 1] += adj[q];
+        terms.resize(adj[p->n]);
+        std::vector<uint32_t> fill(adj.begin(), adj.end() - 1);
+        for (size_t t = 0; t < p->obs_u.size(); ++t) {
+            terms[fill[p->obs_u[t]]++] = (uint32_t)t;
+            terms[fill[p->obs_v[t]]++] = (uint32_t)t;
+        }
+        adj.insert(adj.end(), terms.begin(), terms.end());
+        up(p->d_obs_adj, a, adj, s);
+    }
 
     if (p->kind == STN_PLAN_SV_LDS || p->kind == STN_PLAN_SV_GATES) {
         std::vector<LdsOp> ops = p->lds_ops, sops = p->site_ops;
