@@ -5,6 +5,8 @@
 #include <cstring>
 #include <new>
 
+#include <mutex>
+
 #include "stn_internal.h"
 
 namespace stn {
@@ -48,6 +50,68 @@ void Allocator::release(void* p) const {
     if (!p) return;
     if (ffn) ffn(p, ctx);
     else (void)hipFree(p);
+}
+
+namespace {
+// released pinned buffers (pointer, bytes); never destroyed, so that no
+// hipHostFree runs after the runtime has shut down at process exit
+struct PinnedPool {
+    std::mutex m;
+    std::vector<std::pair<void*, size_t>> bufs;
+    size_t total = 0;
+};
+PinnedPool& pinned_pool() {
+    static PinnedPool* pool = new PinnedPool();
+    return *pool;
+}
+constexpr size_t kPinnedPoolBytes = size_t(2) << 30;
+}  // namespace
+
+void HostBuf::reset() {
+    if (!p) return;
+    PinnedPool& pool = pinned_pool();
+    {
+        std::lock_guard<std::mutex> lk(pool.m);
+        if (pool.total + bytes <= kPinnedPoolBytes) {
+            pool.bufs.emplace_back(p, bytes);
+            pool.total += bytes;
+            p = nullptr;
+            bytes = 0;
+            return;
+        }
+    }
+    (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+void HostBuf::ensure(size_t nbytes) {
+    if (p && bytes >= nbytes) return;
+    reset();
+    const size_t want = nbytes ? nbytes : 1;
+    {
+        // the smallest pooled buffer that is large enough
+        PinnedPool& pool = pinned_pool();
+        std::lock_guard<std::mutex> lk(pool.m);
+        size_t best = pool.bufs.size();
+        for (size_t i = 0; i < pool.bufs.size(); ++i)
+            if (pool.bufs[i].second >= want && (best == pool.bufs.size() || pool.bufs[i].second < pool.bufs[best].second))
+                best = i;
+        if (best < pool.bufs.size()) {
+            p = pool.bufs[best].first;
+            bytes = pool.bufs[best].second;
+            pool.total -= bytes;
+            pool.bufs.erase(pool.bufs.begin() + (ptrdiff_t)best);
+            return;
+        }
+    }
+    void* q = nullptr;
+    if (hipHostMalloc(&q, want) != hipSuccess || !q) {
+        (void)hipGetLastError();
+        fail(STN_E_OOM, "pinned host allocation of " + std::to_string(nbytes) + " bytes failed");
+    }
+    p = q;
+    bytes = want;
 }
 
 void upload(DevBuf& d, const Allocator* a, const void* host, size_t bytes, hipStream_t s) {
@@ -702,21 +766,21 @@ stn_status stn_accum_read(stn_accum* a, stn_result* out, void* stream) {
         double st[4] = {0, 0, 0, 0};
         accum_finish_energy(a, s);
         if ((p->opts.outputs & STN_OUT_ENERGY) && a->k_done) {
-            a->h_energies.resize(a->k_done);
-            STN_HIP(hipMemcpyAsync(a->h_energies.data(), a->d_egather.p, a->k_done * 8, hipMemcpyDeviceToHost, s));
-            out->energies = a->h_energies.data();
+            a->h_energies.ensure(a->k_done * 8);
+            STN_HIP(hipMemcpyAsync(a->h_energies.p, a->d_egather.p, a->k_done * 8, hipMemcpyDeviceToHost, s));
+            out->energies = a->h_energies.as<double>();
         }
         if (p->opts.outputs & (STN_OUT_DIAG | STN_OUT_RHO)) {
             if (p->opts.outputs & STN_OUT_RHO) a->d_rho_out.ensure(&p->alloc, N * N * 16);
             a->d_diag_out.ensure(&p->alloc, N * 8);
             launch_finish_dense(a, s);
-            a->h_diag.resize(N);
-            STN_HIP(hipMemcpyAsync(a->h_diag.data(), a->d_diag_out.p, N * 8, hipMemcpyDeviceToHost, s));
-            out->diag = a->h_diag.data();
+            a->h_diag.ensure(N * 8);
+            STN_HIP(hipMemcpyAsync(a->h_diag.p, a->d_diag_out.p, N * 8, hipMemcpyDeviceToHost, s));
+            out->diag = a->h_diag.as<double>();
             if (p->opts.outputs & STN_OUT_RHO) {
-                a->h_rho.resize(N * N * 2);
-                STN_HIP(hipMemcpyAsync(a->h_rho.data(), a->d_rho_out.p, N * N * 16, hipMemcpyDeviceToHost, s));
-                out->rho = a->h_rho.data();
+                a->h_rho.ensure(N * N * 16);
+                STN_HIP(hipMemcpyAsync(a->h_rho.p, a->d_rho_out.p, N * N * 16, hipMemcpyDeviceToHost, s));
+                out->rho = a->h_rho.as<double>();
             }
         }
         STN_HIP(hipMemcpyAsync(st, a->d_stats.p, 4 * 8, hipMemcpyDeviceToHost, s));

@@ -60,6 +60,23 @@ struct DevBuf {
     template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
+// Pinned host memory, grown as needed: device-to-host copies into it run at
+// the link's rate instead of through a pageable staging copy.  Pinning
+// hundreds of MiB costs tens of milliseconds, so released buffers go to a
+// process-wide pool (at most 2 GiB) from which the next ensure() takes one;
+// a buffer belongs to one owner at a time.
+struct HostBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    HostBuf() = default;
+    HostBuf(const HostBuf&) = delete;
+    HostBuf& operator=(const HostBuf&) = delete;
+    ~HostBuf() { reset(); }
+    void reset();                 // back to the pool (or freed when the pool is full)
+    void ensure(size_t nbytes);   // throws STN_E_OOM when the allocation fails
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
 void upload(DevBuf& d, const Allocator* a, const void* host, size_t bytes, hipStream_t s);
 
 // ---------------------------------------------------------------- plan data
@@ -269,7 +286,7 @@ struct stn_accum {
     stn::DevBuf d_egather;           // double [k_done]: energies in trajectory order
     stn::DevBuf d_cdf;               // double [2^n]: running sums of d_diag (bitstring sampling)
     stn::DevBuf d_parts;             // double [2^n / 2048]: chunk sums of sigma (its trace)
-    std::vector<double> h_rho, h_diag, h_energies;
+    stn::HostBuf h_rho, h_diag, h_energies;   // pinned copies returned by stn_accum_read
 };
 
 namespace stn {
