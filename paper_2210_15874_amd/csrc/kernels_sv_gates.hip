@@ -176,11 +176,21 @@ __global__ __launch_bounds__(kTileThreads) void k_gates_tile(V* __restrict__ psi
             }
         }
         __syncthreads();
-        for (uint32_t i = 0; i < g.n_ops; ++i) {
+        constexpr uint32_t kU = sizeof(V) > 8 ? 2u : 8u;
+        for (uint32_t i = 0; i < g.n_ops;) {
             const LdsOp o = ops[i];
-            if (o.kind == OP_IDENT) continue;   // uniform: no barrier needed
-            apply_lds_op<V, (sizeof(V) > 8 ? 2u : 8u)>(tile, T, o, vals, tid, kTileThreads);
+            if (o.kind == OP_IDENT) {   // uniform: no barrier needed
+                ++i;
+                continue;
+            }
+            // a run of diagonal operators (this trajectory's, so uniform) in one pass
+            uint32_t j = i + 1;
+            if (op_is_diagonal(o))
+                while (j < g.n_ops && op_is_diagonal(ops[j])) ++j;
+            if (j - i > 1) apply_lds_diag_run<V, kU>(tile, T, ops + i, j - i, vals, tid, kTileThreads);
+            else apply_lds_op<V, kU>(tile, T, o, vals, tid, kTileThreads);
             __syncthreads();
+            i = j;
         }
         if constexpr (kPairs) {
 #pragma unroll

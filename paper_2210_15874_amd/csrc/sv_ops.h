@@ -155,4 +155,47 @@ __device__ __forceinline__ void apply_lds_op(V* psi, uint32_t N, const LdsOp& o,
     }
 }
 
+// diagonal operators (and the identity): applied element by element
+__device__ __forceinline__ bool op_is_diagonal(const LdsOp& o) {
+    return o.kind == OP_DIAG1 || o.kind == OP_DIAG2 || (o.kind == OP_PAULI && o.xmask == 0) || o.kind == OP_IDENT;
+}
+
+// A run of diagonal operators ops[0 .. cnt) in one pass over the tile: each
+// element is read once, multiplied by every operator's factor in order, and
+// written once (instead of one pass and one barrier per operator).
+template <class V, uint32_t kOpUnroll = 1>
+__device__ __forceinline__ void apply_lds_diag_run(V* psi, uint32_t N, const LdsOp* ops, uint32_t cnt,
+                                                   const V* __restrict__ vals, uint32_t tid, uint32_t nthreads) {
+    for (uint32_t i0 = tid; i0 < N; i0 += kOpUnroll * nthreads) {
+        V a[kOpUnroll];
+#pragma unroll
+        for (uint32_t u = 0; u < kOpUnroll; ++u)
+            if (i0 + u * nthreads < N) a[u] = psi[i0 + u * nthreads];
+        for (uint32_t k = 0; k < cnt; ++k) {
+            const LdsOp o = ops[k];
+            if (o.kind == OP_DIAG1) {
+                const V d0 = vals[o.mat], d1 = vals[o.mat + 1];
+#pragma unroll
+                for (uint32_t u = 0; u < kOpUnroll; ++u) a[u] = op_cmul(((i0 + u * nthreads) >> o.q0) & 1 ? d1 : d0, a[u]);
+            } else if (o.kind == OP_DIAG2) {
+                const V d0 = vals[o.mat], d1 = vals[o.mat + 1], d2 = vals[o.mat + 2], d3 = vals[o.mat + 3];
+#pragma unroll
+                for (uint32_t u = 0; u < kOpUnroll; ++u) {
+                    const uint32_t i = i0 + u * nthreads;
+                    const bool qa = (i >> o.q0) & 1, qb = (i >> o.q1) & 1;
+                    const V lo = qa ? d1 : d0, hi = qa ? d3 : d2;
+                    a[u] = op_cmul(qb ? hi : lo, a[u]);
+                }
+            } else if (o.kind == OP_PAULI) {
+                const uint32_t z = (uint32_t)o.zmask;
+#pragma unroll
+                for (uint32_t u = 0; u < kOpUnroll; ++u) a[u] = op_neg_if(a[u], __popc((i0 + u * nthreads) & z) & 1);
+            }
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kOpUnroll; ++u)
+            if (i0 + u * nthreads < N) psi[i0 + u * nthreads] = a[u];
+    }
+}
+
 }  // namespace stn
