@@ -185,10 +185,38 @@ __global__ __launch_bounds__(kTileThreads) void k_gates_tile(V* __restrict__ psi
             }
             // a run of diagonal operators (this trajectory's, so uniform) in one pass
             uint32_t j = i + 1;
-            if (op_is_diagonal(o))
+            if (op_is_diagonal(o)) {
                 while (j < g.n_ops && op_is_diagonal(ops[j])) ++j;
-            if (j - i > 1) apply_lds_diag_run<V, kU>(tile, T, ops + i, j - i, vals, tid, kTileThreads);
-            else apply_lds_op<V, kU>(tile, T, o, vals, tid, kTileThreads);
+                if (j - i > 1) apply_lds_diag_run<V, kU>(tile, T, ops + i, j - i, vals, tid, kTileThreads);
+                else apply_lds_op<V, kU>(tile, T, o, vals, tid, kTileThreads);
+                __syncthreads();
+                i = j;
+                continue;
+            }
+            // up to three one-qubit dense operators on distinct qubits (identities
+            // between them skipped) in one pass
+            if (o.kind == OP_DENSE1) {
+                constexpr int kMaxRun = sizeof(V) > 8 ? 2 : 3;   // complex128: registers for 2
+                uint32_t j1 = 0, j2 = 0;   // the run's second and third operator
+                int cnt = 1;
+                uint32_t used = 1u << o.q0;
+                for (; j < g.n_ops && cnt < kMaxRun; ++j) {
+                    const LdsOp& n2 = ops[j];
+                    if (n2.kind == OP_IDENT) continue;
+                    if (n2.kind != OP_DENSE1 || ((used >> n2.q0) & 1u)) break;
+                    used |= 1u << n2.q0;
+                    if (cnt == 1) j1 = j;
+                    else j2 = j;
+                    ++cnt;
+                }
+                if (cnt == 3) apply_lds_dense1_run<V, 3>(tile, T, o, ops[j1], ops[j2], vals, tid, kTileThreads);
+                else if (cnt == 2) apply_lds_dense1_run<V, 2>(tile, T, o, ops[j1], o, vals, tid, kTileThreads);
+                else apply_lds_op<V, kU>(tile, T, o, vals, tid, kTileThreads);
+                __syncthreads();
+                i = j;
+                continue;
+            }
+            apply_lds_op<V, kU>(tile, T, o, vals, tid, kTileThreads);
             __syncthreads();
             i = j;
         }

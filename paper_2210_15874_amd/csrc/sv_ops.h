@@ -198,4 +198,61 @@ __device__ __forceinline__ void apply_lds_diag_run(V* psi, uint32_t N, const Lds
     }
 }
 
+// Up to three one-qubit dense operators on distinct qubits (in order, no
+// identities between them) in one pass over groups of 2^K elements: a group
+// holds every combination of the K qubits, so applying the operators one
+// after another inside it does the same arithmetic, element by element, as
+// one pass per operator.
+template <class V, int K>
+__device__ __forceinline__ void apply_lds_dense1_run(V* psi, uint32_t N, const LdsOp& o0, const LdsOp& o1,
+                                                     const LdsOp& o2, const V* __restrict__ vals, uint32_t tid,
+                                                     uint32_t nthreads) {
+    const uint32_t q[3] = {o0.q0, o1.q0, o2.q0};
+    const uint32_t mat[3] = {o0.mat, o1.mat, o2.mat};
+    uint32_t qs[K];   // the qubits in increasing order (for inserting the zero bits)
+#pragma unroll
+    for (int t = 0; t < K; ++t) qs[t] = q[t];
+#pragma unroll
+    for (int a = 0; a < K; ++a)
+#pragma unroll
+        for (int b = a + 1; b < K; ++b)
+            if (qs[b] < qs[a]) { const uint32_t x = qs[a]; qs[a] = qs[b]; qs[b] = x; }
+    V m[K][4];
+#pragma unroll
+    for (int t = 0; t < K; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) m[t][e] = vals[mat[t] + e];
+    for (uint32_t g = tid; g < (N >> K); g += nthreads) {
+        uint32_t base = g;
+#pragma unroll
+        for (int t = 0; t < K; ++t) base = op_ins0(base, qs[t]);
+        V v[1 << K];
+#pragma unroll
+        for (uint32_t j = 0; j < (1u << K); ++j) {
+            uint32_t i = base;
+#pragma unroll
+            for (int t = 0; t < K; ++t)
+                if ((j >> t) & 1u) i |= 1u << q[t];
+            v[j] = psi[i];
+        }
+#pragma unroll
+        for (int t = 0; t < K; ++t)
+#pragma unroll
+            for (uint32_t j = 0; j < (1u << K); ++j) {
+                if ((j >> t) & 1u) continue;
+                const V a = v[j], c = v[j | (1u << t)];
+                v[j] = op_cadd(op_cmul(m[t][0], a), op_cmul(m[t][1], c));
+                v[j | (1u << t)] = op_cadd(op_cmul(m[t][2], a), op_cmul(m[t][3], c));
+            }
+#pragma unroll
+        for (uint32_t j = 0; j < (1u << K); ++j) {
+            uint32_t i = base;
+#pragma unroll
+            for (int t = 0; t < K; ++t)
+                if ((j >> t) & 1u) i |= 1u << q[t];
+            psi[i] = v[j];
+        }
+    }
+}
+
 }  // namespace stn
