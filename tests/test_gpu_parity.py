@@ -224,6 +224,41 @@ def test_batching_does_not_change_results(precision):
         assert r["energy_mean"] == out[0]["energy_mean"] and r["energy_se"] == out[0]["energy_se"]
 
 
+def test_accumulator_read_buffers_not_shared():
+    """rho_hat, sigma and the energies are read back into pinned host
+    buffers taken from a pool of released ones: two live accumulators never
+    share one, and a buffer released by a closed accumulator serves the next
+    one correctly (each read checked against a fresh accumulator's)."""
+    stn = stn_mod()
+    from workloads import config_problem
+    pr = config_problem(0)
+    pl = stn.Plan(pr, outputs=stn.OUT_RHO | stn.OUT_DIAG | stn.OUT_ENERGY)
+
+    def run(k0, K):
+        acc = pl.accum()
+        b = pl.sample(pr.seed, k0, K)
+        pl.contract(b)
+        pl.reduce(b, acc)
+        b.close()
+        return acc
+
+    a1, a2 = run(0, 40), run(40, 40)
+    r1, r2 = a1.read(), a2.read()
+    r1b = a1.read()                       # a2's read must not have overwritten a1's buffers
+    for key in ("rho", "diag", "energies"):
+        np.testing.assert_array_equal(r1b[key], r1[key])
+    assert np.abs(r1["rho"] - r2["rho"]).max() > 1e-6   # different trajectories
+    a1.close()
+    a3 = run(0, 40)                       # may take a1's released buffers
+    r3 = a3.read()
+    for key in ("rho", "diag", "energies"):
+        np.testing.assert_array_equal(r3[key], r1[key])
+    np.testing.assert_array_equal(a2.read()["rho"], r2["rho"])
+    a2.close()
+    a3.close()
+    pl.close()
+
+
 def test_reduce_same_range_twice_rejected():
     stn = stn_mod()
     from workloads import config_problem
