@@ -493,4 +493,11 @@ void launch_finish_dense(stn_accum* a, hipStream_t s) {
     STN_HIP(hipGetLastError());
 }
 
+// loads this file's device code (the runtime does so at the first use of
+// one of its kernels)
+void warm_code_reduce() {
+    hipFuncAttributes a{};
+    (void)hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_stats));
+}
+
 }  // namespace stn

@@ -109,4 +109,11 @@ void launch_frame(stn_plan* p, stn_batch* b, hipStream_t s) {
     prof_end(p, STN_K_FRAME, s, (double)b->K * (S + 4.0 * b->words + 16.0), 0.0);
 }
 
+// loads this file's device code (the runtime does so at the first use of
+// one of its kernels)
+void warm_code_sample() {
+    hipFuncAttributes a{};
+    (void)hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_sample));
+}
+
 }  // namespace stn

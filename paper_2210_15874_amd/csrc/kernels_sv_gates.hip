@@ -461,4 +461,11 @@ void launch_sv_gates(stn_plan* p, stn_batch* b, hipStream_t s) {
              0.0);
 }
 
+// loads this file's device code (the runtime does so at the first use of
+// one of its kernels)
+void warm_code_sv_gates() {
+    hipFuncAttributes a{};
+    (void)hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_gates_tile<float2>));
+}
+
 }  // namespace stn

@@ -285,4 +285,11 @@ void launch_sv_lds_many(stn_plan* const* plans, stn_batch* const* batches, uint3
     }
 }
 
+// loads this file's device code (the runtime does so at the first use of
+// one of its kernels)
+void warm_code_sv_lds() {
+    hipFuncAttributes a{};
+    (void)hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_sv_lds<float, 256>));
+}
+
 }  // namespace stn

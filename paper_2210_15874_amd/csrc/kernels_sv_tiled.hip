@@ -801,4 +801,11 @@ void launch_sv_tiled(stn_plan* p, stn_batch* b, hipStream_t s) {
 
 uint32_t tiled_variants(const stn_plan* p) { return p->opts.precision == 128 ? 1u : 3u; }
 
+// loads this file's device code (the runtime does so at the first use of
+// one of its kernels)
+void warm_code_sv_tiled() {
+    hipFuncAttributes a{};
+    (void)hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_sv_pass<4, true, false>));
+}
+
 }  // namespace stn

@@ -399,4 +399,11 @@ void launch_sv_tiled128(stn_plan* p, stn_batch* b, hipStream_t s) {
     }
 }
 
+// loads this file's device code (the runtime does so at the first use of
+// one of its kernels)
+void warm_code_sv_tiled128() {
+    hipFuncAttributes a{};
+    (void)hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_sv128_pass));
+}
+
 }  // namespace stn

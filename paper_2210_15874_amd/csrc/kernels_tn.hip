@@ -909,4 +909,11 @@ void launch_lightcone(stn_plan* p, stn_batch* b, hipStream_t s) {
 
 uint32_t tn_variants() { return kTnVariants; }
 
+// loads this file's device code (the runtime does so at the first use of
+// one of its kernels)
+void warm_code_tn() {
+    hipFuncAttributes a{};
+    (void)hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_tn<float>));
+}
+
 }  // namespace stn

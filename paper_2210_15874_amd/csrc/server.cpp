@@ -390,6 +390,7 @@ struct Device {
 
     void init() {
         STN_HIP(hipSetDevice(sv->device));
+        warm_device_code();
         sv->pool->init();
         int c = 0;
         STN_HIP(hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, sv->device));

@@ -340,6 +340,25 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
 // a CPU.
 extern thread_local uint32_t tl_plan_threads;
 
+// load every kernel source file's device code on the current device, so that
+// a job server's first jobs do not pay for it
+void warm_code_sample();
+void warm_code_sv_lds();
+void warm_code_sv_gates();
+void warm_code_sv_tiled();
+void warm_code_sv_tiled128();
+void warm_code_reduce();
+void warm_code_tn();
+inline void warm_device_code() {
+    warm_code_sample();
+    warm_code_sv_lds();
+    warm_code_sv_gates();
+    warm_code_sv_tiled();
+    warm_code_sv_tiled128();
+    warm_code_reduce();
+    warm_code_tn();
+}
+
 // launchers (kernels_*.hip)
 void launch_sample(stn_plan* p, stn_batch* b, uint64_t seed, hipStream_t s);
 void launch_frame(stn_plan* p, stn_batch* b, hipStream_t s);
