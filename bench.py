@@ -125,11 +125,11 @@ def cpu_baseline(problem_cfg, reps=2):
                       f"({wall:.0f} s wall); per-trajectory time weighted by the circuit's gate counts"}
 
 
-def measured_traffic(kernel_source, launch_shape, per_launch):
+def measured_traffic(kernel_source, tile_bits, launch_shape, per_launch):
     """HBM bytes per launch of the tiled pass from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary, or None if the kernel source has changed
-    since the counters were taken or they were taken with another launch
-    shape or another number of trajectories per launch."""
+    since the counters were taken or they were taken with another tile width,
+    launch shape or number of trajectories per launch."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "sv_pass_qaoa_n26_p4_traffic.json")
     if not os.path.exists(path):
@@ -139,7 +139,8 @@ def measured_traffic(kernel_source, launch_shape, per_launch):
     with open(os.path.join(ROOT, kernel_source), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != t["source_sha256"]:
             return None
-    if t.get("launch_shape") != launch_shape or t.get("trajectories_per_launch") != per_launch:
+    if (t.get("tile_bits") != tile_bits or t.get("launch_shape") != launch_shape
+            or t.get("trajectories_per_launch") != per_launch):
         return None
     return t["traffic_bytes_per_launch"] / 1e9
 
@@ -369,11 +370,13 @@ def main():
                    "contraction": "complex64 (FP32), FP64 reductions", "plan": info["plan_name"],
                    "trajectories_per_launch": B, "passes_per_trajectory": info["n_passes"],
                    "stored_amplitudes_per_trajectory": 2 ** (problem.n_qubits - info["half_state"]),
+                   "tile_qubits": info["tile_bits"],
                    "launch_shape": {"chosen": tune["chosen"], "ms_per_variant": tune["ms"]},
                    "plan_ms": plan_ms},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None,
-                     "traffic": measured_traffic("paper_2210_15874_amd/csrc/kernels_sv_tiled.hip", tune["chosen"], B)
+                     "traffic": measured_traffic("paper_2210_15874_amd/csrc/kernels_sv_tiled.hip", info["tile_bits"],
+                                                 tune["chosen"], B)
                      if kname == "sv_pass" else None, "traffic_unit": "GB per launch",
                      "launches": kern["launches"], "avg_launch_ms": kern["ms"] / max(1, kern["launches"]),
                      "bytes_per_launch": kern["bytes"] / max(1, kern["launches"])},

@@ -184,6 +184,10 @@ typedef struct {
                                sets) commutes with X on all qubits and starts from a state it fixes, so
                                psi(~z) = psi(z) exactly, and the ZZ observable takes equal values at z and ~z;
                                needs n >= 15 (complex64) / 13 (complex128) */
+    uint32_t sv_tile_bits;  /* complex64 tiled plans: qubits per tile, 14 (512-thread workgroups, two resident per CU)
+                               or 15 (1024 threads, one per CU; the strided tile of n <= 26 then reads 128-byte
+                               runs); 0 (default) = 15 for n >= 25, else 14.  15 needs n >= 15.  Other values, or
+                               nonzero on a complex128 plan: STN_E_INVALID */
 } stn_plan_opts;
 
 typedef struct {
@@ -215,6 +219,7 @@ typedef struct {
                                stopped at the first step above the rank cap, before finishing the order */
     uint32_t half_state;    /* tiled plan keeps half the amplitudes (see stn_plan_opts.sv_full_state); bytes_per_traj
                                and peak_bytes count those */
+    uint32_t tile_bits;     /* tiled plan: qubits per tile (see stn_plan_opts.sv_tile_bits); 0 for other lowerings */
 } stn_plan_stats;
 
 typedef struct {
@@ -255,6 +260,10 @@ stn_status stn_plan_create(const stn_circuit* circuit, const stn_noise_model* no
                            const stn_observable* observable, const stn_plan_opts* opts,
                            stn_plan** out);
 stn_status stn_plan_info(const stn_plan* plan, stn_plan_stats* out);
+/* Releases the caller's handle (NULL: no-op).  Batches and accumulators made
+ * from the plan keep it alive: its memory goes with the last of them, so the
+ * handles may be destroyed in any order.  The plan must not be used through
+ * this handle afterwards. */
 void stn_plan_destroy(stn_plan* plan);
 
 /* Noise-site table of a plan (Sec. III-G selection rule): *n_ops receives
@@ -298,6 +307,7 @@ stn_status stn_contract(stn_plan* plan, stn_batch* batch, void* stream);
  * doubles; complex64 batches are widened).  Either pointer may be NULL. */
 stn_status stn_batch_results(const stn_batch* batch, double* energies, double* states);
 uint32_t stn_batch_size(const stn_batch* batch);
+/* Syncs the device, frees the batch and releases its hold on the plan. */
 void stn_batch_destroy(stn_batch* batch);
 
 /* Per-kernel timing of a plan's launches, taken with HIP events recorded on
@@ -385,6 +395,7 @@ stn_status stn_reduce(stn_plan* plan, stn_batch* batch, stn_accum* acc, void* st
 /* Finishes the fixed-order reductions and copies the result to host memory
  * owned by the accumulator (valid until the next read or destroy). Syncs. */
 stn_status stn_accum_read(stn_accum* acc, stn_result* out, void* stream);
+/* Syncs the device, frees the accumulator and releases its hold on the plan. */
 void stn_accum_destroy(stn_accum* acc);
 
 /* Bitstring samples from the ensemble's probability vector (Sec. III-G:

@@ -93,7 +93,8 @@ class PlanOpts(C.Structure):
                 ("max_batch", C.c_uint32), ("hbm_budget", C.c_uint64), ("order_restarts", C.c_uint32),
                 ("order_seed", C.c_uint64), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
                 ("alloc_ctx", C.c_void_p), ("lc_max_rank", C.c_uint32), ("lc_slice_bits", C.c_uint32),
-                ("lc_order_fn", ORDER_FN), ("lc_order_ctx", C.c_void_p), ("sv_full_state", C.c_uint32)]
+                ("lc_order_fn", ORDER_FN), ("lc_order_ctx", C.c_void_p), ("sv_full_state", C.c_uint32),
+                ("sv_tile_bits", C.c_uint32)]
 
 
 class PlanStats(C.Structure):
@@ -104,7 +105,8 @@ class PlanStats(C.Structure):
                 ("lc_flops_per_traj", C.c_double), ("variant", C.c_uint32), ("tuned", C.c_uint32),
                 ("graphs", C.c_uint32), ("graph_captures", C.c_uint64), ("graph_replays", C.c_uint64),
                 ("lc_slices", C.c_uint32), ("lc_slice_bits", C.c_uint32), ("est_s_per_traj", C.c_double),
-                ("lc_group", C.c_uint32), ("lc_width_lower_bound", C.c_uint32), ("half_state", C.c_uint32)]
+                ("lc_group", C.c_uint32), ("lc_width_lower_bound", C.c_uint32), ("half_state", C.c_uint32),
+                ("tile_bits", C.c_uint32)]
 
 
 class TuneResult(C.Structure):
@@ -288,7 +290,7 @@ class Plan:
 
     def __init__(self, problem, outputs=OUT_ENERGY, precision=64, plan_kind=PLAN_AUTO, max_batch=0,
                  hbm_budget=0, torch_allocator=True, device=0, lc_max_rank=0, lc_slice_bits=0, lc_order=None,
-                 full_state=False):
+                 full_state=False, tile_bits=0):
         self.lib = load()
         self.problem = problem
         self.n = problem.n_qubits
@@ -305,6 +307,7 @@ class Plan:
         opts.lc_max_rank = lc_max_rank
         opts.lc_slice_bits = lc_slice_bits
         opts.sv_full_state = 1 if full_state else 0
+        opts.sv_tile_bits = tile_bits
         self._order_cb = None
         if lc_order is not None:
             self._order_cb = _order_callback(lc_order)

@@ -6,15 +6,17 @@
 // (Pauli-frame rewrite, see kernels_sample.hip) followed by a final Pauli
 // frame F.  The circuit is H on every qubit, then layers of a diagonal block
 // (zz gates, angle = mult * base) and a mixer block (rx per qubit).  The state
-// psi[b][z] (complex64) is updated in place by passes over tiles of 2^14
-// amplitudes: 14 storage bits vary inside a tile, the others are fixed.  The
+// psi[b][z] (complex64) is updated in place by passes over tiles of 2^14 or
+// 2^15 amplitudes: 14 or 15 storage bits vary inside a tile, the others are
+// fixed.  The
 // planner's schedule (plan.cpp, schedule_tiled) alternates the order of a
 // layer's tiles so that one pass can rotate the last tile of layer l, apply
 // the diagonal of layer l+1 and rotate the same tile for layer l+1: n = 26,
 // p = 4 costs 5 passes per trajectory.
 //
-// Inside a workgroup (512 threads) the tile lives in registers, 32 amplitudes
-// per thread, in three layouts exchanged through LDS; in each layout the
+// Inside a workgroup (512 threads for 14-qubit tiles, 1024 for 15-qubit ones)
+// the tile lives in registers, 32 amplitudes per thread, in three layouts
+// exchanged through LDS; in each layout the
 // thread's 5 register bits are the qubits it rotates.  A pass runs the
 // layouts L0 -> L1 -> L2 for its first segment and L2 -> L1 -> L0 for its
 // second.  The diagonal phase exp(-i base m(z)) with integer
@@ -42,9 +44,13 @@
 // Tiles that hold only two low storage bits read 32-byte runs; the four
 // workgroups that share each 128-byte line get tile indices x, x+8, x+16,
 // x+24, which the dispatcher places on the same XCD at the same time, so each
-// line comes from HBM once.  Workgroups are persistent: either one per CU,
-// prefetching the next tile into registers while working on the current one,
-// or two per CU with the exchange buffer halved (the launch-shape variants).
+// line comes from HBM once.  14-qubit tiles leave a second tile only two low
+// bits at n = 26; 15-qubit tiles leave it four (128-byte runs, whole lines).
+// Workgroups are persistent.  14-qubit tiles: either one per CU, prefetching
+// the next tile into registers while working on the current one, or two per
+// CU with the exchange buffer halved (the launch-shape variants).  15-qubit
+// tiles: one 1024-thread workgroup per CU, exchanging through the halved
+// (4-byte slot) buffer of the whole tile, 135 KB.
 #include <cmath>
 
 #include "stn_internal.h"
@@ -53,8 +59,8 @@ namespace stn {
 
 namespace {
 
-constexpr int kQ = 14;          // tile bits
-constexpr int kThreads = 512;   // 9 thread bits
+constexpr int kQ = 14;          // tile bits (15-qubit tiles: kQ + 1)
+constexpr int kThreads = 512;   // 9 thread bits (15-qubit tiles: 1024, 10)
 constexpr int kRegs = 32;       // 5 register bits
 constexpr int kMaxPhase = 511;  // phase table entries (2M+1) per diagonal
 constexpr int kMaxEdges = 512;  // zz gates of the pass's diagonals
@@ -67,6 +73,15 @@ __device__ constexpr int L1T[9] = {0, 6, 7, 8, 9, 10, 11, 12, 13};
 __device__ constexpr int L2R[5] = {0, 6, 7, 8, 9};
 __device__ constexpr int L2T[9] = {1, 2, 3, 4, 5, 10, 11, 12, 13};
 constexpr int hLR[3][5] = {{0, 10, 11, 12, 13}, {1, 2, 3, 4, 5}, {0, 6, 7, 8, 9}};
+// 15-qubit tiles (1024 threads): the three layouts' register bits partition
+// the tile bits, so tile bit 0 is a register bit in L0 only
+__device__ constexpr int M0R[5] = {0, 11, 12, 13, 14};
+__device__ constexpr int M0T[10] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 10};
+__device__ constexpr int M1R[5] = {1, 2, 3, 4, 5};
+__device__ constexpr int M1T[10] = {0, 6, 7, 8, 9, 10, 11, 12, 13, 14};
+__device__ constexpr int M2R[5] = {6, 7, 8, 9, 10};
+__device__ constexpr int M2T[10] = {0, 1, 2, 3, 4, 5, 11, 12, 13, 14};
+constexpr int hMR[3][5] = {{0, 11, 12, 13, 14}, {1, 2, 3, 4, 5}, {6, 7, 8, 9, 10}};
 
 // zz gates of one diagonal, split by where their qubits sit in a layout:
 // [0] both outside the registers, [1 + r] one in register bit r, [6] both in
@@ -77,7 +92,7 @@ struct DiagTab {
 };
 
 struct Pass2 {
-    uint32_t tb[kQ];            // qubit (storage bit) of tile-index bit i
+    uint32_t tb[kQ + 1];        // qubit (storage bit) of tile-index bit i
     uint64_t fixed_mask;        // storage bits outside the tile (half-state: the top one of a mirror tile excluded)
     uint64_t mirror;            // half-state tile holding qubit n-1: 1 << (n-1); else 0
     uint64_t half_mask;         // half-state: 2^(n-1) - 1
@@ -104,12 +119,16 @@ __host__ __device__ constexpr uint32_t pad(uint32_t t) { return t + 2u * ((t >> 
 // 2-adic valuations 0..4, i.e. 32 distinct banks of 32.
 constexpr int kLdsSlots4 = 16895;  // pad4(2^14 - 1) + 1
 __host__ __device__ constexpr uint32_t pad4(uint32_t t) { return t + ((t >> 5) & 1u) + 2u * (t >> 6); }
+// 15-qubit tiles exchange through the same map (their half-waves see tile
+// bits {1..5}, {0, 6..9} and {0..4}: again 32 distinct banks)
+constexpr int kLdsSlots4x15 = 33791;  // pad4(2^15 - 1) + 1
+static_assert(pad4(16383) + 1 == kLdsSlots4 && pad4(32767) + 1 == kLdsSlots4x15, "exchange buffer sizes");
 
-template <const int* T>
+template <const int* T, int NB>
 __device__ __forceinline__ uint32_t thread_part(uint32_t tid) {
     uint32_t t = 0;
 #pragma unroll
-    for (int b = 0; b < 9; ++b) t |= ((tid >> b) & 1u) << T[b];
+    for (int b = 0; b < NB; ++b) t |= ((tid >> b) & 1u) << T[b];
     return t;
 }
 
@@ -121,11 +140,11 @@ __device__ __forceinline__ uint32_t reg_part(int j) {
     return t;
 }
 
-template <const int* T>
+template <const int* T, int NB>
 __device__ __forceinline__ uint64_t storage_thread(const Pass2& P, uint32_t tid) {
     uint64_t z = 0;
 #pragma unroll
-    for (int b = 0; b < 9; ++b) z |= (uint64_t)((tid >> b) & 1u) << P.tb[T[b]];
+    for (int b = 0; b < NB; ++b) z |= (uint64_t)((tid >> b) & 1u) << P.tb[T[b]];
     return z;
 }
 
@@ -168,22 +187,22 @@ __device__ __forceinline__ void mix(float2 (&v)[kRegs], const float* tt) {
 
 // write registers in layout A, read them back in layout B; TWO: through a
 // buffer of 4-byte slots, real parts first
-template <bool TWO, const int* AR, const int* AT, const int* BR, const int* BT>
+template <bool TWO, int NB, const int* AR, const int* AT, const int* BR, const int* BT>
 __device__ __forceinline__ void exchange(float2 (&v)[kRegs], float* ldsf, uint32_t tid) {
     if constexpr (!TWO) {
         float2* lds = reinterpret_cast<float2*>(ldsf);
-        float2* wa = lds + pad(thread_part<AT>(tid));
+        float2* wa = lds + pad(thread_part<AT, NB>(tid));
 #pragma unroll
         for (int j = 0; j < kRegs; ++j) wa[pad(reg_part<AR>(j))] = v[j];
         __syncthreads();
-        const float2* rb = lds + pad(thread_part<BT>(tid));
+        const float2* rb = lds + pad(thread_part<BT, NB>(tid));
 #pragma unroll
         for (int j = 0; j < kRegs; ++j) v[j] = rb[pad(reg_part<BR>(j))];
         __syncthreads();
     } else {
         // the bases are recomputed here rather than kept live across the
         // pass (register budget of two workgroups per CU)
-        uint32_t ta = pad4(thread_part<AT>(tid)), tb = pad4(thread_part<BT>(tid));
+        uint32_t ta = pad4(thread_part<AT, NB>(tid)), tb = pad4(thread_part<BT, NB>(tid));
         asm volatile("" : "+v"(ta), "+v"(tb));
         float* wa = ldsf + ta;
         const float* rb = ldsf + tb;
@@ -268,8 +287,9 @@ __device__ __forceinline__ uint32_t tile_of(uint32_t x, uint32_t share) {
 // float4 = the amplitude pair of tile bit 0 (storage bit 0): z (bit 0 clear)
 // and z | 1.  MIR (a half-state tile holding qubit n-1): where z holds qubit
 // n-1 the pair is stored at ~z - 1 and ~z (so in the other order).  Qubit
-// n-1 is tile bit 13: register bit 4 of layout L0 (the upper 8 register
-// pairs) and thread bit 8 of layout L2 (threads 256..511, whole waves).
+// n-1 is the top tile bit: register bit 4 of layout L0 (the upper 8 register
+// pairs) and the top thread bit of layout L2 (the upper half of the
+// workgroup, whole waves).
 template <const int* R>
 __device__ __forceinline__ uint64_t reg_off(int jp, const Pass2& P, int nbits) {
     uint64_t off = 0;
@@ -289,7 +309,7 @@ __device__ __forceinline__ void load_tile(float2 (&v)[kRegs], const float2* st, 
             v[2 * jp + 1] = make_float2(w.z, w.w);
         }
     } else {
-        static_assert(R == L0R, "half-state tiles are loaded in layout L0");
+        static_assert(R == L0R || R == M0R, "half-state tiles are loaded in layout L0");
         const uint64_t rb = P.half_mask - 1u - z0;   // z0 holds no bit of qubit n-1 in L0
 #pragma unroll
         for (int jp = 0; jp < kRegs / 2; ++jp) {
@@ -327,7 +347,7 @@ __device__ __forceinline__ void store_tile(const float2 (&v)[kRegs], float2* st,
     };
     if constexpr (!MIR) {
         plain(z0, 4, 0, kRegs / 2);
-    } else if constexpr (R == L0R) {
+    } else if constexpr (R == L0R || R == M0R) {
         plain(z0, 3, 0, 8);
         mirrored(P.half_mask - 1u - z0, 3, 8, kRegs / 2);
     } else {
@@ -336,6 +356,28 @@ __device__ __forceinline__ void store_tile(const float2 (&v)[kRegs], float2* st,
             mirrored(P.half_mask - 1u - (z0 & P.half_mask), 4, 0, kRegs / 2);
         else
             plain(z0, 4, 0, kRegs / 2);
+    }
+}
+
+// Layout L2 of 15-qubit tiles: tile bit 0 is a thread bit, so each
+// amplitude is stored on its own (8 bytes; the 64 lanes of a wave cover 64
+// consecutive tile indices).  The wave's threads all hold qubit n-1 = 1, or
+// all 0 (top thread bit).
+template <const int* R, bool MIR>
+__device__ __forceinline__ void store_tile_elems(const float2 (&v)[kRegs], float2* st, uint64_t z0, const Pass2& P) {
+    auto off = [&](int j) {
+        uint64_t o = 0;
+#pragma unroll
+        for (int r = 0; r < 5; ++r) o |= (uint64_t)((j >> r) & 1) << P.tb[R[r]];
+        return o;
+    };
+    if (MIR && __builtin_amdgcn_readfirstlane((uint32_t)((z0 & P.mirror) != 0))) {
+        const uint64_t rc = P.half_mask - (z0 & P.half_mask);
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) st[rc - off(j)] = v[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) st[z0 | off(j)] = v[j];
     }
 }
 
@@ -400,8 +442,8 @@ __device__ __forceinline__ float energy_part(const float2 (&v)[kRegs], const Pas
 // TWO: two resident workgroups per CU (half the LDS, at most 128 registers,
 // no prefetch): one workgroup's loads and stores overlap the other's
 // arithmetic and exchanges.
-template <int FL, bool TWO, bool MIR>
-__global__ __launch_bounds__(kThreads, TWO ? 4 : 1) void k_sv_pass(float2* __restrict__ psi, const Pass2 P, uint32_t n,
+template <int Q, int FL, bool TWO, bool MIR>
+__global__ __launch_bounds__(Q == 15 ? 2 * kThreads : kThreads, (Q == 14 && TWO) ? 4 : 1) void k_sv_pass(float2* __restrict__ psi, const Pass2 P, uint32_t n,
                                                       uint32_t tiles_log2, uint32_t total,
                                                       const uint32_t* __restrict__ signs, uint32_t words,
                                                       const uint64_t* __restrict__ frame,
@@ -410,10 +452,22 @@ __global__ __launch_bounds__(kThreads, TWO ? 4 : 1) void k_sv_pass(float2* __res
                                                       const int2* __restrict__ eedges,
                                                       const double* __restrict__ ew,
                                                       double* __restrict__ partials) {
-    __shared__ __align__(16) float lds[TWO ? kLdsSlots4 : 2 * kLdsSlots];
+    // 15-qubit tiles: 1024 threads, exchange through 4-byte slots, no prefetch
+    static_assert(Q == 14 || (Q == 15 && TWO), "15-qubit tiles use the split exchange");
+    constexpr int NT = Q == 15 ? 2 * kThreads : kThreads, NB = Q == 15 ? 10 : 9;
+    constexpr const int* R0 = Q == 15 ? M0R : L0R;
+    constexpr const int* T0 = Q == 15 ? M0T : L0T;
+    constexpr const int* R1 = Q == 15 ? M1R : L1R;
+    constexpr const int* T1 = Q == 15 ? M1T : L1T;
+    constexpr const int* R2 = Q == 15 ? M2R : L2R;
+    constexpr const int* T2 = Q == 15 ? M2T : L2T;
+    // 14-qubit tiles hold tile bit 0 in the registers of L0 and L2; it is
+    // rotated in the segment's first of them
+    constexpr int SKIP0 = Q == 15 ? 5 : 0;
+    __shared__ __align__(16) float lds[Q == 15 ? kLdsSlots4x15 : (TWO ? kLdsSlots4 : 2 * kLdsSlots)];
     __shared__ uint32_t sg[64];
     __shared__ float2 pha[kMaxPhase], phb[kMaxPhase];
-    __shared__ double red[kThreads / 64];
+    __shared__ double red[NT / 64];
     __shared__ int wt[kMaxEdges];  // this trajectory's signed multiplicities of the pass's zz gates
     __shared__ float tt[32];       // this trajectory's signed rotation coefficients [segment][layout][r]
     __shared__ int m6[2][kRegs];   // register-pair parts of the two diagonals' m (see diag)
@@ -422,13 +476,13 @@ __global__ __launch_bounds__(kThreads, TWO ? 4 : 1) void k_sv_pass(float2* __res
     // segment); two-segment passes load it after finishing the current one
     constexpr bool kPrefetch = !kSeg2 && !TWO;
     const uint32_t tid = threadIdx.x;
-    const uint64_t zt0 = storage_thread<L0T>(P, tid), zt2 = storage_thread<L2T>(P, tid);
+    const uint64_t zt0 = storage_thread<T0, NB>(P, tid), zt2 = storage_thread<T2, NB>(P, tid);
     const uint32_t tmask = (1u << tiles_log2) - 1u;
 
     if (kDiagA)
-        for (uint32_t i = tid; i <= 2 * P.da.ph_mid; i += kThreads) pha[i] = phase[P.da.ph_off + i];
+        for (uint32_t i = tid; i <= 2 * P.da.ph_mid; i += NT) pha[i] = phase[P.da.ph_off + i];
     if (kSeg2)
-        for (uint32_t i = tid; i <= 2 * P.db.ph_mid; i += kThreads) phb[i] = phase[P.db.ph_off + i];
+        for (uint32_t i = tid; i <= 2 * P.db.ph_mid; i += NT) phb[i] = phase[P.db.ph_off + i];
 
     uint32_t x = blockIdx.x;
     if (x >= total) return;
@@ -440,7 +494,7 @@ __global__ __launch_bounds__(kThreads, TWO ? 4 : 1) void k_sv_pass(float2* __res
 #pragma unroll
         for (int j = 0; j < kRegs; ++j) v[j] = make_float2(P.amp0, 0.f);
     } else {
-        load_tile<L0R, MIR>(v, psi + ((size_t)b << n), base | zt0, P);
+        load_tile<R0, MIR>(v, psi + ((size_t)b << n), base | zt0, P);
     }
     uint32_t sb = 0xffffffffu;  // trajectory whose signs are in LDS
     while (true) {
@@ -454,13 +508,13 @@ __global__ __launch_bounds__(kThreads, TWO ? 4 : 1) void k_sv_pass(float2* __res
             fn = tile_of(xn, P.share);
             bn = fn >> tiles_log2;
             basen = pdep64(fn & tmask, P.fixed_mask);
-            if (!kInit && kPrefetch) load_tile<L0R, MIR>(nx, psi + ((size_t)bn << n), basen | zt0, P);
+            if (!kInit && kPrefetch) load_tile<R0, MIR>(nx, psi + ((size_t)bn << n), basen | zt0, P);
         }
         if (b != sb) {  // uniform: a new trajectory's signs and zz weights
             __syncthreads();
-            for (uint32_t w = tid; w < words; w += kThreads) sg[w] = signs[(size_t)b * words + w];
+            for (uint32_t w = tid; w < words; w += NT) sg[w] = signs[(size_t)b * words + w];
             __syncthreads();
-            for (uint32_t e = tid; e < P.w_n; e += kThreads) {
+            for (uint32_t e = tid; e < P.w_n; e += NT) {
                 const int4 E = dedges[P.w_off + e];
                 wt[e] = sign_bit(sg, E.w) ? -E.z : E.z;
             }
@@ -484,28 +538,29 @@ __global__ __launch_bounds__(kThreads, TWO ? 4 : 1) void k_sv_pass(float2* __res
         if (kDiagA) diag(v, P.da, base | zt0, dedges, wt, P.w_off, pha, m6[0]);
         if constexpr (TWO) __builtin_amdgcn_sched_barrier(0);
         mix<0, 0, 5>(v, tt);
-        exchange<TWO, L0R, L0T, L1R, L1T>(v, lds, tid);
+        exchange<TWO, NB, R0, T0, R1, T1>(v, lds, tid);
         mix<0, 1, 5>(v, tt);
-        exchange<TWO, L1R, L1T, L2R, L2T>(v, lds, tid);
-        mix<0, 2, 0>(v, tt);
+        exchange<TWO, NB, R1, T1, R2, T2>(v, lds, tid);
+        mix<0, 2, SKIP0>(v, tt);
         if (kSeg2) {
             if constexpr (TWO) __builtin_amdgcn_sched_barrier(0);
             diag(v, P.db, base | zt2, dedges, wt, P.w_off, phb, m6[1]);
             if constexpr (TWO) __builtin_amdgcn_sched_barrier(0);
             mix<1, 2, 5>(v, tt);
-            exchange<TWO, L2R, L2T, L1R, L1T>(v, lds, tid);
+            exchange<TWO, NB, R2, T2, R1, T1>(v, lds, tid);
             mix<1, 1, 5>(v, tt);
-            exchange<TWO, L1R, L1T, L0R, L0T>(v, lds, tid);
-            mix<1, 0, 0>(v, tt);
+            exchange<TWO, NB, R1, T1, R0, T0>(v, lds, tid);
+            mix<1, 0, SKIP0>(v, tt);
         }
 
         if (!kLast) {
-            if (kSeg2) store_tile<L0R, MIR>(v, st, base | zt0, P);
-            else store_tile<L2R, MIR>(v, st, base | zt2, P);
+            if (kSeg2) store_tile<R0, MIR>(v, st, base | zt0, P);
+            else if constexpr (Q == 15) store_tile_elems<R2, MIR>(v, st, base | zt2, P);
+            else store_tile<R2, MIR>(v, st, base | zt2, P);
         } else {
             const uint64_t fx = frame[2 * (size_t)b];
-            const float accf = kSeg2 ? energy_part<L0R>(v, P, base | zt0, fx, eedges, ew)
-                                     : energy_part<L2R>(v, P, base | zt2, fx, eedges, ew);
+            const float accf = kSeg2 ? energy_part<R0>(v, P, base | zt0, fx, eedges, ew)
+                                     : energy_part<R2>(v, P, base | zt2, fx, eedges, ew);
             double acc = (double)accf;
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
@@ -513,7 +568,7 @@ __global__ __launch_bounds__(kThreads, TWO ? 4 : 1) void k_sv_pass(float2* __res
             __syncthreads();
             if (tid == 0) {
                 double s = 0.0;
-                for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+                for (int w = 0; w < NT / 64; ++w) s += red[w];
                 partials[f] = s * P.e_scale;
             }
         }
@@ -529,7 +584,7 @@ __global__ __launch_bounds__(kThreads, TWO ? 4 : 1) void k_sv_pass(float2* __res
 #pragma unroll
             for (int j = 0; j < kRegs; ++j) v[j] = nx[j];
         } else {
-            load_tile<L0R, MIR>(v, psi + ((size_t)b << n), base | zt0, P);
+            load_tile<R0, MIR>(v, psi + ((size_t)b << n), base | zt0, P);
         }
     }
 }
@@ -553,19 +608,21 @@ __global__ __launch_bounds__(256) void k_tile_sum(const double* __restrict__ par
 typedef void (*PassKernel)(float2*, const Pass2, uint32_t, uint32_t, uint32_t, const uint32_t*, uint32_t,
                            const uint64_t*, const int4*, const float2*, const int2*, const double*, double*);
 
-template <bool TWO, bool MIR>
+template <int Q, bool TWO, bool MIR>
 PassKernel pass_kernel_of(int fl) {
     static const PassKernel tab[16] = {
-        k_sv_pass<0, TWO, MIR>,  k_sv_pass<1, TWO, MIR>,  k_sv_pass<2, TWO, MIR>,  k_sv_pass<3, TWO, MIR>,
-        k_sv_pass<4, TWO, MIR>,  k_sv_pass<5, TWO, MIR>,  k_sv_pass<6, TWO, MIR>,  k_sv_pass<7, TWO, MIR>,
-        k_sv_pass<8, TWO, MIR>,  k_sv_pass<9, TWO, MIR>,  k_sv_pass<10, TWO, MIR>, k_sv_pass<11, TWO, MIR>,
-        k_sv_pass<12, TWO, MIR>, k_sv_pass<13, TWO, MIR>, k_sv_pass<14, TWO, MIR>, k_sv_pass<15, TWO, MIR>};
+        k_sv_pass<Q, 0, TWO, MIR>,  k_sv_pass<Q, 1, TWO, MIR>,  k_sv_pass<Q, 2, TWO, MIR>,  k_sv_pass<Q, 3, TWO, MIR>,
+        k_sv_pass<Q, 4, TWO, MIR>,  k_sv_pass<Q, 5, TWO, MIR>,  k_sv_pass<Q, 6, TWO, MIR>,  k_sv_pass<Q, 7, TWO, MIR>,
+        k_sv_pass<Q, 8, TWO, MIR>,  k_sv_pass<Q, 9, TWO, MIR>,  k_sv_pass<Q, 10, TWO, MIR>, k_sv_pass<Q, 11, TWO, MIR>,
+        k_sv_pass<Q, 12, TWO, MIR>, k_sv_pass<Q, 13, TWO, MIR>, k_sv_pass<Q, 14, TWO, MIR>, k_sv_pass<Q, 15, TWO, MIR>};
     return tab[fl & 15];
 }
 
-PassKernel pass_kernel(int fl, bool two, bool mir) {
-    if (mir) return two ? pass_kernel_of<true, true>(fl) : pass_kernel_of<false, true>(fl);
-    return two ? pass_kernel_of<true, false>(fl) : pass_kernel_of<false, false>(fl);
+// q = 15: one 1024-thread workgroup per CU (two is ignored)
+PassKernel pass_kernel(uint32_t q, int fl, bool two, bool mir) {
+    if (q == 15) return mir ? pass_kernel_of<15, true, true>(fl) : pass_kernel_of<15, true, false>(fl);
+    if (mir) return two ? pass_kernel_of<14, true, true>(fl) : pass_kernel_of<14, false, true>(fl);
+    return two ? pass_kernel_of<14, true, false>(fl) : pass_kernel_of<14, false, false>(fl);
 }
 
 struct TiledTables {
@@ -578,9 +635,11 @@ struct TiledTables {
     std::vector<double> ew;
 };
 
-int reg_index(int layout, const uint32_t* tb, uint32_t q) {
+// register bit of qubit q in a layout of tiles with Q qubits (-1: none)
+int reg_index(uint32_t Q, int layout, const uint32_t* tb, uint32_t q) {
+    const int (*lr)[5] = Q == 15 ? hMR : hLR;
     for (int r = 0; r < 5; ++r)
-        if (tb[hLR[layout][r]] == q) return r;
+        if (tb[lr[layout][r]] == q) return r;
     return -1;
 }
 
@@ -592,7 +651,7 @@ DiagTab diag_table(stn_plan* p, TiledTables& T, const Pass2& P, int layer, int l
     std::vector<int4> cat[7];
     for (size_t e = 0; e < L.zz_gates.size(); ++e) {
         const GateRec& g = p->gates[L.zz_gates[e]];
-        const int ru = reg_index(layout, P.tb, g.q0), rv = reg_index(layout, P.tb, g.q1);
+        const int ru = reg_index(p->tile_bits, layout, P.tb, g.q0), rv = reg_index(p->tile_bits, layout, P.tb, g.q1);
         const int mult = L.zz_mult[e], gi = (int)L.zz_gates[e];
         if (ru < 0 && rv < 0) cat[0].push_back({(int)g.q0, (int)g.q1, mult, gi});
         else if (ru >= 0 && rv < 0) cat[1 + ru].push_back({(int)g.q1, 0, mult, gi});
@@ -623,7 +682,9 @@ TiledTables build_tables(stn_plan* p) {
         int t = 0;
         for (uint32_t q = 0; q < n; ++q)
             if ((ps.tile_mask >> q) & 1) P.tb[t++] = q;
-        if (t != kQ || P.tb[0] != 0) fail(STN_E_INVALID, "tile must hold 14 storage bits including bit 0");
+        const uint32_t Q = p->tile_bits;
+        if ((Q != 14 && Q != 15) || t != (int)Q || P.tb[0] != 0)
+            fail(STN_E_INVALID, "tile must hold 14 or 15 storage bits including bit 0");
         if (p->sv_half) {
             // stored: qubits 0 .. n-2; a tile holding qubit n-1 (tile bit 13)
             // also covers the complemented tile, so its top fixed bit is 0
@@ -631,7 +692,7 @@ TiledTables build_tables(stn_plan* p) {
             P.half_mask = Nh - 1;
             P.fixed_mask = (Nh - 1) & ~(uint64_t)ps.tile_mask;
             if ((ps.tile_mask >> (n - 1)) & 1) {
-                if (P.tb[kQ - 1] != n - 1 || !P.fixed_mask) fail(STN_E_INVALID, "half-state tile layout");
+                if (P.tb[Q - 1] != n - 1 || !P.fixed_mask) fail(STN_E_INVALID, "half-state tile layout");
                 P.mirror = 1ull << (n - 1);
                 P.fixed_mask &= ~(1ull << (63 - __builtin_clzll(P.fixed_mask)));
             }
@@ -652,7 +713,7 @@ TiledTables build_tables(stn_plan* p) {
                 for (int r = 0; r < 5; ++r) {
                     P.mix_gate[seg][l][r] = -1;
                     P.mix_coef[seg][l][r] = 0.f;
-                    const uint32_t q = P.tb[hLR[l][r]];
+                    const uint32_t q = P.tb[(Q == 15 ? hMR : hLR)[l][r]];
                     if (layer < 0 || !((mask >> q) & 1) || ((done >> q) & 1)) continue;
                     done |= 1u << q;
                     const int g = p->layers[layer].rx_gate[q];
@@ -689,7 +750,7 @@ TiledTables build_tables(stn_plan* p) {
             std::vector<double> cw[7];
             for (size_t t2 = 0; t2 < p->obs_u.size(); ++t2) {
                 const uint32_t u = p->obs_u[t2], v = p->obs_v[t2];
-                const int ru = reg_index(layout, P.tb, u), rv = reg_index(layout, P.tb, v);
+                const int ru = reg_index(p->tile_bits, layout, P.tb, u), rv = reg_index(p->tile_bits, layout, P.tb, v);
                 int c = 0;
                 int2 e{(int)u, (int)v};
                 if (ru >= 0 && rv < 0) {
@@ -752,7 +813,8 @@ void launch_sv_tiled(stn_plan* p, stn_batch* b, hipStream_t s) {
     // N: amplitudes stored per trajectory (2^(n-1) for half-state plans)
     const uint32_t n = p->n, ns = p->sv_half ? n - 1 : n;
     const uint64_t N = 1ull << ns;
-    const uint32_t tiles_log2 = ns - kQ;
+    const uint32_t Q = p->tile_bits, tiles_log2 = ns - Q;
+    if ((Q != 14 && Q != 15) || ns < Q) fail(STN_E_INVALID, "tiled plan without a valid tile width");
     const uint32_t tiles = 1u << tiles_log2;
     const uint32_t B = std::min(p->max_batch, b->K);
     if (b->words > 64) fail(STN_E_UNSUPPORTED, "tiled lowering supports at most 2048 gates");
@@ -764,11 +826,14 @@ void launch_sv_tiled(stn_plan* p, stn_batch* b, hipStream_t s) {
     int dev = 0, cus = 0;
     STN_HIP(hipGetDevice(&dev));
     STN_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    // variant 0: one workgroup per CU; 1: two per CU, the second queued behind
-    // the first; 2: two resident per CU (the half-buffer kernels).  The grid is
-    // a multiple of 32 (XCD rounds of line groups).
-    const bool two = p->variant == 2;
-    const uint32_t per_cu = p->variant == 0 ? 1u : 2u;
+    // 14-qubit tiles: variant 0: one workgroup per CU; 1: two per CU, the
+    // second queued behind the first; 2: two resident per CU (the half-buffer
+    // kernels).  15-qubit tiles: one 1024-thread workgroup per CU.  The grid
+    // is a multiple of 32 (XCD rounds of line groups).
+    const bool big = Q == 15;
+    const bool two = !big && p->variant == 2;
+    const uint32_t per_cu = (big || p->variant == 0) ? 1u : 2u;
+    const uint32_t threads = big ? 2u * kThreads : (uint32_t)kThreads;
     uint32_t grid_max = std::max(32u, (uint32_t)cus / 32u * 32u) * per_cu;
     // a job server may keep some CUs free for other jobs' kernels
     if (p->grid_cap) grid_max = std::min(grid_max, std::max(32u, p->grid_cap * (two ? 2u : 1u) / 32u * 32u));
@@ -782,7 +847,7 @@ void launch_sv_tiled(stn_plan* p, stn_batch* b, hipStream_t s) {
             if (blocks % (8u << P.share) || grid % 32) P.share = 0;  // grouping needs whole XCD rounds
             const double elems = (double)nb * (double)N;
             prof_begin(p, STN_K_SV_PASS, s);
-            hipLaunchKernelGGL(pass_kernel(fl, two, P.mirror != 0), dim3(grid), dim3(kThreads), 0, s, p->d_work.as<float2>(), P, ns,
+            hipLaunchKernelGGL(pass_kernel(Q, fl, two, P.mirror != 0), dim3(grid), dim3(threads), 0, s, p->d_work.as<float2>(), P, ns,
                                tiles_log2, blocks, b->d_signs.as<uint32_t>() + (size_t)c0 * b->words, b->words,
                                b->d_frame.as<uint64_t>() + 2 * (size_t)c0, d->dedges.as<int4>(),
                                d->phase.as<float2>(), d->eedges.as<int2>(), d->ew.as<double>(),
@@ -799,13 +864,13 @@ void launch_sv_tiled(stn_plan* p, stn_batch* b, hipStream_t s) {
     }
 }
 
-uint32_t tiled_variants(const stn_plan* p) { return p->opts.precision == 128 ? 1u : 3u; }
+uint32_t tiled_variants(const stn_plan* p) { return (p->opts.precision == 128 || p->tile_bits == 15) ? 1u : 3u; }
 
 // loads this file's device code (the runtime does so at the first use of
 // one of its kernels)
 void warm_code_sv_tiled() {
     hipFuncAttributes a{};
-    (void)hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_sv_pass<4, true, false>));
+    (void)hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_sv_pass<15, 4, true, false>));
 }
 
 }  // namespace stn

@@ -406,10 +406,30 @@ bool build_tiled(stn_plan* p, std::string& why) {
 // it, so every trajectory has psi(~z) = psi(z); the ZZ observable takes the
 // same value at z and ~z.  The kernels then store the amplitudes with qubit
 // n-1 = 0 and read psi(z', 1) at ~z'.  A tile must fit in the stored
-// qubits with one fixed bit left: n >= 15 for the 14-qubit complex64
+// qubits with one fixed bit left: n >= tile bits + 1 for the complex64
 // tiles, n >= 13 for the 12-qubit complex128 ones.
 static bool tiled_half(const stn_plan* p) {
-    return p->n >= (p->opts.precision == 64 ? 15u : 13u) && !p->opts.sv_full_state;
+    return p->n >= (p->opts.precision == 64 ? p->tile_bits + 1 : 13u) && !p->opts.sv_full_state;
+}
+
+// Qubits per tile.  complex64: 15-qubit tiles (a 1024-thread workgroup per
+// CU) leave the strided tile 4 low storage bits up to n = 26 (128-byte runs,
+// whole lines), where 14-qubit tiles leave 3 at n = 25 and 2 at n = 26.
+// Up to n = 24 the 14-qubit tiles keep 128-byte runs too, and their two
+// resident workgroups per CU overlap one's memory traffic with the other's
+// exchanges, which makes their contiguous passes faster.
+static uint32_t tiled_tile_bits(const stn_plan* p) {
+    if (p->opts.precision == 128) return tiled128_tile_bits();
+    if (p->opts.sv_tile_bits) return p->opts.sv_tile_bits;
+    return p->n >= 25 ? 15u : 14u;
+}
+
+// low storage bits every tile after the first keeps: two tiles of 15 qubits
+// cover 30 - coal qubits (n counts qubit n-1 of a half-state plan)
+static uint32_t tiled_coal(const stn_plan* p) {
+    if (p->opts.precision == 128) return 3;
+    if (p->tile_bits == 14) return 2;
+    return p->n >= 28 ? 2u : (p->n >= 26 ? 30u - p->n : 4u);
 }
 
 // Pass schedule of the tiled lowering.  A layer's rotations are split over
@@ -542,9 +562,9 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
             // (HBM-bound passes; lightcone networks: their own estimate)
             double sv_t = -1, tn_t = -1;
             const bool c128 = p->opts.precision == 128;
-            if (n >= (c128 ? 13u : 14u) && build_tiled(p, why)) {
-                if (c128) schedule_tiled(p, tiled128_tile_bits(), 3);
-                else schedule_tiled(p, 14, 2);
+            p->tile_bits = tiled_tile_bits(p);
+            if (n >= (c128 ? 13u : p->tile_bits) && build_tiled(p, why)) {
+                schedule_tiled(p, p->tile_bits, tiled_coal(p));
                 double bytes = 0;
                 const int stored = (int)n - (tiled_half(p) ? 1 : 0);
                 for (auto& ps : p->passes)
@@ -591,8 +611,10 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
     } else if (kind == STN_PLAN_SV_TILED) {
         if (dense_out) fail(STN_E_UNSUPPORTED, "the tiled lowering produces energies only");
         const bool c128 = p->opts.precision == 128;
-        if (n < (c128 ? tiled128_tile_bits() : 14u))
-            fail(STN_E_UNSUPPORTED, std::string("the tiled lowering needs n >= ") + (c128 ? "12" : "14"));
+        p->tile_bits = tiled_tile_bits(p);
+        if (n < p->tile_bits)
+            fail(STN_E_UNSUPPORTED, "the tiled lowering with " + std::to_string(p->tile_bits) +
+                                        "-qubit tiles needs n >= " + std::to_string(p->tile_bits));
         if (p->layers.empty() && !build_tiled(p, why)) fail(STN_E_UNSUPPORTED, "tiled lowering: " + why);
         if (c128) {
             // the complex128 kernels apply every rx as given
@@ -600,10 +622,8 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
                 g.det_x = 0;
                 g.theta_eff = g.theta;
             }
-            schedule_tiled(p, tiled128_tile_bits(), 3);
-        } else {
-            schedule_tiled(p, 14, 2);
         }
+        schedule_tiled(p, p->tile_bits, tiled_coal(p));
         p->sv_half = tiled_half(p);
     } else if (kind == STN_PLAN_LIGHTCONE) {
         if (dense_out) fail(STN_E_UNSUPPORTED, "the lightcone lowering produces energies only");
@@ -627,10 +647,10 @@ void build_plan(stn_plan* p, const stn_circuit* c, const stn_noise_model* nm, co
         fail(STN_E_INVALID, "unknown plan kind");
     }
     p->kind = kind;
-    // launch shape before any tuning: for the tiled complex64 kernels, two
+    // launch shape before any tuning: for the 14-qubit complex64 tiles, two
     // resident workgroups per CU (variant 2), the autotuner's choice on every
-    // size measured
-    if (kind == STN_PLAN_SV_TILED && p->opts.precision == 64) p->variant = 2;
+    // size measured; the 15-qubit tiles have one shape
+    if (kind == STN_PLAN_SV_TILED && p->opts.precision == 64) p->variant = p->tile_bits == 15 ? 0 : 2;
     // cost model and batch size
     const double elem = p->opts.precision == 128 ? 16.0 : 8.0;
     const double N = std::ldexp(1.0, (int)n);

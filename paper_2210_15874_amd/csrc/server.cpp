@@ -254,7 +254,7 @@ uint64_t estimate_bytes(const stn_plan* p, uint32_t B, uint64_t K) {
     double b = 0;
     const double N = std::ldexp(1.0, (int)p->n);
     const double elem = p->opts.precision == 128 ? 16.0 : 8.0;
-    if (p->kind == STN_PLAN_SV_TILED) b += (double)B * N * elem + (double)B * std::ldexp(1.0, (int)p->n - 14) * 8.0;
+    if (p->kind == STN_PLAN_SV_TILED) b += (double)B * N * elem + (double)B * std::ldexp(1.0, (int)p->n - (int)p->tile_bits) * 8.0;
     if (p->kind == STN_PLAN_LIGHTCONE) b += (double)B * p->obs_u.size() * 8.0 + p->lc_arena_bytes;
     if (p->kind == STN_PLAN_SV_GATES) b += (double)B * (N * elem + 64.0 * 8.0);
     b += kChunksInFlight * (double)B * (S + 4.0 * words + 16.0 + 8.0);     // batches
@@ -304,10 +304,12 @@ void plan_job(stn_server* sv, Job& j) {
     // statevector chunks only as large as it takes to fill the device
     // (~32k tiles per launch): the rest of the memory serves other jobs
     if (p->kind == STN_PLAN_SV_TILED) {
-        const int tile_bits = p->opts.precision == 128 ? (int)tiled128_tile_bits() : 14;
+        const int tile_bits = (int)p->tile_bits;
         const int stored = (int)p->n - (p->sv_half ? 1 : 0);   // half-state plans keep 2^(n-1) amplitudes
         const double tiles = std::ldexp(1.0, std::max(0, stored - tile_bits));
-        j.B = (uint32_t)std::max(1.0, std::min((double)j.B, std::ceil(kChunkTiles / tiles)));
+        // the same amplitudes per launch for 15-qubit tiles (half the tiles)
+        const double target = tile_bits == 15 ? kChunkTiles / 2 : kChunkTiles;
+        j.B = (uint32_t)std::max(1.0, std::min((double)j.B, std::ceil(target / tiles)));
     }
     j.est_s = p->est_seconds_per_traj() * (double)j.K;
     // a job for the small-job stream runs in chunks of about kSmallChunkSeconds,

@@ -206,6 +206,53 @@ def test_tiled_energies_same_draws(n, p, K, lam, precision, tol):
     assert abs(r["energy_mean"] - got.mean()) < 1e-9
 
 
+@pytest.mark.parametrize("n,p,K,lam", [(15, 2, 16, (0.02, 0.1)), (16, 3, 12, (0.02, 0.1)), (17, 2, 10, (1e-2, 5e-2))])
+def test_tiled15_energies_same_draws(n, p, K, lam):
+    """15-qubit tiles (one 1024-thread workgroup per CU, the layouts'
+    register bits disjoint): Pauli-frame rewrite and tiled passes against
+    literal Kraus insertion.  n = 15 is a single full-state tile; n = 16
+    and 17 keep half the state, the second tile holding qubit n-1."""
+    from oracle import simulate as sim
+    stn = stn_mod()
+    pr = qaoa(n, p, 100 + n + p, lam[0], lam[1], K)
+    pl = stn.Plan(pr, plan_kind=stn.PLAN_SV_TILED, max_batch=5, precision=64, tile_bits=15)
+    info = pl.info()
+    assert info["plan_name"] == "sv_tiled" and info["tile_bits"] == 15 and info["half_state"] == (1 if n >= 16 else 0)
+    acc = pl.accum()
+    b = pl.sample(pr.seed, 0, K)
+    pl.contract(b)
+    pl.reduce(b, acc)
+    got = b.energies()
+    ens = sim.ensemble(pr, pr.seed, 0, K, want_states=False)
+    m = len(pr.edges)
+    assert (ens["idx"] != 0).any(axis=1).mean() > 0.1
+    np.testing.assert_allclose(got / m, ens["energies"] / m, atol=1e-5)
+    with pytest.raises(stn.StnError) as ei:
+        stn.Plan(qaoa(14, 1, 5, 1e-3, 1e-2, 4), plan_kind=stn.PLAN_SV_TILED, precision=64, tile_bits=15)
+    assert ei.value.status == 2 and "n >= 15" in str(ei.value)
+
+
+def test_plan_handle_released_before_batch_and_accumulator():
+    """A plan whose handle is released first stays alive until its last
+    batch and accumulator are destroyed: their results can still be read,
+    and their device buffers are freed through the plan's allocator
+    afterwards (C ABI lifetime rule)."""
+    stn = stn_mod()
+    pr = qaoa(16, 2, 321, 1e-3, 1e-2, 8)
+    pl = stn.Plan(pr, plan_kind=stn.PLAN_SV_TILED)
+    acc = pl.accum()
+    b = pl.sample(pr.seed, 0, pr.K)
+    pl.contract(b)
+    pl.reduce(b, acc)
+    pl.close()
+    e = b.energies()
+    r = acc.read()
+    assert abs(r["energy_mean"] - e.mean()) < 1e-9
+    b.close()
+    acc.close()
+    torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("precision", [64, 128])
 def test_batching_does_not_change_results(precision):
     stn = stn_mod()
@@ -304,21 +351,26 @@ def test_lightcone_energies_same_draws(n, p, K, lam, precision):
     np.testing.assert_allclose(got / m, ens["energies"] / m, atol=tol)
 
 
-@pytest.mark.parametrize("n,p,precision", [(15, 2, 64), (17, 3, 64), (27, 2, 64), (13, 2, 128), (17, 3, 128)])
-def test_tiled_half_state_against_full_state(n, p, precision):
+@pytest.mark.parametrize("n,p,precision,tile_bits", [(15, 2, 64, 14), (17, 3, 64, 14), (27, 2, 64, 14),
+                                                     (16, 2, 64, 15), (17, 3, 64, 15), (27, 2, 64, 15),
+                                                     (13, 2, 128, 0), (17, 3, 128, 0)])
+def test_tiled_half_state_against_full_state(n, p, precision, tile_bits):
     """Half-state plans (only qubit n-1 = 0 stored; the tile holding qubit
     n-1 also covers the complemented tile, stored in reverse) against
-    full-state plans on the same draws, in every launch shape.  n = 15
-    (complex64) and 13 (complex128) have a single tile per pass; n = 27 has
-    three tiles per layer."""
+    full-state plans on the same draws, in every launch shape.  n = 15 with
+    14-qubit tiles, 16 with 15-qubit tiles (complex64) and 13 (complex128)
+    have a single tile per pass; n = 27 has three 14-qubit tiles per layer,
+    or two 15-qubit tiles with 64-byte runs."""
     stn = stn_mod()
     pr = qaoa(n, p, 700 + n, 2e-2, 1e-1, 10)
     res = {}
-    variants = (0, 1, 2) if precision == 64 else (0,)
+    variants = (0, 1, 2) if tile_bits == 14 else (0,)
     for full in (True, False):
-        pl = stn.Plan(pr, plan_kind=stn.PLAN_SV_TILED, full_state=full, max_batch=4, precision=precision)
+        pl = stn.Plan(pr, plan_kind=stn.PLAN_SV_TILED, full_state=full, max_batch=4, precision=precision,
+                      tile_bits=tile_bits)
         info = pl.info()
         assert info["half_state"] == (0 if full else 1)
+        assert info["tile_bits"] == (tile_bits or 12)
         for variant in variants:
             pl.set_variant(variant)
             b = pl.sample(pr.seed, 0, pr.K)
@@ -334,38 +386,42 @@ def test_tiled_half_state_against_full_state(n, p, precision):
 
 
 def test_tiled_complex64_against_complex128_n22():
-    """Same draws, n = 22: the complex64 passes against the complex128 twin."""
+    """Same draws, n = 22: the complex64 passes (14- and 15-qubit tiles)
+    against the complex128 twin."""
     stn = stn_mod()
     pr = qaoa(22, 3, 51, 1e-3, 1e-2, 64)
     res = {}
-    for precision in (64, 128):
-        pl = stn.Plan(pr, plan_kind=stn.PLAN_SV_TILED, precision=precision)
+    for precision, tb in ((64, 14), (64, 15), (128, 0)):
+        pl = stn.Plan(pr, plan_kind=stn.PLAN_SV_TILED, precision=precision, tile_bits=tb)
         b = pl.sample(pr.seed, 0, pr.K)
         pl.contract(b)
-        res[precision] = b.energies()
+        res[tb] = b.energies()
     m = len(pr.edges)
-    np.testing.assert_allclose(res[64] / m, res[128] / m, atol=1e-5)
-    assert np.abs(res[64] - res[128]).max() > 0     # two different arithmetics
+    for tb in (14, 15):
+        np.testing.assert_allclose(res[tb] / m, res[0] / m, atol=1e-5)
+        assert np.abs(res[tb] - res[0]).max() > 0     # two different arithmetics
 
 
 @pytest.mark.parametrize("n,p", [(30, 2), (18, 3), (28, 1)])
 def test_tiled_tile_counts_complex64_against_complex128(n, p):
-    """Tiles of 3 (n=28, 30) and 2 (n=18) per layer, merged layer
+    """14-qubit tiles: 3 (n=28, 30) and 2 (n=18) per layer; 15-qubit tiles:
+    3 (n=30) and 2 (n=18, 28; 32-byte runs at 28) per layer; merged layer
     boundaries: energies of the same draws against the complex128 passes
     (12-qubit tiles, another schedule)."""
     stn = stn_mod()
     pr = qaoa(n, p, 60 + n, 2e-3, 2e-2, 6)
     res = {}
-    for precision in (64, 128):
-        pl = stn.Plan(pr, plan_kind=stn.PLAN_SV_TILED, precision=precision, hbm_budget=64 << 30)
+    for precision, tile_bits in ((64, 14), (64, 15), (128, 0)):
+        pl = stn.Plan(pr, plan_kind=stn.PLAN_SV_TILED, precision=precision, hbm_budget=64 << 30, tile_bits=tile_bits)
         b = pl.sample(pr.seed, 0, pr.K)
         pl.contract(b)
-        res[precision] = b.energies()
+        res[tile_bits] = b.energies()
         b.close()
         pl.close()
         torch.cuda.empty_cache()
     m = len(pr.edges)
-    np.testing.assert_allclose(res[64] / m, res[128] / m, atol=1e-5)
+    np.testing.assert_allclose(res[14] / m, res[0] / m, atol=1e-5)
+    np.testing.assert_allclose(res[15] / m, res[0] / m, atol=1e-5)
 
 
 def test_lightcone_matches_tiled_statevector():
@@ -405,13 +461,13 @@ def test_lightcone_noiseless_p1_closed_form_large_n(n, precision, tol):
 
 # ----------------------------------------------------------------------------- full-size workload
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
-def test_full_size_workload_sampled_trajectories(variant):
+@pytest.mark.parametrize("tile_bits,variant", [(15, 0), (14, 0), (14, 1), (14, 2)])
+def test_full_size_workload_sampled_trajectories(tile_bits, variant):
     """n=26, p=4, K=4096 in the launch configurations the benchmark times
-    (trajectories per launch from a 160 GiB budget, each launch shape the
-    autotuner may pick): sampled trajectories against stored oracle values
-    (complex128, literal Kraus insertion, same draws), plus properties that
-    hold at any size."""
+    (trajectories per launch from a 160 GiB budget; 15-qubit tiles, the
+    default at this size, and each launch shape of the 14-qubit tiles):
+    sampled trajectories against stored oracle values (complex128, literal
+    Kraus insertion, same draws), plus properties that hold at any size."""
     import json
     from workloads import config_problem
     stn = stn_mod()
@@ -421,10 +477,10 @@ def test_full_size_workload_sampled_trajectories(variant):
     pr = config_problem(2)
     assert [list(e) for e in pr.edges] == gold["edges"]
     m = len(pr.edges)
-    pl = stn.Plan(pr, outputs=stn.OUT_ENERGY, precision=64, hbm_budget=160 << 30)
+    pl = stn.Plan(pr, outputs=stn.OUT_ENERGY, precision=64, hbm_budget=160 << 30, tile_bits=tile_bits)
     pl.set_variant(variant)
     info = pl.info()
-    assert info["plan_name"] == "sv_tiled" and info["variant"] == variant
+    assert info["plan_name"] == "sv_tiled" and info["variant"] == variant and info["tile_bits"] == tile_bits
     B = info["max_batch"]
     acc = pl.accum()
     for k0 in range(0, pr.K, B):
@@ -564,7 +620,7 @@ def test_dedup_contraction_matches_plain(kind, n, p, precision, lam):
 # ----------------------------------------------------------------------------- contraction graphs
 
 @pytest.mark.parametrize("kind,n,p,precision", [("sv_lds", 10, 2, 64), ("sv_lds", 12, 2, 128),
-                                                ("sv_tiled", 18, 2, 64), ("sv_tiled", 16, 2, 128),
+                                                ("sv_tiled", 18, 2, 64), ("sv_tiled", 16, 2, 128), ("sv_tiled15", 20, 2, 64),
                                                 ("lightcone", 20, 1, 64), ("lightcone", 22, 2, 64)])
 def test_contraction_graph_replays_match_eager(kind, n, p, precision):
     """One batch refilled chunk after chunk and contracted through a HIP
@@ -572,10 +628,12 @@ def test_contraction_graph_replays_match_eager(kind, n, p, precision):
     bit for bit, with unrelated eager work and synchronisation between the
     replays; then a change of K and of launch shape, which start over."""
     stn = stn_mod()
-    kinds = {"sv_lds": stn.PLAN_SV_LDS, "lightcone": stn.PLAN_LIGHTCONE, "sv_tiled": stn.PLAN_SV_TILED}
+    kinds = {"sv_lds": stn.PLAN_SV_LDS, "lightcone": stn.PLAN_LIGHTCONE, "sv_tiled": stn.PLAN_SV_TILED,
+             "sv_tiled15": stn.PLAN_SV_TILED}
+    tb = 15 if kind == "sv_tiled15" else 0
     pr = qaoa(n, p, 800 + n, 5e-3, 2e-2, 96)
-    ref = stn.Plan(pr, plan_kind=kinds[kind], precision=precision)
-    pl = stn.Plan(pr, plan_kind=kinds[kind], precision=precision)
+    ref = stn.Plan(pr, plan_kind=kinds[kind], precision=precision, tile_bits=tb)
+    pl = stn.Plan(pr, plan_kind=kinds[kind], precision=precision, tile_bits=tb)
     pl.set_graphs(True)
     stream = torch.cuda.Stream()
     K, chunks = 48, 6
@@ -606,7 +664,7 @@ def test_contraction_graph_replays_match_eager(kind, n, p, precision):
             check(b, 1000 + c * 17, 17)
         info = pl.info()
         assert info["graph_captures"] == 2 and info["graph_replays"] == chunks - 1
-        if kind != "sv_tiled" or precision == 64:
+        if not kind.startswith("sv_tiled") or pl.info()["tile_bits"] == 14:
             pl.set_variant(1)
             for c in range(3):
                 pl.resample(b, pr.seed, 2000 + c * 17, 17)
@@ -615,7 +673,7 @@ def test_contraction_graph_replays_match_eager(kind, n, p, precision):
             assert pl.info()["graph_captures"] == 3
         b.close()
     # the NULL stream never captures
-    pl2 = stn.Plan(pr, plan_kind=kinds[kind], precision=precision)
+    pl2 = stn.Plan(pr, plan_kind=kinds[kind], precision=precision, tile_bits=tb)
     pl2.set_graphs(True)
     b2 = pl2.sample(pr.seed, 0, K, stream=ctypes.c_void_p(0))
     for c in range(3):
