@@ -267,6 +267,8 @@ stn_status stn_plan_create(const stn_circuit* circuit, const stn_noise_model* no
         if (opts) p->opts = *opts;
         else stn_plan_opts_default(&p->opts);
         if (p->opts.precision != 64 && p->opts.precision != 128) fail(STN_E_INVALID, "precision must be 64 or 128");
+        if (p->opts.sv_tile_bits && (p->opts.precision != 64 || (p->opts.sv_tile_bits != 14 && p->opts.sv_tile_bits != 15)))
+            fail(STN_E_INVALID, "sv_tile_bits must be 0, 14 or 15 (complex64 plans only)");
         if ((p->opts.dev_alloc == nullptr) != (p->opts.dev_free == nullptr))
             fail(STN_E_INVALID, "dev_alloc and dev_free must be given together");
         if (p->opts.lc_order_fn && p->opts.lc_slice_bits)
@@ -311,10 +313,18 @@ stn_status stn_plan_info(const stn_plan* p, stn_plan_stats* o) {
     o->lc_group = p->lc_group;
     o->lc_width_lower_bound = p->lc_width_lb;
     o->half_state = p->sv_half ? 1u : 0u;
+    o->tile_bits = p->kind == STN_PLAN_SV_TILED ? p->tile_bits : 0u;
     return STN_OK;
 }
 
-void stn_plan_destroy(stn_plan* p) { delete p; }
+namespace {
+void plan_ref(stn_plan* p) { p->refs.fetch_add(1, std::memory_order_relaxed); }
+void plan_unref(stn_plan* p) {
+    if (p && p->refs.fetch_sub(1, std::memory_order_acq_rel) == 1) delete p;
+}
+}  // namespace
+
+void stn_plan_destroy(stn_plan* p) { plan_unref(p); }
 
 stn_status stn_profile(stn_plan* p, int enable) {
     if (!p) return set_error(STN_E_INVALID, "NULL argument");
@@ -372,6 +382,7 @@ stn_status stn_sample(stn_plan* p, uint64_t seed, uint64_t k0, uint32_t K, stn_b
         delete b;
         return st;
     }
+    plan_ref(p);
     *out = b;
     return STN_OK;
 }
@@ -415,6 +426,7 @@ stn_status stn_batch_from_indices(stn_plan* p, const uint8_t* idx, uint64_t k0, 
         delete b;
         return st;
     }
+    plan_ref(p);
     *out = b;
     return STN_OK;
 }
@@ -702,8 +714,11 @@ stn_status stn_batch_results(const stn_batch* b, double* energies, double* state
 uint32_t stn_batch_size(const stn_batch* b) { return b ? b->K : 0; }
 
 void stn_batch_destroy(stn_batch* b) {
-    if (b) (void)hipDeviceSynchronize();
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    stn_plan* p = b->plan;
     delete b;
+    plan_unref(p);
 }
 
 stn_status stn_accum_create(stn_plan* p, stn_accum** out) {
@@ -727,6 +742,7 @@ stn_status stn_accum_create(stn_plan* p, stn_accum** out) {
         delete a;
         return st;
     }
+    plan_ref(p);
     *out = a;
     return STN_OK;
 }
@@ -792,8 +808,11 @@ stn_status stn_accum_read(stn_accum* a, stn_result* out, void* stream) {
 }
 
 void stn_accum_destroy(stn_accum* a) {
-    if (a) (void)hipDeviceSynchronize();
+    if (!a) return;
+    (void)hipDeviceSynchronize();
+    stn_plan* p = a->plan;
     delete a;
+    plan_unref(p);
 }
 
 stn_status stn_accum_sample(stn_accum* a, const double* u, uint32_t m, uint32_t* out, void* stream) {

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <array>
+#include <atomic>
 #include <complex>
 #include <cstdint>
 #include <string>
@@ -168,6 +169,9 @@ struct ProfClass {
 }  // namespace stn
 
 struct stn_plan {
+    // the caller's handle plus one per batch and accumulator made through the
+    // C ABI (they free their buffers through alloc): the last release deletes
+    std::atomic<uint32_t> refs{1};
     stn::Allocator alloc;
     stn_plan_opts opts{};
     uint32_t n = 0;
@@ -237,6 +241,7 @@ struct stn_plan {
     uint32_t lc_group = 0;                       // lightcone: trajectories per workgroup work item
     uint32_t lc_width_lb = 0;                    // lightcone: lc_width is a lower bound (search stopped at the cap)
     bool sv_half = false;                        // tiled complex64: psi(~z) = psi(z), only qubit n-1 = 0 stored
+    uint32_t tile_bits = 0;                      // tiled: qubits per tile (complex64: 14 or 15)
     bool graphs = false;                    // stn_contract replays HIP graphs (stn_plan_set_graphs)
     uint64_t graph_captures = 0, graph_replays = 0;
     bool tuned = false;

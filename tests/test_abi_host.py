@@ -96,6 +96,28 @@ def test_plan_kinds_and_cost_model():
     assert full["half_state"] == 0 and full["n_passes"] == i2["n_passes"]
     assert full["bytes_per_traj"] == 2 * i2["bytes_per_traj"]
     assert plan(config_problem(2), precision=128).info()["half_state"] == 1
+    # 15-qubit tiles by default at this size (one launch shape); 14-qubit
+    # tiles on request: the same passes and bytes, three launch shapes
+    assert i2["tile_bits"] == 15 and i2["variant"] == 0
+    i14 = plan(config_problem(2), tile_bits=14).info()
+    assert i14["tile_bits"] == 14 and i14["variant"] == 2
+    assert (i14["n_passes"], i14["bytes_per_traj"], i14["max_batch"]) == (i2["n_passes"], i2["bytes_per_traj"],
+                                                                          i2["max_batch"])
+
+
+def test_plan_released_before_its_accumulators():
+    """The C ABI lets a plan's handle be released before the accumulators
+    made from it (they hold the plan until their own destroy), in either
+    order; energy-only accumulators touch no device."""
+    from workloads import config_problem
+    for plan_first in (True, False):
+        pl = plan(config_problem(0))
+        accs = [pl.accum() for _ in range(3)]
+        if plan_first:
+            pl.close()
+        for a in accs:
+            a.close()
+        pl.close()
 
 
 def test_validation_errors():
@@ -115,6 +137,9 @@ def test_validation_errors():
         plan(config_problem(2), outputs=OUT_RHO)
     with pytest.raises(StnError, match="INVALID"):
         plan(bad_q)  # ENERGY without edges is fine, bad qubit is not
+    for kw in ({"tile_bits": 13}, {"tile_bits": 16}, {"tile_bits": 15, "precision": 128}):
+        with pytest.raises(StnError, match="sv_tile_bits"):
+            plan(config_problem(2), **kw)
 
 
 def test_complex128_tiled_plan():
