@@ -73,6 +73,30 @@ def test_served_jobs_equal_plan_api_bit_for_bit():
     assert len(set(ids)) == len(ids)
 
 
+def test_served_wide_tile_job_equals_plan_api_bit_for_bit():
+    """An n=26 p=3 job, planned with 15-qubit tiles: the server runs it in
+    chunks sized by its tiles (16 trajectories here), the plan API in one
+    batch; the results agree bit for bit."""
+    from workloads import make_problem, random_regular_graph, uniform_angles
+    stn = stn_mod()
+    g, b = uniform_angles(3, 31)
+    pr = make_problem(26, random_regular_graph(26, 3, 77), g, b, 1e-3, 1e-2, 40, 5, name="wide")
+    pl = stn.Plan(pr)
+    info = pl.info()
+    assert info["plan_name"] == "sv_tiled" and info["tile_bits"] == 15 and info["max_batch"] >= pr.K
+    ref = stn.simulate_batch_ensemble(pr, plan=pl)
+    pl.close()
+    torch.cuda.empty_cache()
+    with stn.Server(hbm_budget=24 << 30, n_streams=2, max_active=2) as sv:
+        sv.submit(pr, tag=1)
+        sv.drain(300)
+        res = sv.poll(cap=4)
+    assert len(res) == 1 and res[0]["status"] == 0, res
+    r = res[0]
+    assert r["plan_name"] == "sv_tiled" and r["k_done"] == pr.K and r["chunks"] >= 2
+    assert r["energy_mean"] == ref["energy_mean"] and r["energy_se"] == ref["energy_se"]
+
+
 def test_same_result_alone_and_in_mix():
     """A job's result does not depend on what else the server runs."""
     stn = stn_mod()
