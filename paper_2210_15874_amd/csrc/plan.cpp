@@ -425,11 +425,13 @@ static uint32_t tiled_tile_bits(const stn_plan* p) {
 }
 
 // low storage bits every tile after the first keeps: two tiles of 15 qubits
-// cover 30 - coal qubits (n counts qubit n-1 of a half-state plan)
+// cover 30 - coal qubits (n counts qubit n-1 of a half-state plan), so
+// n = 27 and 28 keep two tiles per layer with 3 and 2; from n = 29 a layer
+// needs three tiles anyway, and all of them keep 4 (whole 128-byte lines)
 static uint32_t tiled_coal(const stn_plan* p) {
     if (p->opts.precision == 128) return 3;
     if (p->tile_bits == 14) return 2;
-    return p->n >= 28 ? 2u : (p->n >= 26 ? 30u - p->n : 4u);
+    return (p->n == 27 || p->n == 28) ? 30u - p->n : 4u;
 }
 
 // Pass schedule of the tiled lowering.  A layer's rotations are split over
