@@ -196,6 +196,8 @@ def main():
                          "lowering, or sliced lightcone networks when slice bits are given")
     ap.add_argument("--dedup", type=int, default=1,
                     help="time one extra headline job contracting each distinct trajectory once (0: skip)")
+    ap.add_argument("--tile-bits", type=int, default=0,
+                    help="qubits per tile of the headline plan (14 or 15; 0: the planner's default, 15 at n=26)")
     ap.add_argument("--job-tune", action="store_true",
                     help="with --job: autotune the launch shape on 256 sampled trajectories first")
     ap.add_argument("--graph-leg", action="store_true",
@@ -248,7 +250,7 @@ def main():
     stn.load()
     t0 = time.perf_counter()
     plan = stn.Plan(problem, outputs=stn.OUT_ENERGY, precision=64, max_batch=args.batch,
-                    hbm_budget=int(args.hbm_budget_gib * (1 << 30)))
+                    hbm_budget=int(args.hbm_budget_gib * (1 << 30)), tile_bits=args.tile_bits)
     plan_ms = (time.perf_counter() - t0) * 1e3
     info = plan.info()
     B = info["max_batch"]
@@ -336,7 +338,8 @@ def main():
     fp64 = fp64_leg(stn, problem, res["energies"], args.fp64_prefix) if args.fp64_prefix > 0 else None
     torch.cuda.empty_cache()
     note("plain per-trajectory loop")
-    plain = plain_loop(stn, problem, args.plain_traj, value, tune["chosen"]) if args.plain_traj > 0 else None
+    plain = (plain_loop(stn, problem, args.plain_traj, value, tune["chosen"], args.tile_bits)
+             if args.plain_traj > 0 else None)
     torch.cuda.empty_cache()
     note("rho_hat leg")
     rho_leg = rho_hat_leg(stn) if args.rho_leg else None
@@ -423,12 +426,12 @@ def fp64_leg(stn, problem, e64, prefix):
     return out
 
 
-def plain_loop(stn, problem, n_traj, batched_value, variant=None):
-    """Plain per-trajectory loop: the same kernels (and launch shape),
+def plain_loop(stn, problem, n_traj, batched_value, variant=None, tile_bits=0):
+    """Plain per-trajectory loop: the same kernels (tiles and launch shape),
     one trajectory per launch, sequential (sample, contract, reduce,
     synchronise)."""
     import torch
-    pl = stn.Plan(problem, outputs=stn.OUT_ENERGY, precision=64, max_batch=1)
+    pl = stn.Plan(problem, outputs=stn.OUT_ENERGY, precision=64, max_batch=1, tile_bits=tile_bits)
     if variant is not None:
         pl.set_variant(variant)
     acc = pl.accum()

@@ -123,6 +123,10 @@ __host__ __device__ constexpr uint32_t pad4(uint32_t t) { return t + ((t >> 5) &
 // bits {1..5}, {0, 6..9} and {0..4}: again 32 distinct banks)
 constexpr int kLdsSlots4x15 = 33791;  // pad4(2^15 - 1) + 1
 static_assert(pad4(16383) + 1 == kLdsSlots4 && pad4(32767) + 1 == kLdsSlots4x15, "exchange buffer sizes");
+// blocks of 2^11 tile indices (one wave's amplitudes in layouts L1 and L2)
+// map to disjoint slot ranges 2112 apart in both exchange maps
+static_assert(pad(2048) == 2112 && pad(2047) < 2112 && pad4(2048) == 2112 && pad4(2047) < 2112,
+              "wave blocks of the exchange maps");
 
 template <const int* T, int NB>
 __device__ __forceinline__ uint32_t thread_part(uint32_t tid) {
@@ -185,20 +189,49 @@ __device__ __forceinline__ void mix(float2 (&v)[kRegs], const float* tt) {
     }
 }
 
+// whether layouts A and B map thread bits 6 and up (the wave bits) to the
+// same tile bits
+template <const int* A, const int* B, int NB>
+__device__ constexpr bool same_wave_bits() {
+    for (int b = 6; b < NB; ++b)
+        if (A[b] != B[b]) return false;
+    return true;
+}
+
+// Orders one wave's LDS accesses across its lanes: a wave's LDS operations
+// execute in issue order, so wave-scope fences (keeping the compiler from
+// moving accesses across) suffice where no other wave touches the slots.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // write registers in layout A, read them back in layout B; TWO: through a
-// buffer of 4-byte slots, real parts first
-template <bool TWO, int NB, const int* AR, const int* AT, const int* BR, const int* BT>
+// buffer of 4-byte slots, real parts first.  LOCAL: A and B put the same
+// tile bits on the wave bits (thread bits 6 and up), so each wave writes and
+// reads only its own block of 2^11 consecutive tile indices, whose slots no
+// other wave's slots interleave (both maps add 2112 per block), and no
+// workgroup barrier is needed.  TRAIL: a barrier after the last read (not
+// needed when the next writes to the buffer are a wave's own block, or
+// start with a barrier of their own).
+template <bool TWO, int NB, bool LOCAL, bool TRAIL, const int* AR, const int* AT, const int* BR, const int* BT>
 __device__ __forceinline__ void exchange(float2 (&v)[kRegs], float* ldsf, uint32_t tid) {
+    static_assert(!LOCAL || same_wave_bits<AT, BT, NB>(), "a wave-local exchange needs layouts with the same wave bits");
+    auto sync = [] {
+        if constexpr (LOCAL) wave_lds_sync();
+        else __syncthreads();
+    };
     if constexpr (!TWO) {
         float2* lds = reinterpret_cast<float2*>(ldsf);
         float2* wa = lds + pad(thread_part<AT, NB>(tid));
 #pragma unroll
         for (int j = 0; j < kRegs; ++j) wa[pad(reg_part<AR>(j))] = v[j];
-        __syncthreads();
+        sync();
         const float2* rb = lds + pad(thread_part<BT, NB>(tid));
 #pragma unroll
         for (int j = 0; j < kRegs; ++j) v[j] = rb[pad(reg_part<BR>(j))];
-        __syncthreads();
+        if constexpr (TRAIL) sync();
     } else {
         // the bases are recomputed here rather than kept live across the
         // pass (register budget of two workgroups per CU)
@@ -210,16 +243,16 @@ __device__ __forceinline__ void exchange(float2 (&v)[kRegs], float* ldsf, uint32
         // layout A
 #pragma unroll
         for (int j = 0; j < kRegs; ++j) wa[pad4(reg_part<AR>(j))] = v[j].x;
-        __syncthreads();
+        sync();
 #pragma unroll
         for (int j = 0; j < kRegs; ++j) v[j].x = rb[pad4(reg_part<BR>(j))];
-        __syncthreads();
+        sync();
 #pragma unroll
         for (int j = 0; j < kRegs; ++j) wa[pad4(reg_part<AR>(j))] = v[j].y;
-        __syncthreads();
+        sync();
 #pragma unroll
         for (int j = 0; j < kRegs; ++j) v[j].y = rb[pad4(reg_part<BR>(j))];
-        __syncthreads();
+        if constexpr (TRAIL) sync();
     }
 }
 
@@ -538,18 +571,22 @@ __global__ __launch_bounds__(Q == 15 ? 2 * kThreads : kThreads, (Q == 14 && TWO)
         if (kDiagA) diag(v, P.da, base | zt0, dedges, wt, P.w_off, pha, m6[0]);
         if constexpr (TWO) __builtin_amdgcn_sched_barrier(0);
         mix<0, 0, 5>(v, tt);
-        exchange<TWO, NB, R0, T0, R1, T1>(v, lds, tid);
+        // the previous tile's exchanges may still be reading (wave-local
+        // ones their own blocks, the last one of a two-segment pass any
+        // block), and this exchange's writes cover every block
+        __syncthreads();
+        exchange<TWO, NB, false, false, R0, T0, R1, T1>(v, lds, tid);
         mix<0, 1, 5>(v, tt);
-        exchange<TWO, NB, R1, T1, R2, T2>(v, lds, tid);
+        exchange<TWO, NB, true, true, R1, T1, R2, T2>(v, lds, tid);
         mix<0, 2, SKIP0>(v, tt);
         if (kSeg2) {
             if constexpr (TWO) __builtin_amdgcn_sched_barrier(0);
             diag(v, P.db, base | zt2, dedges, wt, P.w_off, phb, m6[1]);
             if constexpr (TWO) __builtin_amdgcn_sched_barrier(0);
             mix<1, 2, 5>(v, tt);
-            exchange<TWO, NB, R2, T2, R1, T1>(v, lds, tid);
+            exchange<TWO, NB, true, true, R2, T2, R1, T1>(v, lds, tid);
             mix<1, 1, 5>(v, tt);
-            exchange<TWO, NB, R1, T1, R0, T0>(v, lds, tid);
+            exchange<TWO, NB, false, false, R1, T1, R0, T0>(v, lds, tid);
             mix<1, 0, SKIP0>(v, tt);
         }
 
