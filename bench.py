@@ -127,18 +127,23 @@ def cpu_baseline(problem_cfg, reps=2):
 
 def measured_traffic(kernel_source, tile_bits, launch_shape, per_launch):
     """HBM bytes per launch of the tiled pass from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary, or None if the kernel source has changed
-    since the counters were taken or they were taken with another tile width,
-    launch shape or number of trajectories per launch."""
+    FETCH_SIZE / WRITE_SIZE summary, or None if the kernel source or the
+    planner (pass schedule) has changed since the counters were taken or they
+    were taken with another tile width, launch shape or number of
+    trajectories per launch."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "sv_pass_qaoa_n26_p4_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    with open(os.path.join(ROOT, kernel_source), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != t["source_sha256"]:
+    # the kernel source and the planner that sets the pass schedule
+    for src, key in ((kernel_source, "source_sha256"), (t.get("schedule_source"), "schedule_source_sha256")):
+        if not src:
             return None
+        with open(os.path.join(ROOT, src), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != t.get(key):
+                return None
     if (t.get("tile_bits") != tile_bits or t.get("launch_shape") != launch_shape
             or t.get("trajectories_per_launch") != per_launch):
         return None

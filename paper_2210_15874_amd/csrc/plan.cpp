@@ -461,10 +461,14 @@ void schedule_tiled(stn_plan* p, uint32_t tile_bits, uint32_t coal) {
     struct Op { int32_t layer; uint32_t tile; uint32_t mask; bool first; };
     std::vector<Op> ops;
     const uint32_t k = (uint32_t)tiles.size();
+    // 15-qubit complex64 tiles start with the last (strided, whole-line)
+    // tile: the generating and the reducing pass are then strided and the
+    // read/write passes on the contiguous tile become one more
+    const bool strided_first = p->opts.precision == 64 && tile_bits == 15 && k >= 2;
     for (uint32_t l = 0; l < p->layers.size(); ++l) {
         uint32_t mixed = 0;
         for (uint32_t i = 0; i < k; ++i) {
-            const uint32_t t = (l % 2 == 0) ? i : k - 1 - i;
+            const uint32_t t = ((l % 2 == 0) != strided_first) ? i : k - 1 - i;
             uint32_t mm = 0;
             for (uint32_t qb = 0; qb < n; ++qb)
                 if (((tiles[t] >> qb) & 1) && !((mixed >> qb) & 1) && p->layers[l].rx_gate[qb] >= 0) mm |= 1u << qb;
