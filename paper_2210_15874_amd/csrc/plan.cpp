@@ -461,10 +461,12 @@ void schedule_tiled(stn_plan* p, uint32_t tile_bits, uint32_t coal) {
     struct Op { int32_t layer; uint32_t tile; uint32_t mask; bool first; };
     std::vector<Op> ops;
     const uint32_t k = (uint32_t)tiles.size();
-    // 15-qubit complex64 tiles start with the last (strided, whole-line)
-    // tile: the generating and the reducing pass are then strided and the
-    // read/write passes on the contiguous tile become one more
-    const bool strided_first = p->opts.precision == 64 && tile_bits == 15 && k >= 2;
+    // 15-qubit complex64 tiles whose strided tiles read whole 128-byte lines
+    // start with the last tile: the generating and the reducing pass are
+    // then strided and the read/write passes on the contiguous tile become
+    // one more (shorter runs make strided writes without the line's reads
+    // costly, so n = 27, 28 keep the contiguous tile first)
+    const bool strided_first = p->opts.precision == 64 && tile_bits == 15 && k >= 2 && coal >= 4;
     for (uint32_t l = 0; l < p->layers.size(); ++l) {
         uint32_t mixed = 0;
         for (uint32_t i = 0; i < k; ++i) {
